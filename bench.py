@@ -1,0 +1,254 @@
+#!/usr/bin/env python3
+"""Throughput of sampled-compression-ratio structure prediction on one MI355X.
+
+A step is one whole prediction, ssp_predict_structure, on device-resident
+inputs: row sampling, per-row products of the sample, exact distinct counts of
+the sampled rows, the sampled ratio, and the streaming pass that writes the
+predicted nnz of every row.  The default workload is C = A.A with A the
+2^20 x 2^20 R-MAT (0.57, 0.19, 0.19, 0.05) matrix of 16 edges per row,
+duplicates merged, sampled at 0.5%.
+
+Prints one JSON line.  `value` is predicted rows per second.  Beside it:
+algorithmic HBM GB/s of the step, the roofline of the dominant phase (its
+duration from HIP events recorded on the launch stream inside the timed
+region), the reference design and exact structure timed on the same input,
+the accuracy of the prediction against the exact structure, and the CPU
+oracle timed on the host (rank 0, N = 1 only).
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
+WORKLOADS = ("rmat20", "uniform4096", "stencil128", "stencil128_x_uniform")
+
+
+def parse():
+    ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--workload", default="rmat20", choices=WORKLOADS)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-extras", action="store_true",
+                    help="skip the reference/exact timings and the accuracy figures")
+    ap.add_argument("--cpu-budget-s", type=float, default=20.0,
+                    help="seconds of oracle work for the CPU baseline")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2207_13848_amd", "csrc")
+    for f in sorted(os.listdir(csrc)):
+        with open(os.path.join(csrc, f), "rb") as fh:
+            h.update(f.encode() + b"\0" + fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_phase: str, workload: str, src_hash: str):
+    """HBM bytes per launch from committed rocprofv3 --pmc summaries, if they
+    were taken on the current kernel sources."""
+    path = os.path.join(ROOT, "profiles", f"pmc_{kernel_phase}_{workload}.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        d = json.load(f)
+    if d.get("source_hash") != src_hash:
+        return None
+    return d.get("hbm_bytes_per_launch")
+
+
+def get_workload(name: str):
+    import workloads
+    return getattr(workloads, name)()
+
+
+def phase_times(ssp, handle):
+    from paper_2207_13848_amd import _native
+    buf = (_native.SspPhaseTime * 16)()
+    n = handle._lib.ssp_timing_read(handle.ptr, buf, 16)
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(n)}
+
+
+def main():
+    args = parse()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: bench.py --gpus 1 "
+                                   "(the multi-GPU sharding is a design note, not built)"}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_2207_13848_amd as ssp
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    dev = "cuda:0"
+    t_gen = time.time()
+    w = get_workload(args.workload)
+    A, B = w.A, w.B
+    aliased = B is A
+    Ad = ssp.DeviceCSR.from_csr(A, dev)
+    Bd = Ad if aliased else ssp.DeviceCSR.from_csr(B, dev)
+    t_gen = time.time() - t_gen
+    M = A.nrows
+    h = ssp.default_handle(dev)
+    out = torch.empty(M, dtype=torch.int64, device=dev)
+    st = torch.zeros(8, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    for _ in range(args.warmup):
+        ssp.predict_structure(Ad, Bd, w.rate, w.seed, handle=h, out=out, stats=st)
+    torch.cuda.synchronize()
+    h._lib.ssp_timing_enable(h.ptr, 1)
+    phase_times(ssp, h)  # clear
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        ssp.predict_structure(Ad, Bd, w.rate, w.seed, handle=h, out=out, stats=st)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    phases = phase_times(ssp, h)
+    h._lib.ssp_timing_enable(h.ptr, 0)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    stats = ssp.read_stats(st)
+
+    # ---- algorithmic bytes (integers of the CSR format: 4-byte indices)
+    nnzA, K = A.nnz, A.ncols
+    flop_bytes = 4 * (M + 1) + 4 * nnzA + (0 if aliased else 4 * (K + 1)) + 8 * M
+    n_s, a_s, f_s = stats["n_sampled"], stats["a_sample_nnz"], stats["sample_flop"]
+    sym_bytes = 8 * n_s + 12 * a_s + 4 * f_s
+    sample_bytes = 8 * n_s + 12 * a_s
+    step_bytes = flop_bytes + sym_bytes
+    per_phase = {}
+    for name, (n, ms) in phases.items():
+        per_phase[name] = {"launches": n, "avg_us": 1e3 * ms / max(n, 1)}
+    phase_bytes = {"flop": flop_bytes, "symbolic": sym_bytes, "sample_bin": sample_bytes,
+                   "finalize": 0}
+    dom = max((p for p in per_phase if p in phase_bytes and phase_bytes[p] > 0),
+              key=lambda p: per_phase[p]["avg_us"])
+    dom_us = per_phase[dom]["avg_us"]
+    achieved = phase_bytes[dom] / (dom_us * 1e-6) / 1e9
+    src_hash = kernel_source_hash()
+    traffic = load_traffic(dom, w.name, src_hash)
+    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": traffic, "algorithmic_bytes": phase_bytes[dom],
+                "avg_launch_us": round(dom_us, 2)}
+    phase_report = {}
+    for p, d in per_phase.items():
+        r = dict(d)
+        r["avg_us"] = round(r["avg_us"], 2)
+        if phase_bytes.get(p):
+            r["algorithmic_bytes"] = phase_bytes[p]
+            r["gbps"] = round(phase_bytes[p] / (d["avg_us"] * 1e-6) / 1e9, 1)
+            r["frac_of_hbm_peak"] = round(r["gbps"] / HBM_PEAK_GBS, 4)
+        phase_report[p] = r
+
+    result = {
+        "metric": "predicted rows/s (sampled-CR SpGEMM structure prediction)",
+        "value": round(M / (ms_per_step * 1e-3), 1),
+        "unit": "rows/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_per_step, 4),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": w.name, "rows": M, "cols": B.ncols, "nnz_A": nnzA,
+                   "nnz_B": B.nnz, "sample_rate": w.rate, "seed": w.seed,
+                   "sampler": "bernoulli-splitmix64"},
+        "hbm_gbps_algorithmic": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
+        "nnz_A_per_s": round(nnzA / (ms_per_step * 1e-3), 1),
+        "products_per_s": round(stats["total_flop"] / (ms_per_step * 1e-3), 1),
+        "step_algorithmic_bytes": step_bytes,
+        "roofline": roofline,
+        "phases": phase_report,
+        "stats": stats,
+        "kernel_source_hash": src_hash,
+        "generate_s": round(t_gen, 2),
+    }
+
+    if not args.no_extras:
+        # reference design and exact structure on the same input
+        ref_out = torch.empty(M, dtype=torch.int64, device=dev)
+        ref_st = torch.zeros(8, dtype=torch.int64, device=dev)
+        ex_out = torch.empty(M, dtype=torch.int64, device=dev)
+        ex_st = torch.zeros(8, dtype=torch.int64, device=dev)
+        for fn in ("ref", "exact"):
+            reps = 5
+            for i in range(reps + 1):
+                if i == 1:
+                    torch.cuda.synchronize()
+                    ta = time.perf_counter()
+                if fn == "ref":
+                    ssp.reference_estimate(Ad, Bd, w.rate, w.seed, handle=h, out=ref_out,
+                                           stats=ref_st)
+                else:
+                    ssp.exact_structure(Ad, Bd, handle=h, out=ex_out, stats=ex_st)
+            torch.cuda.synchronize()
+            result[f"{fn}_ms"] = round((time.perf_counter() - ta) * 1e3 / reps, 4)
+        Z = ssp.read_stats(ex_st)["out_sum"]
+        F = stats["total_flop"]
+        z1 = stats["sample_nnz"] * M / n_s if n_s else None
+        fstar = f_s * M / n_s if n_s else None
+        z2 = F * stats["sample_nnz"] / f_s if f_s else None
+        exact_np = ex_out.cpu().numpy()
+        pred_np = out.cpu().numpy()
+        nz = exact_np > 0
+        result["accuracy"] = {
+            "Z": Z, "F": F, "CR": round(F / Z, 4) if Z else None,
+            "eps1": (z1 / Z - 1) if (Z and z1 is not None) else None,
+            "epsf": (fstar / F - 1) if (F and fstar is not None) else None,
+            "eps2": (z2 / Z - 1) if (Z and z2 is not None) else None,
+            "eps2_alloc": stats["out_sum"] / Z - 1 if Z else None,
+            "rows_under_predicted": int(np.sum(pred_np < exact_np)),
+            "mean_abs_row_rel_err": float(np.mean(np.abs(pred_np[nz] - exact_np[nz]) /
+                                                  exact_np[nz])) if nz.any() else None,
+        }
+        result["predict_vs_exact_time"] = round(ms_per_step / result["exact_ms"], 4)
+
+    if not args.no_cpu_baseline:
+        import oracle
+        cores = 1
+        oracle.predict(A, B, w.rate, w.seed)  # warm-up (page-in)
+        runs, tc0 = 0, time.perf_counter()
+        while True:
+            oracle.predict(A, B, w.rate, w.seed)
+            runs += 1
+            if time.perf_counter() - tc0 >= args.cpu_budget_s or runs >= 10:
+                break
+        t_cpu = (time.perf_counter() - tc0) / runs
+        cpu_model = ""
+        try:
+            for line in open("/proc/cpuinfo"):
+                if line.startswith("model name"):
+                    cpu_model = line.split(":", 1)[1].strip()
+                    break
+        except OSError:
+            pass
+        result["cpu_baseline"] = {
+            "value": round(M / t_cpu, 1), "unit": "rows/s", "cores": cores, "kind": "oracle",
+            "sample": f"the whole {w.name} prediction (all {M} rows), serial C oracle, "
+                      f"1 warm-up + {runs} timed runs, {t_cpu:.2f} s each",
+            "host_cpu": cpu_model, "host_nproc": os.cpu_count()}
+
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,204 @@
+/*
+ * ssp.h -- sampled-compression-ratio structure prediction for SpGEMM on AMD
+ * Instinct MI355X (gfx950).
+ *
+ * The method is that of Du et al., "Predicting the Output Structure of Sparse
+ * Matrix Multiplication with Sampled Compression Ratio" (arXiv 2207.13848):
+ * for C = A.B it counts the intermediate products of every output row
+ * (Sec. V-A, Alg. 1), samples rows of A (Sec. IV-A), counts the distinct
+ * output columns of the sampled rows exactly (Sec. IV-B, Alg. 2), forms the
+ * sampled compression ratio r* = f* / z* and predicts every row as its product
+ * count divided by r* (Sec. IV-D, Eq. (4)).
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Matrices are CSR, structure only (no values): int32 row pointers
+ *    rpt[nrows+1] with rpt[0] = 0, non-decreasing, rpt[nrows] = nnz, and int32
+ *    column indices col[nnz] in [0, ncols).  Rows may be unsorted and may
+ *    repeat a column: product counts count stored entries, distinct counts
+ *    count distinct columns.  nnz must fit in int32.
+ *  - All array pointers in ssp_csr, all outputs and the optional ssp_stats
+ *    are DEVICE pointers on the handle's device.  The caller owns them and
+ *    keeps them alive until the work queued on `stream` has finished.
+ *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
+ *    Every compute entry point only enqueues work: it returns once the
+ *    kernels are queued and never waits for the device.
+ *  - The library owns one device workspace per handle.  It grows on demand
+ *    (hipMalloc) up to the handle's HBM budget; once a call of a given size
+ *    has run, repeated calls of that size or smaller allocate nothing.  A
+ *    handle serves one stream at a time: calls on one handle must not run
+ *    concurrently on different streams.
+ *  - Host-checkable problems return a negative status synchronously and queue
+ *    nothing: null pointers, negative sizes, A.ncols != B.nrows, a rate that
+ *    is NaN or outside [0, 1], nnz beyond int32, a workspace beyond the
+ *    budget.  The CONTENTS of the CSR arrays are not checked on the compute
+ *    path (out-of-range columns are undefined behaviour); ssp_validate_csr is
+ *    the explicit check.  HIP failures return SSP_ERR_HIP; ssp_last_error()
+ *    gives the HIP message.
+ *  - Degenerate shapes are valid: M = 0 only clears the stats; K = 0 or N = 0 give
+ *    zero counts.  A and B may alias (C = A.A).
+ *  - All results are integers and are independent of launch configuration,
+ *    thread timing and tuning: two calls with the same inputs give the same
+ *    bytes.
+ */
+#ifndef SSP_H
+#define SSP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#if defined(__GNUC__) || defined(__clang__)
+#define SSP_API __attribute__((visibility("default")))
+#else
+#define SSP_API
+#endif
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SSP_OK = 0,
+    SSP_ERR_INVALID_ARG = -1,  /* null pointer, negative size, bad rate    */
+    SSP_ERR_DIM_MISMATCH = -2, /* A.ncols != B.nrows                        */
+    SSP_ERR_OVERFLOW = -3,     /* a size does not fit the int32 CSR format  */
+    SSP_ERR_BUDGET = -4,       /* workspace would exceed the HBM budget     */
+    SSP_ERR_OOM = -5,          /* hipMalloc failed                          */
+    SSP_ERR_HIP = -6,          /* a HIP runtime call failed                 */
+    SSP_ERR_NO_DEVICE = -7,    /* no such device / not a usable GPU         */
+    SSP_ERR_INVALID_CSR = -8,  /* reserved for CSR validation results       */
+    SSP_ERR_BUSY = -9,         /* a resource (slot, queue) is full          */
+    SSP_ERR_NOT_READY = -10    /* asynchronous result not finished yet      */
+} ssp_status;
+
+typedef struct ssp_context* ssp_handle;
+
+/* Structure-only CSR matrix in device memory. */
+typedef struct {
+    int64_t nrows;
+    int64_t ncols;
+    int64_t nnz;        /* = rpt[nrows]                                     */
+    const int32_t* rpt; /* device, nrows + 1 entries                        */
+    const int32_t* col; /* device, nnz entries, each in [0, ncols)          */
+} ssp_csr;
+
+/*
+ * Statistics of one call, written to device memory (64 bytes).  Names follow
+ * the paper: F = FLOP(C) (Alg. 1), n_s sampled rows, f* = sampled FLOP and
+ * z* = sampled NNZ (Alg. 2).  The predicted total of Eq. (4) is the exact
+ * rational Z2* = F z* / f*; the reference design's is Z1* = z* M / n_s.
+ */
+typedef struct {
+    uint64_t total_flop;  /* F                                            */
+    uint64_t n_sampled;   /* n_s (paper sampler: number of draws)         */
+    uint64_t sample_flop; /* f*                                           */
+    uint64_t sample_nnz;  /* z*                                           */
+    uint64_t out_sum;     /* sum of the per-row output of this call       */
+    uint64_t nrows;       /* M                                            */
+    uint64_t flags;       /* SSP_FLAG_* bits                              */
+    uint64_t a_sample_nnz; /* stored entries of A in the sampled rows     */
+} ssp_stats;
+
+/* f* = 0 (no sampled row has a product): the ratio is undefined and every
+ * row falls back to its product count, the upper bound. */
+#define SSP_FLAG_EMPTY_SAMPLE 1u
+/* some row of the reference design exceeded INT64_MAX and was saturated */
+#define SSP_FLAG_SATURATED 2u
+
+/* Row sampler.  BERNOULLI: row i is sampled iff
+ * (splitmix64(seed, i) >> 11) < floor(rate * 2^53), splitmix64(seed, i) being
+ * the (i+1)-th output of the splitmix64 stream (Steele, Lea & Flood 2014)
+ * whose state starts at seed.  PAPER: the fixed-count sampler of Alg. 2 and
+ * Sec. V-B, min(floor(0.003 M), 300) draws with replacement, draw r picking
+ * row (M * (splitmix64(seed, r) >> 11)) >> 53; `rate` is ignored. */
+typedef enum { SSP_SAMPLER_BERNOULLI = 0, SSP_SAMPLER_PAPER = 1 } ssp_sampler;
+
+/* ------------------------------------------------------------ lifetime */
+
+/* Create a handle on HIP device `device`.  hbm_budget_bytes bounds the
+ * workspace the handle may allocate (0 = no bound).  Allocates nothing yet. */
+SSP_API ssp_status ssp_create(ssp_handle* h, int device, size_t hbm_budget_bytes);
+
+/* Release the handle and its workspace.  Waits for the device first. */
+SSP_API ssp_status ssp_destroy(ssp_handle h);
+
+/* Workspace bytes the handle holds now. */
+SSP_API size_t ssp_workspace_bytes(ssp_handle h);
+
+/* ------------------------------------------------------ the hot path */
+
+/*
+ * Predicted nonzeros per row of C = A.B by the proposed method (Sec. IV-D,
+ * Eq. (4); Alg. 2): with the Bernoulli sampler at `sample_rate` and `seed`,
+ *     nnz_pred[i] = ceil(row_flop[i] * z* / f*)      (exact integers),
+ * row_flop[i] being the intermediate products of row i (Alg. 1).  When
+ * f* = 0 every row gets row_flop[i] and SSP_FLAG_EMPTY_SAMPLE is set.
+ *   nnz_pred : device int64[A.nrows], written.
+ *   row_flop : device int64[A.nrows] or NULL; if given, the per-row product
+ *              counts (the upper-bound structure) are written too.
+ *   stats    : device ssp_stats or NULL.
+ */
+SSP_API ssp_status ssp_predict_structure(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
+                                 double sample_rate, uint64_t seed, int64_t* nnz_pred,
+                                 int64_t* row_flop, ssp_stats* stats, void* stream);
+
+/* As ssp_predict_structure with an explicit sampler (see ssp_sampler). */
+SSP_API ssp_status ssp_predict_structure_ex(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
+                                    ssp_sampler sampler, double sample_rate, uint64_t seed,
+                                    int64_t* nnz_pred, int64_t* row_flop, ssp_stats* stats,
+                                    void* stream);
+
+/*
+ * The reference design of the existing sampling estimator on the same sample
+ * (Sec. IV-C, Eq. (2)): Z1* = z* / p with p = n_s / M, and every row gets
+ *     nnz_ref[i] = ceil(row_flop[i] * z* * M / (n_s * F)),
+ * not clamped; INT64_MAX with SSP_FLAG_SATURATED if a value does not fit.
+ * Same fallback as above when f* = 0.
+ *   nnz_ref : device int64[A.nrows], written.
+ */
+SSP_API ssp_status ssp_reference_estimate(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
+                                  ssp_sampler sampler, double sample_rate, uint64_t seed,
+                                  int64_t* nnz_ref, ssp_stats* stats, void* stream);
+
+/*
+ * The precise method (Sec. I, the symbolic phase): the exact number of
+ * distinct columns of every row of C = A.B.  stats->out_sum = Z = NNZ(C),
+ * stats->total_flop = F; the sample fields are zero.
+ *   nnz_exact : device int64[A.nrows], written.
+ */
+SSP_API ssp_status ssp_exact_structure(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
+                               int64_t* nnz_exact, ssp_stats* stats, void* stream);
+
+/*
+ * Explicit CSR check (the compute entry points do not check contents):
+ * counts the violations of rpt[0] = 0, rpt[i] <= rpt[i+1], rpt[nrows] = nnz
+ * and 0 <= col < ncols, and writes the count to the device int64 *n_bad.
+ */
+SSP_API ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* M, int64_t* n_bad, void* stream);
+
+/* ------------------------------------------------ diagnostics, strings */
+
+/* Per-phase device timing.  While enabled, every phase a call enqueues is
+ * bracketed by two hipEvents on the call's stream (phases: "sample_bin",
+ * "symbolic", "finalize", "flop", "ref_rows").  ssp_timing_read waits for the
+ * recorded events, writes up to `max` aggregated entries and clears them. */
+typedef struct {
+    char name[24];
+    uint64_t launches;
+    double total_ms;
+} ssp_phase_time;
+
+SSP_API ssp_status ssp_timing_enable(ssp_handle h, int enable);
+SSP_API int ssp_timing_read(ssp_handle h, ssp_phase_time* out, int max);
+
+SSP_API const char* ssp_status_string(ssp_status s);
+/* Message of the last failing HIP call made through this handle ("" if none). */
+SSP_API const char* ssp_last_error(ssp_handle h);
+/* Library version string. */
+SSP_API const char* ssp_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SSP_H */

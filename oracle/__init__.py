@@ -52,7 +52,7 @@ def build(force: bool = False) -> str:
 class _Stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in
                 ("total_flop", "n_sampled", "sample_flop", "sample_nnz", "out_sum", "nrows",
-                 "flags", "reserved")]
+                 "flags", "a_sample_nnz")]
 
 
 _lib = None
@@ -111,11 +111,12 @@ class Stats:
     out_sum: int      # sum of the per-row outputs
     nrows: int        # M
     flags: int
+    a_sample_nnz: int  # stored entries of A in the sampled rows
 
     @classmethod
     def _from(cls, s: _Stats) -> "Stats":
         return cls(s.total_flop, s.n_sampled, s.sample_flop, s.sample_nnz, s.out_sum, s.nrows,
-                   s.flags)
+                   s.flags, s.a_sample_nnz)
 
     # --- Eq. (2)-(4) as exact rationals (None where undefined) --------------
     @property

@@ -35,7 +35,7 @@ typedef struct {
     uint64_t out_sum;     /* sum of the per-row output                               */
     uint64_t nrows;       /* M                                                       */
     uint64_t flags;       /* bit 0 empty sample (fallback), bit 1 saturated output   */
-    uint64_t reserved;
+    uint64_t a_sample_nnz; /* stored entries of A in the sampled rows (per draw)     */
 } orc_stats;
 
 #define ORC_FLAG_EMPTY_SAMPLE 1u
@@ -204,16 +204,18 @@ static int sample_sums(int64_t M, const int32_t* Arpt, const int32_t* Acol, cons
     }
     int32_t* buf = (int32_t*)malloc((size_t)(maxf > 0 ? maxf : 1) * sizeof(int32_t));
     if (!buf) { free(rows); return ORC_ERR_MEM; }
-    uint64_t fs = 0, zs = 0;
+    uint64_t fs = 0, zs = 0, as = 0;
     for (int64_t s = 0; s < n; ++s) {
         fs += orc_row_flop_one(rows[s], Arpt, Acol, Brpt);
         zs += orc_row_nnz_one(rows[s], Arpt, Acol, Brpt, Bcol, buf);
+        as += (uint64_t)(Arpt[rows[s] + 1] - Arpt[rows[s]]);
     }
     free(buf);
     free(rows);
     st->n_sampled = (uint64_t)n;
     st->sample_flop = fs;
     st->sample_nnz = zs;
+    st->a_sample_nnz = as;
     return ORC_OK;
 }
 

@@ -1,0 +1,206 @@
+"""Sampled-compression-ratio structure prediction for SpGEMM on MI355X.
+
+Python binding of the C ABI in ``include/ssp.h``.  Every step of the method
+runs in the HIP kernels of ``libssp.so``; this module only marshals arguments.
+PyTorch supplies device memory and the current stream.
+
+    import paper_2207_13848_amd as ssp
+    A = ssp.DeviceCSR.from_host(rpt, col, ncols)          # int32 CSR
+    pred, row_flop, stats = ssp.predict_structure(A, A, 0.01, seed=1001)
+
+Method: Du et al., arXiv 2207.13848 -- row FLOP (Alg. 1), row sampling of A
+(Sec. IV-A), exact NNZ of the sampled rows (Alg. 2), sampled compression ratio
+and per-row prediction ceil(row_flop * z* / f*) (Sec. IV-D, Eq. (4)).
+"""
+from __future__ import annotations
+
+import ctypes
+from dataclasses import dataclass
+
+import torch
+
+from . import _native
+from ._native import (FLAG_EMPTY_SAMPLE, FLAG_SATURATED, SAMPLER_BERNOULLI, SAMPLER_PAPER,
+                      SspError)
+
+__all__ = ["DeviceCSR", "Handle", "predict_structure", "reference_estimate", "exact_structure",
+           "validate_csr", "read_stats", "default_handle", "SspError", "FLAG_EMPTY_SAMPLE",
+           "FLAG_SATURATED", "SAMPLER_BERNOULLI", "SAMPLER_PAPER", "version"]
+
+
+def version() -> str:
+    return _native.load().ssp_version().decode()
+
+
+@dataclass
+class DeviceCSR:
+    """Structure-only CSR on the GPU: rpt int32[nrows+1], col int32[nnz]."""
+    rpt: torch.Tensor
+    col: torch.Tensor
+    ncols: int
+
+    @property
+    def nrows(self) -> int:
+        return int(self.rpt.numel()) - 1
+
+    @property
+    def nnz(self) -> int:
+        return int(self.col.numel())
+
+    @property
+    def device(self) -> torch.device:
+        return self.rpt.device
+
+    @classmethod
+    def from_host(cls, rpt, col, ncols: int, device="cuda") -> "DeviceCSR":
+        r = torch.as_tensor(rpt, dtype=torch.int32).to(device).contiguous()
+        c = torch.as_tensor(col, dtype=torch.int32).to(device).contiguous()
+        return cls(r, c, int(ncols))
+
+    @classmethod
+    def from_csr(cls, m, device="cuda") -> "DeviceCSR":
+        """From any host object with rpt, col (int32 arrays) and ncols."""
+        return cls.from_host(m.rpt, m.col, m.ncols, device)
+
+    def _c(self) -> _native.SspCsr:
+        if self.rpt.dtype != torch.int32 or self.col.dtype != torch.int32:
+            raise TypeError("CSR arrays must be int32")
+        if not (self.rpt.is_contiguous() and self.col.is_contiguous()):
+            raise ValueError("CSR arrays must be contiguous")
+        return _native.SspCsr(self.nrows, self.ncols, self.nnz, self.rpt.data_ptr(),
+                              self.col.data_ptr() if self.nnz else 0)
+
+
+class Handle:
+    """Owns the library handle (and its device workspace) for one device."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self._lib = _native.load()
+        h = ctypes.c_void_p()
+        st = self._lib.ssp_create(ctypes.byref(h), int(device), int(hbm_budget_bytes))
+        if st != 0:
+            raise SspError(st, "ssp_create")
+        self.ptr = h
+        self.device = int(device)
+
+    def close(self):
+        if self.ptr:
+            self._lib.ssp_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self._lib.ssp_workspace_bytes(self.ptr))
+
+    def check(self, status: int, where: str):
+        if status != 0:
+            detail = self._lib.ssp_last_error(self.ptr).decode(errors="replace")
+            raise SspError(status, where, detail)
+
+
+_handles: dict = {}
+
+
+def default_handle(device=None) -> Handle:
+    dev = torch.device(device if device is not None else "cuda")
+    idx = dev.index if dev.index is not None else torch.cuda.current_device()
+    if idx not in _handles:
+        _handles[idx] = Handle(idx)
+    return _handles[idx]
+
+
+def _stream_ptr(stream) -> int:
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+def _sampler_id(sampler) -> int:
+    if sampler in (SAMPLER_BERNOULLI, "bernoulli"):
+        return SAMPLER_BERNOULLI
+    if sampler in (SAMPLER_PAPER, "paper"):
+        return SAMPLER_PAPER
+    raise ValueError(f"unknown sampler {sampler!r}")
+
+
+def _new_stats(device) -> torch.Tensor:
+    return torch.zeros(8, dtype=torch.int64, device=device)
+
+
+def read_stats(stats: torch.Tensor) -> dict:
+    """Copy a device ssp_stats (int64[8] tensor) to a dict of Python ints."""
+    vals = [int(v) % (1 << 64) for v in stats.cpu().tolist()]
+    return dict(zip(_native.STATS_FIELDS, vals))
+
+
+def predict_structure(A: DeviceCSR, B: DeviceCSR, sample_rate: float, seed: int, *,
+                      sampler="bernoulli", return_row_flop: bool = False, handle=None,
+                      stream=None, out=None, stats=None):
+    """Predicted nnz per row of C = A.B (int64[M] on A's device).
+
+    Returns (nnz_pred, row_flop or None, stats tensor int64[8]).  Asynchronous
+    on `stream` (default: torch's current stream).
+    """
+    h = handle or default_handle(A.device)
+    M = A.nrows
+    pred = out if out is not None else torch.empty(M, dtype=torch.int64, device=A.device)
+    rf = torch.empty(M, dtype=torch.int64, device=A.device) if return_row_flop else None
+    st = stats if stats is not None else _new_stats(A.device)
+    a, b = A._c(), B._c()
+    status = h._lib.ssp_predict_structure_ex(
+        h.ptr, ctypes.byref(a), ctypes.byref(b), _sampler_id(sampler), float(sample_rate),
+        int(seed) % (1 << 64), pred.data_ptr() if M else 0, rf.data_ptr() if rf is not None and M
+        else 0, st.data_ptr(), _stream_ptr(stream))
+    h.check(status, "ssp_predict_structure")
+    return pred, rf, st
+
+
+def reference_estimate(A: DeviceCSR, B: DeviceCSR, sample_rate: float, seed: int, *,
+                       sampler="bernoulli", handle=None, stream=None, out=None, stats=None):
+    """Reference design (Sec. IV-C, Eq. (2)) on the same sample: (nnz_ref, stats)."""
+    h = handle or default_handle(A.device)
+    M = A.nrows
+    ref = out if out is not None else torch.empty(M, dtype=torch.int64, device=A.device)
+    st = stats if stats is not None else _new_stats(A.device)
+    a, b = A._c(), B._c()
+    status = h._lib.ssp_reference_estimate(
+        h.ptr, ctypes.byref(a), ctypes.byref(b), _sampler_id(sampler), float(sample_rate),
+        int(seed) % (1 << 64), ref.data_ptr() if M else 0, st.data_ptr(), _stream_ptr(stream))
+    h.check(status, "ssp_reference_estimate")
+    return ref, st
+
+
+def exact_structure(A: DeviceCSR, B: DeviceCSR, *, handle=None, stream=None, out=None,
+                    stats=None):
+    """Exact nnz per row of C = A.B (the precise method): (nnz_exact, stats)."""
+    h = handle or default_handle(A.device)
+    M = A.nrows
+    ex = out if out is not None else torch.empty(M, dtype=torch.int64, device=A.device)
+    st = stats if stats is not None else _new_stats(A.device)
+    a, b = A._c(), B._c()
+    status = h._lib.ssp_exact_structure(h.ptr, ctypes.byref(a), ctypes.byref(b),
+                                        ex.data_ptr() if M else 0, st.data_ptr(),
+                                        _stream_ptr(stream))
+    h.check(status, "ssp_exact_structure")
+    return ex, st
+
+
+def validate_csr(M: DeviceCSR, *, handle=None, stream=None) -> int:
+    """Number of CSR violations in M (synchronises)."""
+    h = handle or default_handle(M.device)
+    bad = torch.zeros(1, dtype=torch.int64, device=M.device)
+    m = M._c()
+    h.check(h._lib.ssp_validate_csr(h.ptr, ctypes.byref(m), bad.data_ptr(), _stream_ptr(stream)),
+            "ssp_validate_csr")
+    return int(bad.item())

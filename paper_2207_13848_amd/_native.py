@@ -1,0 +1,97 @@
+"""ctypes declarations of the C ABI in include/ssp.h (libssp.so, built in-tree).
+
+No fallback: if the HIP library is missing, loading fails with an error that
+names the build step.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "lib", "libssp.so")
+
+SSP_OK = 0
+STATUS_NAMES = {
+    0: "SSP_OK", -1: "SSP_ERR_INVALID_ARG", -2: "SSP_ERR_DIM_MISMATCH", -3: "SSP_ERR_OVERFLOW",
+    -4: "SSP_ERR_BUDGET", -5: "SSP_ERR_OOM", -6: "SSP_ERR_HIP", -7: "SSP_ERR_NO_DEVICE",
+    -8: "SSP_ERR_INVALID_CSR", -9: "SSP_ERR_BUSY", -10: "SSP_ERR_NOT_READY",
+}
+SAMPLER_BERNOULLI, SAMPLER_PAPER = 0, 1
+FLAG_EMPTY_SAMPLE, FLAG_SATURATED = 1, 2
+
+# every symbol include/ssp.h declares (checked by the ABI tests)
+EXPORTED = (
+    "ssp_create", "ssp_destroy", "ssp_workspace_bytes", "ssp_predict_structure",
+    "ssp_predict_structure_ex", "ssp_reference_estimate", "ssp_exact_structure",
+    "ssp_validate_csr", "ssp_status_string", "ssp_last_error", "ssp_version",
+    "ssp_timing_enable", "ssp_timing_read",
+)
+
+
+class SspCsr(ctypes.Structure):
+    _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
+                ("rpt", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+STATS_FIELDS = ("total_flop", "n_sampled", "sample_flop", "sample_nnz", "out_sum", "nrows",
+                "flags", "a_sample_nnz")
+
+
+class SspStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in STATS_FIELDS]
+
+
+class SspPhaseTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char * 24), ("launches", ctypes.c_uint64),
+                ("total_ms", ctypes.c_double)]
+
+
+class SspError(RuntimeError):
+    def __init__(self, status: int, where: str, detail: str = ""):
+        self.status = status
+        msg = f"{where}: {STATUS_NAMES.get(status, status)}"
+        if detail:
+            msg += f" ({detail})"
+        super().__init__(msg)
+
+
+_lib = None
+
+
+def load():
+    """Load libssp.so, declaring argument types.  Raises if it is not built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build the HIP library first "
+                          "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(LIB_PATH)
+    vp, i64, u64, dbl, cint = (ctypes.c_void_p, ctypes.c_int64, ctypes.c_uint64, ctypes.c_double,
+                               ctypes.c_int)
+    csr_p = ctypes.POINTER(SspCsr)
+    lib.ssp_create.argtypes = [ctypes.POINTER(vp), cint, ctypes.c_size_t]
+    lib.ssp_destroy.argtypes = [vp]
+    lib.ssp_workspace_bytes.argtypes = [vp]
+    lib.ssp_workspace_bytes.restype = ctypes.c_size_t
+    lib.ssp_predict_structure.argtypes = [vp, csr_p, csr_p, dbl, u64, vp, vp, vp, vp]
+    lib.ssp_predict_structure_ex.argtypes = [vp, csr_p, csr_p, cint, dbl, u64, vp, vp, vp, vp]
+    lib.ssp_reference_estimate.argtypes = [vp, csr_p, csr_p, cint, dbl, u64, vp, vp, vp]
+    lib.ssp_exact_structure.argtypes = [vp, csr_p, csr_p, vp, vp, vp]
+    lib.ssp_validate_csr.argtypes = [vp, csr_p, vp, vp]
+    for f in ("ssp_create", "ssp_destroy", "ssp_predict_structure", "ssp_predict_structure_ex",
+              "ssp_reference_estimate", "ssp_exact_structure", "ssp_validate_csr"):
+        getattr(lib, f).restype = cint
+    lib.ssp_status_string.argtypes = [cint]
+    lib.ssp_status_string.restype = ctypes.c_char_p
+    lib.ssp_last_error.argtypes = [vp]
+    lib.ssp_last_error.restype = ctypes.c_char_p
+    lib.ssp_timing_enable.argtypes = [vp, cint]
+    lib.ssp_timing_enable.restype = cint
+    lib.ssp_timing_read.argtypes = [vp, ctypes.POINTER(SspPhaseTime), cint]
+    lib.ssp_timing_read.restype = cint
+    lib.ssp_version.argtypes = []
+    lib.ssp_version.restype = ctypes.c_char_p
+    _lib = lib
+    return lib

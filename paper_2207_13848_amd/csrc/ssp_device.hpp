@@ -1,0 +1,254 @@
+// Device-side helpers shared by the HIP kernels: the row sampler's
+// splitmix64, exact 128-bit arithmetic for the per-row ceilings, and
+// wave64 / workgroup scans and reductions.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace ssp {
+
+constexpr int kWave = 64;
+
+// ------------------------------------------------------------- sampler
+
+// splitmix64 (Steele, Lea & Flood, OOPSLA 2014): the state starts at `seed`
+// and advances by the golden-ratio increment; the (i+1)-th output is the
+// state after i+1 steps passed through the finaliser.
+__host__ __device__ __forceinline__ uint64_t splitmix64_at(uint64_t seed, uint64_t i)
+{
+    uint64_t z = seed + (i + 1u) * 0x9E3779B97F4A7C15ull;
+    z ^= z >> 30;
+    z *= 0xBF58476D1CE4E5B9ull;
+    z ^= z >> 27;
+    z *= 0x94D049BB133111EBull;
+    z ^= z >> 31;
+    return z;
+}
+
+// --------------------------------------------------- 128-bit arithmetic
+
+struct u128 {
+    uint64_t lo, hi;
+};
+
+__device__ __forceinline__ u128 mul_64x64(uint64_t a, uint64_t b)
+{
+    u128 r;
+    r.lo = a * b;
+    r.hi = __umul64hi(a, b);
+    return r;
+}
+
+// Reciprocal of a normalised divisor d (top bit set):
+//   v = floor((2^128 - 1) / d) - 2^64,
+// i.e. the 64-bit quotient of the 128-bit number (~d, ~0) by d.  Plain
+// restoring division; run once per call, not per row.
+__device__ inline uint64_t reciprocal_of_normalised(uint64_t d)
+{
+    uint64_t rem = ~d, low = ~0ull, q = 0;
+    for (int b = 0; b < 64; ++b) {
+        const uint64_t top = rem >> 63;
+        rem = (rem << 1) | (low >> 63);
+        low <<= 1;
+        q <<= 1;
+        if (top || rem >= d) {
+            rem -= d;
+            q |= 1;
+        }
+    }
+    return q;
+}
+
+// 2-by-1 division with a precomputed reciprocal (Moller & Granlund,
+// "Improved division by invariant integers", IEEE TC 2011, Algorithm 4):
+// divides (u1, u0) by normalised d, needs u1 < d; returns the quotient and
+// stores the remainder.
+__device__ __forceinline__ uint64_t div_2by1(uint64_t u1, uint64_t u0, uint64_t d, uint64_t v,
+                                             uint64_t* rem)
+{
+    const u128 p = mul_64x64(v, u1);
+    const uint64_t q0 = p.lo + u0;
+    const uint64_t carry = q0 < u0;
+    uint64_t q1 = p.hi + u1 + carry + 1;
+    uint64_t r = u0 - q1 * d;
+    if (r > q0) {
+        q1 -= 1;
+        r += d;
+    }
+    if (r >= d) {
+        q1 += 1;
+        r -= d;
+    }
+    *rem = r;
+    return q1;
+}
+
+// Per-call constants to divide by the invariant f* (the sampled FLOP).
+struct Divisor {
+    uint64_t dn;    // f* << shift
+    uint64_t v;     // reciprocal of dn
+    uint32_t shift; // leading zeros of f*
+    uint32_t pad;
+};
+
+__device__ inline Divisor make_divisor(uint64_t d)
+{
+    Divisor D;
+    D.shift = (uint32_t)__clzll((long long)d);
+    D.dn = d << D.shift;
+    D.v = reciprocal_of_normalised(D.dn);
+    D.pad = 0;
+    return D;
+}
+
+// ceil(a * b / d) for a * b / d < 2^63 (true when b <= d and a < 2^63).
+__device__ __forceinline__ uint64_t ceil_mul_div(uint64_t a, uint64_t b, const Divisor& D)
+{
+    const u128 x = mul_64x64(a, b);
+    const uint32_t s = D.shift;
+    const uint64_t u1 = s ? ((x.hi << s) | (x.lo >> (64 - s))) : x.hi;
+    const uint64_t u0 = x.lo << s;
+    uint64_t r;
+    const uint64_t q = div_2by1(u1, u0, D.dn, D.v, &r);
+    return q + (r != 0);
+}
+
+__device__ __forceinline__ bool u128_lt(u128 a, u128 b)
+{
+    return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
+}
+
+__device__ __forceinline__ u128 u128_sub(u128 a, u128 b)
+{
+    u128 r;
+    r.lo = a.lo - b.lo;
+    r.hi = a.hi - b.hi - (a.lo < b.lo);
+    return r;
+}
+
+__device__ __forceinline__ int u128_clz(u128 a)
+{
+    return a.hi ? __clzll((long long)a.hi) : 64 + (a.lo ? __clzll((long long)a.lo) : 64);
+}
+
+__device__ __forceinline__ u128 u128_shl(u128 a, int s)
+{
+    if (s == 0) return a;
+    if (s >= 64) return u128{0, a.lo << (s - 64)};
+    return u128{a.lo << s, (a.hi << s) | (a.lo >> (64 - s))};
+}
+
+// ceil(n / d) for 128-bit n and d > 0, by shift-and-subtract (the
+// reference design only; not on the proposed method's path).
+__device__ inline u128 u128_ceil_div(u128 n, u128 d)
+{
+    u128 q{0, 0};
+    if (u128_lt(n, d)) {
+        return (n.lo | n.hi) ? u128{1, 0} : u128{0, 0};
+    }
+    const int sh = u128_clz(d) - u128_clz(n);
+    u128 dd = u128_shl(d, sh);
+    u128 r = n;
+    for (int b = sh; b >= 0; --b) {
+        if (!u128_lt(r, dd)) {
+            r = u128_sub(r, dd);
+            if (b >= 64) q.hi |= 1ull << (b - 64);
+            else q.lo |= 1ull << b;
+        }
+        dd = u128{(dd.lo >> 1) | (dd.hi << 63), dd.hi >> 1};
+    }
+    if (r.lo | r.hi) {
+        q.lo += 1;
+        q.hi += (q.lo == 0);
+    }
+    return q;
+}
+
+// ---------------------------------------------------- wave / block ops
+
+__device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
+
+template <typename T>
+__device__ __forceinline__ T wave_sum(T v)
+{
+#pragma unroll
+    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
+    return v;
+}
+
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T v)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int o = 1; o < kWave; o <<= 1) {
+        const T u = __shfl_up(v, o, kWave);
+        if (lane >= o) v += u;
+    }
+    return v;
+}
+
+// Exclusive scan over the workgroup (NT threads, a multiple of 64).  `sm`
+// needs NT/64 entries.  Ends with a barrier so `sm` can be reused.
+template <int NT, typename T>
+__device__ __forceinline__ T block_excl_scan(T v, T* sm, T* total)
+{
+    const T inc = wave_incl_scan(v);
+    if constexpr (NT == kWave) {
+        *total = __shfl(inc, kWave - 1, kWave);
+        return inc - v;
+    } else {
+        const int wid = threadIdx.x / kWave;
+        if (lane_id() == kWave - 1) sm[wid] = inc;
+        __syncthreads();
+        T pre = 0, tot = 0;
+#pragma unroll
+        for (int w = 0; w < NT / kWave; ++w) {
+            const T x = sm[w];
+            pre += (w < wid) ? x : T(0);
+            tot += x;
+        }
+        __syncthreads();
+        *total = tot;
+        return pre + inc - v;
+    }
+}
+
+// Sum over the workgroup, returned to every thread.  `sm` needs NT/64 entries.
+template <int NT, typename T>
+__device__ __forceinline__ T block_sum(T v, T* sm)
+{
+    v = wave_sum(v);
+    if constexpr (NT == kWave) {
+        return v;
+    } else {
+        const int wid = threadIdx.x / kWave;
+        if (lane_id() == 0) sm[wid] = v;
+        __syncthreads();
+        T tot = 0;
+#pragma unroll
+        for (int w = 0; w < NT / kWave; ++w) tot += sm[w];
+        __syncthreads();
+        return tot;
+    }
+}
+
+// Rank of this lane among the lanes whose bit is set in `mask`.
+__device__ __forceinline__ uint32_t rank_in(uint64_t mask)
+{
+    return __builtin_amdgcn_mbcnt_hi((uint32_t)(mask >> 32),
+                                     __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
+}
+
+// Length of row k of a CSR matrix from its row pointers: one 8-byte read
+// of rpt[k], rpt[k+1] (4-byte aligned).
+__device__ __forceinline__ uint32_t csr_row_len(const int32_t* __restrict__ rpt, int32_t k)
+{
+    typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
+    i32x2 v;
+    __builtin_memcpy(&v, rpt + k, sizeof(v));
+    return (uint32_t)(v.y - v.x);
+}
+
+} // namespace ssp
