@@ -42,7 +42,22 @@ def parse():
                     help="skip the reference/exact timings and the accuracy figures")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0,
                     help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
+                    help="only run a plain device copy of BYTES three times (the reference "
+                         "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
     return ap.parse_args()
+
+
+def copy_calibration(nbytes: int):
+    import torch
+    n = nbytes // 4
+    src = torch.arange(n, dtype=torch.int32, device="cuda:0")
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    for _ in range(3):
+        dst.copy_(src)
+    torch.cuda.synchronize()
+    print(json.dumps({"copy_calibration_bytes": 4 * n, "launches": 3}), flush=True)
 
 
 def kernel_source_hash() -> str:
@@ -81,6 +96,9 @@ def phase_times(ssp, handle):
 
 def main():
     args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(json.dumps({"error": "this build runs on one GPU only: bench.py --gpus 1 "

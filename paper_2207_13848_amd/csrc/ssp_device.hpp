@@ -241,6 +241,71 @@ __device__ __forceinline__ uint32_t rank_in(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
+// OR `bits` into word `word` of an LDS bitmap for every lane of the wave
+// (all 64 lanes must call it; an inactive lane passes word = kNoWord).
+// First the word is read and only bits not yet set go on: repeated columns
+// (hub columns appear in most B rows) then cost a broadcast read instead of
+// an LDS atomic, and atomics on one word serialise.  Bits are only ever set,
+// so a stale read merely costs an extra atomic.  Runs of neighbouring lanes
+// that still target one word (sorted B rows put consecutive products in one
+// word) are then combined by a segmented OR over the wave, one atomic per run.
+constexpr uint32_t kNoWord = 0xFFFFFFFFu;
+
+// Atomic part of the above for lanes whose bits are known to be needed
+// (word = kNoWord for lanes with nothing to set).
+__device__ __forceinline__ void wave_bitmap_or_needed(uint32_t* bm, uint32_t word, uint32_t need)
+{
+    const int lane = lane_id();
+    const uint64_t valid = __ballot(word != kNoWord);
+    if (valid == 0) return;
+    const uint32_t prev = __shfl_up(word, 1, kWave);
+    const bool head = lane == 0 || prev != word;
+    const uint64_t heads = __ballot(head && word != kNoWord);
+    if (heads == valid) {  // no two neighbours share a word
+        if (word != kNoWord) atomicOr(&bm[word], need);
+        return;
+    }
+    uint32_t acc = need;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t ow = __shfl_down(word, off, kWave);
+        const uint32_t ob = __shfl_down(acc, off, kWave);
+        if (lane + off < kWave && ow == word) acc |= ob;
+    }
+    if (head && word != kNoWord) atomicOr(&bm[word], acc);
+}
+
+__device__ __forceinline__ void wave_bitmap_or(uint32_t* bm, uint32_t word, uint32_t bits)
+{
+    uint32_t need = 0;
+    if (word != kNoWord) need = bits & ~bm[word];
+    wave_bitmap_or_needed(bm, need ? word : kNoWord, need);
+}
+
+// U columns per lane at once (kNoWord = none): the U bitmap words are read
+// together, so one LDS latency covers all of them; columns outside the window
+// [clo, clo + wc) are skipped.
+template <int U>
+__device__ __forceinline__ void wave_bitmap_insert(uint32_t* bm, const uint32_t (&col)[U],
+                                                   uint32_t clo, uint32_t wc)
+{
+    uint32_t word[U], bit[U], old[U];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t cw = col[u] - clo;  // columns < 2^31: wraps above wc when col < clo
+        const bool in = col[u] != kNoWord && cw < wc;
+        word[u] = in ? (cw >> 5) : kNoWord;
+        bit[u] = 1u << (cw & 31);
+    }
+#pragma unroll
+    for (int u = 0; u < U; ++u) old[u] = bm[word[u] != kNoWord ? word[u] : 0u];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        const uint32_t need = word[u] != kNoWord ? (bit[u] & ~old[u]) : 0u;
+        wave_bitmap_or_needed(bm, need ? word[u] : kNoWord, need);
+    }
+}
+
 // Length of row k of a CSR matrix from its row pointers: one 8-byte read
 // of rpt[k], rpt[k+1] (4-byte aligned).
 __device__ __forceinline__ uint32_t csr_row_len(const int32_t* __restrict__ rpt, int32_t k)

@@ -1,18 +1,18 @@
 // HIP kernels of the prediction path for gfx950 (wave64).
 //
-// Order of one prediction (sample first, then one streaming pass):
-//   k_init          clear the statistics and counters
-//   k_sample_bin    pick the sampled rows (splitmix64), count each one's
-//                   products with one wave, add them to f*, bin the row
-//   k_sym / k_sym_big
-//                   exact distinct-column count of every binned row (LDS hash
-//                   table or LDS bitmap; long rows split over workgroups that
-//                   merge bitmaps in a global slot), summed into z*
-//   k_finalize_*    per-call constants (divisor of f*, reference fractions)
-//   k_flop          one coalesced pass over A: products of every row as a
-//                   pattern SpMV with the row lengths of B, then the per-row
-//                   output (prediction, product count, or bin for the exact
-//                   count), and the total F
+// One prediction (sample first, then one streaming pass):
+//   k_init             clear statistics and counters
+//   k_sample           per block of rows: the merge-path tile starts of the
+//                      streaming pass; the sampled rows (splitmix64), their
+//                      products (f*) and their bins
+//   k_sym, k_sym_big   exact distinct-column count of every binned row (LDS hash
+//                      table or LDS bitmap), summed into z*; long rows are cut into
+//                      parts that leave their bitmaps in global scratch
+//   k_sym_merge        ORs the parts' bitmaps; its last workgroup computes the
+//                      per-call divisor of f*
+//   k_flop             merge-path tiles over A: products of every row (a pattern
+//                      SpMV with the row lengths of B) and the per-row output
+//   k_flop_fixup       rows that span tiles, and the totals
 #pragma once
 
 #include "ssp_device.hpp"
@@ -31,7 +31,10 @@ struct BinLists {
     BinItem* b2;
     BinItem* b3;
     BigItem* b4;
-    uint32_t* slots;
+    MergeItem* merge;
+    uint32_t* scratch; // kMaxPartWindows x window words
+    int32_t win_words; // words per bitmap window (<= kWinWords)
+    int32_t nwin;      // windows covering the N columns
 };
 
 typedef unsigned long long ull;
@@ -45,7 +48,9 @@ __global__ void k_init(Ctl* ctl, ssp_stats* st, uint64_t M)
     const int t = threadIdx.x;
     if (t < 8) ctl->bin_cnt[t] = 0;
     if (t == 0) {
-        ctl->slot_ctr = 0;
+        ctl->pw_ctr = 0;
+        ctl->done_ctr = 0;
+        ctl->big_next = 0;
         ctl->fallback = 0;
         st->total_flop = 0;
         st->n_sampled = 0;
@@ -60,19 +65,53 @@ __global__ void k_init(Ctl* ctl, ssp_stats* st, uint64_t M)
 
 // ------------------------------------------------------------- binning
 
-// Bin-4 items of one long row: the row's products are cut into `nparts`
-// near-equal ranges when a global merge slot is free.
-__device__ inline void append_big(int32_t row, uint64_t rf, int64_t N, Ctl* ctl,
-                                  const BinLists& L)
+__device__ __forceinline__ int bin_of(uint64_t rf)
 {
-    const int64_t nwin = (N + kWinCols - 1) / kWinCols;
+    return rf == 0 ? 0 : rf <= kBin1Max ? 1 : rf <= kBin2Max ? 2 : rf <= kBin3Max ? 3 : 4;
+}
+
+// Merge items of a split row: one per (window, slice of kMergeSlice words).
+__device__ inline void append_merge_items(int32_t row, int32_t slot, int32_t nparts, int64_t N,
+                                          Ctl* ctl, const BinLists& L)
+{
+    const int64_t wcols_full = (int64_t)L.win_words * 32;
+    for (int w = 0; w < L.nwin; ++w) {
+        const int64_t cols = (N - w * wcols_full) < wcols_full ? (N - w * wcols_full) : wcols_full;
+        const int words = (int)((cols + 31) / 32);
+        const int slices = (words + kMergeSlice - 1) / kMergeSlice;
+        const uint32_t mb = atomicAdd(&ctl->bin_cnt[5], (uint32_t)slices);
+        for (int sl = 0; sl < slices; ++sl) {
+            MergeItem m;
+            m.row = row;
+            m.slot = slot;
+            m.nparts = nparts;
+            m.window = w;
+            m.slice = sl;
+            m.pad = 0;
+            L.merge[mb + sl] = m;
+        }
+    }
+}
+
+// Bin-4 items of one long row (single lane).  A row above kSplitTarget
+// products is cut into parts of near-equal numbers of A entries when enough
+// global part windows are left.  (The sampled path cuts its long rows by
+// products instead, in k_sample; this form serves the exact path.)
+__device__ inline void append_big(int32_t row, uint64_t rf, int32_t e0, int32_t e1, int64_t N,
+                                  Ctl* ctl, const BinLists& L)
+{
+    const int64_t alen = (int64_t)e1 - e0;
+    const int nwin = L.nwin;
     int32_t nparts = 1, slot = -1;
-    if (rf > kSplitTarget && nwin <= kSlotWindows) {
-        const uint32_t s = atomicAdd(&ctl->slot_ctr, 1u);
-        if (s < (uint32_t)kMaxSlots) {
+    if (rf > kSplitTarget && nwin <= kMaxSplitWindows && alen > 1) {
+        uint64_t want = (rf + kSplitTarget - 1) / kSplitTarget;
+        if (want > (uint64_t)kMaxParts) want = kMaxParts;
+        if (want > (uint64_t)alen) want = (uint64_t)alen;
+        const uint32_t need = (uint32_t)want * (uint32_t)nwin;
+        const uint32_t s = atomicAdd(&ctl->pw_ctr, need);
+        if (s + need <= (uint32_t)kMaxPartWindows) {
             slot = (int32_t)s;
-            const uint64_t want = (rf + kSplitTarget - 1) / kSplitTarget;
-            nparts = (int32_t)(want < (uint64_t)kMaxParts ? want : (uint64_t)kMaxParts);
+            nparts = (int32_t)want;
         }
     }
     const uint32_t base = atomicAdd(&ctl->bin_cnt[4], (uint32_t)nparts);
@@ -82,24 +121,21 @@ __device__ inline void append_big(int32_t row, uint64_t rf, int64_t N, Ctl* ctl,
         it.slot = slot;
         it.part = p;
         it.nparts = nparts;
-        it.rf = rf;
+        it.e_lo = e0 + (int32_t)(alen * p / nparts);
+        it.e_hi = e0 + (int32_t)(alen * (p + 1) / nparts);
         L.b4[base + p] = it;
     }
-}
-
-__device__ __forceinline__ int bin_of(uint64_t rf)
-{
-    return rf == 0 ? 0 : rf <= kBin1Max ? 1 : rf <= kBin2Max ? 2 : rf <= kBin3Max ? 3 : 4;
+    if (slot >= 0) append_merge_items(row, slot, nparts, N, ctl, L);
 }
 
 // One row, appended by a single lane.
-__device__ inline void append_row(int32_t row, uint64_t rf, int64_t N, Ctl* ctl,
-                                  const BinLists& L)
+__device__ inline void append_row(int32_t row, uint64_t rf, int32_t e0, int32_t e1, int64_t N,
+                                  Ctl* ctl, const BinLists& L)
 {
     const int b = bin_of(rf);
     if (b == 0) return;
     if (b == 4) {
-        append_big(row, rf, N, ctl, L);
+        append_big(row, rf, e0, e1, N, ctl, L);
         return;
     }
     BinItem it;
@@ -109,45 +145,254 @@ __device__ inline void append_row(int32_t row, uint64_t rf, int64_t N, Ctl* ctl,
     (b == 1 ? L.b1 : b == 2 ? L.b2 : L.b3)[i] = it;
 }
 
-// ----------------------------------------------------- k_sample_bin
+// --------------------------------------------------------- k_sample
 
-// One thread per candidate (a row of A in Bernoulli mode, a draw in paper
-// mode); every wave then walks its sampled rows one by one, counting each
-// row's products with all 64 lanes.
-template <bool PAPER>
-__global__ __launch_bounds__(256) void k_sample_bin(Csr A, Csr B, uint64_t seed, uint64_t thresh,
-                                                   int64_t ndraws, Ctl* ctl, ssp_stats* st,
-                                                   BinLists L)
+constexpr int kSampleThreads = 512;
+constexpr int kSampleBlock = 4096;     // candidates per block (8 per thread)
+constexpr int32_t kRowflopWaveMax = 512; // sampled rows with more entries take the workgroup
+
+// Workgroup per block of 4096 candidates (rows of A; draws of the paper's
+// sampler).  (1) Row g of the block: the merge-path tiles of the streaming
+// pass whose start diagonal b * kFlopTile lies in [rpt[g] + g, rpt[g+1] + g + 1)
+// start in row g.  (2) The block's sampled rows are compacted in LDS; each
+// gets its product count from one wave (or from the whole workgroup when the
+// row is long), 4..8 independent gathers in flight per lane.  (3) The rows go
+// to their bins with one global atomic per bin per block; n_s, f* and the
+// sampled rows' entries are added once per workgroup.  Same-address device
+// atomics serialise, so they are kept few.
+template <bool PAPER, bool SAMPLE>
+__global__ __launch_bounds__(kSampleThreads) void k_sample(Csr A, Csr B, uint64_t seed,
+                                                          uint64_t thresh, int64_t ndraws,
+                                                          int64_t ntiles,
+                                                          int32_t* __restrict__ tile_row, Ctl* ctl,
+                                                          ssp_stats* st, BinLists L)
 {
-    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
-    const int lane = lane_id();
-    int32_t row = -1;
-    if (PAPER) {
-        if (g < ndraws) {
-            const u128 x = mul_64x64((uint64_t)A.nrows, splitmix64_at(seed, (uint64_t)g) >> 11);
-            row = (int32_t)((x.lo >> 53) | (x.hi << 11));
+    constexpr int NT = kSampleThreads, NW = NT / kWave, PER = kSampleBlock / NT;
+    __shared__ int32_t s_rows[SAMPLE ? kSampleBlock : 1];
+    __shared__ uint64_t s_rf[SAMPLE ? kSampleBlock : 1];
+    __shared__ int32_t s_long[SAMPLE ? kSampleBlock : 1];
+    __shared__ uint32_t s_n, s_nlong, s_nbig, s_cnt[4], s_cur[4], s_base[4];
+    __shared__ int32_t s_E[kMaxParts + 1];
+    __shared__ int32_t s_qlast;
+    __shared__ uint32_t s_split[3];
+    __shared__ uint64_t s_red[NW + 1];
+    const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+    const int64_t M = A.nrows;
+    const int64_t ncand = SAMPLE ? (PAPER ? ndraws : M) : 0;
+    const int64_t nblocks = ((M > ncand ? M : ncand) + kSampleBlock - 1) / kSampleBlock;
+    if (blockIdx.x == 0 && t == 0) tile_row[ntiles] = (int32_t)M;
+    uint64_t fsum = 0, asum = 0, nsum = 0;
+    for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
+        const int64_t base = blk * kSampleBlock;
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int64_t g = base + u * NT + t;
+            if (g < M) {
+                const int64_t f0 = (int64_t)A.rpt[g] + g, f1 = (int64_t)A.rpt[g + 1] + g + 1;
+                for (int64_t b = (f0 + kFlopTile - 1) / kFlopTile; b * kFlopTile < f1; ++b)
+                    tile_row[b] = (int32_t)g;
+            }
         }
-    } else {
-        if (g < A.nrows && (splitmix64_at(seed, (uint64_t)g) >> 11) < thresh) row = (int32_t)g;
+        if (!SAMPLE || base >= ncand) continue;
+        if (t < 4) {
+            s_cnt[t] = 0;
+            s_cur[t] = 0;
+        }
+        if (t == 0) {
+            s_n = 0;
+            s_nlong = 0;
+            s_nbig = 0;
+        }
+        __syncthreads();
+#pragma unroll
+        for (int u = 0; u < PER; ++u) {
+            const int64_t g = base + u * NT + t;
+            int32_t row = -1;
+            if (g < ncand) {
+                if (PAPER) {
+                    const u128 x = mul_64x64((uint64_t)M, splitmix64_at(seed, (uint64_t)g) >> 11);
+                    row = (int32_t)((x.lo >> 53) | (x.hi << 11));
+                } else if ((splitmix64_at(seed, (uint64_t)g) >> 11) < thresh) {
+                    row = (int32_t)g;
+                }
+            }
+            const uint64_t mask = __ballot(row >= 0);
+            if (mask) {
+                const int leader = __ffsll((long long)mask) - 1;
+                uint32_t pos = 0;
+                if (lane == leader) pos = atomicAdd(&s_n, (uint32_t)__popcll(mask));
+                pos = __shfl(pos, leader, kWave);
+                if (row >= 0) s_rows[pos + rank_in(mask)] = row;
+            }
+        }
+        __syncthreads();
+        const uint32_t n = s_n;
+        for (uint32_t i = wave; i < n; i += NW) {  // one wave per (short) sampled row
+            const int32_t r = s_rows[i];
+            const int32_t a0 = A.rpt[r], a1 = A.rpt[r + 1];
+            if (a1 - a0 > kRowflopWaveMax) {
+                if (lane == 0) s_long[atomicAdd(&s_nlong, 1u)] = (int32_t)i;
+                continue;
+            }
+            uint64_t sum = 0;
+            for (int32_t j = a0 + lane; j < a1; j += kWave * 4) {
+                // clamped unconditional loads, masked afterwards (see flop_issue_tile)
+                int32_t c[4];
+                uint32_t len[4];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) c[v] = A.col[(j + kWave * v) < a1 ? (j + kWave * v) : a1 - 1];
+#pragma unroll
+                for (int v = 0; v < 4; ++v) len[v] = csr_row_len(B.rpt, c[v]);
+#pragma unroll
+                for (int v = 0; v < 4; ++v) sum += (j + kWave * v < a1) ? len[v] : 0u;
+            }
+            sum = wave_sum(sum);
+            if (lane == 0) {
+                s_rf[i] = sum;
+                asum += (uint64_t)(a1 - a0);
+            }
+        }
+        __syncthreads();
+        const uint32_t nlong = s_nlong;
+        for (uint32_t li = 0; li < nlong; ++li) {  // long sampled rows: the whole workgroup
+            const uint32_t i = (uint32_t)s_long[li];
+            const int32_t r = s_rows[i];
+            const int32_t a0 = A.rpt[r], a1 = A.rpt[r + 1];
+            uint64_t sum = 0;
+            for (int32_t j = a0 + t; j < a1; j += NT * 8) {
+                int32_t c[8];
+                uint32_t len[8];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) c[v] = A.col[(j + NT * v) < a1 ? (j + NT * v) : a1 - 1];
+#pragma unroll
+                for (int v = 0; v < 8; ++v) len[v] = csr_row_len(B.rpt, c[v]);
+#pragma unroll
+                for (int v = 0; v < 8; ++v) sum += (j + NT * v < a1) ? len[v] : 0u;
+            }
+            sum = block_sum<NT, uint64_t>(sum, s_red);
+            if (t == 0) {
+                s_rf[i] = sum;
+                asum += (uint64_t)(a1 - a0);
+            }
+        }
+        __syncthreads();
+        for (uint32_t i = t; i < n; i += NT) {
+            const uint64_t rf = s_rf[i];
+            fsum += rf;
+            const int b = bin_of(rf);
+            if (b >= 1 && b <= 3) atomicAdd(&s_cnt[b], 1u);
+            else if (b == 4) s_long[atomicAdd(&s_nbig, 1u)] = (int32_t)i;
+        }
+        __syncthreads();
+        if (t >= 1 && t <= 3 && s_cnt[t]) s_base[t] = atomicAdd(&ctl->bin_cnt[t], s_cnt[t]);
+        __syncthreads();
+        for (uint32_t i = t; i < n; i += NT) {
+            const uint64_t rf = s_rf[i];
+            const int b = bin_of(rf);
+            if (b >= 1 && b <= 3) {
+                const uint32_t pos = s_base[b] + atomicAdd(&s_cur[b], 1u);
+                BinItem it;
+                it.row = s_rows[i];
+                it.rf = (uint32_t)rf;
+                (b == 1 ? L.b1 : b == 2 ? L.b2 : L.b3)[pos] = it;
+            }
+        }
+        // Long rows (bin 4).  A row above kSplitTarget products is cut into
+        // parts of near-equal products: entry e (products before it: pre_e)
+        // goes to part floor(pre_e / S), S = ceil(rf / nparts), found with a
+        // workgroup scan over the row's entries.
+        __syncthreads();
+        const uint32_t nbig = s_nbig;
+        for (uint32_t bi = 0; bi < nbig; ++bi) {
+            const uint32_t i = (uint32_t)s_long[bi];
+            const int32_t r = s_rows[i];
+            const uint64_t rf = s_rf[i];
+            const int32_t e0 = A.rpt[r], e1 = A.rpt[r + 1];
+            const int64_t alen = (int64_t)e1 - e0;
+            if (t == 0) {
+                uint32_t want = 1;
+                int32_t slot = -1;
+                if (rf > kSplitTarget && L.nwin <= kMaxSplitWindows && alen > 1) {
+                    uint64_t wv = (rf + kSplitTarget - 1) / kSplitTarget;
+                    if (wv > (uint64_t)kMaxParts) wv = kMaxParts;
+                    if (wv > (uint64_t)alen) wv = (uint64_t)alen;
+                    const uint32_t need = (uint32_t)wv * (uint32_t)L.nwin;
+                    const uint32_t s0 = atomicAdd(&ctl->pw_ctr, need);
+                    if (s0 + need <= (uint32_t)kMaxPartWindows) {
+                        want = (uint32_t)wv;
+                        slot = (int32_t)s0;
+                    }
+                }
+                s_split[0] = want;
+                s_split[1] = (uint32_t)slot;
+                s_split[2] = atomicAdd(&ctl->bin_cnt[4], want);
+                s_qlast = -1;
+            }
+            __syncthreads();
+            const uint32_t want = s_split[0];
+            const int32_t slot = (int32_t)s_split[1];
+            const uint32_t base = s_split[2];
+            if (want > 1) {
+                const uint64_t S = (rf + want - 1) / want;
+                for (int p = t; p <= kMaxParts; p += NT) s_E[p] = p == 0 ? e0 : e1;
+                uint64_t carry = 0;
+                for (int32_t a = e0; a < e1; a += NT) {
+                    const int32_t j = a + t;
+                    const bool live = j < e1;
+                    const uint64_t len = live ? csr_row_len(B.rpt, A.col[j]) : 0u;
+                    uint64_t tot;
+                    __syncthreads();  // s_qlast of the previous chunk is read below
+                    const int32_t qprev_chunk = s_qlast;
+                    const uint64_t pre = carry + block_excl_scan<NT, uint64_t>(len, s_red, &tot);
+                    uint64_t qe = pre / S;
+                    if (qe > want - 1) qe = want - 1;
+                    // q of the previous entry: lane below, or the previous chunk's last
+                    int32_t qprev = __shfl_up((int32_t)qe, 1, kWave);
+                    __shared__ int32_t s_qwave[NT / kWave];
+                    if (lane == kWave - 1) s_qwave[wave] = (int32_t)qe;
+                    __syncthreads();
+                    if (lane == 0) qprev = wave == 0 ? qprev_chunk : s_qwave[wave - 1];
+                    if (live)
+                        for (int32_t p = qprev + 1; p <= (int32_t)qe; ++p) s_E[p] = j;
+                    __syncthreads();
+                    if (t == NT - 1) s_qlast = (int32_t)qe;  // live unless this is the last chunk
+                    carry += tot;
+                }
+                __syncthreads();
+                for (uint32_t p = t; p < want; p += NT) {
+                    BigItem it;
+                    it.row = r;
+                    it.slot = slot;
+                    it.part = (int32_t)p;
+                    it.nparts = (int32_t)want;
+                    it.e_lo = p == 0 ? e0 : s_E[p];
+                    it.e_hi = p + 1 == want ? e1 : s_E[p + 1];
+                    L.b4[base + p] = it;
+                }
+                if (t == 0) append_merge_items(r, slot, (int32_t)want, B.ncols, ctl, L);
+            } else if (t == 0) {
+                BigItem it;
+                it.row = r;
+                it.slot = -1;
+                it.part = 0;
+                it.nparts = 1;
+                it.e_lo = e0;
+                it.e_hi = e1;
+                L.b4[base] = it;
+            }
+            __syncthreads();
+        }
+        if (t == 0) nsum += n;
+        __syncthreads();
     }
-    uint64_t mask = __ballot(row >= 0);
-    if (mask == 0) return;
-    if (lane == 0) atomicAdd(as_ull(&st->n_sampled), (ull)__popcll(mask));
-    uint64_t fsum = 0, asum = 0;
-    while (mask) {
-        const int l = __ffsll((long long)mask) - 1;
-        mask &= mask - 1;
-        const int32_t r = __shfl(row, l, kWave);
-        const int32_t a0 = A.rpt[r], a1 = A.rpt[r + 1];
-        uint64_t s = 0;
-        for (int32_t j = a0 + lane; j < a1; j += kWave) s += csr_row_len(B.rpt, A.col[j]);
-        const uint64_t rf = wave_sum(s);
-        fsum += rf;
-        asum += (uint64_t)(a1 - a0);
-        if (lane == 0) append_row(r, rf, B.ncols, ctl, L);
+    if (!SAMPLE) return;
+    const uint64_t Fs = block_sum<NT, uint64_t>(fsum, s_red);
+    const uint64_t As = block_sum<NT, uint64_t>(asum, s_red);
+    if (t == 0) {
+        if (nsum) atomicAdd(as_ull(&st->n_sampled), (ull)nsum);
+        if (Fs) atomicAdd(as_ull(&st->sample_flop), (ull)Fs);
+        if (As) atomicAdd(as_ull(&st->a_sample_nnz), (ull)As);
     }
-    if (lane == 0 && fsum) atomicAdd(as_ull(&st->sample_flop), (ull)fsum);
-    if (lane == 0 && asum) atomicAdd(as_ull(&st->a_sample_nnz), (ull)asum);
 }
 
 // ------------------------------------------------- distinct counting
@@ -193,6 +438,7 @@ __global__ __launch_bounds__(TEAM) void k_sym(Csr A, Csr B, const BinItem* __res
     const uint32_t n = *count;
     const int t = threadIdx.x;
     const int64_t N = B.ncols;
+    uint64_t zsum = 0;
     for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
         const BinItem item = items[it];
         const uint32_t bound = (uint32_t)((int64_t)item.rf < N ? (int64_t)item.rf : N);
@@ -221,16 +467,31 @@ __global__ __launch_bounds__(TEAM) void k_sym(Csr A, Csr B, const BinItem* __res
             s_off[t] = off;
             __syncthreads();
             const int na = (a1 - a) < TEAM ? (a1 - a) : TEAM;
-            for (uint32_t p = t; p < tot; p += TEAM) {
-                int lo = 0, hi = na;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_off[mid] <= p) lo = mid;
-                    else hi = mid;
+            constexpr int U = 4;
+            // same trip count in every lane; U independent loads in flight per lane
+            for (uint32_t p0 = 0; p0 < tot; p0 += TEAM * U) {
+                uint32_t c[U];
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    // clamped product index, unconditional load, masked after
+                    const uint32_t pr = p0 + u * TEAM + t;
+                    const uint32_t p = pr < tot ? pr : tot - 1;
+                    int lo = 0, hi = na;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_off[mid] <= p) lo = mid;
+                        else hi = mid;
+                    }
+                    const uint32_t cv = (uint32_t)B.col[s_b0[lo] + (int32_t)(p - s_off[lo])];
+                    c[u] = pr < tot ? cv : kNoWord;
                 }
-                const uint32_t c = (uint32_t)B.col[s_b0[lo] + (int32_t)(p - s_off[lo])];
-                if (bitmap) atomicOr(&tab[c >> 5], 1u << (c & 31));
-                else cnt += hash_insert(tab, c, lg);
+#pragma unroll
+                for (int u = 0; u < U; ++u) {
+                    if (bitmap)
+                        wave_bitmap_or(tab, c[u] == kNoWord ? kNoWord : (c[u] >> 5), 1u << (c[u] & 31));
+                    else if (c[u] != kNoWord)
+                        cnt += hash_insert(tab, c[u], lg);
+                }
             }
             __syncthreads();
         }
@@ -238,84 +499,131 @@ __global__ __launch_bounds__(TEAM) void k_sym(Csr A, Csr B, const BinItem* __res
             for (uint32_t w = t; w < words; w += TEAM) cnt += (uint32_t)__popc(tab[w]);
         const uint32_t total = block_sum<TEAM, uint32_t>(cnt, s_red);
         if (t == 0) {
-            if (MODE == 0) {
-                atomicAdd(as_ull(&st->sample_nnz), (ull)total);
-            } else {
-                out[item.row] = (int64_t)total;
-                atomicAdd(as_ull(&st->out_sum), (ull)total);
-            }
+            zsum += total;
+            if (MODE == 1) out[item.row] = (int64_t)total;
         }
         __syncthreads();
     }
+    if (t == 0 && zsum) atomicAdd(as_ull(MODE == 0 ? &st->sample_nnz : &st->out_sum), (ull)zsum);
 }
 
-// Bin 4: long rows.  1024 threads per item, an LDS bitmap per window of
-// 2^20 columns.  An item covers the product range [plo, phi) of its row; when
-// a row is split (slot >= 0), every part ORs its window bitmap into the
-// row's global slot, and the last part to finish a window counts the merged
-// bits and clears the slot again (slots are all-zero between calls).
+// Bin 4: long rows, 1024 threads per item, an LDS bitmap per window of
+// `win_words` words.  An item covers the A entries [e_lo, e_hi) of its row (all
+// of them unless the row is split into parts).  The entries are taken 1024 at
+// a time and split by the length of the B row they name: huge ones are walked
+// by the whole workgroup, medium ones by one wave each, short ones flattened
+// (owner by binary search), so reads of B's columns stay coalesced; every
+// loop issues several independent loads per lane before using them.  An
+// unsplit item counts its bits; a part of a split row stores its window bitmap
+// to global scratch for k_sym_merge.
 template <int MODE>
 __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
                                                        const BigItem* __restrict__ items,
-                                                       const uint32_t* count, uint32_t* slots,
-                                                       ssp_stats* st, int64_t* __restrict__ out)
+                                                       const uint32_t* count, uint32_t* next,
+                                                       BinLists L, ssp_stats* st,
+                                                       int64_t* __restrict__ out)
 {
-    constexpr int TEAM = kBin4Team;
-    __shared__ uint32_t bm[kWinWords];
+    constexpr int TEAM = kBin4Team, NWAVE = TEAM / kWave;
+    extern __shared__ uint32_t bm[];
     __shared__ int32_t s_b0[TEAM];
-    __shared__ uint64_t s_off[TEAM];
+    __shared__ uint32_t s_len[TEAM];
+    __shared__ uint32_t s_soff[TEAM];
+    __shared__ int16_t s_med[TEAM];
+    __shared__ int16_t s_huge[TEAM];
     __shared__ uint64_t s_red[TEAM / kWave + 1];
-    __shared__ uint32_t s_last;
     const uint32_t n = *count;
-    const int t = threadIdx.x;
+    const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
     const int64_t N = B.ncols;
-    const int64_t nwin = (N + kWinCols - 1) / kWinCols;
-    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    const int64_t wcols_full = (int64_t)L.win_words * 32;
+    __shared__ uint32_t s_it;
+    uint64_t zsum = 0;
+    for (;;) {  // work queue: items are taken one at a time as workgroups free up
+        if (t == 0) s_it = atomicAdd(next, 1u);
+        __syncthreads();
+        const uint32_t it = s_it;
+        __syncthreads();
+        if (it >= n) break;
         const BigItem item = items[it];
-        const uint64_t np = (uint64_t)item.nparts, pp = (uint64_t)item.part;
-        const uint64_t qq = item.rf / np, rr = item.rf % np;
-        const uint64_t plo = qq * pp + (pp < rr ? pp : rr);
-        const uint64_t phi = plo + qq + (pp < rr ? 1 : 0);
-        const int32_t a0 = A.rpt[item.row], a1 = A.rpt[item.row + 1];
+        const int32_t a0 = item.e_lo, a1 = item.e_hi;
         uint64_t total = 0;
-        for (int64_t w = 0; w < nwin; ++w) {
-            const int64_t c_lo = w * kWinCols;
-            const int64_t wcols = (N - c_lo) < kWinCols ? (N - c_lo) : kWinCols;
+        for (int w = 0; w < L.nwin; ++w) {
+            const int64_t c_lo = w * wcols_full;
+            const int64_t wcols = (N - c_lo) < wcols_full ? (N - c_lo) : wcols_full;
             const int words = (int)((wcols + 31) / 32);
             for (int i = t; i < words; i += TEAM) bm[i] = 0u;
+            const uint32_t clo32 = (uint32_t)c_lo, wc32 = (uint32_t)wcols;
             __syncthreads();
-            uint64_t goff = 0;
-            for (int32_t a = a0; a < a1 && goff < phi; a += TEAM) {
+            for (int32_t a = a0; a < a1; a += TEAM) {
                 const int32_t j = a + t;
-                uint64_t len = 0;
-                int32_t b0 = 0;
-                if (j < a1) {
-                    const int32_t k = A.col[j];
-                    b0 = B.rpt[k];
-                    len = (uint64_t)(uint32_t)(B.rpt[k + 1] - b0);
-                }
-                uint64_t tot;
-                const uint64_t off = block_excl_scan<TEAM, uint64_t>(len, s_red, &tot);
+                const bool live = j < a1;
+                const int32_t k = A.col[live ? j : a1 - 1];
+                const int32_t b0 = B.rpt[k];
+                const uint32_t len = live ? (uint32_t)(B.rpt[k + 1] - b0) : 0u;
+                const bool huge = len >= kHugeLen, med = !huge && len >= kMediumLen;
+                const uint64_t packed = (med ? (1ull << 32) : 0ull) | (huge ? (1ull << 48) : 0ull) |
+                                        (uint64_t)((med || huge) ? 0u : len);
+                uint64_t ptot;
+                const uint64_t pk = block_excl_scan<TEAM, uint64_t>(packed, s_red, &ptot);
                 s_b0[t] = b0;
-                s_off[t] = off;
+                s_len[t] = len;
+                s_soff[t] = (uint32_t)pk;
+                if (med) s_med[(pk >> 32) & 0xFFFF] = (int16_t)t;
+                if (huge) s_huge[pk >> 48] = (int16_t)t;
                 __syncthreads();
+                const uint32_t nshort = (uint32_t)ptot;
+                const int nmed = (int)((ptot >> 32) & 0xFFFF), nhuge = (int)(ptot >> 48);
                 const int na = (a1 - a) < TEAM ? (a1 - a) : TEAM;
-                const uint64_t lo_p = plo > goff ? plo : goff;
-                const uint64_t hi_p = (goff + tot) < phi ? (goff + tot) : phi;
-                for (uint64_t p = lo_p + t; p < hi_p; p += TEAM) {
-                    const uint64_t q = p - goff;
-                    int lo = 0, hi = na;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_off[mid] <= q) lo = mid;
-                        else hi = mid;
+                // Every loop below has the same trip count in all lanes of a wave
+                // (wave_bitmap_or needs that) and issues U independent loads per
+                // lane before using any, to keep memory busy.
+                constexpr int U = 8, US = 4;
+                for (int h = 0; h < nhuge; ++h) {
+                    const int e = s_huge[h];
+                    const uint32_t elen = s_len[e];
+                    const int32_t* bc = B.col + s_b0[e];
+                    for (uint32_t k0 = 0; k0 < elen; k0 += TEAM * U) {
+                        uint32_t c[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const uint32_t kk = k0 + u * TEAM + t;
+                            const uint32_t cv = (uint32_t)bc[kk < elen ? kk : elen - 1];
+                            c[u] = kk < elen ? cv : kNoWord;
+                        }
+                        wave_bitmap_insert<U>(bm, c, clo32, wc32);
                     }
-                    const uint64_t c =
-                        (uint64_t)(uint32_t)B.col[(int64_t)s_b0[lo] + (int64_t)(q - s_off[lo])];
-                    const uint64_t cw = c - (uint64_t)c_lo;
-                    if (cw < (uint64_t)wcols) atomicOr(&bm[cw >> 5], 1u << (cw & 31));
                 }
-                goff += tot;
+                for (int m = wave; m < nmed; m += NWAVE) {
+                    const int e = s_med[m];
+                    const uint32_t elen = s_len[e];
+                    const int32_t* bc = B.col + s_b0[e];
+                    for (uint32_t k0 = 0; k0 < elen; k0 += kWave * U) {
+                        uint32_t c[U];
+#pragma unroll
+                        for (int u = 0; u < U; ++u) {
+                            const uint32_t kk = k0 + u * kWave + lane;
+                            const uint32_t cv = (uint32_t)bc[kk < elen ? kk : elen - 1];
+                            c[u] = kk < elen ? cv : kNoWord;
+                        }
+                        wave_bitmap_insert<U>(bm, c, clo32, wc32);
+                    }
+                }
+                for (uint32_t q0 = 0; q0 < nshort; q0 += TEAM * US) {
+                    uint32_t c[US];
+#pragma unroll
+                    for (int u = 0; u < US; ++u) {
+                        const uint32_t qr = q0 + u * TEAM + t;
+                        const uint32_t q = qr < nshort ? qr : nshort - 1;
+                        int lo = 0, hi = na;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_soff[mid] <= q) lo = mid;
+                            else hi = mid;
+                        }
+                        const uint32_t cv = (uint32_t)B.col[s_b0[lo] + (int32_t)(q - s_soff[lo])];
+                        c[u] = qr < nshort ? cv : kNoWord;
+                    }
+                    wave_bitmap_insert<US>(bm, c, clo32, wc32);
+                }
                 __syncthreads();
             }
             if (item.slot < 0) {
@@ -323,55 +631,82 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
                 for (int i = t; i < words; i += TEAM) cnt += (uint64_t)__popc(bm[i]);
                 total += block_sum<TEAM, uint64_t>(cnt, s_red);
             } else {
-                uint32_t* g = slots + (int64_t)item.slot * kSlotWords + w * kWinWords;
-                uint32_t* ctr = slots + (int64_t)item.slot * kSlotWords +
-                                (int64_t)kSlotWindows * kWinWords + w;
-                for (int i = t; i < words; i += TEAM) {
-                    const uint32_t x = bm[i];
-                    if (x) atomicOr(&g[i], x);
-                }
-                __threadfence();
-                __syncthreads();
-                if (t == 0) s_last = (atomicAdd(ctr, 1u) == (uint32_t)item.nparts - 1u);
-                __syncthreads();
-                if (s_last) {
-                    __threadfence();
-                    uint64_t cnt = 0;
-                    for (int i = t; i < words; i += TEAM) {
-                        const uint32_t x =
-                            __hip_atomic_load(&g[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                        cnt += (uint64_t)__popc(x);
-                        if (x) __hip_atomic_store(&g[i], 0u, __ATOMIC_RELAXED,
-                                                  __HIP_MEMORY_SCOPE_AGENT);
-                    }
-                    total += block_sum<TEAM, uint64_t>(cnt, s_red);
-                    if (t == 0)
-                        __hip_atomic_store(ctr, 0u, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-                }
+                uint32_t* g = L.scratch + ((int64_t)item.slot + (int64_t)item.part * L.nwin + w) *
+                                              (int64_t)L.win_words;
+                for (int i = t; i < words; i += TEAM) g[i] = bm[i];
             }
             __syncthreads();
         }
         if (t == 0 && total) {
-            if (MODE == 0) {
-                atomicAdd(as_ull(&st->sample_nnz), (ull)total);
-            } else {
-                atomicAdd(reinterpret_cast<ull*>(&out[item.row]), (ull)total);
-                atomicAdd(as_ull(&st->out_sum), (ull)total);
-            }
+            zsum += total;
+            if (MODE == 1) atomicAdd(reinterpret_cast<ull*>(&out[item.row]), (ull)total);
         }
-        __syncthreads();
     }
+    if (t == 0 && zsum) atomicAdd(as_ull(MODE == 0 ? &st->sample_nnz : &st->out_sum), (ull)zsum);
 }
 
-// ---------------------------------------------------------- finalize
-
-__global__ void k_finalize_predict(Ctl* ctl, ssp_stats* st)
+// ORs the part bitmaps of split rows, one slice of a window per item.  With
+// `finalize`, the last workgroup to finish (after every symbolic kernel has
+// added to z*) computes the per-call divisor of f*.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_sym_merge(const MergeItem* __restrict__ items,
+                                                  const uint32_t* count, BinLists L, int64_t N,
+                                                  Ctl* ctl, ssp_stats* st,
+                                                  int64_t* __restrict__ out, int finalize)
 {
-    if (threadIdx.x != 0) return;
-    const uint64_t fs = st->sample_flop;
+    __shared__ uint64_t s_red[256 / kWave + 1];
+    __shared__ uint32_t s_last;
+    const uint32_t n = *count;
+    const int t = threadIdx.x;
+    const int64_t wcols_full = (int64_t)L.win_words * 32;
+    uint64_t zsum = 0;
+    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+        const MergeItem m = items[it];
+        const int64_t c_lo = (int64_t)m.window * wcols_full;
+        const int64_t wcols = (N - c_lo) < wcols_full ? (N - c_lo) : wcols_full;
+        const int words = (int)((wcols + 31) / 32);
+        uint64_t cnt = 0;
+#pragma unroll
+        for (int u = 0; u < kMergeSlice / 256; ++u) {
+            const int word = m.slice * kMergeSlice + u * 256 + t;
+            if (word < words) {
+                // 8 independent loads in flight, then OR
+                const uint32_t* src = L.scratch + ((int64_t)m.slot + m.window) * (int64_t)L.win_words +
+                                      word;
+                const int64_t stride = (int64_t)L.nwin * L.win_words;
+                uint32_t x = 0;
+                for (int p0 = 0; p0 < m.nparts; p0 += 8) {
+                    uint32_t v[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) {
+                        const int pp = p0 + u < m.nparts ? p0 + u : m.nparts - 1;
+                        v[u] = src[(int64_t)pp * stride];
+                    }
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) x |= v[u];
+                }
+                cnt += (uint64_t)__popc(x);
+            }
+        }
+        const uint64_t total = block_sum<256, uint64_t>(cnt, s_red);
+        if (t == 0 && total) {
+            zsum += total;
+            if (MODE == 1) atomicAdd(reinterpret_cast<ull*>(&out[m.row]), (ull)total);
+        }
+    }
+    if (t == 0 && zsum) atomicAdd(as_ull(MODE == 0 ? &st->sample_nnz : &st->out_sum), (ull)zsum);
+    if (!finalize) return;
+    __threadfence();
+    __syncthreads();
+    if (t == 0) s_last = (atomicAdd(&ctl->done_ctr, 1u) == gridDim.x - 1u);
+    __syncthreads();
+    if (!s_last || t != 0) return;
+    __threadfence();
+    const uint64_t fs = __hip_atomic_load(&st->sample_flop, __ATOMIC_RELAXED,
+                                          __HIP_MEMORY_SCOPE_AGENT);
     if (fs == 0) {
         ctl->fallback = 1;
-        st->flags |= SSP_FLAG_EMPTY_SAMPLE;
+        atomicOr(as_ull(&st->flags), (ull)SSP_FLAG_EMPTY_SAMPLE);
         return;
     }
     ctl->fallback = 0;
@@ -380,6 +715,8 @@ __global__ void k_finalize_predict(Ctl* ctl, ssp_stats* st)
     ctl->div_v = D.v;
     ctl->div_shift = D.shift;
 }
+
+// ---------------------------------------------------------- finalize
 
 __global__ void k_finalize_reference(Ctl* ctl, ssp_stats* st, uint64_t M)
 {
@@ -409,21 +746,127 @@ struct FlopArgs {
     ssp_stats* st;
     Ctl* ctl;
     BinLists L;
+    const int32_t* tile_row; // first row of every tile, tile_row[ntiles] = M
+    TileMeta* meta;
+    int64_t ntiles;
 };
 
-// Tile = 256 * RPT consecutive rows.  The tile's entries of A are streamed in
-// chunks of 2048 (two 16-byte loads per thread, each load instruction fully
-// coalesced); each entry contributes the length of the B row it names.  An
-// exclusive scan of these lengths over the chunk gives the running product
-// count at every row boundary of the tile (kept in LDS), and a row's count is
-// the difference of its two boundaries.  Rows longer than a chunk simply span
-// several chunks.
-template <int MODE, int RPT, bool VEC>
+// Output of one finished row: prediction, product count, or bin.  Returns
+// the value added to out_sum.
+template <int MODE>
+__device__ __forceinline__ uint64_t emit_row(const FlopArgs& a, int64_t row, uint64_t rf,
+                                             uint32_t fallback, const Divisor& D, uint64_t zs)
+{
+    if (MODE == FLOP_PREDICT) {
+        const uint64_t pred = fallback ? rf : (rf ? ceil_mul_div(rf, zs, D) : 0);
+        a.out[row] = (int64_t)pred;
+        if (a.out_flop) a.out_flop[row] = (int64_t)rf;
+        return pred;
+    } else if (MODE == FLOP_ONLY) {
+        a.out[row] = (int64_t)rf;
+        return 0;
+    } else {
+        const int b = bin_of(rf);
+        if (b == 0 || b == 4) a.out[row] = 0;
+        if (b != 0) append_row((int32_t)row, rf, a.A.rpt[row], a.A.rpt[row + 1], a.B.ncols, a.ctl, a.L);
+        return 0;
+    }
+}
+
+// Merge-path tile b covers the items [b T, (b+1) T) of the sequence that
+// interleaves A's entries with one end marker per row (Merrill & Garland,
+// SC16), so every tile has at most T = kFlopTile rows + entries whatever the
+// row lengths.  A tile's entries are loaded with two 16-byte loads per thread
+// (each load instruction fully coalesced, non-temporal so the stream does not
+// evict B's row pointers from L2) and each contributes the length of the B row
+// it names (one 8-byte gather).  An exclusive scan of these lengths gives the
+// running product count at every row boundary, and a row's count is the
+// difference of its two boundaries.  Rows that begin in an earlier tile or end
+// in a later one leave their partial counts in the tile's metadata for
+// k_flop_fixup.
+//
+// The kernel is persistent: workgroup g takes tiles g, g + G, g + 2G, ...
+// and software-pipelines them.  While tile b's gathers are in flight it
+// issues the loads of tile b + G, and the tile starts of b + 2G are read one
+// tile further ahead.
+struct FlopTileRegs {
+    int64_t i0, i1, j0, j1, a0;
+    int4 col[2];   // as loaded; shifted by sh[q] positions when the load was clamped
+    int32_t sh[2];
+    int32_t rp[kFlopTile / kFlopThreads + 1];
+};
+
+// Column index of position l of the loaded quad (see flop_issue_tile).
+// (written with masks, not an index, so the quad stays in registers)
+__device__ __forceinline__ int32_t quad_at(int32_t w0, int32_t w1, int32_t w2, int32_t w3, int sh,
+                                           int l)
+{
+    const int i = l + sh;  // 0..6; only 0..3 are used unmasked
+    const int32_t m0 = -(int32_t)(i == 0), m1 = -(int32_t)(i == 1), m2 = -(int32_t)(i == 2);
+    const int32_t m3 = ~(m0 | m1 | m2);
+    return (w0 & m0) | (w1 & m1) | (w2 & m2) | (w3 & m3);
+}
+
+template <bool VEC>
+__device__ __forceinline__ void flop_issue_tile(const FlopArgs& a, int64_t b, int64_t i0,
+                                                int64_t i1, FlopTileRegs& R)
+{
+    constexpr int NT = kFlopThreads, HALF = kFlopChunk / 2, NRP = kFlopTile / kFlopThreads + 1;
+    const int t = threadIdx.x;
+    const int64_t M = a.A.nrows, nnzA = a.A.nnz;
+    const int64_t d0 = b * kFlopTile;
+    const int64_t d1 = (d0 + kFlopTile) < (M + nnzA) ? (d0 + kFlopTile) : (M + nnzA);
+    // the tile scalars are uniform: keep them in scalar registers
+    i0 = (int64_t)__builtin_amdgcn_readfirstlane((int)i0);
+    i1 = (int64_t)__builtin_amdgcn_readfirstlane((int)i1);
+    R.i0 = i0;
+    R.i1 = i1;
+    R.j0 = d0 - i0;
+    R.j1 = d1 - i1;
+    R.a0 = R.j0 & ~(int64_t)3;
+    const int64_t rlast = i1 < M ? i1 : M - 1;
+    const int nb = (int)(rlast - i0 + 2);
+#pragma unroll
+    for (int u = 0; u < NRP; ++u) {
+        const int k = t + u * NT;
+        R.rp[u] = a.A.rpt[i0 + (k < nb ? k : nb - 1)];
+    }
+    // Loads are unconditional from clamped in-range addresses (masked later):
+    // a load under a lane condition becomes a branch, and loads in separate
+    // branches are not kept in flight together.  VEC needs nnz(A) >= 4.
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const int64_t p = R.a0 + q * HALF + 4 * t;
+        int4 v;
+        if (VEC) {
+            typedef int v4i __attribute__((ext_vector_type(4)));
+            const int64_t pl = (p + 3 < nnzA) ? p : nnzA - 4; // 4-byte aligned when clamped
+            const v4i w = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(a.A.col + pl));
+            v = make_int4(w.x, w.y, w.z, w.w);
+            // positions >= nnz(A) are masked anyway; cap the shift so quad_at stays in range
+            const int64_t sh = p - pl;
+            R.sh[q] = (int32_t)(sh < 3 ? sh : 3);
+        } else {
+            R.sh[q] = 0;
+            v = make_int4(0, 0, 0, 0);
+            if (nnzA > 0) {  // A may have no entries (and no column array) at all
+                const int64_t last = nnzA - 1;
+                v.x = a.A.col[(p + 0) < last ? (p + 0) : last];
+                v.y = a.A.col[(p + 1) < last ? (p + 1) : last];
+                v.z = a.A.col[(p + 2) < last ? (p + 2) : last];
+                v.w = a.A.col[(p + 3) < last ? (p + 3) : last];
+            }
+        }
+        R.col[q] = v;
+    }
+}
+
+template <int MODE, bool VEC>
 __global__ __launch_bounds__(kFlopThreads) void k_flop(FlopArgs a)
 {
-    constexpr int NT = kFlopThreads, RT = NT * RPT, CH = kFlopChunk, HALF = CH / 2;
-    __shared__ int32_t s_bnd[RT + 1];
-    __shared__ uint64_t s_rowP[RT + 1];
+    constexpr int NT = kFlopThreads, CH = kFlopChunk, HALF = CH / 2;
+    constexpr int T = (int)kFlopTile, NRP = kFlopTile / kFlopThreads + 1;
+    __shared__ int32_t s_bnd[T + 2];
     __shared__ uint32_t s_x[CH];
     __shared__ uint64_t s_pre0[NT], s_pre1[NT];
     __shared__ uint64_t s_w[2 * (NT / kWave)];
@@ -431,59 +874,102 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(FlopArgs a)
 
     const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
     const int64_t M = a.A.nrows;
-    const int64_t r0 = (int64_t)blockIdx.x * RT;
-    const int nr = (int)((M - r0) < RT ? (M - r0) : RT);
-    const int32_t* __restrict__ Arpt = a.A.rpt;
-    const int32_t* __restrict__ Acol = a.A.col;
+    const int64_t G = gridDim.x, ntiles = a.ntiles;
     const int32_t* __restrict__ Brpt = a.B.rpt;
-    const int64_t nnzA = a.A.nnz;
 
-    for (int k = t; k <= nr; k += NT) s_bnd[k] = Arpt[r0 + k];
-    __syncthreads();
-    const int64_t e0 = s_bnd[0], e1 = s_bnd[nr];
-    const int64_t a0 = e0 & ~(int64_t)3;
-    uint64_t carry = 0;
-    int64_t c0 = a0;
-    for (; c0 < e1; c0 += CH) {
-        uint64_t s[2] = {0, 0};
+    uint32_t fallback = 0;
+    Divisor D;
+    uint64_t zs = 0;
+    if (MODE == FLOP_PREDICT) {
+        fallback = a.ctl->fallback;
+        D.dn = a.ctl->div_dn;
+        D.v = a.ctl->div_v;
+        D.shift = a.ctl->div_shift;
+        zs = a.st->sample_nnz;
+    }
+
+    // The tile starts of this workgroup's tiles are staged in LDS, kTrow at a
+    // time: reading them from LDS does not wait on the vector loads in flight.
+    constexpr int kTrow = 64;
+    __shared__ int32_t s_trow[kTrow + 1];
+    int64_t b = blockIdx.x;
+    if (b >= ntiles) return;
+    auto stage_trow = [&](int64_t bfirst) {  // tiles bfirst + k G, k < kTrow
+        for (int k = t; k <= kTrow; k += NT) {
+            const int64_t bk = bfirst + (int64_t)k * G;
+            s_trow[k] = bk <= ntiles ? a.tile_row[bk] : (int32_t)M;
+        }
+    };
+    // tile_row[b + 1] is the start of the tile after b, i.e. of a tile of
+    // another workgroup; it is staged alongside as s_next[k]
+    __shared__ int32_t s_next[kTrow + 1];
+    auto stage_all = [&](int64_t bfirst) {
+        stage_trow(bfirst);
+        for (int k = t; k <= kTrow; k += NT) {
+            const int64_t bk = bfirst + (int64_t)k * G;
+            s_next[k] = bk < ntiles ? a.tile_row[bk + 1] : (int32_t)M;
+        }
+        __syncthreads();
+    };
+    int64_t stage_base = b;
+    stage_all(stage_base);
+    int kk = 0;  // index of tile b in the staged window
+    FlopTileRegs cur, nxt;
+    flop_issue_tile<VEC>(a, b, s_trow[0], s_next[0], cur);
+    for (;;) {
+        const int64_t bn = b + G;
+        // 1. gathers of the current tile
+        const int64_t i0 = cur.i0, i1 = cur.i1, j0 = cur.j0, j1 = cur.j1, a0 = cur.a0;
+        uint32_t x[8];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int64_t p = c0 + q * HALF + 4 * t;
-            uint32_t x[4] = {0, 0, 0, 0};
-            if (p < e1 && p + 3 >= e0) {
-                int32_t cc[4];
-                if (VEC && p + 3 < nnzA) {
-                    const int4 v = *reinterpret_cast<const int4*>(Acol + p);
-                    cc[0] = v.x; cc[1] = v.y; cc[2] = v.z; cc[3] = v.w;
-                } else {
-#pragma unroll
-                    for (int l = 0; l < 4; ++l) cc[l] = (p + l < e1) ? Acol[p + l] : 0;
-                }
-#pragma unroll
-                for (int l = 0; l < 4; ++l) {
-                    const int64_t j = p + l;
-                    x[l] = (j >= e0 && j < e1) ? csr_row_len(Brpt, cc[l]) : 0u;
-                }
-            }
+            const int64_t p = a0 + q * HALF + 4 * t;
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
-                s_x[q * HALF + 4 * t + l] = x[l];
-                s[q] += x[l];
+                const int64_t j = p + l;
+                const bool in = j >= j0 && j < j1;
+                const int32_t cc = quad_at(cur.col[q].x, cur.col[q].y, cur.col[q].z,
+                                           cur.col[q].w, cur.sh[q], l);
+                uint32_t len = 0;
+                // row 0 of B when masked; with no entries at all (then K may be
+                // 0 and B's row pointers hold one value) nothing is read
+                if (VEC || a.A.nnz > 0) len = csr_row_len(Brpt, in ? cc : 0);
+                x[4 * q + l] = in ? len : 0u;
             }
         }
+        // 2. loads of the next tile, unconditionally (a branch here would make
+        //    the compiler drain every load in flight at its join); past the
+        //    last tile the staged starts are M and the loads clamp in range
+        flop_issue_tile<VEC>(a, bn, s_trow[kk + 1], s_next[kk + 1], nxt);
+        // 3. the current tile
+        const int64_t rlast = i1 < M ? i1 : M - 1;
+        const int nb = (int)(rlast - i0 + 2);
+#pragma unroll
+        for (int u = 0; u < NRP; ++u) {
+            const int k = t + u * NT;
+            if (k < nb) s_bnd[k] = cur.rp[u];
+        }
+        uint64_t s0 = 0, s1 = 0;
+#pragma unroll
+        for (int l = 0; l < 4; ++l) {
+            s_x[4 * t + l] = x[l];
+            s_x[HALF + 4 * t + l] = x[4 + l];
+            s0 += x[l];
+            s1 += x[4 + l];
+        }
         // exclusive scans of the two halves, in lockstep
-        uint64_t i0 = s[0], i1 = s[1];
+        uint64_t i0s = s0, i1s = s1;
 #pragma unroll
         for (int o = 1; o < kWave; o <<= 1) {
-            const uint64_t u0 = __shfl_up(i0, o, kWave), u1 = __shfl_up(i1, o, kWave);
+            const uint64_t u0 = __shfl_up(i0s, o, kWave), u1 = __shfl_up(i1s, o, kWave);
             if (lane >= o) {
-                i0 += u0;
-                i1 += u1;
+                i0s += u0;
+                i1s += u1;
             }
         }
         if (lane == kWave - 1) {
-            s_w[wid] = i0;
-            s_w[NT / kWave + wid] = i1;
+            s_w[wid] = i0s;
+            s_w[NT / kWave + wid] = i1s;
         }
         __syncthreads();
         uint64_t w0 = 0, w1 = 0, tot0 = 0, tot1 = 0;
@@ -495,81 +981,136 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(FlopArgs a)
             tot0 += x0;
             tot1 += x1;
         }
-        s_pre0[t] = w0 + i0 - s[0];
-        s_pre1[t] = tot0 + w1 + i1 - s[1];
+        s_pre0[t] = w0 + i0s - s0;
+        s_pre1[t] = tot0 + w1 + i1s - s1;
         __syncthreads();
-        for (int k = t; k <= nr; k += NT) {
-            const int64_t d = (int64_t)s_bnd[k] - c0;
-            if (d >= 0 && d < CH) {
-                const int q = (int)(d / HALF), tt = (int)((d % HALF) >> 2), l = (int)(d & 3);
-                uint64_t v = carry + (q ? s_pre1[tt] : s_pre0[tt]);
-                const int base = q * HALF + 4 * tt;
-                for (int m = 0; m < l; ++m) v += s_x[base + m];
-                s_rowP[k] = v;
-            }
-        }
-        carry += tot0 + tot1;
-        __syncthreads();
-    }
-    for (int k = t; k <= nr; k += NT)
-        if ((int64_t)s_bnd[k] >= c0) s_rowP[k] = carry;
-    __syncthreads();
+        const uint64_t tile_total = tot0 + tot1;
 
-    // ---- epilogue: one row per thread per pass
-    uint64_t fsum = 0, osum = 0;
-    Divisor D;
-    uint64_t zs = 0;
-    uint32_t fallback = 0;
-    if (MODE == FLOP_PREDICT) {
-        fallback = a.ctl->fallback;
-        D.dn = a.ctl->div_dn;
-        D.v = a.ctl->div_v;
-        D.shift = a.ctl->div_shift;
-        zs = a.st->sample_nnz;
-    }
-#pragma unroll
-    for (int rr = 0; rr < RPT; ++rr) {
-        const int k = t + rr * NT;
-        const bool valid = k < nr;
-        const int64_t row = r0 + k;
-        const uint64_t rf = valid ? s_rowP[k + 1] - s_rowP[k] : 0;
-        fsum += rf;
-        if (MODE == FLOP_PREDICT) {
-            if (valid) {
-                const uint64_t pred = fallback ? rf : (rf ? ceil_mul_div(rf, zs, D) : 0);
-                a.out[row] = (int64_t)pred;
-                if (a.out_flop) a.out_flop[row] = (int64_t)rf;
-                osum += pred;
-            }
-        } else if (MODE == FLOP_ONLY) {
-            if (valid) a.out[row] = (int64_t)rf;
-        } else {
-            const int b = valid ? bin_of(rf) : 0;
-#pragma unroll
-            for (int bb = 1; bb <= 3; ++bb) {
-                const uint64_t m = __ballot(b == bb);
-                if (m) {
-                    const int leader = __ffsll((long long)m) - 1;
-                    uint32_t base = 0;
-                    if (lane == leader) base = atomicAdd(&a.ctl->bin_cnt[bb], (uint32_t)__popcll(m));
-                    base = __shfl(base, leader, kWave);
-                    if (b == bb) {
-                        BinItem it;
-                        it.row = (int32_t)row;
-                        it.rf = (uint32_t)rf;
-                        (bb == 1 ? a.L.b1 : bb == 2 ? a.L.b2 : a.L.b3)[base + rank_in(m)] = it;
-                    }
+        // running product count before entry position `pos` (a0 <= pos <= a0 + CH)
+        auto prefix = [&](int64_t pos) -> uint64_t {
+            const int d = (int)(pos - a0);
+            if (d >= CH) return tile_total;
+            const int q = d >> 10, tt = (d & (HALF - 1)) >> 2, l = d & 3;
+            uint64_t v = q ? s_pre1[tt] : s_pre0[tt];
+            const int base = q * HALF + 4 * tt;
+            for (int m = 0; m < l; ++m) v += s_x[base + m];
+            return v;
+        };
+
+        uint64_t osum = 0;
+        const int nrows_t = (int)(rlast - i0 + 1);
+        for (int base = 0; base < nrows_t; base += NT) {  // same trip count in every lane
+            const int k = base + t;
+            bool emit = false;
+            int64_t r = 0;
+            uint64_t sum = 0;
+            if (k < nrows_t) {
+                r = i0 + k;
+                const int64_t rs = s_bnd[k], re = s_bnd[k + 1];
+                const bool open = (r == i1);
+                if (!(open && rs >= j1)) {
+                    const int64_t st_ = rs > j0 ? rs : j0;
+                    const int64_t en = re < j1 ? re : j1;
+                    sum = prefix(en) - prefix(st_);
+                    if (rs < j0) a.meta[b].head = sum;
+                    else if (open) a.meta[b].carry = sum;
+                    else emit = true;
                 }
             }
-            if (valid && (b == 0 || b == 4)) a.out[row] = 0;
-            if (b == 4) append_big((int32_t)row, rf, a.B.ncols, a.ctl, a.L);
+            if (MODE == FLOP_EXACT_BIN) {
+                // bins 1..3 with one atomic per wave and bin
+                const int bn_ = emit ? bin_of(sum) : 0;
+#pragma unroll
+                for (int bb = 1; bb <= 3; ++bb) {
+                    const uint64_t m = __ballot(bn_ == bb);
+                    if (m) {
+                        const int leader = __ffsll((long long)m) - 1;
+                        uint32_t pos = 0;
+                        if (lane == leader)
+                            pos = atomicAdd(&a.ctl->bin_cnt[bb], (uint32_t)__popcll(m));
+                        pos = __shfl(pos, leader, kWave);
+                        if (bn_ == bb) {
+                            BinItem it;
+                            it.row = (int32_t)r;
+                            it.rf = (uint32_t)sum;
+                            (bb == 1 ? a.L.b1 : bb == 2 ? a.L.b2 : a.L.b3)[pos + rank_in(m)] = it;
+                        }
+                    }
+                }
+                if (emit && (bn_ == 0 || bn_ == 4)) a.out[r] = 0;
+                if (emit && bn_ == 4) append_big((int32_t)r, sum, s_bnd[k], s_bnd[k + 1], a.B.ncols, a.ctl, a.L);
+            } else if (emit) {
+                if (MODE == FLOP_PREDICT) {
+                    const uint64_t pred = fallback ? sum : (sum ? ceil_mul_div(sum, zs, D) : 0);
+                    __builtin_nontemporal_store((int64_t)pred, a.out + r);
+                    if (a.out_flop) __builtin_nontemporal_store((int64_t)sum, a.out_flop + r);
+                    osum += pred;
+                } else {
+                    __builtin_nontemporal_store((int64_t)sum, a.out + r);
+                }
+            }
+        }
+        const uint64_t O = block_sum<NT, uint64_t>(osum, s_red);
+        if (t == 0) {
+            a.meta[b].fsum = tile_total;
+            a.meta[b].osum = O;
+        }
+        if (bn >= ntiles) break;
+        b = bn;
+        cur = nxt;
+        if (++kk == kTrow) {  // restage; k = 0..kTrow are staged, so kk + 1 always is
+                              // (the block_sum above ended with a barrier)
+            stage_base = b;
+            stage_all(stage_base);
+            kk = 0;
         }
     }
-    const uint64_t F = block_sum<NT, uint64_t>(fsum, s_red);
-    if (t == 0 && F) atomicAdd(as_ull(&a.st->total_flop), (ull)F);
-    if (MODE == FLOP_PREDICT) {
-        const uint64_t O = block_sum<NT, uint64_t>(osum, s_red);
-        if (t == 0 && O) atomicAdd(as_ull(&a.st->out_sum), (ull)O);
+}
+
+// One thread per tile: a row that begins in tile b and goes on (its partial
+// is b's carry) collects the heads of the following tiles until the tile
+// holding its end marker, then gets its output.  Adds F and out_sum.
+template <int MODE>
+__global__ __launch_bounds__(256) void k_flop_fixup(FlopArgs a)
+{
+    __shared__ uint64_t s_red[256 / kWave + 1];
+    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t M = a.A.nrows, nnzA = a.A.nnz;
+    uint64_t F = 0, O = 0;
+    if (b < a.ntiles) {
+        F = a.meta[b].fsum;
+        O = a.meta[b].osum;
+        const int64_t d0 = b * kFlopTile;
+        const int64_t d1 = (d0 + kFlopTile) < (M + nnzA) ? (d0 + kFlopTile) : (M + nnzA);
+        const int64_t i1 = a.tile_row[b + 1];
+        const int64_t j0 = d0 - a.tile_row[b], j1 = d1 - i1;
+        if (i1 < M) {
+            const int64_t rs = a.A.rpt[i1];
+            if (rs >= j0 && rs < j1) {
+                uint64_t total = a.meta[b].carry;
+                for (int64_t bb = b + 1; bb < a.ntiles; ++bb) {
+                    total += a.meta[bb].head;
+                    if (a.tile_row[bb + 1] > i1) break;
+                }
+                uint32_t fallback = 0;
+                Divisor D;
+                uint64_t zs = 0;
+                if (MODE == FLOP_PREDICT) {
+                    fallback = a.ctl->fallback;
+                    D.dn = a.ctl->div_dn;
+                    D.v = a.ctl->div_v;
+                    D.shift = a.ctl->div_shift;
+                    zs = a.st->sample_nnz;
+                }
+                O += emit_row<MODE>(a, i1, total, fallback, D, zs);
+            }
+        }
+    }
+    const uint64_t Fs = block_sum<256, uint64_t>(F, s_red);
+    const uint64_t Os = block_sum<256, uint64_t>(O, s_red);
+    if (threadIdx.x == 0) {
+        if (Fs) atomicAdd(as_ull(&a.st->total_flop), (ull)Fs);
+        if (MODE == FLOP_PREDICT && Os) atomicAdd(as_ull(&a.st->out_sum), (ull)Os);
     }
 }
 

@@ -158,8 +158,8 @@ int64_t paper_sample_num(int64_t M)
     return s < 300 ? s : 300;
 }
 
-// Grow the workspace to `bytes`.  The slot region of a fresh buffer is
-// cleared here (the kernels keep it clear afterwards).
+// Grow the workspace to `bytes` (hipMalloc; freed buffers are released
+// after the device is idle).
 ssp_status ensure_workspace(ssp_handle h, size_t bytes)
 {
     if (bytes <= h->ws_bytes) return SSP_OK;
@@ -183,9 +183,6 @@ ssp_status ensure_workspace(ssp_handle h, size_t bytes)
         h->last_error = std::string("hipMalloc: ") + hipGetErrorString(e);
         return SSP_ERR_OOM;
     }
-    const Layout L0 = make_layout(0, 0, false);
-    SSP_HIP(h, hipMemset(p, 0, L0.bin1));
-    SSP_HIP(h, hipDeviceSynchronize());
     h->ws = p;
     h->ws_bytes = want;
     return SSP_OK;
@@ -194,10 +191,26 @@ ssp_status ensure_workspace(ssp_handle h, size_t bytes)
 struct Bound {
     Ctl* ctl;
     BinLists L;
+    int32_t* tile_row;
+    TileMeta* meta;
     int64_t* rowtmp;
 };
 
-Bound bind(ssp_handle h, const Layout& L)
+// Columns per bitmap window of the long-row kernel: all N columns when they
+// fit the LDS window, else 2^20-column windows.
+void window_shape(int64_t N, int32_t* words, int32_t* nwin)
+{
+    const int64_t need = (N + 31) / 32;
+    if (need <= kWinWords) {
+        *words = (int32_t)std::max<int64_t>(need, 1);
+        *nwin = 1;
+    } else {
+        *words = kWinWords;
+        *nwin = (int32_t)((N + (int64_t)kWinWords * 32 - 1) / ((int64_t)kWinWords * 32));
+    }
+}
+
+Bound bind(ssp_handle h, const Layout& L, int64_t N)
 {
     char* base = static_cast<char*>(h->ws);
     Bound b;
@@ -206,7 +219,11 @@ Bound bind(ssp_handle h, const Layout& L)
     b.L.b2 = reinterpret_cast<BinItem*>(base + L.bin2);
     b.L.b3 = reinterpret_cast<BinItem*>(base + L.bin3);
     b.L.b4 = reinterpret_cast<BigItem*>(base + L.bin4);
-    b.L.slots = reinterpret_cast<uint32_t*>(base + L.slots);
+    b.L.merge = reinterpret_cast<MergeItem*>(base + L.merge);
+    b.L.scratch = reinterpret_cast<uint32_t*>(base + L.scratch);
+    window_shape(N, &b.L.win_words, &b.L.nwin);
+    b.tile_row = reinterpret_cast<int32_t*>(base + L.tiles);
+    b.meta = reinterpret_cast<TileMeta*>(base + L.meta);
     b.rowtmp = reinterpret_cast<int64_t*>(base + L.rowtmp);
     return b;
 }
@@ -217,56 +234,92 @@ unsigned grid_for(int64_t items, int64_t cap)
     return (unsigned)std::min<int64_t>(items, cap);
 }
 
-// Rows per thread of the streaming kernel: aim at ~4096 entries of A per tile.
-int pick_rpt(const ssp_csr* A)
-{
-    const double d = A->nrows ? (double)A->nnz / (double)A->nrows : 0.0;
-    const double want = 4096.0 / (kFlopThreads * std::max(d, 1e-9));
-    if (want >= 8) return 8;
-    if (want >= 4) return 4;
-    if (want >= 2) return 2;
-    return 1;
-}
-
 template <int MODE>
-void launch_flop(const FlopArgs& fa, int rpt, bool vec, hipStream_t s)
+void launch_flop(const FlopArgs& fa, bool vec, int cus, hipStream_t s)
 {
-    const int64_t M = fa.A.nrows;
-    const unsigned grid = (unsigned)((M + (int64_t)kFlopThreads * rpt - 1) / ((int64_t)kFlopThreads * rpt));
-    const dim3 blk(kFlopThreads);
-#define SSP_FLOP_CASE(R)                                                                        \
-    case R:                                                                                    \
-        if (vec) hipLaunchKernelGGL((k_flop<MODE, R, true>), dim3(grid), blk, 0, s, fa);       \
-        else hipLaunchKernelGGL((k_flop<MODE, R, false>), dim3(grid), blk, 0, s, fa);          \
-        break;
-    switch (rpt) {
-        SSP_FLOP_CASE(1)
-        SSP_FLOP_CASE(2)
-        SSP_FLOP_CASE(4)
-        SSP_FLOP_CASE(8)
+    // persistent: as many workgroups as can be resident at once, each walks
+    // its tiles (grid-stride)
+    static int resident[2] = {0, 0};
+    int& r = resident[vec ? 1 : 0];
+    if (r == 0) {
+        int per_cu = 0;
+        const hipError_t e =
+            vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_flop<MODE, true>,
+                                                               kFlopThreads, 0)
+                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_flop<MODE, false>,
+                                                               kFlopThreads, 0);
+        r = (e == hipSuccess && per_cu > 0) ? per_cu : 4;
     }
-#undef SSP_FLOP_CASE
+    const unsigned grid =
+        (unsigned)std::max<int64_t>(std::min<int64_t>(fa.ntiles, (int64_t)r * cus), 1);
+    if (fa.ntiles > 0) {
+        if (vec) hipLaunchKernelGGL((k_flop<MODE, true>), dim3(grid), dim3(kFlopThreads), 0, s, fa);
+        else hipLaunchKernelGGL((k_flop<MODE, false>), dim3(grid), dim3(kFlopThreads), 0, s, fa);
+    }
+    const unsigned fgrid = (unsigned)std::max<int64_t>((fa.ntiles + 255) / 256, 1);
+    hipLaunchKernelGGL((k_flop_fixup<MODE>), dim3(fgrid), dim3(256), 0, s, fa);
 }
 
-// Symbolic kernels over the four bins (sizes of the lists are device-side;
-// the grids are upper bounds and every kernel walks its list grid-stride).
+// Symbolic kernels over the four bins and the merge of split rows (sizes of
+// the lists are device-side; the grids are upper bounds and every kernel
+// walks its list grid-stride).
 template <int MODE>
-void launch_symbolic(ssp_handle h, const Csr& A, const Csr& B, const Bound& b, int64_t nitems,
-                     int64_t nbig, ssp_stats* st, int64_t* out, hipStream_t s)
+ssp_status launch_symbolic(ssp_handle h, const Csr& A, const Csr& B, const Bound& b,
+                           const Layout& L, ssp_stats* st, int64_t* out, hipStream_t s)
 {
     const int cus = h->num_cus;
+    const int64_t nitems = L.cap13;
     hipLaunchKernelGGL((k_sym<kBin1Team, kBin1Words, MODE>), dim3(grid_for(nitems, 16LL * cus)),
                        dim3(kBin1Team), 0, s, A, B, b.L.b1, &b.ctl->bin_cnt[1], st, out);
     hipLaunchKernelGGL((k_sym<kBin2Team, kBin2Words, MODE>), dim3(grid_for(nitems, 4LL * cus)),
                        dim3(kBin2Team), 0, s, A, B, b.L.b2, &b.ctl->bin_cnt[2], st, out);
     hipLaunchKernelGGL((k_sym<kBin3Team, kBin3Words, MODE>), dim3(grid_for(nitems, 2LL * cus)),
                        dim3(kBin3Team), 0, s, A, B, b.L.b3, &b.ctl->bin_cnt[3], st, out);
-    hipLaunchKernelGGL((k_sym_big<MODE>), dim3(grid_for(nbig, 1LL * cus)), dim3(kBin4Team), 0, s,
-                       A, B, b.L.b4, &b.ctl->bin_cnt[4], b.L.slots, st, out);
+    const size_t lds = (size_t)b.L.win_words * sizeof(uint32_t);
+    static bool attr_set[2] = {false, false};
+    if (!attr_set[MODE]) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sym_big<MODE>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)(kWinWords * sizeof(uint32_t)));
+        attr_set[MODE] = true;
+    }
+    static int big_resident[2] = {0, 0};
+    if (big_resident[MODE] == 0) {
+        int per_cu = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sym_big<MODE>, kBin4Team,
+                                                         kWinWords * sizeof(uint32_t)) != hipSuccess ||
+            per_cu < 1)
+            per_cu = 1;
+        big_resident[MODE] = per_cu;
+    }
+    hipLaunchKernelGGL((k_sym_big<MODE>), dim3(grid_for(L.cap4, (int64_t)big_resident[MODE] * cus)),
+                       dim3(kBin4Team), lds, s, A, B, b.L.b4, &b.ctl->bin_cnt[4], &b.ctl->big_next,
+                       b.L, st, out);
+    hipLaunchKernelGGL((k_sym_merge<MODE>), dim3((unsigned)(2 * cus)), dim3(256), 0, s, b.L.merge,
+                       &b.ctl->bin_cnt[5], b.L, B.ncols, b.ctl, st, out, MODE == 0 ? 1 : 0);
+    SSP_LAUNCHED(h);
+    return SSP_OK;
 }
 
-// Sampling, per-row products of the sample, binning and distinct counting:
-// leaves n_s, f* and z* in *st.
+FlopArgs flop_args(const ssp_csr* A, const ssp_csr* B, const Bound& b, const Layout& L,
+                   int64_t* out, int64_t* out_flop, ssp_stats* st)
+{
+    FlopArgs fa;
+    fa.A = to_csr(A);
+    fa.B = to_csr(B);
+    fa.out = out;
+    fa.out_flop = out_flop;
+    fa.st = st;
+    fa.ctl = b.ctl;
+    fa.L = b.L;
+    fa.tile_row = b.tile_row;
+    fa.meta = b.meta;
+    fa.ntiles = L.ntiles;
+    return fa;
+}
+
+// Tile starts, sampling, per-row products of the sample, binning and
+// distinct counting: leaves n_s, f*, z* in *st and the divisor of f* in ctl.
 ssp_status sampled_part(ssp_handle h, const ssp_csr* A, const ssp_csr* B, ssp_sampler sampler,
                         double rate, uint64_t seed, const Bound& b, const Layout& L,
                         ssp_stats* st, hipStream_t s)
@@ -274,25 +327,21 @@ ssp_status sampled_part(ssp_handle h, const ssp_csr* A, const ssp_csr* B, ssp_sa
     const Csr a = to_csr(A), bb = to_csr(B);
     const int64_t M = A->nrows;
     {
-    PhaseTimer pt(h, PH_SAMPLE, s);
-    if (sampler == SSP_SAMPLER_PAPER) {
-        const int64_t nd = paper_sample_num(M);
-        const unsigned grid = (unsigned)std::max<int64_t>(1, (nd + 255) / 256);
-        hipLaunchKernelGGL((k_sample_bin<true>), dim3(grid), dim3(256), 0, s, a, bb, seed,
-                           (uint64_t)0, nd, b.ctl, st, b.L);
-    } else {
-        const unsigned grid = (unsigned)((M + 255) / 256);
-        hipLaunchKernelGGL((k_sample_bin<false>), dim3(grid), dim3(256), 0, s, a, bb, seed,
-                           rate_threshold(rate), (int64_t)0, b.ctl, st, b.L);
-    }
-    }
-    SSP_LAUNCHED(h);
-    {
-        PhaseTimer pt(h, PH_SYMBOLIC, s);
-        launch_symbolic<0>(h, a, bb, b, L.cap13, L.cap4, st, nullptr, s);
+        PhaseTimer pt(h, PH_SAMPLE, s);
+        const int64_t nd = sampler == SSP_SAMPLER_PAPER ? paper_sample_num(M) : M;
+        const unsigned grid = grid_for((std::max(M, nd) + kSampleBlock - 1) / kSampleBlock,
+                                       2LL * h->num_cus);
+        if (sampler == SSP_SAMPLER_PAPER)
+            hipLaunchKernelGGL((k_sample<true, true>), dim3(grid), dim3(kSampleThreads), 0, s, a,
+                               bb, seed, (uint64_t)0, nd, L.ntiles, b.tile_row, b.ctl, st, b.L);
+        else
+            hipLaunchKernelGGL((k_sample<false, true>), dim3(grid), dim3(kSampleThreads), 0, s, a,
+                               bb, seed, rate_threshold(rate), (int64_t)0, L.ntiles, b.tile_row,
+                               b.ctl, st, b.L);
     }
     SSP_LAUNCHED(h);
-    return SSP_OK;
+    PhaseTimer pt(h, PH_SYMBOLIC, s);
+    return launch_symbolic<0>(h, a, bb, b, L, st, nullptr, s);
 }
 
 ssp_status common_checks(ssp_handle h, const ssp_csr* A, const ssp_csr* B, ssp_sampler sampler,
@@ -420,31 +469,20 @@ ssp_status ssp_predict_structure_ex(ssp_handle h, const ssp_csr* A, const ssp_cs
     if (!g.ok()) return SSP_ERR_NO_DEVICE;
     const int64_t M = A->nrows;
     const int64_t nitems = sampler == SSP_SAMPLER_PAPER ? paper_sample_num(M) : M;
-    const Layout L = make_layout(nitems, M, false);
+    const Layout L = make_layout(nitems, M, A->nnz, false);
     if ((s = ensure_workspace(h, L.total)) != SSP_OK) return s;
-    const Bound b = bind(h, L);
+    const Bound b = bind(h, L, B->ncols);
     hipStream_t hs = static_cast<hipStream_t>(stream);
     ssp_stats* st = stats ? stats : &b.ctl->stats;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, hs, b.ctl, st, (uint64_t)M);
     SSP_LAUNCHED(h);
     if (M == 0) return SSP_OK;
     if ((s = sampled_part(h, A, B, sampler, rate, seed, b, L, st, hs)) != SSP_OK) return s;
-    {
-        PhaseTimer pt(h, PH_FINALIZE, hs);
-        hipLaunchKernelGGL(k_finalize_predict, dim3(1), dim3(64), 0, hs, b.ctl, st);
-    }
-    FlopArgs fa;
-    fa.A = to_csr(A);
-    fa.B = to_csr(B);
-    fa.out = nnz_pred;
-    fa.out_flop = row_flop;
-    fa.st = st;
-    fa.ctl = b.ctl;
-    fa.L = b.L;
-    const bool vec = (reinterpret_cast<uintptr_t>(A->col) & 15u) == 0;
+    const FlopArgs fa = flop_args(A, B, b, L, nnz_pred, row_flop, st);
+    const bool vec = (reinterpret_cast<uintptr_t>(A->col) & 15u) == 0 && A->nnz >= 4;
     {
         PhaseTimer pt(h, PH_FLOP, hs);
-        launch_flop<FLOP_PREDICT>(fa, pick_rpt(A), vec, hs);
+        launch_flop<FLOP_PREDICT>(fa, vec, h->num_cus, hs);
     }
     SSP_LAUNCHED(h);
     return SSP_OK;
@@ -468,27 +506,20 @@ ssp_status ssp_reference_estimate(ssp_handle h, const ssp_csr* A, const ssp_csr*
     if (!g.ok()) return SSP_ERR_NO_DEVICE;
     const int64_t M = A->nrows;
     const int64_t nitems = sampler == SSP_SAMPLER_PAPER ? paper_sample_num(M) : M;
-    const Layout L = make_layout(nitems, M, true);
+    const Layout L = make_layout(nitems, M, A->nnz, true);
     if ((s = ensure_workspace(h, L.total)) != SSP_OK) return s;
-    const Bound b = bind(h, L);
+    const Bound b = bind(h, L, B->ncols);
     hipStream_t hs = static_cast<hipStream_t>(stream);
     ssp_stats* st = stats ? stats : &b.ctl->stats;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, hs, b.ctl, st, (uint64_t)M);
     SSP_LAUNCHED(h);
     if (M == 0) return SSP_OK;
     if ((s = sampled_part(h, A, B, sampler, rate, seed, b, L, st, hs)) != SSP_OK) return s;
-    FlopArgs fa;
-    fa.A = to_csr(A);
-    fa.B = to_csr(B);
-    fa.out = b.rowtmp;
-    fa.out_flop = nullptr;
-    fa.st = st;
-    fa.ctl = b.ctl;
-    fa.L = b.L;
-    const bool vec = (reinterpret_cast<uintptr_t>(A->col) & 15u) == 0;
+    const FlopArgs fa = flop_args(A, B, b, L, b.rowtmp, nullptr, st);
+    const bool vec = (reinterpret_cast<uintptr_t>(A->col) & 15u) == 0 && A->nnz >= 4;
     {
         PhaseTimer pt(h, PH_FLOP, hs);
-        launch_flop<FLOP_ONLY>(fa, pick_rpt(A), vec, hs);
+        launch_flop<FLOP_ONLY>(fa, vec, h->num_cus, hs);
     }
     {
         PhaseTimer pt(h, PH_FINALIZE, hs);
@@ -512,33 +543,33 @@ ssp_status ssp_exact_structure(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
     DeviceGuard g(h->device);
     if (!g.ok()) return SSP_ERR_NO_DEVICE;
     const int64_t M = A->nrows;
-    const Layout L = make_layout(M, M, false);
+    const Layout L = make_layout(M, M, A->nnz, false);
     if ((s = ensure_workspace(h, L.total)) != SSP_OK) return s;
-    const Bound b = bind(h, L);
+    const Bound b = bind(h, L, B->ncols);
     hipStream_t hs = static_cast<hipStream_t>(stream);
     ssp_stats* st = stats ? stats : &b.ctl->stats;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, hs, b.ctl, st, (uint64_t)M);
     SSP_LAUNCHED(h);
     if (M == 0) return SSP_OK;
-    FlopArgs fa;
-    fa.A = to_csr(A);
-    fa.B = to_csr(B);
-    fa.out = nnz_exact;
-    fa.out_flop = nullptr;
-    fa.st = st;
-    fa.ctl = b.ctl;
-    fa.L = b.L;
-    const bool vec = (reinterpret_cast<uintptr_t>(A->col) & 15u) == 0;
+    const Csr a = to_csr(A);
+    {
+        PhaseTimer pt(h, PH_SAMPLE, hs);
+        hipLaunchKernelGGL((k_sample<false, false>),
+                           dim3(grid_for((M + kSampleBlock - 1) / kSampleBlock, 4LL * h->num_cus)),
+                           dim3(kSampleThreads), 0, hs, a, to_csr(B), (uint64_t)0, (uint64_t)0,
+                           (int64_t)0, L.ntiles, b.tile_row, b.ctl, st, b.L);
+    }
+    const FlopArgs fa = flop_args(A, B, b, L, nnz_exact, nullptr, st);
+    const bool vec = (reinterpret_cast<uintptr_t>(A->col) & 15u) == 0 && A->nnz >= 4;
     {
         PhaseTimer pt(h, PH_FLOP, hs);
-        launch_flop<FLOP_EXACT_BIN>(fa, pick_rpt(A), vec, hs);
+        launch_flop<FLOP_EXACT_BIN>(fa, vec, h->num_cus, hs);
     }
     SSP_LAUNCHED(h);
     {
         PhaseTimer pt(h, PH_SYMBOLIC, hs);
-        launch_symbolic<1>(h, fa.A, fa.B, b, L.cap13, L.cap4, st, nnz_exact, hs);
+        if ((s = launch_symbolic<1>(h, fa.A, fa.B, b, L, st, nnz_exact, hs)) != SSP_OK) return s;
     }
-    SSP_LAUNCHED(h);
     return SSP_OK;
 }
 

@@ -205,19 +205,30 @@ def test_bin_boundaries(ssp):
 
 
 def _long_rows(ncols, nbig, seed):
-    # a few rows whose product counts exceed the split threshold (2^16): each
-    # names hub B rows of several thousand entries
+    # long rows whose entries name B rows of all three length classes the
+    # long-row kernel treats differently: huge (>= 2048 entries), medium
+    # (32..2047) and short (< 32); the largest rows exceed the split
+    # threshold (2^18 products) several times over
     rng = np.random.default_rng(seed)
     K = 3000
     brows = []
     for k in range(K):
-        L = 4000 if k < 60 else int(rng.integers(0, 20))
+        if k < 400:
+            L = 3000
+        elif k < 700:
+            L = int(rng.integers(32, 1500))
+        else:
+            L = int(rng.integers(0, 20))
         brows.append(sorted(rng.choice(ncols, size=L, replace=False).tolist()))
     B = from_rows(brows, ncols)
     arows = []
     for i in range(400):
         if i % (400 // nbig) == 0:
-            arows.append(list(range(60)) + rng.choice(K, size=500, replace=False).tolist())
+            hubs = rng.choice(400, size=int(rng.integers(20, 400)), replace=False).tolist()
+            meds = (400 + rng.choice(300, size=150, replace=False)).tolist()
+            arows.append(hubs + meds + rng.choice(K, size=500, replace=False).tolist())
+        elif i % 7 == 0:
+            arows.append((400 + rng.choice(300, size=40, replace=False)).tolist())
         else:
             arows.append(rng.choice(K, size=int(rng.integers(0, 30)), replace=False).tolist())
     return from_rows(arows, K), B
@@ -226,7 +237,7 @@ def _long_rows(ncols, nbig, seed):
 def test_split_long_rows(ssp):
     A, B = _long_rows(300_000, 8, 1)
     rf, _ = oracle.row_flop(A, B)
-    assert rf.max() > 2 ** 17
+    assert rf.max() > 4 * 2 ** 18
     _say(f"split long rows max rf={rf.max()}")
     check_all(ssp, A, B, 1.0, 1)
     check_all(ssp, A, B, 0.3, 2)
