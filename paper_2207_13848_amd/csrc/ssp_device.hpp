@@ -282,27 +282,38 @@ __device__ __forceinline__ void wave_bitmap_or(uint32_t* bm, uint32_t word, uint
     wave_bitmap_or_needed(bm, need ? word : kNoWord, need);
 }
 
-// U columns per lane at once (kNoWord = none): the U bitmap words are read
-// together, so one LDS latency covers all of them; columns outside the window
-// [clo, clo + wc) are skipped.
-template <int U>
-__device__ __forceinline__ void wave_bitmap_insert(uint32_t* bm, const uint32_t (&col)[U],
+// V columns per lane (kNoWord = none), normally neighbours in one B row:
+// runs of them that fall in one bitmap word (sorted rows make such runs
+// contiguous) are first combined inside the lane; then every remaining word
+// is read and only the bits not yet set go on to an LDS atomic OR.  Bits are
+// only ever set, so a stale read costs at most an extra atomic, and columns
+// seen before (hub columns appear in most B rows) cost a read instead of an
+// atomic.  Unsorted or repeated columns stay correct, merely slower.  Columns
+// outside the window [clo, clo + wc) are skipped.  No cross-lane traffic.
+template <int V>
+__device__ __forceinline__ void lane_bitmap_insert(uint32_t* bm, const uint32_t (&col)[V],
                                                    uint32_t clo, uint32_t wc)
 {
-    uint32_t word[U], bit[U], old[U];
+    uint32_t word[V], bits[V], old[V];
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint32_t cw = col[u] - clo;  // columns < 2^31: wraps above wc when col < clo
-        const bool in = col[u] != kNoWord && cw < wc;
-        word[u] = in ? (cw >> 5) : kNoWord;
-        bit[u] = 1u << (cw & 31);
+    for (int v = 0; v < V; ++v) {
+        const uint32_t cw = col[v] - clo;  // columns < 2^31: wraps above wc when col < clo
+        const bool in = col[v] != kNoWord && cw < wc;
+        word[v] = in ? (cw >> 5) : kNoWord;
+        bits[v] = 1u << (cw & 31);
     }
 #pragma unroll
-    for (int u = 0; u < U; ++u) old[u] = bm[word[u] != kNoWord ? word[u] : 0u];
+    for (int v = 1; v < V; ++v) {
+        const bool same = word[v] == word[v - 1];
+        bits[v] = same ? (bits[v] | bits[v - 1]) : bits[v];
+        word[v - 1] = same ? kNoWord : word[v - 1];
+    }
 #pragma unroll
-    for (int u = 0; u < U; ++u) {
-        const uint32_t need = word[u] != kNoWord ? (bit[u] & ~old[u]) : 0u;
-        wave_bitmap_or_needed(bm, need ? word[u] : kNoWord, need);
+    for (int v = 0; v < V; ++v) old[v] = bm[word[v] != kNoWord ? word[v] : 0u];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const uint32_t need = word[v] != kNoWord ? (bits[v] & ~old[v]) : 0u;
+        if (need) atomicOr(&bm[word[v]], need);
     }
 }
 

@@ -27,7 +27,6 @@ constexpr int kMaxSplitWindows = 4;           // rows needing more windows are n
 constexpr int kMergeSlice = 1024;             // words per merge item
 // entries of a long row whose B row has at least this many products get a
 // wave (medium) or the whole workgroup (huge); shorter ones are flattened
-constexpr uint32_t kMediumLen = 32, kHugeLen = 2048;
 
 // Streaming FLOP kernels: 256 threads, tiles of kFlopTile merge-path items
 // (rows + entries of A), at most kFlopTile + 3 < 2048 entries per tile.

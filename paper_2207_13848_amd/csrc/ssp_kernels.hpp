@@ -510,12 +510,23 @@ __global__ __launch_bounds__(TEAM) void k_sym(Csr A, Csr B, const BinItem* __res
 // Bin 4: long rows, 1024 threads per item, an LDS bitmap per window of
 // `win_words` words.  An item covers the A entries [e_lo, e_hi) of its row (all
 // of them unless the row is split into parts).  The entries are taken 1024 at
-// a time and split by the length of the B row they name: huge ones are walked
-// by the whole workgroup, medium ones by one wave each, short ones flattened
-// (owner by binary search), so reads of B's columns stay coalesced; every
-// loop issues several independent loads per lane before using them.  An
-// unsplit item counts its bits; a part of a split row stores its window bitmap
-// to global scratch for k_sym_merge.
+// a time.  Those naming a B row of at least kLongLen columns are cut into
+// units of kUnitCols columns; every wave walks its own contiguous range of the
+// chunk's units, lane l reading columns [4l, 4l + 4) of a unit with one
+// 16-byte load, two units ahead of the inserts.  The short B rows are
+// flattened (owner by binary search in LDS) and shared out over the whole
+// workgroup.  An unsplit item counts its bits; a part of a split row stores
+// its window bitmap to global scratch for k_sym_merge.
+constexpr uint32_t kLongLen = 32;
+constexpr uint32_t kUnitCols = 4 * kWave;
+
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
                                                        const BigItem* __restrict__ items,
@@ -524,18 +535,19 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
                                                        int64_t* __restrict__ out)
 {
     constexpr int TEAM = kBin4Team, NWAVE = TEAM / kWave;
+    typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
     extern __shared__ uint32_t bm[];
+    // compacted entries of a chunk: short ones from the front, long ones from the back
     __shared__ int32_t s_b0[TEAM];
     __shared__ uint32_t s_len[TEAM];
-    __shared__ uint32_t s_soff[TEAM];
-    __shared__ int16_t s_med[TEAM];
-    __shared__ int16_t s_huge[TEAM];
+    __shared__ uint64_t s_start[TEAM]; // short: first product; long: first unit
     __shared__ uint64_t s_red[TEAM / kWave + 1];
+    __shared__ uint32_t s_it;
     const uint32_t n = *count;
-    const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
+    const int t = threadIdx.x, lane = lane_id();
+    const int wave = __builtin_amdgcn_readfirstlane(t / kWave);
     const int64_t N = B.ncols;
     const int64_t wcols_full = (int64_t)L.win_words * 32;
-    __shared__ uint32_t s_it;
     uint64_t zsum = 0;
     for (;;) {  // work queue: items are taken one at a time as workgroups free up
         if (t == 0) s_it = atomicAdd(next, 1u);
@@ -559,70 +571,108 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
                 const int32_t k = A.col[live ? j : a1 - 1];
                 const int32_t b0 = B.rpt[k];
                 const uint32_t len = live ? (uint32_t)(B.rpt[k + 1] - b0) : 0u;
-                const bool huge = len >= kHugeLen, med = !huge && len >= kMediumLen;
-                const uint64_t packed = (med ? (1ull << 32) : 0ull) | (huge ? (1ull << 48) : 0ull) |
-                                        (uint64_t)((med || huge) ? 0u : len);
-                uint64_t ptot;
+                const bool lng = len >= kLongLen, shrt = !lng && len != 0;
+                // short products (bits 0..19), short entries (20..39), long entries (40..)
+                const uint64_t packed = (shrt ? (uint64_t)len | (1ull << 20) : 0ull) |
+                                        (lng ? (1ull << 40) : 0ull);
+                const uint64_t nunits = lng ? (len + kUnitCols - 1) / kUnitCols : 0u;
+                uint64_t ptot, utot;
                 const uint64_t pk = block_excl_scan<TEAM, uint64_t>(packed, s_red, &ptot);
-                s_b0[t] = b0;
-                s_len[t] = len;
-                s_soff[t] = (uint32_t)pk;
-                if (med) s_med[(pk >> 32) & 0xFFFF] = (int16_t)t;
-                if (huge) s_huge[pk >> 48] = (int16_t)t;
+                const uint64_t uk = block_excl_scan<TEAM, uint64_t>(nunits, s_red, &utot);
+                if (shrt) {
+                    const int i = (int)((pk >> 20) & 0xFFFFF);
+                    s_b0[i] = b0;
+                    s_start[i] = pk & 0xFFFFF;
+                }
+                if (lng) {
+                    const int i = TEAM - 1 - (int)(pk >> 40);
+                    s_b0[i] = b0;
+                    s_len[i] = len;
+                    s_start[i] = uk;
+                }
                 __syncthreads();
-                const uint32_t nshort = (uint32_t)ptot;
-                const int nmed = (int)((ptot >> 32) & 0xFFFF), nhuge = (int)(ptot >> 48);
-                const int na = (a1 - a) < TEAM ? (a1 - a) : TEAM;
-                // Every loop below has the same trip count in all lanes of a wave
-                // (wave_bitmap_or needs that) and issues U independent loads per
-                // lane before using any, to keep memory busy.
-                constexpr int U = 8, US = 4;
-                for (int h = 0; h < nhuge; ++h) {
-                    const int e = s_huge[h];
-                    const uint32_t elen = s_len[e];
-                    const int32_t* bc = B.col + s_b0[e];
-                    for (uint32_t k0 = 0; k0 < elen; k0 += TEAM * U) {
-                        uint32_t c[U];
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const uint32_t kk = k0 + u * TEAM + t;
-                            const uint32_t cv = (uint32_t)bc[kk < elen ? kk : elen - 1];
-                            c[u] = kk < elen ? cv : kNoWord;
+                ptot = uniform_u64(ptot);
+                utot = uniform_u64(utot);
+                const uint32_t nsp = (uint32_t)(ptot & 0xFFFFF);
+                const int nse = (int)((ptot >> 20) & 0xFFFFF), nle = (int)(ptot >> 40);
+                // long entries: units [ub, ue) of this wave
+                const uint64_t ub = utot * (uint64_t)wave / NWAVE;
+                const uint64_t ue = utot * (uint64_t)(wave + 1) / NWAVE;
+                if (ub < ue) {
+                    // owner of unit ub: the last long entry starting at or before it
+                    int lo = 0, hi = nle;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_start[TEAM - 1 - mid] <= ub) lo = mid;
+                        else hi = mid;
+                    }
+                    // issue cursor (unit, owner); clamped at the last unit so the
+                    // prefetches past the end re-read a valid unit
+                    uint64_t uq = ub;
+                    int rq = __builtin_amdgcn_readfirstlane(lo);
+                    // Three units in flight in registers of fixed roles (the loop is
+                    // unrolled by three so no loaded register is moved before use,
+                    // which would make the compiler wait for every load).
+                    i32x4 va, vb, vc;
+                    bool oa, ob, oc;
+                    auto issue = [&](i32x4& v, bool& ok) {
+                        const int e = TEAM - 1 - rq;
+                        const uint32_t elen = __builtin_amdgcn_readfirstlane(s_len[e]);
+                        const int32_t eb0 = __builtin_amdgcn_readfirstlane(s_b0[e]);
+                        const uint32_t ui = (uint32_t)(uq - uniform_u64(s_start[e]));
+                        const uint32_t base = ui * kUnitCols + 4u * lane;
+                        const uint32_t off = base < elen - 4u ? base : elen - 4u;
+                        __builtin_memcpy(&v, B.col + eb0 + off, sizeof(v));
+                        ok = base < elen;
+                        __builtin_amdgcn_sched_barrier(0);  // keep the load ahead of the inserts
+                    };
+                    auto advance = [&]() {
+                        if (uq + 1 < ue) {
+                            ++uq;
+                            if (rq + 1 < nle && uniform_u64(s_start[TEAM - 2 - rq]) <= uq) ++rq;
                         }
-                        wave_bitmap_insert<U>(bm, c, clo32, wc32);
+                    };
+                    auto insert = [&](const i32x4& v, bool ok) {
+                        const uint32_t c[4] = {ok ? (uint32_t)v.x : kNoWord,
+                                               ok ? (uint32_t)v.y : kNoWord,
+                                               ok ? (uint32_t)v.z : kNoWord,
+                                               ok ? (uint32_t)v.w : kNoWord};
+                        lane_bitmap_insert<4>(bm, c, clo32, wc32);
+                    };
+                    issue(va, oa);
+                    advance();
+                    issue(vb, ob);
+                    for (uint64_t u = ub; u < ue; u += 3) {
+                        advance();
+                        issue(vc, oc);
+                        insert(va, oa);
+                        advance();
+                        issue(va, oa);
+                        if (u + 1 < ue) insert(vb, ob);
+                        advance();
+                        issue(vb, ob);
+                        if (u + 2 < ue) insert(vc, oc);
                     }
                 }
-                for (int m = wave; m < nmed; m += NWAVE) {
-                    const int e = s_med[m];
-                    const uint32_t elen = s_len[e];
-                    const int32_t* bc = B.col + s_b0[e];
-                    for (uint32_t k0 = 0; k0 < elen; k0 += kWave * U) {
-                        uint32_t c[U];
-#pragma unroll
-                        for (int u = 0; u < U; ++u) {
-                            const uint32_t kk = k0 + u * kWave + lane;
-                            const uint32_t cv = (uint32_t)bc[kk < elen ? kk : elen - 1];
-                            c[u] = kk < elen ? cv : kNoWord;
-                        }
-                        wave_bitmap_insert<U>(bm, c, clo32, wc32);
-                    }
-                }
-                for (uint32_t q0 = 0; q0 < nshort; q0 += TEAM * US) {
+                // short entries: products flattened over the workgroup
+                constexpr int US = 4;
+                for (uint32_t q0 = 0; q0 < nsp; q0 += TEAM * US) {
                     uint32_t c[US];
 #pragma unroll
                     for (int u = 0; u < US; ++u) {
                         const uint32_t qr = q0 + u * TEAM + t;
-                        const uint32_t q = qr < nshort ? qr : nshort - 1;
-                        int lo = 0, hi = na;
+                        const uint32_t q = qr < nsp ? qr : nsp - 1;
+                        int lo = 0, hi = nse;
                         while (hi - lo > 1) {
                             const int mid = (lo + hi) >> 1;
-                            if (s_soff[mid] <= q) lo = mid;
+                            if (s_start[mid] <= q) lo = mid;
                             else hi = mid;
                         }
-                        const uint32_t cv = (uint32_t)B.col[s_b0[lo] + (int32_t)(q - s_soff[lo])];
-                        c[u] = qr < nshort ? cv : kNoWord;
+                        const uint32_t cv =
+                            (uint32_t)B.col[s_b0[lo] + (int32_t)(q - (uint32_t)s_start[lo])];
+                        c[u] = qr < nsp ? cv : kNoWord;
                     }
-                    wave_bitmap_insert<US>(bm, c, clo32, wc32);
+                    lane_bitmap_insert<US>(bm, c, clo32, wc32);
                 }
                 __syncthreads();
             }
