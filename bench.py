@@ -82,6 +82,34 @@ def load_traffic(kernel_phase: str, workload: str, src_hash: str):
     return d.get("hbm_bytes_per_launch")
 
 
+KERNEL_OF_PHASE = {"flop": "k_flop", "sym_long": "k_sym_big", "sym_merge": "k_sym_merge",
+                   "pred_rows": "k_pred_rows"}
+
+
+def bernoulli_sample(M: int, rate: float, seed: int):
+    """Indices of the rows the Bernoulli sampler keeps: the top 53 bits of
+    splitmix64(seed, i) below floor(rate 2^53) (splitmix64: Steele, Lea &
+    Flood 2014), the rule the library documents.  Used here only to split the
+    byte count over kernels."""
+    import numpy as np
+    with np.errstate(over="ignore"):
+        z = np.uint64(seed) + (np.arange(M, dtype=np.uint64) + np.uint64(1)) * \
+            np.uint64(0x9E3779B97F4A7C15)
+        z = (z ^ (z >> np.uint64(30))) * np.uint64(0xBF58476D1CE4E5B9)
+        z = (z ^ (z >> np.uint64(27))) * np.uint64(0x94D049BB133111EB)
+        z = z ^ (z >> np.uint64(31))
+    thresh = 0 if rate <= 0 else (1 << 53) if rate >= 1 else int(rate * 9007199254740992.0)
+    return np.nonzero((z >> np.uint64(11)) < np.uint64(thresh))[0]
+
+
+def long_row_mask(rf_s, ncols: int):
+    """Sampled rows the long-row kernel serves: above 8192 products, or above
+    1024 when all columns fit one 2^20-column bitmap window but not a
+    16384-word table."""
+    lim = 1024 if (2 ** 19 < ncols <= 2 ** 20) else 8192
+    return rf_s > lim
+
+
 def get_workload(name: str):
     import workloads
     return getattr(workloads, name)()
@@ -143,26 +171,40 @@ def main():
     stats = ssp.read_stats(st)
 
     # ---- algorithmic bytes (integers of the CSR format: 4-byte indices)
+    # Per-row products and the sampled set, to split the symbolic bytes over
+    # the kernels that serve each row (one call outside the timed region).
+    _, rf_t, _ = ssp.predict_structure(Ad, Bd, w.rate, w.seed, handle=h, return_row_flop=True)
+    rf_np = rf_t.cpu().numpy().astype(np.uint64)
+    sampled = bernoulli_sample(M, w.rate, w.seed)
+    alen = np.diff(A.rpt.astype(np.int64))[sampled]
+    rf_s = rf_np[sampled].astype(np.int64)
+    long_rows = long_row_mask(rf_s, B.ncols)
     nnzA, K = A.nnz, A.ncols
-    flop_bytes = 4 * (M + 1) + 4 * nnzA + (0 if aliased else 4 * (K + 1)) + 8 * M
     n_s, a_s, f_s = stats["n_sampled"], stats["a_sample_nnz"], stats["sample_flop"]
-    sym_bytes = 8 * n_s + 12 * a_s + 4 * f_s
-    sample_bytes = 8 * n_s + 12 * a_s
-    step_bytes = flop_bytes + sym_bytes
+    assert n_s == len(rf_s) and f_s == int(rf_s.sum()) and a_s == int(alen.sum())
+
+    def sym(mask):  # A.rpt pair + A.col and B.rpt pair per entry + B.col per product
+        return int(np.sum(8 + 12 * alen[mask] + 4 * rf_s[mask]))
+
+    flop_bytes = 4 * (M + 1) + 4 * nnzA + (0 if aliased else 4 * (K + 1)) + 8 * M
+    phase_bytes = {"flop": flop_bytes, "sym_long": sym(long_rows), "sym_bins": sym(~long_rows),
+                   "sample_bin": 16 * n_s, "pred_rows": 16 * M, "tiles": 4 * (M + 1)}
+    # the whole call: the stream, the sampled rows, the nnz_pred output
+    step_bytes = flop_bytes + sym(np.ones_like(long_rows))
     per_phase = {}
     for name, (n, ms) in phases.items():
         per_phase[name] = {"launches": n, "avg_us": 1e3 * ms / max(n, 1)}
-    phase_bytes = {"flop": flop_bytes, "symbolic": sym_bytes, "sample_bin": sample_bytes,
-                   "finalize": 0}
-    dom = max((p for p in per_phase if p in phase_bytes and phase_bytes[p] > 0),
-              key=lambda p: per_phase[p]["avg_us"])
+    # the dominant kernel: each of these phases times one kernel
+    single = [p for p in ("flop", "sym_long", "sym_merge", "pred_rows") if p in per_phase]
+    dom = max(single, key=lambda p: per_phase[p]["avg_us"])
     dom_us = per_phase[dom]["avg_us"]
-    achieved = phase_bytes[dom] / (dom_us * 1e-6) / 1e9
+    dom_bytes = phase_bytes.get(dom, 0)
+    achieved = dom_bytes / (dom_us * 1e-6) / 1e9
     src_hash = kernel_source_hash()
     traffic = load_traffic(dom, w.name, src_hash)
-    roofline = {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+    roofline = {"bound": "hbm", "kernel": KERNEL_OF_PHASE[dom], "achieved": round(achieved, 1),
                 "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": traffic, "algorithmic_bytes": phase_bytes[dom],
+                "traffic": traffic, "algorithmic_bytes": dom_bytes,
                 "avg_launch_us": round(dom_us, 2)}
     phase_report = {}
     for p, d in per_phase.items():
@@ -173,6 +215,11 @@ def main():
             r["gbps"] = round(phase_bytes[p] / (d["avg_us"] * 1e-6) / 1e9, 1)
             r["frac_of_hbm_peak"] = round(r["gbps"] / HBM_PEAK_GBS, 4)
         phase_report[p] = r
+    products_long = int(rf_s[long_rows].sum())
+    if "sym_long" in per_phase:
+        phase_report["sym_long"]["products_per_s"] = round(
+            products_long / (per_phase["sym_long"]["avg_us"] * 1e-6), 1)
+        phase_report["sym_long"]["rows"] = int(long_rows.sum())
 
     result = {
         "metric": "predicted rows/s (sampled-CR SpGEMM structure prediction)",
@@ -192,7 +239,6 @@ def main():
                    "sampler": "bernoulli-splitmix64"},
         "hbm_gbps_algorithmic": round(step_bytes / (ms_per_step * 1e-3) / 1e9, 1),
         "nnz_A_per_s": round(nnzA / (ms_per_step * 1e-3), 1),
-        "products_per_s": round(stats["total_flop"] / (ms_per_step * 1e-3), 1),
         "step_algorithmic_bytes": step_bytes,
         "roofline": roofline,
         "phases": phase_report,

@@ -25,8 +25,6 @@ constexpr int kMaxParts = 64;
 constexpr int kMaxPartWindows = 1024;         // global part bitmaps (x window words)
 constexpr int kMaxSplitWindows = 4;           // rows needing more windows are not split
 constexpr int kMergeSlice = 1024;             // words per merge item
-// entries of a long row whose B row has at least this many products get a
-// wave (medium) or the whole workgroup (huge); shorter ones are flattened
 
 // Streaming FLOP kernels: 256 threads, tiles of kFlopTile merge-path items
 // (rows + entries of A), at most kFlopTile + 3 < 2048 entries per tile.
@@ -72,16 +70,29 @@ struct MergeItem {  // one slice of one window of a split row
     int32_t pad;
 };
 
+// Per-workgroup counters of the sampling passes.  k_sample_count writes
+//   c[0..2] rows of bins 1..3, c[3] rows of bin 4, c[4] bin-4 items if its
+//   split-eligible rows are split, c[5] their merge items, c[6] part windows
+//   they request;
+// k_sample_scan rewrites them in place as
+//   c[0..2] offsets in bins 1..3, c[3] offset in bin 4, c[4] offset in the
+//   merge list, c[5] first part window, c[6] 1 if the rows are split.
+struct SampleCounts {
+    uint32_t c[8];
+    uint64_t ns, fs, as, pad; // sampled rows, their products, their A entries
+};
+constexpr int kSampleGroups = 512; // workgroups of the sampling passes (at most)
+
 struct TileMeta {   // per streaming tile
     uint64_t head;  // products of its first row here, when that row began earlier
     uint64_t carry; // products of its last row here, when that row begins here and goes on
     uint64_t fsum;  // products of all its entries
-    uint64_t osum;  // sum of the outputs it wrote
+    uint64_t pad;
 };
 
 // Workspace layout of one call (byte offsets, each 256-aligned).
 struct Layout {
-    size_t ctl, scratch, bin1, bin2, bin3, bin4, merge, tiles, meta, rowtmp, total;
+    size_t ctl, scratch, bin1, bin2, bin3, bin4, merge, tiles, meta, samp, rowtmp, total;
     int64_t cap13, cap4, cap5, ntiles;
 };
 
@@ -109,6 +120,7 @@ inline Layout make_layout(int64_t nitems, int64_t M, int64_t nnzA, bool need_row
     L.merge = o;   o = align256(o + (size_t)L.cap5 * sizeof(MergeItem));
     L.tiles = o;   o = align256(o + (size_t)(L.ntiles + 1) * sizeof(int32_t));
     L.meta = o;    o = align256(o + (size_t)(L.ntiles > 0 ? L.ntiles : 1) * sizeof(TileMeta));
+    L.samp = o;    o = align256(o + (size_t)kSampleGroups * sizeof(SampleCounts));
     L.rowtmp = o;
     if (need_rowtmp) o = align256(o + (size_t)(M > 0 ? M : 1) * sizeof(int64_t));
     L.total = o;

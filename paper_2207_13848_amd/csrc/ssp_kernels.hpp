@@ -35,6 +35,8 @@ struct BinLists {
     uint32_t* scratch; // kMaxPartWindows x window words
     int32_t win_words; // words per bitmap window (<= kWinWords)
     int32_t nwin;      // windows covering the N columns
+    int32_t big3;      // bin-3 rows go to the long-row kernel (see bin_route)
+    int32_t merge_per_row; // merge items of one split row (slices over all windows)
 };
 
 typedef unsigned long long ull;
@@ -70,6 +72,15 @@ __device__ __forceinline__ int bin_of(uint64_t rf)
     return rf == 0 ? 0 : rf <= kBin1Max ? 1 : rf <= kBin2Max ? 2 : rf <= kBin3Max ? 3 : 4;
 }
 
+// Bin of a row for the kernels: bin-3 rows go to the long-row kernel when all
+// N columns fit one LDS bitmap window but not bin 3's table as a bitmap (bin 3
+// would hash); the bitmap kernel then counts them far faster.
+__device__ __forceinline__ int bin_route(uint64_t rf, const BinLists& L)
+{
+    const int b = bin_of(rf);
+    return (b == 3 && L.big3) ? 4 : b;
+}
+
 // Merge items of a split row: one per (window, slice of kMergeSlice words).
 __device__ inline void append_merge_items(int32_t row, int32_t slot, int32_t nparts, int64_t N,
                                           Ctl* ctl, const BinLists& L)
@@ -94,20 +105,23 @@ __device__ inline void append_merge_items(int32_t row, int32_t slot, int32_t npa
 }
 
 // Bin-4 items of one long row (single lane).  A row above kSplitTarget
-// products is cut into parts of near-equal numbers of A entries when enough
-// global part windows are left.  (The sampled path cuts its long rows by
-// products instead, in k_sample; this form serves the exact path.)
+// products is cut into P parts when enough global part windows are left; part
+// p takes the entries e0 + p, e0 + p + P, e0 + p + 2P, ...  In skewed rows the
+// heavy entries (hub columns, long B rows) sit together, and a stride deals
+// them out evenly, so the parts get near-equal product counts without a scan
+// of the row.  Unsplit rows are one part (P = 1).
 __device__ inline void append_big(int32_t row, uint64_t rf, int32_t e0, int32_t e1, int64_t N,
                                   Ctl* ctl, const BinLists& L)
 {
     const int64_t alen = (int64_t)e1 - e0;
-    const int nwin = L.nwin;
     int32_t nparts = 1, slot = -1;
-    if (rf > kSplitTarget && nwin <= kMaxSplitWindows && alen > 1) {
+    if (rf > kSplitTarget && L.nwin <= kMaxSplitWindows && alen > 1 &&
+        __hip_atomic_load(&ctl->pw_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+            (uint32_t)kMaxPartWindows) {  // (bounds the counter: it cannot wrap)
         uint64_t want = (rf + kSplitTarget - 1) / kSplitTarget;
         if (want > (uint64_t)kMaxParts) want = kMaxParts;
         if (want > (uint64_t)alen) want = (uint64_t)alen;
-        const uint32_t need = (uint32_t)want * (uint32_t)nwin;
+        const uint32_t need = (uint32_t)want * (uint32_t)L.nwin;
         const uint32_t s = atomicAdd(&ctl->pw_ctr, need);
         if (s + need <= (uint32_t)kMaxPartWindows) {
             slot = (int32_t)s;
@@ -121,18 +135,42 @@ __device__ inline void append_big(int32_t row, uint64_t rf, int32_t e0, int32_t 
         it.slot = slot;
         it.part = p;
         it.nparts = nparts;
-        it.e_lo = e0 + (int32_t)(alen * p / nparts);
-        it.e_hi = e0 + (int32_t)(alen * (p + 1) / nparts);
+        it.e_lo = e0;
+        it.e_hi = e1;
         L.b4[base + p] = it;
     }
     if (slot >= 0) append_merge_items(row, slot, nparts, N, ctl, L);
+}
+
+// Bins 1..3 of a wave's rows with one atomic per wave and bin (every lane
+// calls it; b = 0 for lanes with nothing to append).
+__device__ __forceinline__ void append_small_bins(int b, int32_t row, uint64_t rf, Ctl* ctl,
+                                                  const BinLists& L)
+{
+    const int lane = lane_id();
+#pragma unroll
+    for (int bb = 1; bb <= 3; ++bb) {
+        const uint64_t m = __ballot(b == bb);
+        if (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            uint32_t pos = 0;
+            if (lane == leader) pos = atomicAdd(&ctl->bin_cnt[bb], (uint32_t)__popcll(m));
+            pos = __shfl(pos, leader, kWave);
+            if (b == bb) {
+                BinItem it;
+                it.row = row;
+                it.rf = (uint32_t)rf;
+                (bb == 1 ? L.b1 : bb == 2 ? L.b2 : L.b3)[pos + rank_in(m)] = it;
+            }
+        }
+    }
 }
 
 // One row, appended by a single lane.
 __device__ inline void append_row(int32_t row, uint64_t rf, int32_t e0, int32_t e1, int64_t N,
                                   Ctl* ctl, const BinLists& L)
 {
-    const int b = bin_of(rf);
+    const int b = bin_route(rf, L);
     if (b == 0) return;
     if (b == 4) {
         append_big(row, rf, e0, e1, N, ctl, L);
@@ -145,253 +183,277 @@ __device__ inline void append_row(int32_t row, uint64_t rf, int32_t e0, int32_t 
     (b == 1 ? L.b1 : b == 2 ? L.b2 : L.b3)[i] = it;
 }
 
-// --------------------------------------------------------- k_sample
+// ------------------------------------------------------------ k_tiles
 
-constexpr int kSampleThreads = 512;
-constexpr int kSampleBlock = 4096;     // candidates per block (8 per thread)
-constexpr int32_t kRowflopWaveMax = 512; // sampled rows with more entries take the workgroup
-
-// Workgroup per block of 4096 candidates (rows of A; draws of the paper's
-// sampler).  (1) Row g of the block: the merge-path tiles of the streaming
-// pass whose start diagonal b * kFlopTile lies in [rpt[g] + g, rpt[g+1] + g + 1)
-// start in row g.  (2) The block's sampled rows are compacted in LDS; each
-// gets its product count from one wave (or from the whole workgroup when the
-// row is long), 4..8 independent gathers in flight per lane.  (3) The rows go
-// to their bins with one global atomic per bin per block; n_s, f* and the
-// sampled rows' entries are added once per workgroup.  Same-address device
-// atomics serialise, so they are kept few.
-template <bool PAPER, bool SAMPLE>
-__global__ __launch_bounds__(kSampleThreads) void k_sample(Csr A, Csr B, uint64_t seed,
-                                                          uint64_t thresh, int64_t ndraws,
-                                                          int64_t ntiles,
-                                                          int32_t* __restrict__ tile_row, Ctl* ctl,
-                                                          ssp_stats* st, BinLists L)
+// Merge-path partition of the streaming FLOP pass: tile b starts in row g
+// when its first item b * kFlopTile lies in [rpt[g] + g, rpt[g+1] + g + 1),
+// the span of row g's entries and end marker.  tile_row[ntiles] = M.
+__global__ __launch_bounds__(256) void k_tiles(Csr A, int64_t ntiles, int32_t* __restrict__ tile_row)
 {
-    constexpr int NT = kSampleThreads, NW = NT / kWave, PER = kSampleBlock / NT;
-    __shared__ int32_t s_rows[SAMPLE ? kSampleBlock : 1];
-    __shared__ uint64_t s_rf[SAMPLE ? kSampleBlock : 1];
-    __shared__ int32_t s_long[SAMPLE ? kSampleBlock : 1];
-    __shared__ uint32_t s_n, s_nlong, s_nbig, s_cnt[4], s_cur[4], s_base[4];
-    __shared__ int32_t s_E[kMaxParts + 1];
-    __shared__ int32_t s_qlast;
-    __shared__ uint32_t s_split[3];
-    __shared__ uint64_t s_red[NW + 1];
-    const int t = threadIdx.x, lane = lane_id(), wave = t / kWave;
     const int64_t M = A.nrows;
-    const int64_t ncand = SAMPLE ? (PAPER ? ndraws : M) : 0;
-    const int64_t nblocks = ((M > ncand ? M : ncand) + kSampleBlock - 1) / kSampleBlock;
-    if (blockIdx.x == 0 && t == 0) tile_row[ntiles] = (int32_t)M;
-    uint64_t fsum = 0, asum = 0, nsum = 0;
-    for (int64_t blk = blockIdx.x; blk < nblocks; blk += gridDim.x) {
-        const int64_t base = blk * kSampleBlock;
-#pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int64_t g = base + u * NT + t;
-            if (g < M) {
-                const int64_t f0 = (int64_t)A.rpt[g] + g, f1 = (int64_t)A.rpt[g + 1] + g + 1;
-                for (int64_t b = (f0 + kFlopTile - 1) / kFlopTile; b * kFlopTile < f1; ++b)
-                    tile_row[b] = (int32_t)g;
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < M; g += stride) {
+        const int64_t f0 = (int64_t)A.rpt[g] + g, f1 = (int64_t)A.rpt[g + 1] + g + 1;
+        for (int64_t b = (f0 + kFlopTile - 1) / kFlopTile; b * kFlopTile < f1 && b < ntiles; ++b)
+            tile_row[b] = (int32_t)g;
+    }
+    if (blockIdx.x == 0 && threadIdx.x == 0) tile_row[ntiles] = (int32_t)M;
+}
+
+// --------------------------------------------------------- sampling
+
+constexpr int kSampleThreads = 256;
+
+// Candidate i of a sampler: row i for the Bernoulli sampler (kept when the
+// top 53 bits of splitmix64(seed, i) fall below the threshold), the i-th draw
+// for the paper's (row floor(M u / 2^53) of the draw's top 53 bits u).
+// Returns -1 for a candidate that is not sampled.
+template <bool PAPER>
+__device__ __forceinline__ int64_t candidate_row(int64_t i, int64_t M, uint64_t seed,
+                                                 uint64_t thresh)
+{
+    const uint64_t x = splitmix64_at(seed, (uint64_t)i) >> 11;
+    if (PAPER) {
+        const u128 p = mul_64x64((uint64_t)M, x);
+        return (int64_t)((p.lo >> 53) | (p.hi << 11));
+    }
+    return x < thresh ? i : -1;
+}
+
+// What a sampled row contributes to the lists: its bin, and for bin 4
+// whether it may be split and into how many parts.
+struct SampledRow {
+    int64_t g;
+    uint64_t rf;
+    int32_t e0, e1;
+    int bin;
+    uint32_t want;  // parts when split (1 unless eligible)
+    bool elig;
+};
+
+__device__ __forceinline__ SampledRow classify_row(int64_t g, const Csr& A,
+                                                   const int64_t* __restrict__ rf,
+                                                   const BinLists& L)
+{
+    SampledRow r;
+    r.g = g;
+    r.rf = 0;
+    r.e0 = r.e1 = 0;
+    r.bin = 0;
+    r.want = 1;
+    r.elig = false;
+    if (g < 0) return r;
+    r.rf = (uint64_t)rf[g];
+    r.e0 = A.rpt[g];
+    r.e1 = A.rpt[g + 1];
+    r.bin = bin_route(r.rf, L);
+    const int64_t alen = (int64_t)r.e1 - r.e0;
+    if (r.bin == 4 && r.rf > kSplitTarget && L.nwin <= kMaxSplitWindows && alen > 1) {
+        uint64_t want = (r.rf + kSplitTarget - 1) / kSplitTarget;
+        if (want > (uint64_t)kMaxParts) want = kMaxParts;
+        if (want > (uint64_t)alen) want = (uint64_t)alen;
+        r.want = (uint32_t)want;
+        r.elig = true;
+    }
+    return r;
+}
+
+// The candidates of sampling workgroup b: [b C, min((b + 1) C, ncand)).
+__device__ __forceinline__ int64_t sample_chunk(int64_t ncand)
+{
+    const int64_t per = (ncand + gridDim.x - 1) / gridDim.x;
+    return (per + kSampleThreads - 1) / kSampleThreads * kSampleThreads;
+}
+
+// Pass 1: per workgroup, the counts of SampleCounts and the sums of n_s, f*
+// and the sample's A entries.  No atomics: the passes hand over per-group
+// counters (same-address device atomics serialise on this part).
+template <bool PAPER>
+__global__ __launch_bounds__(kSampleThreads) void k_sample_count(Csr A,
+                                                                const int64_t* __restrict__ rf,
+                                                                uint64_t seed, uint64_t thresh,
+                                                                int64_t ncand, BinLists L,
+                                                                SampleCounts* __restrict__ cnt)
+{
+    constexpr int NT = kSampleThreads;
+    __shared__ uint64_t s_red[NT / kWave + 1];
+    const int64_t C = sample_chunk(ncand);
+    const int64_t lo = (int64_t)blockIdx.x * C;
+    const int64_t hi = (lo + C) < ncand ? (lo + C) : ncand;
+    uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
+    uint64_t ns = 0, fs = 0, as = 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
+        const SampledRow r = classify_row(candidate_row<PAPER>(i, A.nrows, seed, thresh), A, rf, L);
+        if (r.g < 0) continue;
+        ns += 1;
+        fs += r.rf;
+        as += (uint64_t)(r.e1 - r.e0);
+        c[0] += r.bin == 1;  // (selects, not an index: c stays in registers)
+        c[1] += r.bin == 2;
+        c[2] += r.bin == 3;
+        if (r.bin == 4) {
+            c[3] += 1;
+            c[4] += r.want;
+            if (r.elig) {
+                c[5] += (uint32_t)L.merge_per_row;
+                c[6] += r.want * (uint32_t)L.nwin;
             }
         }
-        if (!SAMPLE || base >= ncand) continue;
-        if (t < 4) {
-            s_cnt[t] = 0;
-            s_cur[t] = 0;
-        }
-        if (t == 0) {
-            s_n = 0;
-            s_nlong = 0;
-            s_nbig = 0;
-        }
-        __syncthreads();
+    }
+    uint32_t tot[7];
 #pragma unroll
-        for (int u = 0; u < PER; ++u) {
-            const int64_t g = base + u * NT + t;
-            int32_t row = -1;
-            if (g < ncand) {
-                if (PAPER) {
-                    const u128 x = mul_64x64((uint64_t)M, splitmix64_at(seed, (uint64_t)g) >> 11);
-                    row = (int32_t)((x.lo >> 53) | (x.hi << 11));
-                } else if ((splitmix64_at(seed, (uint64_t)g) >> 11) < thresh) {
-                    row = (int32_t)g;
-                }
-            }
-            const uint64_t mask = __ballot(row >= 0);
-            if (mask) {
-                const int leader = __ffsll((long long)mask) - 1;
-                uint32_t pos = 0;
-                if (lane == leader) pos = atomicAdd(&s_n, (uint32_t)__popcll(mask));
-                pos = __shfl(pos, leader, kWave);
-                if (row >= 0) s_rows[pos + rank_in(mask)] = row;
-            }
-        }
-        __syncthreads();
-        const uint32_t n = s_n;
-        for (uint32_t i = wave; i < n; i += NW) {  // one wave per (short) sampled row
-            const int32_t r = s_rows[i];
-            const int32_t a0 = A.rpt[r], a1 = A.rpt[r + 1];
-            if (a1 - a0 > kRowflopWaveMax) {
-                if (lane == 0) s_long[atomicAdd(&s_nlong, 1u)] = (int32_t)i;
-                continue;
-            }
-            uint64_t sum = 0;
-            for (int32_t j = a0 + lane; j < a1; j += kWave * 4) {
-                // clamped unconditional loads, masked afterwards (see flop_issue_tile)
-                int32_t c[4];
-                uint32_t len[4];
+    for (int k = 0; k < 7; ++k) tot[k] = (uint32_t)block_sum<NT, uint64_t>(c[k], s_red);
+    const uint64_t Ns = block_sum<NT, uint64_t>(ns, s_red);
+    const uint64_t Fs = block_sum<NT, uint64_t>(fs, s_red);
+    const uint64_t As = block_sum<NT, uint64_t>(as, s_red);
+    if (threadIdx.x == 0) {
+        SampleCounts o;
 #pragma unroll
-                for (int v = 0; v < 4; ++v) c[v] = A.col[(j + kWave * v) < a1 ? (j + kWave * v) : a1 - 1];
-#pragma unroll
-                for (int v = 0; v < 4; ++v) len[v] = csr_row_len(B.rpt, c[v]);
-#pragma unroll
-                for (int v = 0; v < 4; ++v) sum += (j + kWave * v < a1) ? len[v] : 0u;
+        for (int k = 0; k < 7; ++k) o.c[k] = tot[k];
+        o.c[7] = 0;
+        o.ns = Ns;
+        o.fs = Fs;
+        o.as = As;
+        o.pad = 0;
+        cnt[blockIdx.x] = o;
+    }
+}
+
+// Pass 2, one workgroup: exclusive offsets of every group in every list,
+// the split decision (a group's eligible rows are split when all part
+// windows requested up to and including the group fit the scratch), the
+// list sizes and n_s, f*, the sample's A entries.
+constexpr int kScanThreads = kSampleGroups;
+static_assert(kSampleGroups <= kScanThreads, "one thread per sampling group");
+
+__global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __restrict__ cnt,
+                                                             int ngroups, Ctl* ctl,
+                                                             ssp_stats* st)
+{
+    constexpr int NT = kScanThreads;
+    __shared__ uint64_t s_red[NT / kWave + 1];
+    const int t = threadIdx.x;
+    SampleCounts x{};
+    if (t < ngroups) x = cnt[t];
+    uint64_t tot01, tot2w, tot4m;
+    const uint64_t p01 = block_excl_scan<NT, uint64_t>((uint64_t)x.c[0] | ((uint64_t)x.c[1] << 32),
+                                                       s_red, &tot01);
+    const uint64_t p2w = block_excl_scan<NT, uint64_t>((uint64_t)x.c[2] | ((uint64_t)x.c[6] << 32),
+                                                       s_red, &tot2w);
+    const uint32_t wpre = (uint32_t)(p2w >> 32);
+    const bool split = x.c[6] != 0 && (uint64_t)wpre + x.c[6] <= (uint64_t)kMaxPartWindows;
+    const uint32_t n4 = split ? x.c[4] : x.c[3];
+    const uint32_t nm = split ? x.c[5] : 0u;
+    const uint64_t p4m = block_excl_scan<NT, uint64_t>((uint64_t)n4 | ((uint64_t)nm << 32), s_red,
+                                                       &tot4m);
+    const uint64_t Ns = block_sum<NT, uint64_t>(x.ns, s_red);
+    const uint64_t Fs = block_sum<NT, uint64_t>(x.fs, s_red);
+    const uint64_t As = block_sum<NT, uint64_t>(x.as, s_red);
+    if (t < ngroups) {
+        SampleCounts o = x;
+        o.c[0] = (uint32_t)p01;
+        o.c[1] = (uint32_t)(p01 >> 32);
+        o.c[2] = (uint32_t)p2w;
+        o.c[3] = (uint32_t)p4m;
+        o.c[4] = (uint32_t)(p4m >> 32);
+        o.c[5] = wpre;
+        o.c[6] = split ? 1u : 0u;
+        cnt[t] = o;
+    }
+    if (t == 0) {
+        ctl->bin_cnt[1] = (uint32_t)tot01;
+        ctl->bin_cnt[2] = (uint32_t)(tot01 >> 32);
+        ctl->bin_cnt[3] = (uint32_t)tot2w;
+        ctl->bin_cnt[4] = (uint32_t)tot4m;
+        ctl->bin_cnt[5] = (uint32_t)(tot4m >> 32);
+        st->n_sampled = Ns;
+        st->sample_flop = Fs;
+        st->a_sample_nnz = As;
+    }
+}
+
+// Pass 3: every group regenerates its candidates and writes its rows at its
+// offsets (positions inside the group by workgroup scans, in candidate order).
+template <bool PAPER>
+__global__ __launch_bounds__(kSampleThreads) void k_sample_write(Csr A,
+                                                                const int64_t* __restrict__ rf,
+                                                                uint64_t seed, uint64_t thresh,
+                                                                int64_t ncand, int64_t N,
+                                                                const SampleCounts* __restrict__ cnt,
+                                                                BinLists L)
+{
+    constexpr int NT = kSampleThreads;
+    __shared__ uint64_t s_red[NT / kWave + 1];
+    const int t = threadIdx.x;
+    const int64_t C = sample_chunk(ncand);
+    const int64_t lo = (int64_t)blockIdx.x * C;
+    const int64_t hi = (lo + C) < ncand ? (lo + C) : ncand;
+    if (lo >= hi) return;  // (uniform over the workgroup)
+    const SampleCounts o = cnt[blockIdx.x];
+    const bool split = o.c[6] != 0;
+    uint32_t off1 = o.c[0], off2 = o.c[1], off3 = o.c[2], off4 = o.c[3], offm = o.c[4],
+             offw = o.c[5];
+    for (int64_t i0 = lo; i0 < hi; i0 += NT) {  // same trip count in every lane (scans)
+        const int64_t i = i0 + t;
+        const SampledRow r = classify_row(
+            i < hi ? candidate_row<PAPER>(i, A.nrows, seed, thresh) : -1, A, rf, L);
+        const bool sp = split && r.elig;
+        const uint32_t n4 = r.bin == 4 ? (sp ? r.want : 1u) : 0u;
+        const uint32_t nm = sp ? (uint32_t)L.merge_per_row : 0u;
+        const uint32_t nw = sp ? r.want * (uint32_t)L.nwin : 0u;
+        uint64_t t01, t34, tmw;
+        const uint64_t p01 = block_excl_scan<NT, uint64_t>(
+            (uint64_t)(r.bin == 1) | ((uint64_t)(r.bin == 2) << 32), s_red, &t01);
+        const uint64_t p34 = block_excl_scan<NT, uint64_t>(
+            (uint64_t)(r.bin == 3) | ((uint64_t)n4 << 32), s_red, &t34);
+        const uint64_t pmw = block_excl_scan<NT, uint64_t>((uint64_t)nm | ((uint64_t)nw << 32),
+                                                           s_red, &tmw);
+        if (r.bin >= 1 && r.bin <= 3) {
+            BinItem it;
+            it.row = (int32_t)r.g;
+            it.rf = (uint32_t)r.rf;
+            if (r.bin == 1) L.b1[off1 + (uint32_t)p01] = it;
+            else if (r.bin == 2) L.b2[off2 + (uint32_t)(p01 >> 32)] = it;
+            else L.b3[off3 + (uint32_t)p34] = it;
+        } else if (r.bin == 4) {
+            const uint32_t base = off4 + (uint32_t)(p34 >> 32);
+            const int32_t slot = sp ? (int32_t)(offw + (uint32_t)(pmw >> 32)) : -1;
+            for (uint32_t p = 0; p < n4; ++p) {
+                BigItem it;
+                it.row = (int32_t)r.g;
+                it.slot = slot;
+                it.part = (int32_t)p;
+                it.nparts = (int32_t)n4;
+                it.e_lo = r.e0;
+                it.e_hi = r.e1;
+                L.b4[base + p] = it;
             }
-            sum = wave_sum(sum);
-            if (lane == 0) {
-                s_rf[i] = sum;
-                asum += (uint64_t)(a1 - a0);
-            }
-        }
-        __syncthreads();
-        const uint32_t nlong = s_nlong;
-        for (uint32_t li = 0; li < nlong; ++li) {  // long sampled rows: the whole workgroup
-            const uint32_t i = (uint32_t)s_long[li];
-            const int32_t r = s_rows[i];
-            const int32_t a0 = A.rpt[r], a1 = A.rpt[r + 1];
-            uint64_t sum = 0;
-            for (int32_t j = a0 + t; j < a1; j += NT * 8) {
-                int32_t c[8];
-                uint32_t len[8];
-#pragma unroll
-                for (int v = 0; v < 8; ++v) c[v] = A.col[(j + NT * v) < a1 ? (j + NT * v) : a1 - 1];
-#pragma unroll
-                for (int v = 0; v < 8; ++v) len[v] = csr_row_len(B.rpt, c[v]);
-#pragma unroll
-                for (int v = 0; v < 8; ++v) sum += (j + NT * v < a1) ? len[v] : 0u;
-            }
-            sum = block_sum<NT, uint64_t>(sum, s_red);
-            if (t == 0) {
-                s_rf[i] = sum;
-                asum += (uint64_t)(a1 - a0);
-            }
-        }
-        __syncthreads();
-        for (uint32_t i = t; i < n; i += NT) {
-            const uint64_t rf = s_rf[i];
-            fsum += rf;
-            const int b = bin_of(rf);
-            if (b >= 1 && b <= 3) atomicAdd(&s_cnt[b], 1u);
-            else if (b == 4) s_long[atomicAdd(&s_nbig, 1u)] = (int32_t)i;
-        }
-        __syncthreads();
-        if (t >= 1 && t <= 3 && s_cnt[t]) s_base[t] = atomicAdd(&ctl->bin_cnt[t], s_cnt[t]);
-        __syncthreads();
-        for (uint32_t i = t; i < n; i += NT) {
-            const uint64_t rf = s_rf[i];
-            const int b = bin_of(rf);
-            if (b >= 1 && b <= 3) {
-                const uint32_t pos = s_base[b] + atomicAdd(&s_cur[b], 1u);
-                BinItem it;
-                it.row = s_rows[i];
-                it.rf = (uint32_t)rf;
-                (b == 1 ? L.b1 : b == 2 ? L.b2 : L.b3)[pos] = it;
-            }
-        }
-        // Long rows (bin 4).  A row above kSplitTarget products is cut into
-        // parts of near-equal products: entry e (products before it: pre_e)
-        // goes to part floor(pre_e / S), S = ceil(rf / nparts), found with a
-        // workgroup scan over the row's entries.
-        __syncthreads();
-        const uint32_t nbig = s_nbig;
-        for (uint32_t bi = 0; bi < nbig; ++bi) {
-            const uint32_t i = (uint32_t)s_long[bi];
-            const int32_t r = s_rows[i];
-            const uint64_t rf = s_rf[i];
-            const int32_t e0 = A.rpt[r], e1 = A.rpt[r + 1];
-            const int64_t alen = (int64_t)e1 - e0;
-            if (t == 0) {
-                uint32_t want = 1;
-                int32_t slot = -1;
-                if (rf > kSplitTarget && L.nwin <= kMaxSplitWindows && alen > 1) {
-                    uint64_t wv = (rf + kSplitTarget - 1) / kSplitTarget;
-                    if (wv > (uint64_t)kMaxParts) wv = kMaxParts;
-                    if (wv > (uint64_t)alen) wv = (uint64_t)alen;
-                    const uint32_t need = (uint32_t)wv * (uint32_t)L.nwin;
-                    const uint32_t s0 = atomicAdd(&ctl->pw_ctr, need);
-                    if (s0 + need <= (uint32_t)kMaxPartWindows) {
-                        want = (uint32_t)wv;
-                        slot = (int32_t)s0;
+            if (sp) {
+                uint32_t m = offm + (uint32_t)pmw;
+                const int64_t wcols_full = (int64_t)L.win_words * 32;
+                for (int w = 0; w < L.nwin; ++w) {
+                    const int64_t cols = (N - w * wcols_full) < wcols_full ? (N - w * wcols_full)
+                                                                          : wcols_full;
+                    const int slices = (int)(((cols + 31) / 32 + kMergeSlice - 1) / kMergeSlice);
+                    for (int sl = 0; sl < slices; ++sl) {
+                        MergeItem mi;
+                        mi.row = (int32_t)r.g;
+                        mi.slot = slot;
+                        mi.nparts = (int32_t)n4;
+                        mi.window = w;
+                        mi.slice = sl;
+                        mi.pad = 0;
+                        L.merge[m++] = mi;
                     }
                 }
-                s_split[0] = want;
-                s_split[1] = (uint32_t)slot;
-                s_split[2] = atomicAdd(&ctl->bin_cnt[4], want);
-                s_qlast = -1;
             }
-            __syncthreads();
-            const uint32_t want = s_split[0];
-            const int32_t slot = (int32_t)s_split[1];
-            const uint32_t base = s_split[2];
-            if (want > 1) {
-                const uint64_t S = (rf + want - 1) / want;
-                for (int p = t; p <= kMaxParts; p += NT) s_E[p] = p == 0 ? e0 : e1;
-                uint64_t carry = 0;
-                for (int32_t a = e0; a < e1; a += NT) {
-                    const int32_t j = a + t;
-                    const bool live = j < e1;
-                    const uint64_t len = live ? csr_row_len(B.rpt, A.col[j]) : 0u;
-                    uint64_t tot;
-                    __syncthreads();  // s_qlast of the previous chunk is read below
-                    const int32_t qprev_chunk = s_qlast;
-                    const uint64_t pre = carry + block_excl_scan<NT, uint64_t>(len, s_red, &tot);
-                    uint64_t qe = pre / S;
-                    if (qe > want - 1) qe = want - 1;
-                    // q of the previous entry: lane below, or the previous chunk's last
-                    int32_t qprev = __shfl_up((int32_t)qe, 1, kWave);
-                    __shared__ int32_t s_qwave[NT / kWave];
-                    if (lane == kWave - 1) s_qwave[wave] = (int32_t)qe;
-                    __syncthreads();
-                    if (lane == 0) qprev = wave == 0 ? qprev_chunk : s_qwave[wave - 1];
-                    if (live)
-                        for (int32_t p = qprev + 1; p <= (int32_t)qe; ++p) s_E[p] = j;
-                    __syncthreads();
-                    if (t == NT - 1) s_qlast = (int32_t)qe;  // live unless this is the last chunk
-                    carry += tot;
-                }
-                __syncthreads();
-                for (uint32_t p = t; p < want; p += NT) {
-                    BigItem it;
-                    it.row = r;
-                    it.slot = slot;
-                    it.part = (int32_t)p;
-                    it.nparts = (int32_t)want;
-                    it.e_lo = p == 0 ? e0 : s_E[p];
-                    it.e_hi = p + 1 == want ? e1 : s_E[p + 1];
-                    L.b4[base + p] = it;
-                }
-                if (t == 0) append_merge_items(r, slot, (int32_t)want, B.ncols, ctl, L);
-            } else if (t == 0) {
-                BigItem it;
-                it.row = r;
-                it.slot = -1;
-                it.part = 0;
-                it.nparts = 1;
-                it.e_lo = e0;
-                it.e_hi = e1;
-                L.b4[base] = it;
-            }
-            __syncthreads();
         }
-        if (t == 0) nsum += n;
-        __syncthreads();
-    }
-    if (!SAMPLE) return;
-    const uint64_t Fs = block_sum<NT, uint64_t>(fsum, s_red);
-    const uint64_t As = block_sum<NT, uint64_t>(asum, s_red);
-    if (t == 0) {
-        if (nsum) atomicAdd(as_ull(&st->n_sampled), (ull)nsum);
-        if (Fs) atomicAdd(as_ull(&st->sample_flop), (ull)Fs);
-        if (As) atomicAdd(as_ull(&st->a_sample_nnz), (ull)As);
+        off1 += (uint32_t)t01;
+        off2 += (uint32_t)(t01 >> 32);
+        off3 += (uint32_t)t34;
+        off4 += (uint32_t)(t34 >> 32);
+        offm += (uint32_t)tmw;
+        offw += (uint32_t)(tmw >> 32);
     }
 }
 
@@ -556,7 +618,9 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
         __syncthreads();
         if (it >= n) break;
         const BigItem item = items[it];
-        const int32_t a0 = item.e_lo, a1 = item.e_hi;
+        // entries e0, e0 + P, e0 + 2P, ... below e_hi (P = 1 unless split)
+        const int32_t e0 = item.e_lo + item.part, P = item.nparts;
+        const int64_t cnt = item.e_hi > e0 ? ((int64_t)item.e_hi - e0 + P - 1) / P : 0;
         uint64_t total = 0;
         for (int w = 0; w < L.nwin; ++w) {
             const int64_t c_lo = w * wcols_full;
@@ -565,10 +629,10 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
             for (int i = t; i < words; i += TEAM) bm[i] = 0u;
             const uint32_t clo32 = (uint32_t)c_lo, wc32 = (uint32_t)wcols;
             __syncthreads();
-            for (int32_t a = a0; a < a1; a += TEAM) {
-                const int32_t j = a + t;
-                const bool live = j < a1;
-                const int32_t k = A.col[live ? j : a1 - 1];
+            for (int64_t i0 = 0; i0 < cnt; i0 += TEAM) {
+                const int64_t i = i0 + t;
+                const bool live = i < cnt;
+                const int32_t k = A.col[e0 + (int32_t)((live ? i : cnt - 1) * P)];
                 const int32_t b0 = B.rpt[k];
                 const uint32_t len = live ? (uint32_t)(B.rpt[k + 1] - b0) : 0u;
                 const bool lng = len >= kLongLen, shrt = !lng && len != 0;
@@ -787,12 +851,11 @@ __global__ void k_finalize_reference(Ctl* ctl, ssp_stats* st, uint64_t M)
 
 // -------------------------------------------------------------- k_flop
 
-enum { FLOP_PREDICT = 0, FLOP_ONLY = 1, FLOP_EXACT_BIN = 2 };
+enum { FLOP_ONLY = 1, FLOP_EXACT_BIN = 2 };
 
 struct FlopArgs {
     Csr A, B;
-    int64_t* out;      // PREDICT: nnz_pred; ONLY: row flop; EXACT_BIN: nnz_exact
-    int64_t* out_flop; // PREDICT: optional row flop
+    int64_t* out;      // ONLY: row flop; EXACT_BIN: nnz_exact (0 for rows of bins 0 and 4)
     ssp_stats* st;
     Ctl* ctl;
     BinLists L;
@@ -801,25 +864,16 @@ struct FlopArgs {
     int64_t ntiles;
 };
 
-// Output of one finished row: prediction, product count, or bin.  Returns
-// the value added to out_sum.
+// Output of one finished row: its product count, or its bin.
 template <int MODE>
-__device__ __forceinline__ uint64_t emit_row(const FlopArgs& a, int64_t row, uint64_t rf,
-                                             uint32_t fallback, const Divisor& D, uint64_t zs)
+__device__ __forceinline__ void emit_row(const FlopArgs& a, int64_t row, uint64_t rf)
 {
-    if (MODE == FLOP_PREDICT) {
-        const uint64_t pred = fallback ? rf : (rf ? ceil_mul_div(rf, zs, D) : 0);
-        a.out[row] = (int64_t)pred;
-        if (a.out_flop) a.out_flop[row] = (int64_t)rf;
-        return pred;
-    } else if (MODE == FLOP_ONLY) {
+    if (MODE == FLOP_ONLY) {
         a.out[row] = (int64_t)rf;
-        return 0;
     } else {
-        const int b = bin_of(rf);
+        const int b = bin_route(rf, a.L);
         if (b == 0 || b == 4) a.out[row] = 0;
         if (b != 0) append_row((int32_t)row, rf, a.A.rpt[row], a.A.rpt[row + 1], a.B.ncols, a.ctl, a.L);
-        return 0;
     }
 }
 
@@ -920,23 +974,11 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(FlopArgs a)
     __shared__ uint32_t s_x[CH];
     __shared__ uint64_t s_pre0[NT], s_pre1[NT];
     __shared__ uint64_t s_w[2 * (NT / kWave)];
-    __shared__ uint64_t s_red[NT / kWave + 1];
 
     const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
     const int64_t M = a.A.nrows;
     const int64_t G = gridDim.x, ntiles = a.ntiles;
     const int32_t* __restrict__ Brpt = a.B.rpt;
-
-    uint32_t fallback = 0;
-    Divisor D;
-    uint64_t zs = 0;
-    if (MODE == FLOP_PREDICT) {
-        fallback = a.ctl->fallback;
-        D.dn = a.ctl->div_dn;
-        D.v = a.ctl->div_v;
-        D.shift = a.ctl->div_shift;
-        zs = a.st->sample_nnz;
-    }
 
     // The tile starts of this workgroup's tiles are staged in LDS, kTrow at a
     // time: reading them from LDS does not wait on the vector loads in flight.
@@ -1047,7 +1089,6 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(FlopArgs a)
             return v;
         };
 
-        uint64_t osum = 0;
         const int nrows_t = (int)(rlast - i0 + 1);
         for (int base = 0; base < nrows_t; base += NT) {  // same trip count in every lane
             const int k = base + t;
@@ -1068,48 +1109,22 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(FlopArgs a)
                 }
             }
             if (MODE == FLOP_EXACT_BIN) {
-                // bins 1..3 with one atomic per wave and bin
-                const int bn_ = emit ? bin_of(sum) : 0;
-#pragma unroll
-                for (int bb = 1; bb <= 3; ++bb) {
-                    const uint64_t m = __ballot(bn_ == bb);
-                    if (m) {
-                        const int leader = __ffsll((long long)m) - 1;
-                        uint32_t pos = 0;
-                        if (lane == leader)
-                            pos = atomicAdd(&a.ctl->bin_cnt[bb], (uint32_t)__popcll(m));
-                        pos = __shfl(pos, leader, kWave);
-                        if (bn_ == bb) {
-                            BinItem it;
-                            it.row = (int32_t)r;
-                            it.rf = (uint32_t)sum;
-                            (bb == 1 ? a.L.b1 : bb == 2 ? a.L.b2 : a.L.b3)[pos + rank_in(m)] = it;
-                        }
-                    }
-                }
+                const int bn_ = emit ? bin_route(sum, a.L) : 0;
+                append_small_bins(bn_, (int32_t)r, sum, a.ctl, a.L);
                 if (emit && (bn_ == 0 || bn_ == 4)) a.out[r] = 0;
-                if (emit && bn_ == 4) append_big((int32_t)r, sum, s_bnd[k], s_bnd[k + 1], a.B.ncols, a.ctl, a.L);
+                if (emit && bn_ == 4)
+                    append_big((int32_t)r, sum, s_bnd[k], s_bnd[k + 1], a.B.ncols, a.ctl, a.L);
             } else if (emit) {
-                if (MODE == FLOP_PREDICT) {
-                    const uint64_t pred = fallback ? sum : (sum ? ceil_mul_div(sum, zs, D) : 0);
-                    __builtin_nontemporal_store((int64_t)pred, a.out + r);
-                    if (a.out_flop) __builtin_nontemporal_store((int64_t)sum, a.out_flop + r);
-                    osum += pred;
-                } else {
-                    __builtin_nontemporal_store((int64_t)sum, a.out + r);
-                }
+                __builtin_nontemporal_store((int64_t)sum, a.out + r);
             }
         }
-        const uint64_t O = block_sum<NT, uint64_t>(osum, s_red);
-        if (t == 0) {
-            a.meta[b].fsum = tile_total;
-            a.meta[b].osum = O;
-        }
+        if (t == 0) a.meta[b].fsum = tile_total;
+        __syncthreads();  // s_bnd, s_x and the prefixes are rewritten for the next tile
         if (bn >= ntiles) break;
         b = bn;
         cur = nxt;
         if (++kk == kTrow) {  // restage; k = 0..kTrow are staged, so kk + 1 always is
-                              // (the block_sum above ended with a barrier)
+                              // (the barrier above ends every read of the staged window)
             stage_base = b;
             stage_all(stage_base);
             kk = 0;
@@ -1119,17 +1134,16 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(FlopArgs a)
 
 // One thread per tile: a row that begins in tile b and goes on (its partial
 // is b's carry) collects the heads of the following tiles until the tile
-// holding its end marker, then gets its output.  Adds F and out_sum.
+// holding its end marker, then gets its output.  Adds F.
 template <int MODE>
 __global__ __launch_bounds__(256) void k_flop_fixup(FlopArgs a)
 {
     __shared__ uint64_t s_red[256 / kWave + 1];
     const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
     const int64_t M = a.A.nrows, nnzA = a.A.nnz;
-    uint64_t F = 0, O = 0;
+    uint64_t F = 0;
     if (b < a.ntiles) {
         F = a.meta[b].fsum;
-        O = a.meta[b].osum;
         const int64_t d0 = b * kFlopTile;
         const int64_t d1 = (d0 + kFlopTile) < (M + nnzA) ? (d0 + kFlopTile) : (M + nnzA);
         const int64_t i1 = a.tile_row[b + 1];
@@ -1142,63 +1156,100 @@ __global__ __launch_bounds__(256) void k_flop_fixup(FlopArgs a)
                     total += a.meta[bb].head;
                     if (a.tile_row[bb + 1] > i1) break;
                 }
-                uint32_t fallback = 0;
-                Divisor D;
-                uint64_t zs = 0;
-                if (MODE == FLOP_PREDICT) {
-                    fallback = a.ctl->fallback;
-                    D.dn = a.ctl->div_dn;
-                    D.v = a.ctl->div_v;
-                    D.shift = a.ctl->div_shift;
-                    zs = a.st->sample_nnz;
-                }
-                O += emit_row<MODE>(a, i1, total, fallback, D, zs);
+                emit_row<MODE>(a, i1, total);
             }
         }
     }
     const uint64_t Fs = block_sum<256, uint64_t>(F, s_red);
-    const uint64_t Os = block_sum<256, uint64_t>(O, s_red);
-    if (threadIdx.x == 0) {
-        if (Fs) atomicAdd(as_ull(&a.st->total_flop), (ull)Fs);
-        if (MODE == FLOP_PREDICT && Os) atomicAdd(as_ull(&a.st->out_sum), (ull)Os);
+    if (threadIdx.x == 0 && Fs) atomicAdd(as_ull(&a.st->total_flop), (ull)Fs);
+}
+
+// ------------------------------------------------------ prediction rows
+
+constexpr int kRowsThreads = 256;
+
+// nnz_pred[i] = ceil(rf_i z* / f*) (Eq. 3 per row), rf_i when the sample has
+// no products.  Grid-stride with few workgroups: each adds its part of the
+// output total with one atomic.
+__global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const int64_t* __restrict__ rf_in,
+                                                            int64_t* __restrict__ out, int64_t M,
+                                                            Ctl* ctl, ssp_stats* st)
+{
+    __shared__ uint64_t s_red[kRowsThreads / kWave + 1];
+    const uint32_t fallback = ctl->fallback;
+    Divisor D;
+    D.dn = ctl->div_dn;
+    D.v = ctl->div_v;
+    D.shift = ctl->div_shift;
+    const uint64_t zs = st->sample_nnz;
+    uint64_t osum = 0;
+    constexpr int U = 4;  // rows per thread and step, loaded together
+    const int64_t stride = (int64_t)gridDim.x * kRowsThreads * U;
+    for (int64_t i0 = (int64_t)blockIdx.x * kRowsThreads * U + threadIdx.x; i0 < M; i0 += stride) {
+        uint64_t rf[U];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * kRowsThreads;
+            rf[u] = (uint64_t)__builtin_nontemporal_load(rf_in + (i < M ? i : M - 1));
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * kRowsThreads;
+            if (i < M) {
+                const uint64_t pred = fallback ? rf[u] : (rf[u] ? ceil_mul_div(rf[u], zs, D) : 0);
+                __builtin_nontemporal_store((int64_t)pred, out + i);
+                osum += pred;
+            }
+        }
     }
+    const uint64_t O = block_sum<kRowsThreads, uint64_t>(osum, s_red);
+    if (threadIdx.x == 0 && O) atomicAdd(as_ull(&st->out_sum), (ull)O);
 }
 
 // --------------------------------------------------- reference rows
 
 // nnz_ref[i] = ceil(rf_i * (z* M) / (n_s F)), saturating at INT64_MAX.
-__global__ __launch_bounds__(256) void k_ref_rows(const int64_t* __restrict__ rf_in,
-                                                  int64_t* __restrict__ out, int64_t M, Ctl* ctl,
-                                                  ssp_stats* st)
+// Grid-stride like k_pred_rows.
+__global__ __launch_bounds__(kRowsThreads) void k_ref_rows(const int64_t* __restrict__ rf_in,
+                                                           int64_t* __restrict__ out, int64_t M,
+                                                           Ctl* ctl, ssp_stats* st)
 {
-    __shared__ uint64_t s_red[256 / kWave + 1];
-    const int64_t i = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    __shared__ uint64_t s_red[kRowsThreads / kWave + 1];
     const uint32_t fallback = ctl->fallback;
     const u128 Q = {ctl->ref_q_lo, ctl->ref_q_hi};
     const u128 Dd = {ctl->ref_d_lo, ctl->ref_d_hi};
-    uint64_t v = 0;
-    bool sat = false;
-    if (i < M) {
-        const uint64_t rf = (uint64_t)rf_in[i];
-        if (fallback || rf == 0) {
-            v = rf;
-        } else {
-            const u128 p0 = mul_64x64(rf, Q.lo), p1 = mul_64x64(rf, Q.hi);
-            const uint64_t l1 = p0.hi + p1.lo;
-            const uint64_t l2 = p1.hi + (l1 < p0.hi);
-            if (l2 != 0) {
-                sat = true;
+    uint64_t osum = 0;
+    bool any_sat = false;
+    const int64_t stride = (int64_t)gridDim.x * kRowsThreads;
+    const int64_t iters = (M + stride - 1) / stride;
+    for (int64_t k = 0; k < iters; ++k) {  // same trip count in every lane (ballot below)
+        const int64_t i = k * stride + (int64_t)blockIdx.x * kRowsThreads + threadIdx.x;
+        uint64_t v = 0;
+        bool sat = false;
+        if (i < M) {
+            const uint64_t rf = (uint64_t)rf_in[i];
+            if (fallback || rf == 0) {
+                v = rf;
             } else {
-                const u128 c = u128_ceil_div(u128{p0.lo, l1}, Dd);
-                if (c.hi != 0 || c.lo > 0x7fffffffffffffffull) sat = true;
-                else v = c.lo;
+                const u128 p0 = mul_64x64(rf, Q.lo), p1 = mul_64x64(rf, Q.hi);
+                const uint64_t l1 = p0.hi + p1.lo;
+                const uint64_t l2 = p1.hi + (l1 < p0.hi);
+                if (l2 != 0) {
+                    sat = true;
+                } else {
+                    const u128 c = u128_ceil_div(u128{p0.lo, l1}, Dd);
+                    if (c.hi != 0 || c.lo > 0x7fffffffffffffffull) sat = true;
+                    else v = c.lo;
+                }
+                if (sat) v = 0x7fffffffffffffffull;
             }
-            if (sat) v = 0x7fffffffffffffffull;
+            out[i] = (int64_t)v;
         }
-        out[i] = (int64_t)v;
+        osum += v;
+        any_sat = any_sat || sat;
     }
-    if (__ballot(sat) && lane_id() == 0) atomicOr(as_ull(&st->flags), (ull)SSP_FLAG_SATURATED);
-    const uint64_t O = block_sum<256, uint64_t>(v, s_red);
+    if (__ballot(any_sat) && lane_id() == 0) atomicOr(as_ull(&st->flags), (ull)SSP_FLAG_SATURATED);
+    const uint64_t O = block_sum<kRowsThreads, uint64_t>(osum, s_red);
     if (threadIdx.x == 0 && O) atomicAdd(as_ull(&st->out_sum), (ull)O);
 }
 

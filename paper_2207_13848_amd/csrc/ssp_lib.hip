@@ -16,9 +16,22 @@
 using namespace ssp;
 
 namespace {
-enum Phase { PH_SAMPLE = 0, PH_SYMBOLIC, PH_FINALIZE, PH_FLOP, PH_REF_ROWS, PH_COUNT };
-const char* const kPhaseNames[PH_COUNT] = {"sample_bin", "symbolic", "finalize", "flop",
-                                           "ref_rows"};
+enum Phase {
+    PH_SAMPLE = 0,
+    PH_SYM_BINS,
+    PH_SYM_LONG,
+    PH_SYM_MERGE,
+    PH_FINALIZE,
+    PH_TILES,
+    PH_FLOP,
+    PH_FLOP_FIXUP,
+    PH_REF_ROWS,
+    PH_PRED_ROWS,
+    PH_COUNT
+};
+const char* const kPhaseNames[PH_COUNT] = {"sample_bin", "sym_bins",   "sym_long", "sym_merge",
+                                           "finalize",   "tiles",      "flop",     "flop_fixup",
+                                           "ref_rows",   "pred_rows"};
 struct EventPair {
     int phase;
     hipEvent_t a, b;
@@ -101,11 +114,13 @@ class PhaseTimer {
         p_.b = take_event(h);
         if (p_.a && p_.b) (void)hipEventRecord(p_.a, s);
     }
-    ~PhaseTimer()
+    ~PhaseTimer() { stop(); }
+    void stop()
     {
         if (!h_->timing || !p_.a || !p_.b) return;
         (void)hipEventRecord(p_.b, s_);
         h_->pending.push_back(p_);
+        p_.a = p_.b = nullptr;
     }
 
   private:
@@ -193,6 +208,7 @@ struct Bound {
     BinLists L;
     int32_t* tile_row;
     TileMeta* meta;
+    SampleCounts* samp;
     int64_t* rowtmp;
 };
 
@@ -222,8 +238,19 @@ Bound bind(ssp_handle h, const Layout& L, int64_t N)
     b.L.merge = reinterpret_cast<MergeItem*>(base + L.merge);
     b.L.scratch = reinterpret_cast<uint32_t*>(base + L.scratch);
     window_shape(N, &b.L.win_words, &b.L.nwin);
+    // bin 3 would hash (its table as a bitmap covers fewer than N columns) while
+    // one bitmap window covers all N: those rows go to the long-row kernel
+    b.L.big3 = (b.L.nwin == 1 && N > 32LL * kBin3Words) ? 1 : 0;
+    int32_t mpr = 0;  // merge items of a split row: slices of every window
+    for (int32_t w = 0; w < b.L.nwin; ++w) {
+        const int64_t cols = std::min<int64_t>(N - (int64_t)w * b.L.win_words * 32,
+                                               (int64_t)b.L.win_words * 32);
+        mpr += (int32_t)(((cols + 31) / 32 + kMergeSlice - 1) / kMergeSlice);
+    }
+    b.L.merge_per_row = mpr;
     b.tile_row = reinterpret_cast<int32_t*>(base + L.tiles);
     b.meta = reinterpret_cast<TileMeta*>(base + L.meta);
+    b.samp = reinterpret_cast<SampleCounts*>(base + L.samp);
     b.rowtmp = reinterpret_cast<int64_t*>(base + L.rowtmp);
     return b;
 }
@@ -235,8 +262,9 @@ unsigned grid_for(int64_t items, int64_t cap)
 }
 
 template <int MODE>
-void launch_flop(const FlopArgs& fa, bool vec, int cus, hipStream_t s)
+void launch_flop(ssp_handle h, const FlopArgs& fa, bool vec, hipStream_t s)
 {
+    const int cus = h->num_cus;
     // persistent: as many workgroups as can be resident at once, each walks
     // its tiles (grid-stride)
     static int resident[2] = {0, 0};
@@ -253,9 +281,11 @@ void launch_flop(const FlopArgs& fa, bool vec, int cus, hipStream_t s)
     const unsigned grid =
         (unsigned)std::max<int64_t>(std::min<int64_t>(fa.ntiles, (int64_t)r * cus), 1);
     if (fa.ntiles > 0) {
+        PhaseTimer pt(h, PH_FLOP, s);
         if (vec) hipLaunchKernelGGL((k_flop<MODE, true>), dim3(grid), dim3(kFlopThreads), 0, s, fa);
         else hipLaunchKernelGGL((k_flop<MODE, false>), dim3(grid), dim3(kFlopThreads), 0, s, fa);
     }
+    PhaseTimer pt(h, PH_FLOP_FIXUP, s);
     const unsigned fgrid = (unsigned)std::max<int64_t>((fa.ntiles + 255) / 256, 1);
     hipLaunchKernelGGL((k_flop_fixup<MODE>), dim3(fgrid), dim3(256), 0, s, fa);
 }
@@ -269,12 +299,14 @@ ssp_status launch_symbolic(ssp_handle h, const Csr& A, const Csr& B, const Bound
 {
     const int cus = h->num_cus;
     const int64_t nitems = L.cap13;
+    PhaseTimer pt_bins(h, PH_SYM_BINS, s);
     hipLaunchKernelGGL((k_sym<kBin1Team, kBin1Words, MODE>), dim3(grid_for(nitems, 16LL * cus)),
                        dim3(kBin1Team), 0, s, A, B, b.L.b1, &b.ctl->bin_cnt[1], st, out);
     hipLaunchKernelGGL((k_sym<kBin2Team, kBin2Words, MODE>), dim3(grid_for(nitems, 4LL * cus)),
                        dim3(kBin2Team), 0, s, A, B, b.L.b2, &b.ctl->bin_cnt[2], st, out);
     hipLaunchKernelGGL((k_sym<kBin3Team, kBin3Words, MODE>), dim3(grid_for(nitems, 2LL * cus)),
                        dim3(kBin3Team), 0, s, A, B, b.L.b3, &b.ctl->bin_cnt[3], st, out);
+    pt_bins.stop();
     const size_t lds = (size_t)b.L.win_words * sizeof(uint32_t);
     static bool attr_set[2] = {false, false};
     if (!attr_set[MODE]) {
@@ -292,9 +324,14 @@ ssp_status launch_symbolic(ssp_handle h, const Csr& A, const Csr& B, const Bound
             per_cu = 1;
         big_resident[MODE] = per_cu;
     }
-    hipLaunchKernelGGL((k_sym_big<MODE>), dim3(grid_for(L.cap4, (int64_t)big_resident[MODE] * cus)),
-                       dim3(kBin4Team), lds, s, A, B, b.L.b4, &b.ctl->bin_cnt[4], &b.ctl->big_next,
-                       b.L, st, out);
+    {
+        PhaseTimer pt(h, PH_SYM_LONG, s);
+        hipLaunchKernelGGL((k_sym_big<MODE>),
+                           dim3(grid_for(L.cap4, (int64_t)big_resident[MODE] * cus)),
+                           dim3(kBin4Team), lds, s, A, B, b.L.b4, &b.ctl->bin_cnt[4],
+                           &b.ctl->big_next, b.L, st, out);
+    }
+    PhaseTimer pt_merge(h, PH_SYM_MERGE, s);
     hipLaunchKernelGGL((k_sym_merge<MODE>), dim3((unsigned)(2 * cus)), dim3(256), 0, s, b.L.merge,
                        &b.ctl->bin_cnt[5], b.L, B.ncols, b.ctl, st, out, MODE == 0 ? 1 : 0);
     SSP_LAUNCHED(h);
@@ -302,13 +339,12 @@ ssp_status launch_symbolic(ssp_handle h, const Csr& A, const Csr& B, const Bound
 }
 
 FlopArgs flop_args(const ssp_csr* A, const ssp_csr* B, const Bound& b, const Layout& L,
-                   int64_t* out, int64_t* out_flop, ssp_stats* st)
+                   int64_t* out, ssp_stats* st)
 {
     FlopArgs fa;
     fa.A = to_csr(A);
     fa.B = to_csr(B);
     fa.out = out;
-    fa.out_flop = out_flop;
     fa.st = st;
     fa.ctl = b.ctl;
     fa.L = b.L;
@@ -318,30 +354,67 @@ FlopArgs flop_args(const ssp_csr* A, const ssp_csr* B, const Bound& b, const Lay
     return fa;
 }
 
-// Tile starts, sampling, per-row products of the sample, binning and
-// distinct counting: leaves n_s, f*, z* in *st and the divisor of f* in ctl.
+// Merge-path tile starts and the streaming pass that leaves every row's
+// product count in rf and F in st (mode FLOP_ONLY), or bins every row for the
+// exact count (FLOP_EXACT_BIN).
+template <int MODE>
+ssp_status flop_pass(ssp_handle h, const ssp_csr* A, const ssp_csr* B, const Bound& b,
+                     const Layout& L, int64_t* out, ssp_stats* st, hipStream_t s)
+{
+    const int64_t M = A->nrows;
+    {
+        PhaseTimer pt(h, PH_TILES, s);
+        hipLaunchKernelGGL(k_tiles, dim3(grid_for((M + 255) / 256, 16LL * h->num_cus)), dim3(256),
+                           0, s, to_csr(A), L.ntiles, b.tile_row);
+    }
+    const FlopArgs fa = flop_args(A, B, b, L, out, st);
+    const bool vec = (reinterpret_cast<uintptr_t>(A->col) & 15u) == 0 && A->nnz >= 4;
+    launch_flop<MODE>(h, fa, vec, s);
+    SSP_LAUNCHED(h);
+    return SSP_OK;
+}
+
+// The sampled part: row FLOP of every row into rf, sampling and binning,
+// distinct counting of the sampled rows.  Leaves F, n_s, f*, z* in *st and
+// the divisor of f* in ctl.
 ssp_status sampled_part(ssp_handle h, const ssp_csr* A, const ssp_csr* B, ssp_sampler sampler,
                         double rate, uint64_t seed, const Bound& b, const Layout& L,
-                        ssp_stats* st, hipStream_t s)
+                        int64_t* rf, ssp_stats* st, hipStream_t s)
 {
+    ssp_status e = flop_pass<FLOP_ONLY>(h, A, B, b, L, rf, st, s);
+    if (e != SSP_OK) return e;
     const Csr a = to_csr(A), bb = to_csr(B);
     const int64_t M = A->nrows;
     {
         PhaseTimer pt(h, PH_SAMPLE, s);
-        const int64_t nd = sampler == SSP_SAMPLER_PAPER ? paper_sample_num(M) : M;
-        const unsigned grid = grid_for((std::max(M, nd) + kSampleBlock - 1) / kSampleBlock,
-                                       2LL * h->num_cus);
-        if (sampler == SSP_SAMPLER_PAPER)
-            hipLaunchKernelGGL((k_sample<true, true>), dim3(grid), dim3(kSampleThreads), 0, s, a,
-                               bb, seed, (uint64_t)0, nd, L.ntiles, b.tile_row, b.ctl, st, b.L);
+        const bool paper = sampler == SSP_SAMPLER_PAPER;
+        const int64_t nc = paper ? paper_sample_num(M) : M;
+        const uint64_t thr = paper ? 0 : rate_threshold(rate);
+        // count, scan, write: per-group counters instead of device atomics
+        const unsigned grid = grid_for((nc + 2047) / 2048, kSampleGroups);
+        const int64_t* rfc = rf;
+        if (paper)
+            hipLaunchKernelGGL((k_sample_count<true>), dim3(grid), dim3(kSampleThreads), 0, s, a,
+                               rfc, seed, thr, nc, b.L, b.samp);
         else
-            hipLaunchKernelGGL((k_sample<false, true>), dim3(grid), dim3(kSampleThreads), 0, s, a,
-                               bb, seed, rate_threshold(rate), (int64_t)0, L.ntiles, b.tile_row,
-                               b.ctl, st, b.L);
+            hipLaunchKernelGGL((k_sample_count<false>), dim3(grid), dim3(kSampleThreads), 0, s, a,
+                               rfc, seed, thr, nc, b.L, b.samp);
+        hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(kScanThreads), 0, s, b.samp, (int)grid,
+                           b.ctl, st);
+        if (paper)
+            hipLaunchKernelGGL((k_sample_write<true>), dim3(grid), dim3(kSampleThreads), 0, s, a,
+                               rfc, seed, thr, nc, B->ncols, (const SampleCounts*)b.samp, b.L);
+        else
+            hipLaunchKernelGGL((k_sample_write<false>), dim3(grid), dim3(kSampleThreads), 0, s, a,
+                               rfc, seed, thr, nc, B->ncols, (const SampleCounts*)b.samp, b.L);
     }
     SSP_LAUNCHED(h);
-    PhaseTimer pt(h, PH_SYMBOLIC, s);
     return launch_symbolic<0>(h, a, bb, b, L, st, nullptr, s);
+}
+
+unsigned rows_grid(ssp_handle h, int64_t M)
+{
+    return grid_for((M + 4 * kRowsThreads - 1) / (4 * kRowsThreads), 2LL * h->num_cus);
 }
 
 ssp_status common_checks(ssp_handle h, const ssp_csr* A, const ssp_csr* B, ssp_sampler sampler,
@@ -469,20 +542,20 @@ ssp_status ssp_predict_structure_ex(ssp_handle h, const ssp_csr* A, const ssp_cs
     if (!g.ok()) return SSP_ERR_NO_DEVICE;
     const int64_t M = A->nrows;
     const int64_t nitems = sampler == SSP_SAMPLER_PAPER ? paper_sample_num(M) : M;
-    const Layout L = make_layout(nitems, M, A->nnz, false);
+    const Layout L = make_layout(nitems, M, A->nnz, row_flop == nullptr);
     if ((s = ensure_workspace(h, L.total)) != SSP_OK) return s;
     const Bound b = bind(h, L, B->ncols);
     hipStream_t hs = static_cast<hipStream_t>(stream);
     ssp_stats* st = stats ? stats : &b.ctl->stats;
+    int64_t* rf = row_flop ? row_flop : b.rowtmp;
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, hs, b.ctl, st, (uint64_t)M);
     SSP_LAUNCHED(h);
     if (M == 0) return SSP_OK;
-    if ((s = sampled_part(h, A, B, sampler, rate, seed, b, L, st, hs)) != SSP_OK) return s;
-    const FlopArgs fa = flop_args(A, B, b, L, nnz_pred, row_flop, st);
-    const bool vec = (reinterpret_cast<uintptr_t>(A->col) & 15u) == 0 && A->nnz >= 4;
+    if ((s = sampled_part(h, A, B, sampler, rate, seed, b, L, rf, st, hs)) != SSP_OK) return s;
     {
-        PhaseTimer pt(h, PH_FLOP, hs);
-        launch_flop<FLOP_PREDICT>(fa, vec, h->num_cus, hs);
+        PhaseTimer pt(h, PH_PRED_ROWS, hs);
+        hipLaunchKernelGGL(k_pred_rows, dim3(rows_grid(h, M)), dim3(kRowsThreads), 0, hs,
+                           (const int64_t*)rf, nnz_pred, M, b.ctl, st);
     }
     SSP_LAUNCHED(h);
     return SSP_OK;
@@ -514,13 +587,8 @@ ssp_status ssp_reference_estimate(ssp_handle h, const ssp_csr* A, const ssp_csr*
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, hs, b.ctl, st, (uint64_t)M);
     SSP_LAUNCHED(h);
     if (M == 0) return SSP_OK;
-    if ((s = sampled_part(h, A, B, sampler, rate, seed, b, L, st, hs)) != SSP_OK) return s;
-    const FlopArgs fa = flop_args(A, B, b, L, b.rowtmp, nullptr, st);
-    const bool vec = (reinterpret_cast<uintptr_t>(A->col) & 15u) == 0 && A->nnz >= 4;
-    {
-        PhaseTimer pt(h, PH_FLOP, hs);
-        launch_flop<FLOP_ONLY>(fa, vec, h->num_cus, hs);
-    }
+    if ((s = sampled_part(h, A, B, sampler, rate, seed, b, L, b.rowtmp, st, hs)) != SSP_OK)
+        return s;
     {
         PhaseTimer pt(h, PH_FINALIZE, hs);
         hipLaunchKernelGGL(k_finalize_reference, dim3(1), dim3(64), 0, hs, b.ctl, st,
@@ -528,7 +596,7 @@ ssp_status ssp_reference_estimate(ssp_handle h, const ssp_csr* A, const ssp_csr*
     }
     {
         PhaseTimer pt(h, PH_REF_ROWS, hs);
-        hipLaunchKernelGGL(k_ref_rows, dim3((unsigned)((M + 255) / 256)), dim3(256), 0, hs,
+        hipLaunchKernelGGL(k_ref_rows, dim3(rows_grid(h, M)), dim3(kRowsThreads), 0, hs,
                            (const int64_t*)b.rowtmp, nnz_ref, M, b.ctl, st);
     }
     SSP_LAUNCHED(h);
@@ -551,25 +619,9 @@ ssp_status ssp_exact_structure(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
     hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, hs, b.ctl, st, (uint64_t)M);
     SSP_LAUNCHED(h);
     if (M == 0) return SSP_OK;
-    const Csr a = to_csr(A);
-    {
-        PhaseTimer pt(h, PH_SAMPLE, hs);
-        hipLaunchKernelGGL((k_sample<false, false>),
-                           dim3(grid_for((M + kSampleBlock - 1) / kSampleBlock, 4LL * h->num_cus)),
-                           dim3(kSampleThreads), 0, hs, a, to_csr(B), (uint64_t)0, (uint64_t)0,
-                           (int64_t)0, L.ntiles, b.tile_row, b.ctl, st, b.L);
-    }
-    const FlopArgs fa = flop_args(A, B, b, L, nnz_exact, nullptr, st);
-    const bool vec = (reinterpret_cast<uintptr_t>(A->col) & 15u) == 0 && A->nnz >= 4;
-    {
-        PhaseTimer pt(h, PH_FLOP, hs);
-        launch_flop<FLOP_EXACT_BIN>(fa, vec, h->num_cus, hs);
-    }
-    SSP_LAUNCHED(h);
-    {
-        PhaseTimer pt(h, PH_SYMBOLIC, hs);
-        if ((s = launch_symbolic<1>(h, fa.A, fa.B, b, L, st, nnz_exact, hs)) != SSP_OK) return s;
-    }
+    if ((s = flop_pass<FLOP_EXACT_BIN>(h, A, B, b, L, nnz_exact, st, hs)) != SSP_OK) return s;
+    if ((s = launch_symbolic<1>(h, to_csr(A), to_csr(B), b, L, st, nnz_exact, hs)) != SSP_OK)
+        return s;
     return SSP_OK;
 }
 
