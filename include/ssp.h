@@ -183,8 +183,9 @@ SSP_API ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* M, int64_t* n_b
  * merge-path tile partition), "flop" (the streaming row-FLOP kernel alone),
  * "flop_fixup" (rows spanning tiles, F), "sample_bin" (sampling and
  * binning), "sym_bins" (distinct counts of short and medium rows), "sym_long"
- * (the long-row kernel alone), "sym_merge" (OR of split rows' parts and the
- * divisor of f*), "finalize" (reference design constants), "pred_rows" and
+ * (the long-row kernel alone), "sym_merge" (OR of split rows' parts),
+ * "finalize" (z* or the exact total, the divisor of f*, and the reference
+ * design's constants), "pred_rows" and
  * "ref_rows" (the per-row outputs).  ssp_timing_read waits for the recorded
  * events, writes up to `max` aggregated entries (one per phase seen) and
  * clears them; it returns the number written, -1 on a bad argument.  Timing

@@ -317,6 +317,45 @@ __device__ __forceinline__ void lane_bitmap_insert(uint32_t* bm, const uint32_t 
     }
 }
 
+// The same for one window holding all N columns (columns are < N, so no
+// window test): four neighbouring columns of one lane, as loaded.
+__device__ __forceinline__ void lane_bitmap_insert4(uint32_t* bm, const int32_t __attribute__((ext_vector_type(4)))& v)
+{
+    const uint32_t c0 = (uint32_t)v.x, c1 = (uint32_t)v.y, c2 = (uint32_t)v.z, c3 = (uint32_t)v.w;
+    const uint32_t w0 = c0 >> 5, w1 = c1 >> 5, w2 = c2 >> 5, w3 = c3 >> 5;
+    uint32_t b0 = 1u << (c0 & 31), b1 = 1u << (c1 & 31), b2 = 1u << (c2 & 31),
+             b3 = 1u << (c3 & 31);
+    const bool s1 = w1 == w0, s2 = w2 == w1, s3 = w3 == w2;  // run continues
+    b1 |= s1 ? b0 : 0u;
+    b2 |= s2 ? b1 : 0u;
+    b3 |= s3 ? b2 : 0u;
+    const uint32_t o0 = bm[w0], o1 = bm[w1], o2 = bm[w2], o3 = bm[w3];
+    // a word is written at the end of its run only
+    const uint32_t n0 = s1 ? 0u : (b0 & ~o0);
+    const uint32_t n1 = s2 ? 0u : (b1 & ~o1);
+    const uint32_t n2 = s3 ? 0u : (b2 & ~o2);
+    const uint32_t n3 = b3 & ~o3;
+    if (n0) atomicOr(&bm[w0], n0);
+    if (n1) atomicOr(&bm[w1], n1);
+    if (n2) atomicOr(&bm[w2], n2);
+    if (n3) atomicOr(&bm[w3], n3);
+}
+
+// V independent columns per lane (kNoWord = none), one window holding all
+// N columns: read-filtered LDS OR, no merging.
+template <int V>
+__device__ __forceinline__ void lane_bitmap_insert_all(uint32_t* bm, const uint32_t (&col)[V])
+{
+    uint32_t old[V];
+#pragma unroll
+    for (int v = 0; v < V; ++v) old[v] = bm[col[v] != kNoWord ? (col[v] >> 5) : 0u];
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+        const uint32_t need = col[v] != kNoWord ? ((1u << (col[v] & 31)) & ~old[v]) : 0u;
+        if (need) atomicOr(&bm[col[v] >> 5], need);
+    }
+}
+
 // Length of row k of a CSR matrix from its row pointers: one 8-byte read
 // of rpt[k], rpt[k+1] (4-byte aligned).
 __device__ __forceinline__ uint32_t csr_row_len(const int32_t* __restrict__ rpt, int32_t k)

@@ -37,7 +37,7 @@ struct Ctl {
     ssp_stats stats;      // used when the caller passes no stats pointer
     uint32_t bin_cnt[8];  // items in bins 1..4 (index = bin), merge items at 5
     uint32_t pw_ctr;      // part windows handed out
-    uint32_t done_ctr;    // workgroups of the merge kernel that finished
+    uint32_t pad_ctr;
     uint32_t fallback;    // 1: f* = 0, predict row FLOP
     uint32_t big_next;    // work queue of the long-row kernel
     uint32_t pad0[4];
@@ -46,7 +46,12 @@ struct Ctl {
     uint64_t ref_q_lo, ref_q_hi; // reference design: z* M
     uint64_t ref_d_lo, ref_d_hi; // reference design: n_s F
     uint64_t pad2[16];
+    // distinct counts (z*, or the exact total) added by the symbolic kernels
+    // into kAccSlots slots by workgroup: atomics on one address serialise,
+    // atomics on distinct addresses do not; k_finalize sums the slots
+    uint64_t zacc[64];
 };
+constexpr int kAccSlots = 64;
 
 struct BinItem {  // bins 1..3
     int32_t row;

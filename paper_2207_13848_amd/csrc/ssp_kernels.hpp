@@ -49,9 +49,9 @@ __global__ void k_init(Ctl* ctl, ssp_stats* st, uint64_t M)
 {
     const int t = threadIdx.x;
     if (t < 8) ctl->bin_cnt[t] = 0;
+    if (t < kAccSlots) ctl->zacc[t] = 0;
     if (t == 0) {
         ctl->pw_ctr = 0;
-        ctl->done_ctr = 0;
         ctl->big_next = 0;
         ctl->fallback = 0;
         st->total_flop = 0;
@@ -490,7 +490,7 @@ __device__ __forceinline__ uint32_t hash_insert(uint32_t* tab, uint32_t c, int l
 // MODE 0: add the count to z*.  MODE 1: write it to out[row] (and out_sum).
 template <int TEAM, int WORDS, int MODE>
 __global__ __launch_bounds__(TEAM) void k_sym(Csr A, Csr B, const BinItem* __restrict__ items,
-                                             const uint32_t* count, ssp_stats* st,
+                                             const uint32_t* count, uint64_t* zacc,
                                              int64_t* __restrict__ out)
 {
     __shared__ uint32_t tab[WORDS];
@@ -566,7 +566,7 @@ __global__ __launch_bounds__(TEAM) void k_sym(Csr A, Csr B, const BinItem* __res
         }
         __syncthreads();
     }
-    if (t == 0 && zsum) atomicAdd(as_ull(MODE == 0 ? &st->sample_nnz : &st->out_sum), (ull)zsum);
+    if (t == 0 && zsum) atomicAdd(as_ull(&zacc[blockIdx.x % kAccSlots]), (ull)zsum);
 }
 
 // Bin 4: long rows, 1024 threads per item, an LDS bitmap per window of
@@ -589,16 +589,17 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
     return ((uint64_t)hi << 32) | lo;
 }
 
-template <int MODE>
+template <int MODE, bool WIN1>
 __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
                                                        const BigItem* __restrict__ items,
                                                        const uint32_t* count, uint32_t* next,
-                                                       BinLists L, ssp_stats* st,
+                                                       BinLists L, uint64_t* zacc,
                                                        int64_t* __restrict__ out)
 {
     constexpr int TEAM = kBin4Team, NWAVE = TEAM / kWave;
     typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
-    extern __shared__ uint32_t bm[];
+    extern __shared__ __align__(16) uint32_t bm[];
+    uint4* bm4 = reinterpret_cast<uint4*>(bm);
     // compacted entries of a chunk: short ones from the front, long ones from the back
     __shared__ int32_t s_b0[TEAM];
     __shared__ uint32_t s_len[TEAM];
@@ -626,7 +627,8 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
             const int64_t c_lo = w * wcols_full;
             const int64_t wcols = (N - c_lo) < wcols_full ? (N - c_lo) : wcols_full;
             const int words = (int)((wcols + 31) / 32);
-            for (int i = t; i < words; i += TEAM) bm[i] = 0u;
+            const int w4 = (words + 3) / 4;  // 16-byte groups (win_words is a multiple of 4)
+            for (int i = t; i < w4; i += TEAM) bm4[i] = make_uint4(0u, 0u, 0u, 0u);
             const uint32_t clo32 = (uint32_t)c_lo, wc32 = (uint32_t)wcols;
             __syncthreads();
             for (int64_t i0 = 0; i0 < cnt; i0 += TEAM) {
@@ -670,20 +672,27 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
                         if (s_start[TEAM - 1 - mid] <= ub) lo = mid;
                         else hi = mid;
                     }
-                    // issue cursor (unit, owner); clamped at the last unit so the
-                    // prefetches past the end re-read a valid unit
-                    uint64_t uq = ub;
-                    int rq = __builtin_amdgcn_readfirstlane(lo);
+                    // Issue cursor, wave-uniform: long entry r, unit ui of its nu
+                    // units; `left` units of this wave still to issue.  At the last
+                    // unit the cursor stays, so prefetches past the end re-read it.
+                    int r = __builtin_amdgcn_readfirstlane(lo);
+                    uint32_t elen, nu, ui;
+                    int32_t eb0;
+                    auto load_entry = [&]() {
+                        const int e = TEAM - 1 - r;
+                        elen = __builtin_amdgcn_readfirstlane(s_len[e]);
+                        eb0 = __builtin_amdgcn_readfirstlane(s_b0[e]);
+                        nu = (elen + kUnitCols - 1) / kUnitCols;
+                    };
+                    load_entry();
+                    ui = (uint32_t)(ub - uniform_u64(s_start[TEAM - 1 - r]));
+                    uint32_t left = (uint32_t)(ue - ub);  // < 2^29: per-wave share
                     // Three units in flight in registers of fixed roles (the loop is
                     // unrolled by three so no loaded register is moved before use,
                     // which would make the compiler wait for every load).
                     i32x4 va, vb, vc;
                     bool oa, ob, oc;
                     auto issue = [&](i32x4& v, bool& ok) {
-                        const int e = TEAM - 1 - rq;
-                        const uint32_t elen = __builtin_amdgcn_readfirstlane(s_len[e]);
-                        const int32_t eb0 = __builtin_amdgcn_readfirstlane(s_b0[e]);
-                        const uint32_t ui = (uint32_t)(uq - uniform_u64(s_start[e]));
                         const uint32_t base = ui * kUnitCols + 4u * lane;
                         const uint32_t off = base < elen - 4u ? base : elen - 4u;
                         __builtin_memcpy(&v, B.col + eb0 + off, sizeof(v));
@@ -691,31 +700,42 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
                         __builtin_amdgcn_sched_barrier(0);  // keep the load ahead of the inserts
                     };
                     auto advance = [&]() {
-                        if (uq + 1 < ue) {
-                            ++uq;
-                            if (rq + 1 < nle && uniform_u64(s_start[TEAM - 2 - rq]) <= uq) ++rq;
+                        if (left > 1) {
+                            --left;
+                            if (ui + 1 < nu) {
+                                ++ui;
+                            } else {
+                                ++r;
+                                ui = 0;
+                                load_entry();
+                            }
                         }
                     };
                     auto insert = [&](const i32x4& v, bool ok) {
-                        const uint32_t c[4] = {ok ? (uint32_t)v.x : kNoWord,
-                                               ok ? (uint32_t)v.y : kNoWord,
-                                               ok ? (uint32_t)v.z : kNoWord,
-                                               ok ? (uint32_t)v.w : kNoWord};
-                        lane_bitmap_insert<4>(bm, c, clo32, wc32);
+                        if (WIN1) {
+                            if (ok) lane_bitmap_insert4(bm, v);
+                        } else {
+                            const uint32_t c[4] = {ok ? (uint32_t)v.x : kNoWord,
+                                                   ok ? (uint32_t)v.y : kNoWord,
+                                                   ok ? (uint32_t)v.z : kNoWord,
+                                                   ok ? (uint32_t)v.w : kNoWord};
+                            lane_bitmap_insert<4>(bm, c, clo32, wc32);
+                        }
                     };
+                    const uint32_t n = left;
                     issue(va, oa);
                     advance();
                     issue(vb, ob);
-                    for (uint64_t u = ub; u < ue; u += 3) {
+                    for (uint32_t u = 0; u < n; u += 3) {
                         advance();
                         issue(vc, oc);
                         insert(va, oa);
                         advance();
                         issue(va, oa);
-                        if (u + 1 < ue) insert(vb, ob);
+                        if (u + 1 < n) insert(vb, ob);
                         advance();
                         issue(vb, ob);
-                        if (u + 2 < ue) insert(vc, oc);
+                        if (u + 2 < n) insert(vc, oc);
                     }
                 }
                 // short entries: products flattened over the workgroup
@@ -736,18 +756,44 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
                             (uint32_t)B.col[s_b0[lo] + (int32_t)(q - (uint32_t)s_start[lo])];
                         c[u] = qr < nsp ? cv : kNoWord;
                     }
-                    lane_bitmap_insert<US>(bm, c, clo32, wc32);
+                    if (WIN1) lane_bitmap_insert_all<US>(bm, c);
+                    else lane_bitmap_insert<US>(bm, c, clo32, wc32);
                 }
                 __syncthreads();
             }
+            // 16-byte LDS reads, eight issued before any is used (a loop of
+            // single reads would wait on each)
+            constexpr int UR = 8;
             if (item.slot < 0) {
-                uint64_t cnt = 0;
-                for (int i = t; i < words; i += TEAM) cnt += (uint64_t)__popc(bm[i]);
+                uint32_t cnt = 0;
+                for (int i0 = t; i0 < w4; i0 += UR * TEAM) {
+                    uint4 x[UR];
+#pragma unroll
+                    for (int u = 0; u < UR; ++u) {
+                        const int i = i0 + u * TEAM;
+                        x[u] = bm4[i < w4 ? i : w4 - 1];
+                    }
+#pragma unroll
+                    for (int u = 0; u < UR; ++u)
+                        if (i0 + u * TEAM < w4)
+                            cnt += __popc(x[u].x) + __popc(x[u].y) + __popc(x[u].z) + __popc(x[u].w);
+                }
                 total += block_sum<TEAM, uint64_t>(cnt, s_red);
             } else {
-                uint32_t* g = L.scratch + ((int64_t)item.slot + (int64_t)item.part * L.nwin + w) *
-                                              (int64_t)L.win_words;
-                for (int i = t; i < words; i += TEAM) g[i] = bm[i];
+                uint4* g = reinterpret_cast<uint4*>(
+                    L.scratch + ((int64_t)item.slot + (int64_t)item.part * L.nwin + w) *
+                                    (int64_t)L.win_words);
+                for (int i0 = t; i0 < w4; i0 += UR * TEAM) {
+                    uint4 x[UR];
+#pragma unroll
+                    for (int u = 0; u < UR; ++u) {
+                        const int i = i0 + u * TEAM;
+                        x[u] = bm4[i < w4 ? i : w4 - 1];
+                    }
+#pragma unroll
+                    for (int u = 0; u < UR; ++u)
+                        if (i0 + u * TEAM < w4) g[i0 + u * TEAM] = x[u];
+                }
             }
             __syncthreads();
         }
@@ -756,7 +802,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
             if (MODE == 1) atomicAdd(reinterpret_cast<ull*>(&out[item.row]), (ull)total);
         }
     }
-    if (t == 0 && zsum) atomicAdd(as_ull(MODE == 0 ? &st->sample_nnz : &st->out_sum), (ull)zsum);
+    if (t == 0 && zsum) atomicAdd(as_ull(&zacc[blockIdx.x % kAccSlots]), (ull)zsum);
 }
 
 // ORs the part bitmaps of split rows, one slice of a window per item.  With
@@ -765,42 +811,44 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
 template <int MODE>
 __global__ __launch_bounds__(256) void k_sym_merge(const MergeItem* __restrict__ items,
                                                   const uint32_t* count, BinLists L, int64_t N,
-                                                  Ctl* ctl, ssp_stats* st,
-                                                  int64_t* __restrict__ out, int finalize)
+                                                  uint64_t* zacc, int64_t* __restrict__ out)
 {
     __shared__ uint64_t s_red[256 / kWave + 1];
-    __shared__ uint32_t s_last;
     const uint32_t n = *count;
     const int t = threadIdx.x;
     const int64_t wcols_full = (int64_t)L.win_words * 32;
     uint64_t zsum = 0;
+    static_assert(kMergeSlice == 4 * 256, "one 16-byte group per thread and slice");
     for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
         const MergeItem m = items[it];
         const int64_t c_lo = (int64_t)m.window * wcols_full;
         const int64_t wcols = (N - c_lo) < wcols_full ? (N - c_lo) : wcols_full;
-        const int words = (int)((wcols + 31) / 32);
-        uint64_t cnt = 0;
+        const int w4 = (int)((wcols + 127) / 128);  // 16-byte groups of this window
+        const int g4 = m.slice * (kMergeSlice / 4) + t;
+        uint32_t cnt = 0;
+        if (g4 < w4) {
+            // the parts' groups, eight 16-byte loads in flight, then OR
+            const int64_t stride4 = (int64_t)L.nwin * L.win_words / 4;
+            const uint4* src = reinterpret_cast<const uint4*>(
+                                   L.scratch + ((int64_t)m.slot + m.window) * (int64_t)L.win_words) +
+                               g4;
+            uint4 x = make_uint4(0u, 0u, 0u, 0u);
+            for (int p0 = 0; p0 < m.nparts; p0 += 8) {
+                uint4 v[8];
 #pragma unroll
-        for (int u = 0; u < kMergeSlice / 256; ++u) {
-            const int word = m.slice * kMergeSlice + u * 256 + t;
-            if (word < words) {
-                // 8 independent loads in flight, then OR
-                const uint32_t* src = L.scratch + ((int64_t)m.slot + m.window) * (int64_t)L.win_words +
-                                      word;
-                const int64_t stride = (int64_t)L.nwin * L.win_words;
-                uint32_t x = 0;
-                for (int p0 = 0; p0 < m.nparts; p0 += 8) {
-                    uint32_t v[8];
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) {
-                        const int pp = p0 + u < m.nparts ? p0 + u : m.nparts - 1;
-                        v[u] = src[(int64_t)pp * stride];
-                    }
-#pragma unroll
-                    for (int u = 0; u < 8; ++u) x |= v[u];
+                for (int u = 0; u < 8; ++u) {
+                    const int pp = p0 + u < m.nparts ? p0 + u : m.nparts - 1;
+                    v[u] = src[(int64_t)pp * stride4];
                 }
-                cnt += (uint64_t)__popc(x);
+#pragma unroll
+                for (int u = 0; u < 8; ++u) {
+                    x.x |= v[u].x;
+                    x.y |= v[u].y;
+                    x.z |= v[u].z;
+                    x.w |= v[u].w;
+                }
             }
+            cnt = __popc(x.x) + __popc(x.y) + __popc(x.z) + __popc(x.w);
         }
         const uint64_t total = block_sum<256, uint64_t>(cnt, s_red);
         if (t == 0 && total) {
@@ -808,19 +856,31 @@ __global__ __launch_bounds__(256) void k_sym_merge(const MergeItem* __restrict__
             if (MODE == 1) atomicAdd(reinterpret_cast<ull*>(&out[m.row]), (ull)total);
         }
     }
-    if (t == 0 && zsum) atomicAdd(as_ull(MODE == 0 ? &st->sample_nnz : &st->out_sum), (ull)zsum);
-    if (!finalize) return;
-    __threadfence();
-    __syncthreads();
-    if (t == 0) s_last = (atomicAdd(&ctl->done_ctr, 1u) == gridDim.x - 1u);
-    __syncthreads();
-    if (!s_last || t != 0) return;
-    __threadfence();
-    const uint64_t fs = __hip_atomic_load(&st->sample_flop, __ATOMIC_RELAXED,
-                                          __HIP_MEMORY_SCOPE_AGENT);
+    if (t == 0 && zsum) atomicAdd(as_ull(&zacc[blockIdx.x % kAccSlots]), (ull)zsum);
+}
+
+// ---------------------------------------------------------- finalize
+
+// One workgroup of kAccSlots threads after the symbolic kernels: sums the
+// distinct-count slots into z* (MODE 0) or the exact total (MODE 1).  For
+// MODE 0 it also takes the per-call decisions: the empty-sample fallback
+// (f* = 0: every row predicts its own product count) and the divisor of f*
+// for the per-row ceilings.
+template <int MODE>
+__global__ __launch_bounds__(kAccSlots) void k_finalize(Ctl* ctl, ssp_stats* st)
+{
+    __shared__ uint64_t s_red[kAccSlots / kWave + 1];
+    const uint64_t z = block_sum<kAccSlots, uint64_t>(ctl->zacc[threadIdx.x], s_red);
+    if (threadIdx.x != 0) return;
+    if (MODE == 1) {
+        st->out_sum = z;
+        return;
+    }
+    st->sample_nnz = z;
+    const uint64_t fs = st->sample_flop;
     if (fs == 0) {
         ctl->fallback = 1;
-        atomicOr(as_ull(&st->flags), (ull)SSP_FLAG_EMPTY_SAMPLE);
+        st->flags |= SSP_FLAG_EMPTY_SAMPLE;
         return;
     }
     ctl->fallback = 0;
@@ -829,8 +889,6 @@ __global__ __launch_bounds__(256) void k_sym_merge(const MergeItem* __restrict__
     ctl->div_v = D.v;
     ctl->div_shift = D.shift;
 }
-
-// ---------------------------------------------------------- finalize
 
 __global__ void k_finalize_reference(Ctl* ctl, ssp_stats* st, uint64_t M)
 {
@@ -1166,7 +1224,7 @@ __global__ __launch_bounds__(256) void k_flop_fixup(FlopArgs a)
 
 // ------------------------------------------------------ prediction rows
 
-constexpr int kRowsThreads = 256;
+constexpr int kRowsThreads = 1024;
 
 // nnz_pred[i] = ceil(rf_i z* / f*) (Eq. 3 per row), rf_i when the sample has
 // no products.  Grid-stride with few workgroups: each adds its part of the

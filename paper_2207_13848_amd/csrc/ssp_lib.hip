@@ -7,8 +7,10 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <mutex>
 #include <new>
 #include <string>
+#include <unordered_map>
 #include <vector>
 
 #include "ssp_kernels.hpp"
@@ -218,7 +220,7 @@ void window_shape(int64_t N, int32_t* words, int32_t* nwin)
 {
     const int64_t need = (N + 31) / 32;
     if (need <= kWinWords) {
-        *words = (int32_t)std::max<int64_t>(need, 1);
+        *words = (int32_t)std::max<int64_t>((need + 3) / 4 * 4, 4);  // whole 16-byte groups
         *nwin = 1;
     } else {
         *words = kWinWords;
@@ -261,6 +263,25 @@ unsigned grid_for(int64_t items, int64_t cap)
     return (unsigned)std::min<int64_t>(items, cap);
 }
 
+// Workgroups of `kernel` that fit on the device at once (static LDS only),
+// cached per kernel address.
+template <typename K>
+int64_t resident(K kernel, int threads, int cus)
+{
+    static std::mutex mu;
+    static std::unordered_map<const void*, int> cache;
+    const void* key = reinterpret_cast<const void*>(kernel);
+    std::lock_guard<std::mutex> lock(mu);
+    auto it = cache.find(key);
+    if (it == cache.end()) {
+        int n = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n < 1)
+            n = 1;
+        it = cache.emplace(key, n).first;
+    }
+    return (int64_t)it->second * cus;
+}
+
 template <int MODE>
 void launch_flop(ssp_handle h, const FlopArgs& fa, bool vec, hipStream_t s)
 {
@@ -300,40 +321,51 @@ ssp_status launch_symbolic(ssp_handle h, const Csr& A, const Csr& B, const Bound
     const int cus = h->num_cus;
     const int64_t nitems = L.cap13;
     PhaseTimer pt_bins(h, PH_SYM_BINS, s);
-    hipLaunchKernelGGL((k_sym<kBin1Team, kBin1Words, MODE>), dim3(grid_for(nitems, 16LL * cus)),
-                       dim3(kBin1Team), 0, s, A, B, b.L.b1, &b.ctl->bin_cnt[1], st, out);
-    hipLaunchKernelGGL((k_sym<kBin2Team, kBin2Words, MODE>), dim3(grid_for(nitems, 4LL * cus)),
-                       dim3(kBin2Team), 0, s, A, B, b.L.b2, &b.ctl->bin_cnt[2], st, out);
-    hipLaunchKernelGGL((k_sym<kBin3Team, kBin3Words, MODE>), dim3(grid_for(nitems, 2LL * cus)),
-                       dim3(kBin3Team), 0, s, A, B, b.L.b3, &b.ctl->bin_cnt[3], st, out);
+    // bins 1..3: a grid of the resident capacity (rows are walked grid-stride;
+    // more rows in flight hide the latency of each row's chain of loads)
+    hipLaunchKernelGGL((k_sym<kBin1Team, kBin1Words, MODE>),
+                       dim3(grid_for(nitems, resident(k_sym<kBin1Team, kBin1Words, MODE>, kBin1Team, cus))),
+                       dim3(kBin1Team), 0, s, A, B, b.L.b1, &b.ctl->bin_cnt[1], b.ctl->zacc, out);
+    hipLaunchKernelGGL((k_sym<kBin2Team, kBin2Words, MODE>),
+                       dim3(grid_for(nitems, resident(k_sym<kBin2Team, kBin2Words, MODE>, kBin2Team, cus))),
+                       dim3(kBin2Team), 0, s, A, B, b.L.b2, &b.ctl->bin_cnt[2], b.ctl->zacc, out);
+    hipLaunchKernelGGL((k_sym<kBin3Team, kBin3Words, MODE>),
+                       dim3(grid_for(nitems, resident(k_sym<kBin3Team, kBin3Words, MODE>, kBin3Team, cus))),
+                       dim3(kBin3Team), 0, s, A, B, b.L.b3, &b.ctl->bin_cnt[3], b.ctl->zacc, out);
     pt_bins.stop();
     const size_t lds = (size_t)b.L.win_words * sizeof(uint32_t);
-    static bool attr_set[2] = {false, false};
-    if (!attr_set[MODE]) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sym_big<MODE>),
+    // one window holding all N columns: the kernel skips the window tests
+    const bool win1 = b.L.nwin == 1;
+    static bool attr_set[2][2] = {{false, false}, {false, false}};
+    static int big_resident[2][2] = {{0, 0}, {0, 0}};
+    auto kfun = win1 ? k_sym_big<MODE, true> : k_sym_big<MODE, false>;
+    if (!attr_set[MODE][win1]) {
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfun),
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)(kWinWords * sizeof(uint32_t)));
-        attr_set[MODE] = true;
+        attr_set[MODE][win1] = true;
     }
-    static int big_resident[2] = {0, 0};
-    if (big_resident[MODE] == 0) {
+    if (big_resident[MODE][win1] == 0) {
         int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_sym_big<MODE>, kBin4Team,
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfun, kBin4Team,
                                                          kWinWords * sizeof(uint32_t)) != hipSuccess ||
             per_cu < 1)
             per_cu = 1;
-        big_resident[MODE] = per_cu;
+        big_resident[MODE][win1] = per_cu;
     }
     {
         PhaseTimer pt(h, PH_SYM_LONG, s);
-        hipLaunchKernelGGL((k_sym_big<MODE>),
-                           dim3(grid_for(L.cap4, (int64_t)big_resident[MODE] * cus)),
+        hipLaunchKernelGGL(kfun, dim3(grid_for(L.cap4, (int64_t)big_resident[MODE][win1] * cus)),
                            dim3(kBin4Team), lds, s, A, B, b.L.b4, &b.ctl->bin_cnt[4],
-                           &b.ctl->big_next, b.L, st, out);
+                           &b.ctl->big_next, b.L, b.ctl->zacc, out);
     }
-    PhaseTimer pt_merge(h, PH_SYM_MERGE, s);
-    hipLaunchKernelGGL((k_sym_merge<MODE>), dim3((unsigned)(2 * cus)), dim3(256), 0, s, b.L.merge,
-                       &b.ctl->bin_cnt[5], b.L, B.ncols, b.ctl, st, out, MODE == 0 ? 1 : 0);
+    {
+        PhaseTimer pt(h, PH_SYM_MERGE, s);
+        hipLaunchKernelGGL((k_sym_merge<MODE>), dim3((unsigned)(2 * cus)), dim3(256), 0, s,
+                           b.L.merge, &b.ctl->bin_cnt[5], b.L, B.ncols, b.ctl->zacc, out);
+    }
+    PhaseTimer pt_fin(h, PH_FINALIZE, s);
+    hipLaunchKernelGGL((k_finalize<MODE>), dim3(1), dim3(kAccSlots), 0, s, b.ctl, st);
     SSP_LAUNCHED(h);
     return SSP_OK;
 }
@@ -412,9 +444,11 @@ ssp_status sampled_part(ssp_handle h, const ssp_csr* A, const ssp_csr* B, ssp_sa
     return launch_symbolic<0>(h, a, bb, b, L, st, nullptr, s);
 }
 
+// Few large workgroups for the per-row outputs: each adds its part of the
+// output total with one same-address atomic.
 unsigned rows_grid(ssp_handle h, int64_t M)
 {
-    return grid_for((M + 4 * kRowsThreads - 1) / (4 * kRowsThreads), 2LL * h->num_cus);
+    return grid_for((M + 4 * kRowsThreads - 1) / (4 * kRowsThreads), h->num_cus / 2);
 }
 
 ssp_status common_checks(ssp_handle h, const ssp_csr* A, const ssp_csr* B, ssp_sampler sampler,
