@@ -169,6 +169,55 @@ SSP_API ssp_status ssp_reference_estimate(ssp_handle h, const ssp_csr* A, const 
 SSP_API ssp_status ssp_exact_structure(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
                                int64_t* nnz_exact, ssp_stats* stats, void* stream);
 
+/* ----------------------------------------------------------- batches */
+
+/*
+ * One product of a batch: the arguments of ssp_predict_structure_ex.  The
+ * CSR descriptors are copied by value; the arrays they point to, and the
+ * outputs, are device memory the caller owns (as above).
+ */
+typedef struct {
+    ssp_csr A;
+    ssp_csr B;
+    int32_t sampler;      /* ssp_sampler                                   */
+    int32_t reserved;     /* 0                                             */
+    double sample_rate;
+    uint64_t seed;
+    int64_t* nnz_pred;    /* device int64[A.nrows], written                */
+    int64_t* row_flop;    /* device int64[A.nrows] or NULL                 */
+    ssp_stats* stats;     /* device ssp_stats or NULL                      */
+} ssp_case;
+
+/*
+ * Predicts every case of a batch (the workload shape of the paper's 625
+ * products, Sec. VI-A) with one launch sequence whose grids span all cases:
+ * each stage (streaming FLOP pass, sampling, distinct counts, reduction,
+ * prediction) is one kernel for the whole batch, the workgroups of a stage
+ * shared among the cases in proportion to their work.  Every case's outputs
+ * and statistics are bit-identical to ssp_predict_structure_ex on that case
+ * alone.  n = 0 is a no-op.  Errors as for the single call (the first
+ * failing case decides); nothing is queued on an error.
+ */
+SSP_API ssp_status ssp_predict_batch(ssp_handle h, int n, const ssp_case* cases, void* stream);
+
+/*
+ * A batch captured once as a HIP graph, replayed by ssp_batch_graph_launch.
+ * Creation plans the batch, allocates the graph's own workspace (hipMalloc,
+ * bounded by the handle's HBM budget), uploads the case table and captures
+ * the launch sequence; it synchronises with the device.  A launch allocates
+ * nothing and queues one graph on `stream`: the outputs named at creation
+ * are rewritten from the current contents of the inputs, whose sizes and
+ * addresses are fixed at creation.  Launches of one graph must not overlap
+ * (they share its workspace).  Destroy waits for the device and frees the
+ * graph and its workspace; the handle must outlive its graphs.
+ */
+typedef struct ssp_batch_graph_s* ssp_batch_graph;
+SSP_API ssp_status ssp_batch_graph_create(ssp_handle h, int n, const ssp_case* cases,
+                                          ssp_batch_graph* graph);
+SSP_API ssp_status ssp_batch_graph_launch(ssp_batch_graph graph, void* stream);
+SSP_API size_t ssp_batch_graph_workspace_bytes(ssp_batch_graph graph);
+SSP_API ssp_status ssp_batch_graph_destroy(ssp_batch_graph graph);
+
 /*
  * Explicit CSR check (the compute entry points do not check contents):
  * counts the violations of rpt[0] = 0, rpt[i] <= rpt[i+1], rpt[nrows] = nnz

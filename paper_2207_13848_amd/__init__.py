@@ -196,6 +196,91 @@ def exact_structure(A: DeviceCSR, B: DeviceCSR, *, handle=None, stream=None, out
     return ex, st
 
 
+class Case:
+    """One product of a batch and its device outputs (allocated here when not given)."""
+
+    def __init__(self, A: DeviceCSR, B: DeviceCSR, sample_rate: float, seed: int, *,
+                 sampler="bernoulli", return_row_flop: bool = False, out=None, stats=None):
+        self.A, self.B = A, B
+        self.sample_rate, self.seed, self.sampler = float(sample_rate), int(seed), sampler
+        M = A.nrows
+        self.pred = out if out is not None else torch.empty(M, dtype=torch.int64, device=A.device)
+        self.row_flop = (torch.empty(M, dtype=torch.int64, device=A.device) if return_row_flop
+                         else None)
+        self.stats = stats if stats is not None else _new_stats(A.device)
+
+    def _c(self) -> _native.SspCase:
+        c = _native.SspCase()
+        c.A, c.B = self.A._c(), self.B._c()
+        c.sampler = _sampler_id(self.sampler)
+        c.reserved = 0
+        c.sample_rate = self.sample_rate
+        c.seed = self.seed % (1 << 64)
+        c.nnz_pred = self.pred.data_ptr() if self.A.nrows else 0
+        c.row_flop = self.row_flop.data_ptr() if self.row_flop is not None and self.A.nrows else 0
+        c.stats = self.stats.data_ptr() if self.stats is not None else 0
+        return c
+
+
+def _case_array(cases):
+    arr = (_native.SspCase * max(len(cases), 1))()
+    for i, c in enumerate(cases):
+        arr[i] = c._c()
+    return arr
+
+
+def predict_batch(cases, *, handle=None, stream=None):
+    """Predict every Case of `cases` with one launch sequence (ssp_predict_batch).
+
+    Results land in each case's .pred / .row_flop / .stats; returns `cases`.
+    """
+    cases = list(cases)
+    if not cases:
+        return cases
+    h = handle or default_handle(cases[0].A.device)
+    arr = _case_array(cases)
+    h.check(h._lib.ssp_predict_batch(h.ptr, len(cases), arr, _stream_ptr(stream)),
+            "ssp_predict_batch")
+    return cases
+
+
+class BatchGraph:
+    """A batch captured once as a HIP graph (ssp_batch_graph_*); launch() replays it."""
+
+    def __init__(self, cases, *, handle=None):
+        self.cases = list(cases)
+        if not self.cases:
+            raise ValueError("a batch graph needs at least one case")
+        self.handle = handle or default_handle(self.cases[0].A.device)
+        self._lib = self.handle._lib
+        arr = _case_array(self.cases)
+        g = ctypes.c_void_p()
+        self.handle.check(self._lib.ssp_batch_graph_create(self.handle.ptr, len(self.cases), arr,
+                                                           ctypes.byref(g)),
+                          "ssp_batch_graph_create")
+        self.ptr = g
+
+    def launch(self, stream=None):
+        self.handle.check(self._lib.ssp_batch_graph_launch(self.ptr, _stream_ptr(stream)),
+                          "ssp_batch_graph_launch")
+        return self.cases
+
+    @property
+    def workspace_bytes(self) -> int:
+        return int(self._lib.ssp_batch_graph_workspace_bytes(self.ptr)) if self.ptr else 0
+
+    def close(self):
+        if self.ptr:
+            self._lib.ssp_batch_graph_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def validate_csr(M: DeviceCSR, *, handle=None, stream=None) -> int:
     """Number of CSR violations in M (synchronises)."""
     h = handle or default_handle(M.device)

@@ -25,13 +25,21 @@ EXPORTED = (
     "ssp_create", "ssp_destroy", "ssp_workspace_bytes", "ssp_predict_structure",
     "ssp_predict_structure_ex", "ssp_reference_estimate", "ssp_exact_structure",
     "ssp_validate_csr", "ssp_status_string", "ssp_last_error", "ssp_version",
-    "ssp_timing_enable", "ssp_timing_read",
+    "ssp_timing_enable", "ssp_timing_read", "ssp_predict_batch", "ssp_batch_graph_create",
+    "ssp_batch_graph_launch", "ssp_batch_graph_workspace_bytes", "ssp_batch_graph_destroy",
 )
 
 
 class SspCsr(ctypes.Structure):
     _fields_ = [("nrows", ctypes.c_int64), ("ncols", ctypes.c_int64), ("nnz", ctypes.c_int64),
                 ("rpt", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class SspCase(ctypes.Structure):
+    _fields_ = [("A", SspCsr), ("B", SspCsr), ("sampler", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("sample_rate", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("nnz_pred", ctypes.c_void_p),
+                ("row_flop", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
 
 
 STATS_FIELDS = ("total_flop", "n_sampled", "sample_flop", "sample_nnz", "out_sum", "nrows",
@@ -91,6 +99,13 @@ def load():
     lib.ssp_timing_enable.restype = cint
     lib.ssp_timing_read.argtypes = [vp, ctypes.POINTER(SspPhaseTime), cint]
     lib.ssp_timing_read.restype = cint
+    case_p = ctypes.POINTER(SspCase)
+    lib.ssp_predict_batch.argtypes = [vp, cint, case_p, vp]
+    lib.ssp_batch_graph_create.argtypes = [vp, cint, case_p, ctypes.POINTER(vp)]
+    lib.ssp_batch_graph_launch.argtypes = [vp, vp]
+    lib.ssp_batch_graph_workspace_bytes.argtypes = [vp]
+    lib.ssp_batch_graph_workspace_bytes.restype = ctypes.c_size_t
+    lib.ssp_batch_graph_destroy.argtypes = [vp]
     lib.ssp_version.argtypes = []
     lib.ssp_version.restype = ctypes.c_char_p
     _lib = lib

@@ -22,7 +22,7 @@ constexpr int kBin1Team = 64, kBin2Team = 256, kBin3Team = 512, kBin4Team = 1024
 constexpr int kWinWords = 32768;
 constexpr uint64_t kSplitTarget = 1ull << 17; // products per part of a split row
 constexpr int kMaxParts = 64;
-constexpr int kMaxPartWindows = 1024;         // global part bitmaps (x window words)
+constexpr int kMaxPartWindows = 1024;         // global part bitmaps of kWinWords words
 constexpr int kMaxSplitWindows = 4;           // rows needing more windows are not split
 constexpr int kMergeSlice = 1024;             // words per merge item
 
@@ -32,38 +32,77 @@ constexpr int kFlopThreads = 256;
 constexpr int kFlopChunk = 2048;
 constexpr int64_t kFlopTile = 2040;
 
-// Control block at the start of the workspace (device memory).
-struct Ctl {
-    ssp_stats stats;      // used when the caller passes no stats pointer
-    uint32_t bin_cnt[8];  // items in bins 1..4 (index = bin), merge items at 5
-    uint32_t pw_ctr;      // part windows handed out
-    uint32_t pad_ctr;
-    uint32_t fallback;    // 1: f* = 0, predict row FLOP
-    uint32_t big_next;    // work queue of the long-row kernel
-    uint32_t pad0[4];
-    uint64_t div_dn, div_v; // Divisor of f*
-    uint32_t div_shift, pad1;
-    uint64_t ref_q_lo, ref_q_hi; // reference design: z* M
-    uint64_t ref_d_lo, ref_d_hi; // reference design: n_s F
-    uint64_t pad2[16];
-    // distinct counts (z*, or the exact total) added by the symbolic kernels
-    // into kAccSlots slots by workgroup: atomics on one address serialise,
-    // atomics on distinct addresses do not; k_finalize sums the slots
-    uint64_t zacc[64];
-};
+// Distinct counts (z*, or the exact total) are added by the symbolic kernels
+// into kAccSlots slots per case, chosen by workgroup: atomics on one address
+// serialise, atomics on distinct addresses do not.  k_finalize sums them.
 constexpr int kAccSlots = 64;
+
+struct Csr {
+    const int32_t* rpt;
+    const int32_t* col;
+    int64_t nrows, ncols, nnz;
+};
+
+// One product of a call (a batch holds several).  Written by the host before
+// the launches; the kernels find their case from the workgroup prefixes
+// (wg_*: the first workgroup of the case in each kernel's grid) or from the
+// case index an item carries.
+struct CaseDesc {
+    Csr A, B;
+    int64_t* out;        // per-row output (prediction, reference or exact counts)
+    int64_t* rf;         // per-row FLOP (the caller's array or workspace)
+    ssp_stats* st;       // statistics (the caller's, or the case's workspace slot)
+    uint64_t seed, thresh;
+    int64_t ncand;       // sampling candidates: rows (Bernoulli) or draws (paper)
+    int64_t tile_base;   // first entry of this case in the tile-start array
+    int64_t meta_base;   // first entry in the tile metadata
+    int64_t ntiles;      // merge-path tiles of A (at least 1)
+    int64_t group_base;  // first sampling group of this case
+    int64_t group_size;  // candidates per sampling group (a multiple of 256)
+    int64_t ngroups;
+    int32_t win_words;   // long-row bitmap window, words (a multiple of 4)
+    int32_t nwin;        // windows covering B's columns
+    int32_t big3;        // bin-3 rows go to the long-row kernel
+    int32_t merge_per_row;  // merge items of one split row
+    int32_t paper;       // the paper's fixed-count sampler
+    int32_t wg_tiles, wg_flop, wg_fixup, wg_rows;
+    int32_t pad[3];
+};
+
+// Per-case results written by the kernels.
+struct CaseRes {
+    uint64_t zacc[kAccSlots];
+    uint64_t div_dn, div_v;        // Divisor of f*
+    uint32_t div_shift, fallback;  // fallback 1: f* = 0, predict row FLOP
+    uint64_t ref_q_lo, ref_q_hi;   // reference design: z* M
+    uint64_t ref_d_lo, ref_d_hi;   // reference design: n_s F
+    uint64_t pad[8];
+};
+
+// Control block at the start of the workspace (device memory): the shared
+// lists of a call and their counters.
+struct Ctl {
+    uint32_t bin_cnt[8];  // items in bins 1..4 (index = bin), merge items at 5
+    uint32_t pw_ctr;      // part windows handed out (exact path)
+    uint32_t big_next;    // work queue of the long-row kernel
+    uint32_t pad[22];
+};
 
 struct BinItem {  // bins 1..3
     int32_t row;
     uint32_t rf;
+    int32_t cs;     // case
+    int32_t pad;
 };
 
-struct BigItem {  // bin 4: the A entries [e_lo, e_hi) of one long row
+struct BigItem {  // bin 4: entries e_lo + part + k nparts < e_hi of one long row
     int32_t row;
     int32_t slot;   // first part window of a split row, -1 when not split
     int32_t part;   // part index of a split row (0 when not split)
     int32_t nparts;
     int32_t e_lo, e_hi;
+    int32_t cs;     // case
+    int32_t pad;
 };
 
 struct MergeItem {  // one slice of one window of a split row
@@ -72,21 +111,22 @@ struct MergeItem {  // one slice of one window of a split row
     int32_t nparts;
     int32_t window;
     int32_t slice;
-    int32_t pad;
+    int32_t cs;     // case
 };
 
-// Per-workgroup counters of the sampling passes.  k_sample_count writes
+// Per-group counters of the sampling passes.  k_sample_count writes
 //   c[0..2] rows of bins 1..3, c[3] rows of bin 4, c[4] bin-4 items if its
 //   split-eligible rows are split, c[5] their merge items, c[6] part windows
-//   they request;
+//   they request; ns, fs, as: sampled rows, their products, their A entries;
 // k_sample_scan rewrites them in place as
 //   c[0..2] offsets in bins 1..3, c[3] offset in bin 4, c[4] offset in the
-//   merge list, c[5] first part window, c[6] 1 if the rows are split.
+//   merge list, c[5] first part window, c[6] 1 if the rows are split;
+//   ns, fs, as: inclusive prefixes over all groups of the call.
 struct SampleCounts {
     uint32_t c[8];
-    uint64_t ns, fs, as, pad; // sampled rows, their products, their A entries
+    uint64_t ns, fs, as, pad;
 };
-constexpr int kSampleGroups = 512; // workgroups of the sampling passes (at most)
+constexpr int kSampleTarget = 8192; // sampling groups of a call, about (at least 1 per case)
 
 struct TileMeta {   // per streaming tile
     uint64_t head;  // products of its first row here, when that row began earlier
@@ -95,41 +135,12 @@ struct TileMeta {   // per streaming tile
     uint64_t pad;
 };
 
-// Workspace layout of one call (byte offsets, each 256-aligned).
-struct Layout {
-    size_t ctl, scratch, bin1, bin2, bin3, bin4, merge, tiles, meta, samp, rowtmp, total;
-    int64_t cap13, cap4, cap5, ntiles;
-};
-
 inline size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
 inline int64_t flop_tiles(int64_t M, int64_t nnz)
 {
-    return (M + nnz + kFlopTile - 1) / kFlopTile;
-}
-
-inline Layout make_layout(int64_t nitems, int64_t M, int64_t nnzA, bool need_rowtmp)
-{
-    Layout L;
-    L.cap13 = nitems > 0 ? nitems : 1;
-    L.cap4 = L.cap13 + (int64_t)kMaxPartWindows;
-    L.cap5 = (int64_t)kMaxPartWindows * (kWinWords / kMergeSlice) + 64;
-    L.ntiles = flop_tiles(M, nnzA);
-    size_t o = 0;
-    L.ctl = o;     o = align256(o + sizeof(Ctl));
-    L.scratch = o; o = align256(o + (size_t)kMaxPartWindows * kWinWords * sizeof(uint32_t));
-    L.bin1 = o;    o = align256(o + (size_t)L.cap13 * sizeof(BinItem));
-    L.bin2 = o;    o = align256(o + (size_t)L.cap13 * sizeof(BinItem));
-    L.bin3 = o;    o = align256(o + (size_t)L.cap13 * sizeof(BinItem));
-    L.bin4 = o;    o = align256(o + (size_t)L.cap4 * sizeof(BigItem));
-    L.merge = o;   o = align256(o + (size_t)L.cap5 * sizeof(MergeItem));
-    L.tiles = o;   o = align256(o + (size_t)(L.ntiles + 1) * sizeof(int32_t));
-    L.meta = o;    o = align256(o + (size_t)(L.ntiles > 0 ? L.ntiles : 1) * sizeof(TileMeta));
-    L.samp = o;    o = align256(o + (size_t)kSampleGroups * sizeof(SampleCounts));
-    L.rowtmp = o;
-    if (need_rowtmp) o = align256(o + (size_t)(M > 0 ? M : 1) * sizeof(int64_t));
-    L.total = o;
-    return L;
+    const int64_t t = (M + nnz + kFlopTile - 1) / kFlopTile;
+    return t > 0 ? t : 1;
 }
 
 } // namespace ssp

@@ -1,18 +1,21 @@
 // HIP kernels of the prediction path for gfx950 (wave64).
 //
-// One prediction (sample first, then one streaming pass):
-//   k_init             clear statistics and counters
-//   k_sample           per block of rows: the merge-path tile starts of the
-//                      streaming pass; the sampled rows (splitmix64), their
-//                      products (f*) and their bins
+// A call predicts one product or a batch of them (cases).  Launch order:
+//   k_init             clear counters, per-case results and statistics
+//   k_tiles            merge-path tile starts of the streaming pass
+//   k_flop, k_flop_fixup
+//                      products of every row (a pattern SpMV with the row
+//                      lengths of B) into rf, and F
+//   k_sample_count / _scan / _write
+//                      the sampled rows (splitmix64), f*, n_s, and their bins
 //   k_sym, k_sym_big   exact distinct-column count of every binned row (LDS hash
-//                      table or LDS bitmap), summed into z*; long rows are cut into
-//                      parts that leave their bitmaps in global scratch
-//   k_sym_merge        ORs the parts' bitmaps; its last workgroup computes the
-//                      per-call divisor of f*
-//   k_flop             merge-path tiles over A: products of every row (a pattern
-//                      SpMV with the row lengths of B) and the per-row output
-//   k_flop_fixup       rows that span tiles, and the totals
+//                      table or LDS bitmap); long rows are cut into parts that
+//                      leave their bitmaps in global scratch
+//   k_sym_merge        ORs the parts' bitmaps
+//   k_finalize         z* per case, the empty-sample fallback, the divisor of f*
+//   k_pred_rows        the per-row prediction
+// Kernels whose workgroups each serve one case find it by a binary search of
+// the per-case workgroup prefixes; items of the shared bins carry their case.
 #pragma once
 
 #include "ssp_device.hpp"
@@ -20,24 +23,35 @@
 
 namespace ssp {
 
-struct Csr {
-    const int32_t* rpt;
-    const int32_t* col;
-    int64_t nrows, ncols, nnz;
-};
-
 struct BinLists {
     BinItem* b1;
     BinItem* b2;
     BinItem* b3;
     BigItem* b4;
     MergeItem* merge;
-    uint32_t* scratch; // kMaxPartWindows x window words
-    int32_t win_words; // words per bitmap window (<= kWinWords)
-    int32_t nwin;      // windows covering the N columns
-    int32_t big3;      // bin-3 rows go to the long-row kernel (see bin_route)
-    int32_t merge_per_row; // merge items of one split row (slices over all windows)
+    uint32_t* scratch; // kMaxPartWindows windows of kWinWords words
 };
+
+// The case of workgroup `wg` in a grid whose workgroups serve one case each:
+// the last case whose first workgroup (field F) is at or before wg.
+template <int32_t CaseDesc::*F>
+__device__ __forceinline__ int case_of_wg(const CaseDesc* __restrict__ cs, int n, int32_t wg)
+{
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cs[mid].*F <= wg) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
+
+// Workgroups of case c in that grid.
+template <int32_t CaseDesc::*F>
+__device__ __forceinline__ int32_t wgs_of_case(const CaseDesc* __restrict__ cs, int n, int c)
+{
+    return (c + 1 < n ? cs[c + 1].*F : (int32_t)gridDim.x) - cs[c].*F;
+}
 
 typedef unsigned long long ull;
 
@@ -45,21 +59,58 @@ __device__ __forceinline__ ull* as_ull(uint64_t* p) { return reinterpret_cast<ul
 
 // ---------------------------------------------------------------- init
 
-__global__ void k_init(Ctl* ctl, ssp_stats* st, uint64_t M)
+// One workgroup per case (grid-stride): its results and statistics; the
+// first workgroup also clears the control block.
+__global__ __launch_bounds__(64) void k_init(Ctl* ctl, const CaseDesc* __restrict__ cs,
+                                            CaseRes* __restrict__ cr, int n)
 {
     const int t = threadIdx.x;
-    if (t < 8) ctl->bin_cnt[t] = 0;
-    if (t < kAccSlots) ctl->zacc[t] = 0;
+    if (blockIdx.x == 0 && t < (int)(sizeof(Ctl) / 4)) reinterpret_cast<uint32_t*>(ctl)[t] = 0;
+    for (int c = blockIdx.x; c < n; c += gridDim.x) {
+        uint64_t* r = reinterpret_cast<uint64_t*>(&cr[c]);
+        for (int i = t; i < (int)(sizeof(CaseRes) / 8); i += 64) r[i] = 0;
+        if (t == 0) {
+            ssp_stats* st = cs[c].st;
+            st->total_flop = 0;
+            st->n_sampled = 0;
+            st->sample_flop = 0;
+            st->sample_nnz = 0;
+            st->out_sum = 0;
+            st->nrows = (uint64_t)cs[c].A.nrows;
+            st->flags = 0;
+            st->a_sample_nnz = 0;
+        }
+    }
+}
+
+// Calls of at most kArgCases cases pass the case table in the kernel
+// arguments of k_init_args, which writes it to the workspace (kernel
+// arguments are captured at launch, so the host buffer is free at once and no
+// copy is queued on the stream).  One workgroup per case.
+constexpr int kArgCases = 8;
+struct CaseArgs {
+    CaseDesc d[kArgCases];
+};
+
+__global__ __launch_bounds__(64) void k_init_args(Ctl* ctl, CaseDesc* __restrict__ cs,
+                                                 CaseRes* __restrict__ cr, CaseArgs args)
+{
+    const int c = blockIdx.x, t = threadIdx.x;
+    if (c == 0 && t < (int)(sizeof(Ctl) / 4)) reinterpret_cast<uint32_t*>(ctl)[t] = 0;
+    static_assert(sizeof(CaseDesc) % 8 == 0, "copied as 64-bit words");
+    const uint64_t* src = reinterpret_cast<const uint64_t*>(&args.d[c]);
+    uint64_t* dst = reinterpret_cast<uint64_t*>(&cs[c]);
+    for (int i = t; i < (int)(sizeof(CaseDesc) / 8); i += 64) dst[i] = src[i];
+    uint64_t* r = reinterpret_cast<uint64_t*>(&cr[c]);
+    for (int i = t; i < (int)(sizeof(CaseRes) / 8); i += 64) r[i] = 0;
     if (t == 0) {
-        ctl->pw_ctr = 0;
-        ctl->big_next = 0;
-        ctl->fallback = 0;
+        ssp_stats* st = args.d[c].st;
         st->total_flop = 0;
         st->n_sampled = 0;
         st->sample_flop = 0;
         st->sample_nnz = 0;
         st->out_sum = 0;
-        st->nrows = M;
+        st->nrows = (uint64_t)args.d[c].A.nrows;
         st->flags = 0;
         st->a_sample_nnz = 0;
     }
@@ -75,22 +126,21 @@ __device__ __forceinline__ int bin_of(uint64_t rf)
 // Bin of a row for the kernels: bin-3 rows go to the long-row kernel when all
 // N columns fit one LDS bitmap window but not bin 3's table as a bitmap (bin 3
 // would hash); the bitmap kernel then counts them far faster.
-__device__ __forceinline__ int bin_route(uint64_t rf, const BinLists& L)
+__device__ __forceinline__ int bin_route(uint64_t rf, const CaseDesc& cd)
 {
     const int b = bin_of(rf);
-    return (b == 3 && L.big3) ? 4 : b;
+    return (b == 3 && cd.big3) ? 4 : b;
 }
 
 // Merge items of a split row: one per (window, slice of kMergeSlice words).
-__device__ inline void append_merge_items(int32_t row, int32_t slot, int32_t nparts, int64_t N,
-                                          Ctl* ctl, const BinLists& L)
+__device__ inline void write_merge_items(MergeItem* dst, int32_t row, int32_t slot, int32_t nparts,
+                                         int32_t ci, const CaseDesc& cd)
 {
-    const int64_t wcols_full = (int64_t)L.win_words * 32;
-    for (int w = 0; w < L.nwin; ++w) {
+    const int64_t N = cd.B.ncols, wcols_full = (int64_t)cd.win_words * 32;
+    int k = 0;
+    for (int w = 0; w < cd.nwin; ++w) {
         const int64_t cols = (N - w * wcols_full) < wcols_full ? (N - w * wcols_full) : wcols_full;
-        const int words = (int)((cols + 31) / 32);
-        const int slices = (words + kMergeSlice - 1) / kMergeSlice;
-        const uint32_t mb = atomicAdd(&ctl->bin_cnt[5], (uint32_t)slices);
+        const int slices = (int)(((cols + 31) / 32 + kMergeSlice - 1) / kMergeSlice);
         for (int sl = 0; sl < slices; ++sl) {
             MergeItem m;
             m.row = row;
@@ -98,30 +148,31 @@ __device__ inline void append_merge_items(int32_t row, int32_t slot, int32_t npa
             m.nparts = nparts;
             m.window = w;
             m.slice = sl;
-            m.pad = 0;
-            L.merge[mb + sl] = m;
+            m.cs = ci;
+            dst[k++] = m;
         }
     }
 }
 
-// Bin-4 items of one long row (single lane).  A row above kSplitTarget
-// products is cut into P parts when enough global part windows are left; part
-// p takes the entries e0 + p, e0 + p + P, e0 + p + 2P, ...  In skewed rows the
-// heavy entries (hub columns, long B rows) sit together, and a stride deals
-// them out evenly, so the parts get near-equal product counts without a scan
-// of the row.  Unsplit rows are one part (P = 1).
-__device__ inline void append_big(int32_t row, uint64_t rf, int32_t e0, int32_t e1, int64_t N,
-                                  Ctl* ctl, const BinLists& L)
+// Bin-4 items of one long row (single lane; the exact path, which appends
+// with atomics).  A row above kSplitTarget products is cut into P parts when
+// enough global part windows are left; part p takes the entries e0 + p,
+// e0 + p + P, e0 + p + 2P, ...  In skewed rows the heavy entries (hub
+// columns, long B rows) sit together, and a stride deals them out evenly, so
+// the parts get near-equal product counts without a scan of the row.
+// Unsplit rows are one part (P = 1).
+__device__ inline void append_big(int32_t row, uint64_t rf, int32_t e0, int32_t e1, int32_t ci,
+                                  const CaseDesc& cd, Ctl* ctl, const BinLists& L)
 {
     const int64_t alen = (int64_t)e1 - e0;
     int32_t nparts = 1, slot = -1;
-    if (rf > kSplitTarget && L.nwin <= kMaxSplitWindows && alen > 1 &&
+    if (rf > kSplitTarget && cd.nwin <= kMaxSplitWindows && alen > 1 &&
         __hip_atomic_load(&ctl->pw_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
             (uint32_t)kMaxPartWindows) {  // (bounds the counter: it cannot wrap)
         uint64_t want = (rf + kSplitTarget - 1) / kSplitTarget;
         if (want > (uint64_t)kMaxParts) want = kMaxParts;
         if (want > (uint64_t)alen) want = (uint64_t)alen;
-        const uint32_t need = (uint32_t)want * (uint32_t)L.nwin;
+        const uint32_t need = (uint32_t)want * (uint32_t)cd.nwin;
         const uint32_t s = atomicAdd(&ctl->pw_ctr, need);
         if (s + need <= (uint32_t)kMaxPartWindows) {
             slot = (int32_t)s;
@@ -137,15 +188,20 @@ __device__ inline void append_big(int32_t row, uint64_t rf, int32_t e0, int32_t 
         it.nparts = nparts;
         it.e_lo = e0;
         it.e_hi = e1;
+        it.cs = ci;
+        it.pad = 0;
         L.b4[base + p] = it;
     }
-    if (slot >= 0) append_merge_items(row, slot, nparts, N, ctl, L);
+    if (slot >= 0) {
+        const uint32_t mb = atomicAdd(&ctl->bin_cnt[5], (uint32_t)cd.merge_per_row);
+        write_merge_items(L.merge + mb, row, slot, nparts, ci, cd);
+    }
 }
 
 // Bins 1..3 of a wave's rows with one atomic per wave and bin (every lane
 // calls it; b = 0 for lanes with nothing to append).
-__device__ __forceinline__ void append_small_bins(int b, int32_t row, uint64_t rf, Ctl* ctl,
-                                                  const BinLists& L)
+__device__ __forceinline__ void append_small_bins(int b, int32_t row, uint64_t rf, int32_t ci,
+                                                  Ctl* ctl, const BinLists& L)
 {
     const int lane = lane_id();
 #pragma unroll
@@ -160,6 +216,8 @@ __device__ __forceinline__ void append_small_bins(int b, int32_t row, uint64_t r
                 BinItem it;
                 it.row = row;
                 it.rf = (uint32_t)rf;
+                it.cs = ci;
+                it.pad = 0;
                 (bb == 1 ? L.b1 : bb == 2 ? L.b2 : L.b3)[pos + rank_in(m)] = it;
             }
         }
@@ -167,18 +225,20 @@ __device__ __forceinline__ void append_small_bins(int b, int32_t row, uint64_t r
 }
 
 // One row, appended by a single lane.
-__device__ inline void append_row(int32_t row, uint64_t rf, int32_t e0, int32_t e1, int64_t N,
-                                  Ctl* ctl, const BinLists& L)
+__device__ inline void append_row(int32_t row, uint64_t rf, int32_t e0, int32_t e1, int32_t ci,
+                                  const CaseDesc& cd, Ctl* ctl, const BinLists& L)
 {
-    const int b = bin_route(rf, L);
+    const int b = bin_route(rf, cd);
     if (b == 0) return;
     if (b == 4) {
-        append_big(row, rf, e0, e1, N, ctl, L);
+        append_big(row, rf, e0, e1, ci, cd, ctl, L);
         return;
     }
     BinItem it;
     it.row = row;
     it.rf = (uint32_t)rf;
+    it.cs = ci;
+    it.pad = 0;
     const uint32_t i = atomicAdd(&ctl->bin_cnt[b], 1u);
     (b == 1 ? L.b1 : b == 2 ? L.b2 : L.b3)[i] = it;
 }
@@ -188,36 +248,64 @@ __device__ inline void append_row(int32_t row, uint64_t rf, int32_t e0, int32_t 
 // Merge-path partition of the streaming FLOP pass: tile b starts in row g
 // when its first item b * kFlopTile lies in [rpt[g] + g, rpt[g+1] + g + 1),
 // the span of row g's entries and end marker.  tile_row[ntiles] = M.
-__global__ __launch_bounds__(256) void k_tiles(Csr A, int64_t ntiles, int32_t* __restrict__ tile_row)
+__global__ __launch_bounds__(256) void k_tiles(const CaseDesc* __restrict__ cs, int n,
+                                              int32_t* __restrict__ tile_row_all)
 {
-    const int64_t M = A.nrows;
-    const int64_t stride = (int64_t)gridDim.x * 256;
-    for (int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x; g < M; g += stride) {
+    const int c = case_of_wg<&CaseDesc::wg_tiles>(cs, n, blockIdx.x);
+    const int64_t bl = (int64_t)blockIdx.x - cs[c].wg_tiles;
+    const int64_t G = wgs_of_case<&CaseDesc::wg_tiles>(cs, n, c);
+    const Csr A = cs[c].A;
+    const int64_t M = A.nrows, ntiles = cs[c].ntiles;
+    int32_t* __restrict__ tile_row = tile_row_all + cs[c].tile_base;
+    const int64_t stride = G * 256;
+    for (int64_t g = bl * 256 + threadIdx.x; g < M; g += stride) {
         const int64_t f0 = (int64_t)A.rpt[g] + g, f1 = (int64_t)A.rpt[g + 1] + g + 1;
         for (int64_t b = (f0 + kFlopTile - 1) / kFlopTile; b * kFlopTile < f1 && b < ntiles; ++b)
             tile_row[b] = (int32_t)g;
     }
-    if (blockIdx.x == 0 && threadIdx.x == 0) tile_row[ntiles] = (int32_t)M;
+    if (bl == 0 && threadIdx.x == 0) tile_row[ntiles] = (int32_t)M;
 }
 
 // --------------------------------------------------------- sampling
 
 constexpr int kSampleThreads = 256;
 
+// Sampler parameters of a case, in registers.
+struct SamplerArgs {
+    Csr A;
+    const int64_t* rf;
+    uint64_t seed, thresh;
+    int64_t ncand;
+    int32_t paper, nwin, big3, merge_per_row;
+};
+
+__device__ __forceinline__ SamplerArgs sampler_args(const CaseDesc& cd)
+{
+    SamplerArgs a;
+    a.A = cd.A;
+    a.rf = cd.rf;
+    a.seed = cd.seed;
+    a.thresh = cd.thresh;
+    a.ncand = cd.ncand;
+    a.paper = cd.paper;
+    a.nwin = cd.nwin;
+    a.big3 = cd.big3;
+    a.merge_per_row = cd.merge_per_row;
+    return a;
+}
+
 // Candidate i of a sampler: row i for the Bernoulli sampler (kept when the
 // top 53 bits of splitmix64(seed, i) fall below the threshold), the i-th draw
 // for the paper's (row floor(M u / 2^53) of the draw's top 53 bits u).
 // Returns -1 for a candidate that is not sampled.
-template <bool PAPER>
-__device__ __forceinline__ int64_t candidate_row(int64_t i, int64_t M, uint64_t seed,
-                                                 uint64_t thresh)
+__device__ __forceinline__ int64_t candidate_row(int64_t i, const SamplerArgs& a)
 {
-    const uint64_t x = splitmix64_at(seed, (uint64_t)i) >> 11;
-    if (PAPER) {
-        const u128 p = mul_64x64((uint64_t)M, x);
+    const uint64_t x = splitmix64_at(a.seed, (uint64_t)i) >> 11;
+    if (a.paper) {
+        const u128 p = mul_64x64((uint64_t)a.A.nrows, x);
         return (int64_t)((p.lo >> 53) | (p.hi << 11));
     }
-    return x < thresh ? i : -1;
+    return x < a.thresh ? i : -1;
 }
 
 // What a sampled row contributes to the lists: its bin, and for bin 4
@@ -231,9 +319,7 @@ struct SampledRow {
     bool elig;
 };
 
-__device__ __forceinline__ SampledRow classify_row(int64_t g, const Csr& A,
-                                                   const int64_t* __restrict__ rf,
-                                                   const BinLists& L)
+__device__ __forceinline__ SampledRow classify_row(int64_t g, const SamplerArgs& a)
 {
     SampledRow r;
     r.g = g;
@@ -243,12 +329,13 @@ __device__ __forceinline__ SampledRow classify_row(int64_t g, const Csr& A,
     r.want = 1;
     r.elig = false;
     if (g < 0) return r;
-    r.rf = (uint64_t)rf[g];
-    r.e0 = A.rpt[g];
-    r.e1 = A.rpt[g + 1];
-    r.bin = bin_route(r.rf, L);
+    r.rf = (uint64_t)a.rf[g];
+    r.e0 = a.A.rpt[g];
+    r.e1 = a.A.rpt[g + 1];
+    const int b = bin_of(r.rf);
+    r.bin = (b == 3 && a.big3) ? 4 : b;
     const int64_t alen = (int64_t)r.e1 - r.e0;
-    if (r.bin == 4 && r.rf > kSplitTarget && L.nwin <= kMaxSplitWindows && alen > 1) {
+    if (r.bin == 4 && r.rf > kSplitTarget && a.nwin <= kMaxSplitWindows && alen > 1) {
         uint64_t want = (r.rf + kSplitTarget - 1) / kSplitTarget;
         if (want > (uint64_t)kMaxParts) want = kMaxParts;
         if (want > (uint64_t)alen) want = (uint64_t)alen;
@@ -258,32 +345,45 @@ __device__ __forceinline__ SampledRow classify_row(int64_t g, const Csr& A,
     return r;
 }
 
-// The candidates of sampling workgroup b: [b C, min((b + 1) C, ncand)).
-__device__ __forceinline__ int64_t sample_chunk(int64_t ncand)
+// The case of sampling group `grp` (groups of a case are consecutive) and
+// its candidates [lo, hi).
+struct GroupRange {
+    int c;
+    int64_t lo, hi;
+};
+
+__device__ __forceinline__ GroupRange group_range(const CaseDesc* __restrict__ cs, int n,
+                                                  int64_t grp)
 {
-    const int64_t per = (ncand + gridDim.x - 1) / gridDim.x;
-    return (per + kSampleThreads - 1) / kSampleThreads * kSampleThreads;
+    int lo = 0, hi = n;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (cs[mid].group_base <= grp) lo = mid;
+        else hi = mid;
+    }
+    GroupRange r;
+    r.c = lo;
+    const int64_t k = grp - cs[lo].group_base, C = cs[lo].group_size, nc = cs[lo].ncand;
+    r.lo = k * C;
+    r.hi = (r.lo + C) < nc ? (r.lo + C) : nc;
+    return r;
 }
 
-// Pass 1: per workgroup, the counts of SampleCounts and the sums of n_s, f*
-// and the sample's A entries.  No atomics: the passes hand over per-group
+// Pass 1: per group, the counts of SampleCounts and the sums of n_s, f* and
+// the sample's A entries.  No atomics: the passes hand over per-group
 // counters (same-address device atomics serialise on this part).
-template <bool PAPER>
-__global__ __launch_bounds__(kSampleThreads) void k_sample_count(Csr A,
-                                                                const int64_t* __restrict__ rf,
-                                                                uint64_t seed, uint64_t thresh,
-                                                                int64_t ncand, BinLists L,
+__global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc* __restrict__ cs,
+                                                                int n,
                                                                 SampleCounts* __restrict__ cnt)
 {
     constexpr int NT = kSampleThreads;
     __shared__ uint64_t s_red[NT / kWave + 1];
-    const int64_t C = sample_chunk(ncand);
-    const int64_t lo = (int64_t)blockIdx.x * C;
-    const int64_t hi = (lo + C) < ncand ? (lo + C) : ncand;
+    const GroupRange gr = group_range(cs, n, blockIdx.x);
+    const SamplerArgs a = sampler_args(cs[gr.c]);
     uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
     uint64_t ns = 0, fs = 0, as = 0;
-    for (int64_t i = lo + threadIdx.x; i < hi; i += NT) {
-        const SampledRow r = classify_row(candidate_row<PAPER>(i, A.nrows, seed, thresh), A, rf, L);
+    for (int64_t i = gr.lo + threadIdx.x; i < gr.hi; i += NT) {
+        const SampledRow r = classify_row(candidate_row(i, a), a);
         if (r.g < 0) continue;
         ns += 1;
         fs += r.rf;
@@ -295,8 +395,8 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(Csr A,
             c[3] += 1;
             c[4] += r.want;
             if (r.elig) {
-                c[5] += (uint32_t)L.merge_per_row;
-                c[6] += r.want * (uint32_t)L.nwin;
+                c[5] += (uint32_t)a.merge_per_row;
+                c[6] += r.want * (uint32_t)a.nwin;
             }
         }
     }
@@ -310,7 +410,7 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(Csr A,
         SampleCounts o;
 #pragma unroll
         for (int k = 0; k < 7; ++k) o.c[k] = tot[k];
-        o.c[7] = 0;
+        o.c[7] = (uint32_t)gr.c;
         o.ns = Ns;
         o.fs = Fs;
         o.as = As;
@@ -319,88 +419,107 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(Csr A,
     }
 }
 
-// Pass 2, one workgroup: exclusive offsets of every group in every list,
-// the split decision (a group's eligible rows are split when all part
-// windows requested up to and including the group fit the scratch), the
-// list sizes and n_s, f*, the sample's A entries.
-constexpr int kScanThreads = kSampleGroups;
-static_assert(kSampleGroups <= kScanThreads, "one thread per sampling group");
+// Pass 2, one workgroup, the groups taken kScanThreads at a time: exclusive
+// offsets of every group in every list, the split decision (a group's
+// eligible rows are split when all part windows requested up to and
+// including the group fit the scratch), the list sizes, and per case n_s, f*
+// and the sample's A entries (one atomic per case and chunk of groups).
+constexpr int kScanThreads = 512;
 
 __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __restrict__ cnt,
-                                                             int ngroups, Ctl* ctl,
-                                                             ssp_stats* st)
+                                                             int64_t ngroups,
+                                                             const CaseDesc* __restrict__ cs,
+                                                             Ctl* ctl)
 {
     constexpr int NT = kScanThreads;
     __shared__ uint64_t s_red[NT / kWave + 1];
+    __shared__ uint64_t s_e[3][NT];  // exclusive prefixes of ns, fs, as in the chunk
     const int t = threadIdx.x;
-    SampleCounts x{};
-    if (t < ngroups) x = cnt[t];
-    uint64_t tot01, tot2w, tot4m;
-    const uint64_t p01 = block_excl_scan<NT, uint64_t>((uint64_t)x.c[0] | ((uint64_t)x.c[1] << 32),
-                                                       s_red, &tot01);
-    const uint64_t p2w = block_excl_scan<NT, uint64_t>((uint64_t)x.c[2] | ((uint64_t)x.c[6] << 32),
-                                                       s_red, &tot2w);
-    const uint32_t wpre = (uint32_t)(p2w >> 32);
-    const bool split = x.c[6] != 0 && (uint64_t)wpre + x.c[6] <= (uint64_t)kMaxPartWindows;
-    const uint32_t n4 = split ? x.c[4] : x.c[3];
-    const uint32_t nm = split ? x.c[5] : 0u;
-    const uint64_t p4m = block_excl_scan<NT, uint64_t>((uint64_t)n4 | ((uint64_t)nm << 32), s_red,
-                                                       &tot4m);
-    const uint64_t Ns = block_sum<NT, uint64_t>(x.ns, s_red);
-    const uint64_t Fs = block_sum<NT, uint64_t>(x.fs, s_red);
-    const uint64_t As = block_sum<NT, uint64_t>(x.as, s_red);
-    if (t < ngroups) {
-        SampleCounts o = x;
-        o.c[0] = (uint32_t)p01;
-        o.c[1] = (uint32_t)(p01 >> 32);
-        o.c[2] = (uint32_t)p2w;
-        o.c[3] = (uint32_t)p4m;
-        o.c[4] = (uint32_t)(p4m >> 32);
-        o.c[5] = wpre;
-        o.c[6] = split ? 1u : 0u;
-        cnt[t] = o;
+    uint64_t k01 = 0, k2w = 0, k4m = 0;  // carries, two u32 fields each
+    for (int64_t g0 = 0; g0 < ngroups; g0 += NT) {
+        const int64_t g = g0 + t;
+        SampleCounts x{};
+        if (g < ngroups) x = cnt[g];
+        uint64_t t01, t2w, t4m, tns, tfs, tas;
+        const uint64_t p01 = k01 + block_excl_scan<NT, uint64_t>(
+                                       (uint64_t)x.c[0] | ((uint64_t)x.c[1] << 32), s_red, &t01);
+        const uint64_t p2w = k2w + block_excl_scan<NT, uint64_t>(
+                                       (uint64_t)x.c[2] | ((uint64_t)x.c[6] << 32), s_red, &t2w);
+        const uint32_t wpre = (uint32_t)(p2w >> 32);
+        const bool split = x.c[6] != 0 && (uint64_t)wpre + x.c[6] <= (uint64_t)kMaxPartWindows;
+        const uint32_t n4 = split ? x.c[4] : x.c[3];
+        const uint32_t nm = split ? x.c[5] : 0u;
+        const uint64_t p4m =
+            k4m + block_excl_scan<NT, uint64_t>((uint64_t)n4 | ((uint64_t)nm << 32), s_red, &t4m);
+        const uint64_t ens = block_excl_scan<NT, uint64_t>(x.ns, s_red, &tns);
+        const uint64_t efs = block_excl_scan<NT, uint64_t>(x.fs, s_red, &tfs);
+        const uint64_t eas = block_excl_scan<NT, uint64_t>(x.as, s_red, &tas);
+        s_e[0][t] = ens;
+        s_e[1][t] = efs;
+        s_e[2][t] = eas;
+        __syncthreads();
+        if (g < ngroups) {
+            SampleCounts o = x;
+            o.c[0] = (uint32_t)p01;
+            o.c[1] = (uint32_t)(p01 >> 32);
+            o.c[2] = (uint32_t)p2w;
+            o.c[3] = (uint32_t)p4m;
+            o.c[4] = (uint32_t)(p4m >> 32);
+            o.c[5] = wpre;
+            o.c[6] = split ? 1u : 0u;
+            cnt[g] = o;
+            // the last group of its case in this chunk adds the case's part
+            const int c = (int)x.c[7];
+            const int64_t first = cs[c].group_base, last = first + cs[c].ngroups - 1;
+            if (g == last || t == NT - 1 || g == ngroups - 1) {
+                const int k0 = first > g0 ? (int)(first - g0) : 0;
+                const uint64_t dns = ens + x.ns - s_e[0][k0];
+                const uint64_t dfs = efs + x.fs - s_e[1][k0];
+                const uint64_t das = eas + x.as - s_e[2][k0];
+                ssp_stats* st = cs[c].st;
+                if (dns) atomicAdd(as_ull(&st->n_sampled), (ull)dns);
+                if (dfs) atomicAdd(as_ull(&st->sample_flop), (ull)dfs);
+                if (das) atomicAdd(as_ull(&st->a_sample_nnz), (ull)das);
+            }
+        }
+        __syncthreads();  // s_e is rewritten by the next chunk
+        k01 += t01;
+        k2w += t2w;
+        k4m += t4m;
     }
     if (t == 0) {
-        ctl->bin_cnt[1] = (uint32_t)tot01;
-        ctl->bin_cnt[2] = (uint32_t)(tot01 >> 32);
-        ctl->bin_cnt[3] = (uint32_t)tot2w;
-        ctl->bin_cnt[4] = (uint32_t)tot4m;
-        ctl->bin_cnt[5] = (uint32_t)(tot4m >> 32);
-        st->n_sampled = Ns;
-        st->sample_flop = Fs;
-        st->a_sample_nnz = As;
+        ctl->bin_cnt[1] = (uint32_t)k01;
+        ctl->bin_cnt[2] = (uint32_t)(k01 >> 32);
+        ctl->bin_cnt[3] = (uint32_t)k2w;
+        ctl->bin_cnt[4] = (uint32_t)k4m;
+        ctl->bin_cnt[5] = (uint32_t)(k4m >> 32);
     }
 }
 
 // Pass 3: every group regenerates its candidates and writes its rows at its
 // offsets (positions inside the group by workgroup scans, in candidate order).
-template <bool PAPER>
-__global__ __launch_bounds__(kSampleThreads) void k_sample_write(Csr A,
-                                                                const int64_t* __restrict__ rf,
-                                                                uint64_t seed, uint64_t thresh,
-                                                                int64_t ncand, int64_t N,
+__global__ __launch_bounds__(kSampleThreads) void k_sample_write(const CaseDesc* __restrict__ cs,
+                                                                int n,
                                                                 const SampleCounts* __restrict__ cnt,
                                                                 BinLists L)
 {
     constexpr int NT = kSampleThreads;
     __shared__ uint64_t s_red[NT / kWave + 1];
     const int t = threadIdx.x;
-    const int64_t C = sample_chunk(ncand);
-    const int64_t lo = (int64_t)blockIdx.x * C;
-    const int64_t hi = (lo + C) < ncand ? (lo + C) : ncand;
-    if (lo >= hi) return;  // (uniform over the workgroup)
+    const GroupRange gr = group_range(cs, n, blockIdx.x);
+    if (gr.lo >= gr.hi) return;  // (uniform over the workgroup)
+    const SamplerArgs a = sampler_args(cs[gr.c]);
     const SampleCounts o = cnt[blockIdx.x];
     const bool split = o.c[6] != 0;
     uint32_t off1 = o.c[0], off2 = o.c[1], off3 = o.c[2], off4 = o.c[3], offm = o.c[4],
              offw = o.c[5];
-    for (int64_t i0 = lo; i0 < hi; i0 += NT) {  // same trip count in every lane (scans)
+    for (int64_t i0 = gr.lo; i0 < gr.hi; i0 += NT) {  // same trip count in every lane (scans)
         const int64_t i = i0 + t;
-        const SampledRow r = classify_row(
-            i < hi ? candidate_row<PAPER>(i, A.nrows, seed, thresh) : -1, A, rf, L);
+        const SampledRow r = classify_row(i < gr.hi ? candidate_row(i, a) : -1, a);
         const bool sp = split && r.elig;
         const uint32_t n4 = r.bin == 4 ? (sp ? r.want : 1u) : 0u;
-        const uint32_t nm = sp ? (uint32_t)L.merge_per_row : 0u;
-        const uint32_t nw = sp ? r.want * (uint32_t)L.nwin : 0u;
+        const uint32_t nm = sp ? (uint32_t)a.merge_per_row : 0u;
+        const uint32_t nw = sp ? r.want * (uint32_t)a.nwin : 0u;
         uint64_t t01, t34, tmw;
         const uint64_t p01 = block_excl_scan<NT, uint64_t>(
             (uint64_t)(r.bin == 1) | ((uint64_t)(r.bin == 2) << 32), s_red, &t01);
@@ -412,6 +531,8 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_write(Csr A,
             BinItem it;
             it.row = (int32_t)r.g;
             it.rf = (uint32_t)r.rf;
+            it.cs = gr.c;
+            it.pad = 0;
             if (r.bin == 1) L.b1[off1 + (uint32_t)p01] = it;
             else if (r.bin == 2) L.b2[off2 + (uint32_t)(p01 >> 32)] = it;
             else L.b3[off3 + (uint32_t)p34] = it;
@@ -426,27 +547,12 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_write(Csr A,
                 it.nparts = (int32_t)n4;
                 it.e_lo = r.e0;
                 it.e_hi = r.e1;
+                it.cs = gr.c;
+                it.pad = 0;
                 L.b4[base + p] = it;
             }
-            if (sp) {
-                uint32_t m = offm + (uint32_t)pmw;
-                const int64_t wcols_full = (int64_t)L.win_words * 32;
-                for (int w = 0; w < L.nwin; ++w) {
-                    const int64_t cols = (N - w * wcols_full) < wcols_full ? (N - w * wcols_full)
-                                                                          : wcols_full;
-                    const int slices = (int)(((cols + 31) / 32 + kMergeSlice - 1) / kMergeSlice);
-                    for (int sl = 0; sl < slices; ++sl) {
-                        MergeItem mi;
-                        mi.row = (int32_t)r.g;
-                        mi.slot = slot;
-                        mi.nparts = (int32_t)n4;
-                        mi.window = w;
-                        mi.slice = sl;
-                        mi.pad = 0;
-                        L.merge[m++] = mi;
-                    }
-                }
-            }
+            if (sp) write_merge_items(L.merge + offm + (uint32_t)pmw, (int32_t)r.g, slot,
+                                      (int32_t)n4, gr.c, cs[gr.c]);
         }
         off1 += (uint32_t)t01;
         off2 += (uint32_t)(t01 >> 32);
@@ -487,11 +593,12 @@ __device__ __forceinline__ uint32_t hash_insert(uint32_t* tab, uint32_t c, int l
 // handles an equal share of products whatever the B row lengths.  Counting
 // uses an LDS bitmap of all N columns when that is no larger than the hash
 // table, else the hash table (size >= 2 x the row's distinct bound).
-// MODE 0: add the count to z*.  MODE 1: write it to out[row] (and out_sum).
+// MODE 0: add the count to the case's z*.  MODE 1: write it to out[row]
+// (and to the case's total).
 template <int TEAM, int WORDS, int MODE>
-__global__ __launch_bounds__(TEAM) void k_sym(Csr A, Csr B, const BinItem* __restrict__ items,
-                                             const uint32_t* count, uint64_t* zacc,
-                                             int64_t* __restrict__ out)
+__global__ __launch_bounds__(TEAM) void k_sym(const CaseDesc* __restrict__ cs,
+                                             const BinItem* __restrict__ items,
+                                             const uint32_t* count, CaseRes* __restrict__ cr)
 {
     __shared__ uint32_t tab[WORDS];
     __shared__ int32_t s_b0[TEAM];
@@ -499,10 +606,17 @@ __global__ __launch_bounds__(TEAM) void k_sym(Csr A, Csr B, const BinItem* __res
     __shared__ uint32_t s_red[TEAM / kWave + 1];
     const uint32_t n = *count;
     const int t = threadIdx.x;
-    const int64_t N = B.ncols;
+    int zc = -1;  // case of zsum (items of a case are consecutive in the list)
     uint64_t zsum = 0;
     for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
         const BinItem item = items[it];
+        if (item.cs != zc) {
+            if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
+            zsum = 0;
+            zc = item.cs;
+        }
+        const Csr A = cs[zc].A, B = cs[zc].B;
+        const int64_t N = B.ncols;
         const uint32_t bound = (uint32_t)((int64_t)item.rf < N ? (int64_t)item.rf : N);
         uint32_t tsize = 64;
         while (tsize < 2u * bound) tsize <<= 1;
@@ -562,11 +676,11 @@ __global__ __launch_bounds__(TEAM) void k_sym(Csr A, Csr B, const BinItem* __res
         const uint32_t total = block_sum<TEAM, uint32_t>(cnt, s_red);
         if (t == 0) {
             zsum += total;
-            if (MODE == 1) out[item.row] = (int64_t)total;
+            if (MODE == 1) cs[zc].out[item.row] = (int64_t)total;
         }
         __syncthreads();
     }
-    if (t == 0 && zsum) atomicAdd(as_ull(&zacc[blockIdx.x % kAccSlots]), (ull)zsum);
+    if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
 }
 
 // Bin 4: long rows, 1024 threads per item, an LDS bitmap per window of
@@ -590,11 +704,10 @@ __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
 }
 
 template <int MODE, bool WIN1>
-__global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
+__global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restrict__ cs,
                                                        const BigItem* __restrict__ items,
                                                        const uint32_t* count, uint32_t* next,
-                                                       BinLists L, uint64_t* zacc,
-                                                       int64_t* __restrict__ out)
+                                                       BinLists L, CaseRes* __restrict__ cr)
 {
     constexpr int TEAM = kBin4Team, NWAVE = TEAM / kWave;
     typedef int32_t i32x4 __attribute__((ext_vector_type(4)));
@@ -609,8 +722,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
     const uint32_t n = *count;
     const int t = threadIdx.x, lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(t / kWave);
-    const int64_t N = B.ncols;
-    const int64_t wcols_full = (int64_t)L.win_words * 32;
+    int zc = -1;  // case of zsum
     uint64_t zsum = 0;
     for (;;) {  // work queue: items are taken one at a time as workgroups free up
         if (t == 0) s_it = atomicAdd(next, 1u);
@@ -619,11 +731,20 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
         __syncthreads();
         if (it >= n) break;
         const BigItem item = items[it];
+        if (item.cs != zc) {
+            if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
+            zsum = 0;
+            zc = item.cs;
+        }
+        const Csr A = cs[zc].A, B = cs[zc].B;
+        const int64_t N = B.ncols;
+        const int32_t nwin = cs[zc].nwin;
+        const int64_t wcols_full = (int64_t)cs[zc].win_words * 32;
         // entries e0, e0 + P, e0 + 2P, ... below e_hi (P = 1 unless split)
         const int32_t e0 = item.e_lo + item.part, P = item.nparts;
         const int64_t cnt = item.e_hi > e0 ? ((int64_t)item.e_hi - e0 + P - 1) / P : 0;
         uint64_t total = 0;
-        for (int w = 0; w < L.nwin; ++w) {
+        for (int w = 0; w < nwin; ++w) {
             const int64_t c_lo = w * wcols_full;
             const int64_t wcols = (N - c_lo) < wcols_full ? (N - c_lo) : wcols_full;
             const int words = (int)((wcols + 31) / 32);
@@ -781,8 +902,8 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
                 total += block_sum<TEAM, uint64_t>(cnt, s_red);
             } else {
                 uint4* g = reinterpret_cast<uint4*>(
-                    L.scratch + ((int64_t)item.slot + (int64_t)item.part * L.nwin + w) *
-                                    (int64_t)L.win_words);
+                    L.scratch + ((int64_t)item.slot + (int64_t)item.part * nwin + w) *
+                                    (int64_t)kWinWords);
                 for (int i0 = t; i0 < w4; i0 += UR * TEAM) {
                     uint4 x[UR];
 #pragma unroll
@@ -799,28 +920,37 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(Csr A, Csr B,
         }
         if (t == 0 && total) {
             zsum += total;
-            if (MODE == 1) atomicAdd(reinterpret_cast<ull*>(&out[item.row]), (ull)total);
+            if (MODE == 1) atomicAdd(reinterpret_cast<ull*>(&cs[zc].out[item.row]), (ull)total);
         }
     }
-    if (t == 0 && zsum) atomicAdd(as_ull(&zacc[blockIdx.x % kAccSlots]), (ull)zsum);
+    if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
 }
 
 // ORs the part bitmaps of split rows, one slice of a window per item.  With
 // `finalize`, the last workgroup to finish (after every symbolic kernel has
 // added to z*) computes the per-call divisor of f*.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_sym_merge(const MergeItem* __restrict__ items,
-                                                  const uint32_t* count, BinLists L, int64_t N,
-                                                  uint64_t* zacc, int64_t* __restrict__ out)
+__global__ __launch_bounds__(256) void k_sym_merge(const CaseDesc* __restrict__ cs,
+                                                  const MergeItem* __restrict__ items,
+                                                  const uint32_t* count, BinLists L,
+                                                  CaseRes* __restrict__ cr)
 {
     __shared__ uint64_t s_red[256 / kWave + 1];
     const uint32_t n = *count;
     const int t = threadIdx.x;
-    const int64_t wcols_full = (int64_t)L.win_words * 32;
+    int zc = -1;
     uint64_t zsum = 0;
     static_assert(kMergeSlice == 4 * 256, "one 16-byte group per thread and slice");
     for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
         const MergeItem m = items[it];
+        if (m.cs != zc) {
+            if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
+            zsum = 0;
+            zc = m.cs;
+        }
+        const int64_t N = cs[zc].B.ncols;
+        const int32_t nwin = cs[zc].nwin;
+        const int64_t wcols_full = (int64_t)cs[zc].win_words * 32;
         const int64_t c_lo = (int64_t)m.window * wcols_full;
         const int64_t wcols = (N - c_lo) < wcols_full ? (N - c_lo) : wcols_full;
         const int w4 = (int)((wcols + 127) / 128);  // 16-byte groups of this window
@@ -828,9 +958,9 @@ __global__ __launch_bounds__(256) void k_sym_merge(const MergeItem* __restrict__
         uint32_t cnt = 0;
         if (g4 < w4) {
             // the parts' groups, eight 16-byte loads in flight, then OR
-            const int64_t stride4 = (int64_t)L.nwin * L.win_words / 4;
+            const int64_t stride4 = (int64_t)nwin * kWinWords / 4;
             const uint4* src = reinterpret_cast<const uint4*>(
-                                   L.scratch + ((int64_t)m.slot + m.window) * (int64_t)L.win_words) +
+                                   L.scratch + ((int64_t)m.slot + m.window) * (int64_t)kWinWords) +
                                g4;
             uint4 x = make_uint4(0u, 0u, 0u, 0u);
             for (int p0 = 0; p0 < m.nparts; p0 += 8) {
@@ -853,58 +983,66 @@ __global__ __launch_bounds__(256) void k_sym_merge(const MergeItem* __restrict__
         const uint64_t total = block_sum<256, uint64_t>(cnt, s_red);
         if (t == 0 && total) {
             zsum += total;
-            if (MODE == 1) atomicAdd(reinterpret_cast<ull*>(&out[m.row]), (ull)total);
+            if (MODE == 1) atomicAdd(reinterpret_cast<ull*>(&cs[zc].out[m.row]), (ull)total);
         }
     }
-    if (t == 0 && zsum) atomicAdd(as_ull(&zacc[blockIdx.x % kAccSlots]), (ull)zsum);
+    if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
 }
 
 // ---------------------------------------------------------- finalize
 
-// One workgroup of kAccSlots threads after the symbolic kernels: sums the
-// distinct-count slots into z* (MODE 0) or the exact total (MODE 1).  For
-// MODE 0 it also takes the per-call decisions: the empty-sample fallback
-// (f* = 0: every row predicts its own product count) and the divisor of f*
-// for the per-row ceilings.
+// One workgroup of kAccSlots threads per case after the symbolic kernels:
+// sums the case's distinct-count slots into z* (MODE 0) or the exact total
+// (MODE 1).  For MODE 0 it also takes the case's decisions: the empty-sample
+// fallback (f* = 0: every row predicts its own product count) and the divisor
+// of f* for the per-row ceilings.
 template <int MODE>
-__global__ __launch_bounds__(kAccSlots) void k_finalize(Ctl* ctl, ssp_stats* st)
+__global__ __launch_bounds__(kAccSlots) void k_finalize(const CaseDesc* __restrict__ cs,
+                                                       CaseRes* __restrict__ cr, int n)
 {
     __shared__ uint64_t s_red[kAccSlots / kWave + 1];
-    const uint64_t z = block_sum<kAccSlots, uint64_t>(ctl->zacc[threadIdx.x], s_red);
-    if (threadIdx.x != 0) return;
-    if (MODE == 1) {
-        st->out_sum = z;
-        return;
+    for (int c = blockIdx.x; c < n; c += gridDim.x) {
+        const uint64_t z = block_sum<kAccSlots, uint64_t>(cr[c].zacc[threadIdx.x], s_red);
+        if (threadIdx.x != 0) continue;
+        ssp_stats* st = cs[c].st;
+        if (MODE == 1) {
+            st->out_sum = z;
+            continue;
+        }
+        st->sample_nnz = z;
+        const uint64_t fs = st->sample_flop;
+        if (fs == 0) {
+            cr[c].fallback = 1;
+            st->flags |= SSP_FLAG_EMPTY_SAMPLE;
+            continue;
+        }
+        cr[c].fallback = 0;
+        const Divisor D = make_divisor(fs);
+        cr[c].div_dn = D.dn;
+        cr[c].div_v = D.v;
+        cr[c].div_shift = D.shift;
     }
-    st->sample_nnz = z;
-    const uint64_t fs = st->sample_flop;
-    if (fs == 0) {
-        ctl->fallback = 1;
-        st->flags |= SSP_FLAG_EMPTY_SAMPLE;
-        return;
-    }
-    ctl->fallback = 0;
-    const Divisor D = make_divisor(fs);
-    ctl->div_dn = D.dn;
-    ctl->div_v = D.v;
-    ctl->div_shift = D.shift;
 }
 
-__global__ void k_finalize_reference(Ctl* ctl, ssp_stats* st, uint64_t M)
+// Reference design constants per case (Eq. (2)): z* M and n_s F.
+__global__ void k_finalize_reference(const CaseDesc* __restrict__ cs, CaseRes* __restrict__ cr,
+                                     int n)
 {
-    if (threadIdx.x != 0) return;
-    if (st->sample_flop == 0) {
-        ctl->fallback = 1;
-        st->flags |= SSP_FLAG_EMPTY_SAMPLE;
-        return;
+    for (int c = blockIdx.x * blockDim.x + threadIdx.x; c < n; c += gridDim.x * blockDim.x) {
+        ssp_stats* st = cs[c].st;
+        if (st->sample_flop == 0) {
+            cr[c].fallback = 1;
+            st->flags |= SSP_FLAG_EMPTY_SAMPLE;
+            continue;
+        }
+        cr[c].fallback = 0;
+        const u128 q = mul_64x64(st->sample_nnz, (uint64_t)cs[c].A.nrows);
+        const u128 d = mul_64x64(st->n_sampled, st->total_flop);
+        cr[c].ref_q_lo = q.lo;
+        cr[c].ref_q_hi = q.hi;
+        cr[c].ref_d_lo = d.lo;
+        cr[c].ref_d_hi = d.hi;
     }
-    ctl->fallback = 0;
-    const u128 q = mul_64x64(st->sample_nnz, M);
-    const u128 d = mul_64x64(st->n_sampled, st->total_flop);
-    ctl->ref_q_lo = q.lo;
-    ctl->ref_q_hi = q.hi;
-    ctl->ref_d_lo = d.lo;
-    ctl->ref_d_hi = d.hi;
 }
 
 // -------------------------------------------------------------- k_flop
@@ -914,13 +1052,34 @@ enum { FLOP_ONLY = 1, FLOP_EXACT_BIN = 2 };
 struct FlopArgs {
     Csr A, B;
     int64_t* out;      // ONLY: row flop; EXACT_BIN: nnz_exact (0 for rows of bins 0 and 4)
-    ssp_stats* st;
     Ctl* ctl;
     BinLists L;
     const int32_t* tile_row; // first row of every tile, tile_row[ntiles] = M
     TileMeta* meta;
     int64_t ntiles;
+    const CaseDesc* cd;      // the case (window shape, for binning)
+    int32_t ci;
 };
+
+// The streaming-pass arguments of case c.
+template <int MODE>
+__device__ __forceinline__ FlopArgs flop_args(const CaseDesc* __restrict__ cs, int c,
+                                              int32_t* tile_row_all, TileMeta* meta_all,
+                                              Ctl* ctl, const BinLists& L)
+{
+    FlopArgs a;
+    a.A = cs[c].A;
+    a.B = cs[c].B;
+    a.out = MODE == FLOP_ONLY ? cs[c].rf : cs[c].out;
+    a.ctl = ctl;
+    a.L = L;
+    a.tile_row = tile_row_all + cs[c].tile_base;
+    a.meta = meta_all + cs[c].meta_base;
+    a.ntiles = cs[c].ntiles;
+    a.cd = cs + c;
+    a.ci = c;
+    return a;
+}
 
 // Output of one finished row: its product count, or its bin.
 template <int MODE>
@@ -929,9 +1088,10 @@ __device__ __forceinline__ void emit_row(const FlopArgs& a, int64_t row, uint64_
     if (MODE == FLOP_ONLY) {
         a.out[row] = (int64_t)rf;
     } else {
-        const int b = bin_route(rf, a.L);
+        const int b = bin_route(rf, *a.cd);
         if (b == 0 || b == 4) a.out[row] = 0;
-        if (b != 0) append_row((int32_t)row, rf, a.A.rpt[row], a.A.rpt[row + 1], a.B.ncols, a.ctl, a.L);
+        if (b != 0)
+            append_row((int32_t)row, rf, a.A.rpt[row], a.A.rpt[row + 1], a.ci, *a.cd, a.ctl, a.L);
     }
 }
 
@@ -1024,8 +1184,13 @@ __device__ __forceinline__ void flop_issue_tile(const FlopArgs& a, int64_t b, in
 }
 
 template <int MODE, bool VEC>
-__global__ __launch_bounds__(kFlopThreads) void k_flop(FlopArgs a)
+__global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restrict__ cs, int n,
+                                                      int32_t* tile_row_all, TileMeta* meta_all,
+                                                      Ctl* ctl, BinLists L)
 {
+    // the case of this workgroup, and its rank among the case's workgroups
+    const int c = case_of_wg<&CaseDesc::wg_flop>(cs, n, blockIdx.x);
+    const FlopArgs a = flop_args<MODE>(cs, c, tile_row_all, meta_all, ctl, L);
     constexpr int NT = kFlopThreads, CH = kFlopChunk, HALF = CH / 2;
     constexpr int T = (int)kFlopTile, NRP = kFlopTile / kFlopThreads + 1;
     __shared__ int32_t s_bnd[T + 2];
@@ -1035,14 +1200,14 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(FlopArgs a)
 
     const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
     const int64_t M = a.A.nrows;
-    const int64_t G = gridDim.x, ntiles = a.ntiles;
+    const int64_t G = wgs_of_case<&CaseDesc::wg_flop>(cs, n, c), ntiles = a.ntiles;
     const int32_t* __restrict__ Brpt = a.B.rpt;
 
     // The tile starts of this workgroup's tiles are staged in LDS, kTrow at a
     // time: reading them from LDS does not wait on the vector loads in flight.
     constexpr int kTrow = 64;
     __shared__ int32_t s_trow[kTrow + 1];
-    int64_t b = blockIdx.x;
+    int64_t b = (int64_t)blockIdx.x - cs[c].wg_flop;
     if (b >= ntiles) return;
     auto stage_trow = [&](int64_t bfirst) {  // tiles bfirst + k G, k < kTrow
         for (int k = t; k <= kTrow; k += NT) {
@@ -1167,11 +1332,11 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(FlopArgs a)
                 }
             }
             if (MODE == FLOP_EXACT_BIN) {
-                const int bn_ = emit ? bin_route(sum, a.L) : 0;
-                append_small_bins(bn_, (int32_t)r, sum, a.ctl, a.L);
+                const int bn_ = emit ? bin_route(sum, *a.cd) : 0;
+                append_small_bins(bn_, (int32_t)r, sum, a.ci, a.ctl, a.L);
                 if (emit && (bn_ == 0 || bn_ == 4)) a.out[r] = 0;
                 if (emit && bn_ == 4)
-                    append_big((int32_t)r, sum, s_bnd[k], s_bnd[k + 1], a.B.ncols, a.ctl, a.L);
+                    append_big((int32_t)r, sum, s_bnd[k], s_bnd[k + 1], a.ci, *a.cd, a.ctl, a.L);
             } else if (emit) {
                 __builtin_nontemporal_store((int64_t)sum, a.out + r);
             }
@@ -1192,12 +1357,16 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(FlopArgs a)
 
 // One thread per tile: a row that begins in tile b and goes on (its partial
 // is b's carry) collects the heads of the following tiles until the tile
-// holding its end marker, then gets its output.  Adds F.
+// holding its end marker, then gets its output.  Adds the case's F.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_flop_fixup(FlopArgs a)
+__global__ __launch_bounds__(256) void k_flop_fixup(const CaseDesc* __restrict__ cs, int n,
+                                                   int32_t* tile_row_all, TileMeta* meta_all,
+                                                   Ctl* ctl, BinLists L)
 {
     __shared__ uint64_t s_red[256 / kWave + 1];
-    const int64_t b = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int c = case_of_wg<&CaseDesc::wg_fixup>(cs, n, blockIdx.x);
+    const FlopArgs a = flop_args<MODE>(cs, c, tile_row_all, meta_all, ctl, L);
+    const int64_t b = ((int64_t)blockIdx.x - cs[c].wg_fixup) * 256 + threadIdx.x;
     const int64_t M = a.A.nrows, nnzA = a.A.nnz;
     uint64_t F = 0;
     if (b < a.ntiles) {
@@ -1219,7 +1388,7 @@ __global__ __launch_bounds__(256) void k_flop_fixup(FlopArgs a)
         }
     }
     const uint64_t Fs = block_sum<256, uint64_t>(F, s_red);
-    if (threadIdx.x == 0 && Fs) atomicAdd(as_ull(&a.st->total_flop), (ull)Fs);
+    if (threadIdx.x == 0 && Fs) atomicAdd(as_ull(&cs[c].st->total_flop), (ull)Fs);
 }
 
 // ------------------------------------------------------ prediction rows
@@ -1229,21 +1398,27 @@ constexpr int kRowsThreads = 1024;
 // nnz_pred[i] = ceil(rf_i z* / f*) (Eq. 3 per row), rf_i when the sample has
 // no products.  Grid-stride with few workgroups: each adds its part of the
 // output total with one atomic.
-__global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const int64_t* __restrict__ rf_in,
-                                                            int64_t* __restrict__ out, int64_t M,
-                                                            Ctl* ctl, ssp_stats* st)
+__global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __restrict__ cs, int n,
+                                                            const CaseRes* __restrict__ cr)
 {
     __shared__ uint64_t s_red[kRowsThreads / kWave + 1];
-    const uint32_t fallback = ctl->fallback;
+    const int c = case_of_wg<&CaseDesc::wg_rows>(cs, n, blockIdx.x);
+    const int64_t bl = (int64_t)blockIdx.x - cs[c].wg_rows;
+    const int64_t G = wgs_of_case<&CaseDesc::wg_rows>(cs, n, c);
+    const int64_t* __restrict__ rf_in = cs[c].rf;
+    int64_t* __restrict__ out = cs[c].out;
+    const int64_t M = cs[c].A.nrows;
+    ssp_stats* st = cs[c].st;
+    const uint32_t fallback = cr[c].fallback;
     Divisor D;
-    D.dn = ctl->div_dn;
-    D.v = ctl->div_v;
-    D.shift = ctl->div_shift;
+    D.dn = cr[c].div_dn;
+    D.v = cr[c].div_v;
+    D.shift = cr[c].div_shift;
     const uint64_t zs = st->sample_nnz;
     uint64_t osum = 0;
     constexpr int U = 4;  // rows per thread and step, loaded together
-    const int64_t stride = (int64_t)gridDim.x * kRowsThreads * U;
-    for (int64_t i0 = (int64_t)blockIdx.x * kRowsThreads * U + threadIdx.x; i0 < M; i0 += stride) {
+    const int64_t stride = G * kRowsThreads * U;
+    for (int64_t i0 = bl * kRowsThreads * U + threadIdx.x; i0 < M; i0 += stride) {
         uint64_t rf[U];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -1268,20 +1443,26 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const int64_t* __res
 
 // nnz_ref[i] = ceil(rf_i * (z* M) / (n_s F)), saturating at INT64_MAX.
 // Grid-stride like k_pred_rows.
-__global__ __launch_bounds__(kRowsThreads) void k_ref_rows(const int64_t* __restrict__ rf_in,
-                                                           int64_t* __restrict__ out, int64_t M,
-                                                           Ctl* ctl, ssp_stats* st)
+__global__ __launch_bounds__(kRowsThreads) void k_ref_rows(const CaseDesc* __restrict__ cs, int n,
+                                                           const CaseRes* __restrict__ cr)
 {
     __shared__ uint64_t s_red[kRowsThreads / kWave + 1];
-    const uint32_t fallback = ctl->fallback;
-    const u128 Q = {ctl->ref_q_lo, ctl->ref_q_hi};
-    const u128 Dd = {ctl->ref_d_lo, ctl->ref_d_hi};
+    const int c = case_of_wg<&CaseDesc::wg_rows>(cs, n, blockIdx.x);
+    const int64_t bl = (int64_t)blockIdx.x - cs[c].wg_rows;
+    const int64_t G = wgs_of_case<&CaseDesc::wg_rows>(cs, n, c);
+    const int64_t* __restrict__ rf_in = cs[c].rf;
+    int64_t* __restrict__ out = cs[c].out;
+    const int64_t M = cs[c].A.nrows;
+    ssp_stats* st = cs[c].st;
+    const uint32_t fallback = cr[c].fallback;
+    const u128 Q = {cr[c].ref_q_lo, cr[c].ref_q_hi};
+    const u128 Dd = {cr[c].ref_d_lo, cr[c].ref_d_hi};
     uint64_t osum = 0;
     bool any_sat = false;
-    const int64_t stride = (int64_t)gridDim.x * kRowsThreads;
+    const int64_t stride = G * kRowsThreads;
     const int64_t iters = (M + stride - 1) / stride;
     for (int64_t k = 0; k < iters; ++k) {  // same trip count in every lane (ballot below)
-        const int64_t i = k * stride + (int64_t)blockIdx.x * kRowsThreads + threadIdx.x;
+        const int64_t i = k * stride + bl * kRowsThreads + threadIdx.x;
         uint64_t v = 0;
         bool sat = false;
         if (i < M) {

@@ -51,6 +51,21 @@ struct ssp_context {
     bool timing = false;
     std::vector<EventPair> pending;
     std::vector<hipEvent_t> event_pool;
+    // pinned staging of batch case tables
+    void* pin = nullptr;
+    size_t pin_bytes = 0;
+    hipEvent_t pin_ev = nullptr;
+};
+
+// A captured batch: its own workspace and case table, and the launch graph.
+struct ssp_batch_graph_s {
+    ssp_handle h = nullptr;
+    int device = 0;
+    void* ws = nullptr;
+    size_t ws_bytes = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int n = 0;
 };
 
 namespace {
@@ -108,9 +123,9 @@ hipEvent_t take_event(ssp_handle h)
 // Brackets the launches made while it lives with two events on `s`.
 class PhaseTimer {
   public:
-    PhaseTimer(ssp_handle h, int phase, hipStream_t s) : h_(h), s_(s)
+    PhaseTimer(ssp_handle h, int phase, hipStream_t s, bool enabled = true) : h_(h), s_(s)
     {
-        if (!h->timing) return;
+        if (!h->timing || !enabled) return;
         p_.phase = phase;
         p_.a = take_event(h);
         p_.b = take_event(h);
@@ -119,7 +134,7 @@ class PhaseTimer {
     ~PhaseTimer() { stop(); }
     void stop()
     {
-        if (!h_->timing || !p_.a || !p_.b) return;
+        if (!p_.a || !p_.b) return;
         (void)hipEventRecord(p_.b, s_);
         h_->pending.push_back(p_);
         p_.a = p_.b = nullptr;
@@ -205,13 +220,37 @@ ssp_status ensure_workspace(ssp_handle h, size_t bytes)
     return SSP_OK;
 }
 
-struct Bound {
-    Ctl* ctl;
-    BinLists L;
-    int32_t* tile_row;
-    TileMeta* meta;
-    SampleCounts* samp;
-    int64_t* rowtmp;
+// ------------------------------------------------------------- planning
+
+// One case of a call as the host sees it.
+struct CaseIn {
+    Csr A, B;
+    int sampler;     // ssp_sampler
+    double rate;
+    uint64_t seed;
+    int64_t* out;
+    int64_t* rf;     // the caller's row-FLOP array, or null (workspace)
+    ssp_stats* st;   // the caller's stats, or null (workspace)
+};
+
+enum PlanKind { PLAN_PREDICT, PLAN_REFERENCE, PLAN_EXACT };
+
+// Everything the launches of a call need: the case table (device pointers
+// into the workspace resolved by bind_plan), grid sizes and the workspace
+// layout.
+struct Plan {
+    PlanKind kind = PLAN_PREDICT;
+    int n = 0;
+    std::vector<CaseDesc> cs;
+    std::vector<int64_t> rf_off;   // workspace row-FLOP offset per case, -1 = caller's
+    std::vector<int> st_slot;      // workspace stats slot per case, -1 = caller's
+    int64_t cap13 = 1, cap4 = 1, cap5 = 1, ngroups = 0, tiles = 0, meta = 0, rowtmp = 0;
+    int32_t g_tiles = 0, g_flop = 0, g_fixup = 0, g_rows = 0;
+    int32_t win_words_max = 4;
+    bool win1 = true, vec = true;
+    size_t o_ctl = 0, o_scratch = 0, o_b1 = 0, o_b2 = 0, o_b3 = 0, o_b4 = 0, o_merge = 0,
+           o_tiles = 0, o_meta = 0, o_samp = 0, o_cases = 0, o_res = 0, o_stats = 0,
+           o_rowtmp = 0, total = 0;
 };
 
 // Columns per bitmap window of the long-row kernel: all N columns when they
@@ -228,35 +267,6 @@ void window_shape(int64_t N, int32_t* words, int32_t* nwin)
     }
 }
 
-Bound bind(ssp_handle h, const Layout& L, int64_t N)
-{
-    char* base = static_cast<char*>(h->ws);
-    Bound b;
-    b.ctl = reinterpret_cast<Ctl*>(base + L.ctl);
-    b.L.b1 = reinterpret_cast<BinItem*>(base + L.bin1);
-    b.L.b2 = reinterpret_cast<BinItem*>(base + L.bin2);
-    b.L.b3 = reinterpret_cast<BinItem*>(base + L.bin3);
-    b.L.b4 = reinterpret_cast<BigItem*>(base + L.bin4);
-    b.L.merge = reinterpret_cast<MergeItem*>(base + L.merge);
-    b.L.scratch = reinterpret_cast<uint32_t*>(base + L.scratch);
-    window_shape(N, &b.L.win_words, &b.L.nwin);
-    // bin 3 would hash (its table as a bitmap covers fewer than N columns) while
-    // one bitmap window covers all N: those rows go to the long-row kernel
-    b.L.big3 = (b.L.nwin == 1 && N > 32LL * kBin3Words) ? 1 : 0;
-    int32_t mpr = 0;  // merge items of a split row: slices of every window
-    for (int32_t w = 0; w < b.L.nwin; ++w) {
-        const int64_t cols = std::min<int64_t>(N - (int64_t)w * b.L.win_words * 32,
-                                               (int64_t)b.L.win_words * 32);
-        mpr += (int32_t)(((cols + 31) / 32 + kMergeSlice - 1) / kMergeSlice);
-    }
-    b.L.merge_per_row = mpr;
-    b.tile_row = reinterpret_cast<int32_t*>(base + L.tiles);
-    b.meta = reinterpret_cast<TileMeta*>(base + L.meta);
-    b.samp = reinterpret_cast<SampleCounts*>(base + L.samp);
-    b.rowtmp = reinterpret_cast<int64_t*>(base + L.rowtmp);
-    return b;
-}
-
 unsigned grid_for(int64_t items, int64_t cap)
 {
     if (items < 1) items = 1;
@@ -266,7 +276,7 @@ unsigned grid_for(int64_t items, int64_t cap)
 // Workgroups of `kernel` that fit on the device at once (static LDS only),
 // cached per kernel address.
 template <typename K>
-int64_t resident(K kernel, int threads, int cus)
+int64_t resident(K kernel, int threads, int cus, size_t dyn_lds = 0)
 {
     static std::mutex mu;
     static std::unordered_map<const void*, int> cache;
@@ -274,181 +284,365 @@ int64_t resident(K kernel, int threads, int cus)
     std::lock_guard<std::mutex> lock(mu);
     auto it = cache.find(key);
     if (it == cache.end()) {
-        int n = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&n, kernel, threads, 0) != hipSuccess || n < 1)
-            n = 1;
-        it = cache.emplace(key, n).first;
+        int k = 0;
+        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&k, kernel, threads, dyn_lds) != hipSuccess ||
+            k < 1)
+            k = 1;
+        it = cache.emplace(key, k).first;
     }
     return (int64_t)it->second * cus;
 }
 
-template <int MODE>
-void launch_flop(ssp_handle h, const FlopArgs& fa, bool vec, hipStream_t s)
+// Per-case workgroup counts proportional to work, at least 1 for a case with
+// work, at most `cap_c` (the case's useful maximum); returns the prefixes.
+template <typename W, typename Cap>
+int32_t share_wgs(int n, int64_t budget, W work, Cap cap_c, std::vector<int32_t>& first)
 {
-    const int cus = h->num_cus;
-    // persistent: as many workgroups as can be resident at once, each walks
-    // its tiles (grid-stride)
-    static int resident[2] = {0, 0};
-    int& r = resident[vec ? 1 : 0];
-    if (r == 0) {
-        int per_cu = 0;
-        const hipError_t e =
-            vec ? hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_flop<MODE, true>,
-                                                               kFlopThreads, 0)
-                : hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_flop<MODE, false>,
-                                                               kFlopThreads, 0);
-        r = (e == hipSuccess && per_cu > 0) ? per_cu : 4;
+    int64_t total = 0;
+    for (int c = 0; c < n; ++c) total += work(c);
+    first.assign(n, 0);
+    int64_t g = 0;
+    for (int c = 0; c < n; ++c) {
+        first[c] = (int32_t)g;
+        const int64_t w = work(c);
+        if (w <= 0) continue;
+        int64_t k = total > 0 ? (int64_t)((double)budget * (double)w / (double)total + 0.5) : 1;
+        k = std::max<int64_t>(1, std::min<int64_t>(k, cap_c(c)));
+        g += k;
     }
-    const unsigned grid =
-        (unsigned)std::max<int64_t>(std::min<int64_t>(fa.ntiles, (int64_t)r * cus), 1);
-    if (fa.ntiles > 0) {
-        PhaseTimer pt(h, PH_FLOP, s);
-        if (vec) hipLaunchKernelGGL((k_flop<MODE, true>), dim3(grid), dim3(kFlopThreads), 0, s, fa);
-        else hipLaunchKernelGGL((k_flop<MODE, false>), dim3(grid), dim3(kFlopThreads), 0, s, fa);
-    }
-    PhaseTimer pt(h, PH_FLOP_FIXUP, s);
-    const unsigned fgrid = (unsigned)std::max<int64_t>((fa.ntiles + 255) / 256, 1);
-    hipLaunchKernelGGL((k_flop_fixup<MODE>), dim3(fgrid), dim3(256), 0, s, fa);
+    return (int32_t)g;
 }
 
-// Symbolic kernels over the four bins and the merge of split rows (sizes of
-// the lists are device-side; the grids are upper bounds and every kernel
-// walks its list grid-stride).
+Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind)
+{
+    Plan P;
+    P.kind = kind;
+    P.n = (int)in.size();
+    const int n = P.n, cus = h->num_cus;
+    P.cs.assign(n, CaseDesc{});
+    P.rf_off.assign(n, -1);
+    P.st_slot.assign(n, -1);
+    int64_t sumC = 0;
+    for (int c = 0; c < n; ++c) {
+        CaseDesc& d = P.cs[c];
+        const CaseIn& x = in[c];
+        const int64_t M = x.A.nrows, nnz = x.A.nnz, N = x.B.ncols;
+        d.A = x.A;
+        d.B = x.B;
+        d.out = x.out;
+        d.rf = x.rf;
+        d.st = x.st;
+        d.seed = x.seed;
+        d.paper = x.sampler == SSP_SAMPLER_PAPER ? 1 : 0;
+        d.thresh = d.paper ? 0 : rate_threshold(x.rate);
+        d.ncand = (kind == PLAN_EXACT || M == 0) ? 0 : (d.paper ? paper_sample_num(M) : M);
+        window_shape(N, &d.win_words, &d.nwin);
+        // bin 3 would hash (its table as a bitmap covers fewer than N columns)
+        // while one bitmap window covers all N: those rows go to the long-row kernel
+        d.big3 = (d.nwin == 1 && N > 32LL * kBin3Words) ? 1 : 0;
+        int32_t mpr = 0;  // merge items of a split row: slices of every window
+        for (int32_t w = 0; w < d.nwin; ++w) {
+            const int64_t cols = std::min<int64_t>(N - (int64_t)w * d.win_words * 32,
+                                                   (int64_t)d.win_words * 32);
+            mpr += (int32_t)(((cols + 31) / 32 + kMergeSlice - 1) / kMergeSlice);
+        }
+        d.merge_per_row = mpr;
+        d.ntiles = M > 0 ? flop_tiles(M, nnz) : 0;
+        d.tile_base = P.tiles;
+        P.tiles += M > 0 ? d.ntiles + 1 : 0;
+        d.meta_base = P.meta;
+        P.meta += d.ntiles;
+        if (!x.rf && kind != PLAN_EXACT) {
+            P.rf_off[c] = P.rowtmp;
+            P.rowtmp += M;
+        }
+        if (!x.st) P.st_slot[c] = c;
+        sumC += d.ncand;
+        P.win_words_max = std::max(P.win_words_max, d.win_words);
+        if (d.nwin != 1) P.win1 = false;
+        if (M > 0 && !((reinterpret_cast<uintptr_t>(x.A.col) & 15u) == 0 && nnz >= 4)) P.vec = false;
+    }
+    // sampling groups: about kSampleTarget per call, at least 2048 candidates each
+    int64_t gsize = (sumC + kSampleTarget - 1) / kSampleTarget;
+    gsize = std::max<int64_t>(2048, (gsize + 255) / 256 * 256);
+    for (int c = 0; c < n; ++c) {
+        CaseDesc& d = P.cs[c];
+        d.group_size = gsize;
+        d.ngroups = (d.ncand + gsize - 1) / gsize;
+        d.group_base = P.ngroups;
+        P.ngroups += d.ngroups;
+    }
+    // workgroups per case, in proportion to the work
+    std::vector<int32_t> f;
+    auto Mof = [&](int c) { return P.cs[c].A.nrows; };
+    auto T = [&](int c) { return P.cs[c].ntiles; };
+    P.g_tiles = share_wgs(n, 16LL * cus, Mof, [&](int c) { return (Mof(c) + 255) / 256; }, f);
+    for (int c = 0; c < n; ++c) P.cs[c].wg_tiles = f[c];
+    const int64_t rflop = P.vec ? resident(k_flop<FLOP_ONLY, true>, kFlopThreads, cus)
+                                : resident(k_flop<FLOP_ONLY, false>, kFlopThreads, cus);
+    P.g_flop = share_wgs(n, rflop, T, T, f);
+    for (int c = 0; c < n; ++c) P.cs[c].wg_flop = f[c];
+    {
+        int64_t g = 0;
+        for (int c = 0; c < n; ++c) {
+            P.cs[c].wg_fixup = (int32_t)g;
+            g += (P.cs[c].ntiles + 255) / 256;
+        }
+        P.g_fixup = (int32_t)g;
+    }
+    P.g_rows = share_wgs(n, std::max(1, cus / 2), Mof,
+                         [&](int c) { return (Mof(c) + 4 * kRowsThreads - 1) / (4 * kRowsThreads); }, f);
+    for (int c = 0; c < n; ++c) P.cs[c].wg_rows = f[c];
+    // list capacities
+    int64_t sumM = 0;
+    for (int c = 0; c < n; ++c) sumM += P.cs[c].A.nrows;
+    P.cap13 = std::max<int64_t>(1, kind == PLAN_EXACT ? sumM : sumC);
+    P.cap4 = P.cap13 + kMaxPartWindows;
+    P.cap5 = (int64_t)kMaxPartWindows * (kWinWords / kMergeSlice) + 64;
+    // workspace layout
+    size_t o = 0;
+    P.o_ctl = o;     o = align256(o + sizeof(Ctl));
+    P.o_scratch = o; o = align256(o + (size_t)kMaxPartWindows * kWinWords * sizeof(uint32_t));
+    P.o_b1 = o;      o = align256(o + (size_t)P.cap13 * sizeof(BinItem));
+    P.o_b2 = o;      o = align256(o + (size_t)P.cap13 * sizeof(BinItem));
+    P.o_b3 = o;      o = align256(o + (size_t)P.cap13 * sizeof(BinItem));
+    P.o_b4 = o;      o = align256(o + (size_t)P.cap4 * sizeof(BigItem));
+    P.o_merge = o;   o = align256(o + (size_t)P.cap5 * sizeof(MergeItem));
+    P.o_tiles = o;   o = align256(o + (size_t)std::max<int64_t>(P.tiles, 1) * sizeof(int32_t));
+    P.o_meta = o;    o = align256(o + (size_t)std::max<int64_t>(P.meta, 1) * sizeof(TileMeta));
+    P.o_samp = o;    o = align256(o + (size_t)std::max<int64_t>(P.ngroups, 1) * sizeof(SampleCounts));
+    P.o_cases = o;   o = align256(o + (size_t)n * sizeof(CaseDesc));
+    P.o_res = o;     o = align256(o + (size_t)n * sizeof(CaseRes));
+    P.o_stats = o;   o = align256(o + (size_t)n * sizeof(ssp_stats));
+    P.o_rowtmp = o;  o = align256(o + (size_t)std::max<int64_t>(P.rowtmp, 1) * sizeof(int64_t));
+    P.total = o;
+    return P;
+}
+
+// Device pointers of a plan in a workspace at `base`; resolves the case
+// table's workspace-backed row-FLOP arrays and statistics.
+struct Bound {
+    Ctl* ctl;
+    BinLists L;
+    int32_t* tile_row;
+    TileMeta* meta;
+    SampleCounts* samp;
+    CaseDesc* cs;
+    CaseRes* cr;
+};
+
+Bound bind_plan(Plan& P, void* ws)
+{
+    char* base = static_cast<char*>(ws);
+    Bound b;
+    b.ctl = reinterpret_cast<Ctl*>(base + P.o_ctl);
+    b.L.b1 = reinterpret_cast<BinItem*>(base + P.o_b1);
+    b.L.b2 = reinterpret_cast<BinItem*>(base + P.o_b2);
+    b.L.b3 = reinterpret_cast<BinItem*>(base + P.o_b3);
+    b.L.b4 = reinterpret_cast<BigItem*>(base + P.o_b4);
+    b.L.merge = reinterpret_cast<MergeItem*>(base + P.o_merge);
+    b.L.scratch = reinterpret_cast<uint32_t*>(base + P.o_scratch);
+    b.tile_row = reinterpret_cast<int32_t*>(base + P.o_tiles);
+    b.meta = reinterpret_cast<TileMeta*>(base + P.o_meta);
+    b.samp = reinterpret_cast<SampleCounts*>(base + P.o_samp);
+    b.cs = reinterpret_cast<CaseDesc*>(base + P.o_cases);
+    b.cr = reinterpret_cast<CaseRes*>(base + P.o_res);
+    ssp_stats* stats = reinterpret_cast<ssp_stats*>(base + P.o_stats);
+    int64_t* rowtmp = reinterpret_cast<int64_t*>(base + P.o_rowtmp);
+    for (int c = 0; c < P.n; ++c) {
+        if (P.rf_off[c] >= 0) P.cs[c].rf = rowtmp + P.rf_off[c];
+        if (P.st_slot[c] >= 0) P.cs[c].st = stats + P.st_slot[c];
+    }
+    return b;
+}
+
+// ------------------------------------------------------------- launches
+
 template <int MODE>
-ssp_status launch_symbolic(ssp_handle h, const Csr& A, const Csr& B, const Bound& b,
-                           const Layout& L, ssp_stats* st, int64_t* out, hipStream_t s)
+void launch_flop(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s, bool timed)
+{
+    {
+        PhaseTimer pt(h, PH_TILES, s, timed);
+        if (P.g_tiles > 0)
+            hipLaunchKernelGGL(k_tiles, dim3(P.g_tiles), dim3(256), 0, s, b.cs, P.n, b.tile_row);
+    }
+    if (P.g_flop > 0) {
+        PhaseTimer pt(h, PH_FLOP, s, timed);
+        if (P.vec)
+            hipLaunchKernelGGL((k_flop<MODE, true>), dim3(P.g_flop), dim3(kFlopThreads), 0, s, b.cs,
+                               P.n, b.tile_row, b.meta, b.ctl, b.L);
+        else
+            hipLaunchKernelGGL((k_flop<MODE, false>), dim3(P.g_flop), dim3(kFlopThreads), 0, s, b.cs,
+                               P.n, b.tile_row, b.meta, b.ctl, b.L);
+    }
+    PhaseTimer pt(h, PH_FLOP_FIXUP, s, timed);
+    if (P.g_fixup > 0)
+        hipLaunchKernelGGL((k_flop_fixup<MODE>), dim3(P.g_fixup), dim3(256), 0, s, b.cs, P.n,
+                           b.tile_row, b.meta, b.ctl, b.L);
+}
+
+void launch_sampling(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s, bool timed)
+{
+    PhaseTimer pt(h, PH_SAMPLE, s, timed);
+    if (P.ngroups == 0) return;  // (the bin counters stay 0 from k_init)
+    // count, scan, write: per-group counters instead of device atomics
+    hipLaunchKernelGGL(k_sample_count, dim3((unsigned)P.ngroups), dim3(kSampleThreads), 0, s, b.cs,
+                       P.n, b.samp);
+    hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(kScanThreads), 0, s, b.samp, P.ngroups, b.cs,
+                       b.ctl);
+    hipLaunchKernelGGL(k_sample_write, dim3((unsigned)P.ngroups), dim3(kSampleThreads), 0, s, b.cs,
+                       P.n, (const SampleCounts*)b.samp, b.L);
+}
+
+// Symbolic kernels over the four bins, the merge of split rows and the
+// per-case finalize (sizes of the lists are device-side; the grids are upper
+// bounds and every kernel walks its list grid-stride or by work queue).
+template <int MODE>
+void launch_symbolic(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s, bool timed)
 {
     const int cus = h->num_cus;
-    const int64_t nitems = L.cap13;
-    PhaseTimer pt_bins(h, PH_SYM_BINS, s);
-    // bins 1..3: a grid of the resident capacity (rows are walked grid-stride;
-    // more rows in flight hide the latency of each row's chain of loads)
-    hipLaunchKernelGGL((k_sym<kBin1Team, kBin1Words, MODE>),
-                       dim3(grid_for(nitems, resident(k_sym<kBin1Team, kBin1Words, MODE>, kBin1Team, cus))),
-                       dim3(kBin1Team), 0, s, A, B, b.L.b1, &b.ctl->bin_cnt[1], b.ctl->zacc, out);
-    hipLaunchKernelGGL((k_sym<kBin2Team, kBin2Words, MODE>),
-                       dim3(grid_for(nitems, resident(k_sym<kBin2Team, kBin2Words, MODE>, kBin2Team, cus))),
-                       dim3(kBin2Team), 0, s, A, B, b.L.b2, &b.ctl->bin_cnt[2], b.ctl->zacc, out);
-    hipLaunchKernelGGL((k_sym<kBin3Team, kBin3Words, MODE>),
-                       dim3(grid_for(nitems, resident(k_sym<kBin3Team, kBin3Words, MODE>, kBin3Team, cus))),
-                       dim3(kBin3Team), 0, s, A, B, b.L.b3, &b.ctl->bin_cnt[3], b.ctl->zacc, out);
-    pt_bins.stop();
-    const size_t lds = (size_t)b.L.win_words * sizeof(uint32_t);
-    // one window holding all N columns: the kernel skips the window tests
-    const bool win1 = b.L.nwin == 1;
-    static bool attr_set[2][2] = {{false, false}, {false, false}};
-    static int big_resident[2][2] = {{0, 0}, {0, 0}};
-    auto kfun = win1 ? k_sym_big<MODE, true> : k_sym_big<MODE, false>;
-    if (!attr_set[MODE][win1]) {
-        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(kfun),
-                                  hipFuncAttributeMaxDynamicSharedMemorySize,
-                                  (int)(kWinWords * sizeof(uint32_t)));
-        attr_set[MODE][win1] = true;
+    const int64_t nitems = P.cap13;
+    {
+        // bins 1..3: a grid of the resident capacity (more rows in flight hide
+        // the latency of each row's chain of loads)
+        PhaseTimer pt(h, PH_SYM_BINS, s, timed);
+        hipLaunchKernelGGL((k_sym<kBin1Team, kBin1Words, MODE>),
+                           dim3(grid_for(nitems, resident(k_sym<kBin1Team, kBin1Words, MODE>, kBin1Team, cus))),
+                           dim3(kBin1Team), 0, s, b.cs, b.L.b1, &b.ctl->bin_cnt[1], b.cr);
+        hipLaunchKernelGGL((k_sym<kBin2Team, kBin2Words, MODE>),
+                           dim3(grid_for(nitems, resident(k_sym<kBin2Team, kBin2Words, MODE>, kBin2Team, cus))),
+                           dim3(kBin2Team), 0, s, b.cs, b.L.b2, &b.ctl->bin_cnt[2], b.cr);
+        hipLaunchKernelGGL((k_sym<kBin3Team, kBin3Words, MODE>),
+                           dim3(grid_for(nitems, resident(k_sym<kBin3Team, kBin3Words, MODE>, kBin3Team, cus))),
+                           dim3(kBin3Team), 0, s, b.cs, b.L.b3, &b.ctl->bin_cnt[3], b.cr);
     }
-    if (big_resident[MODE][win1] == 0) {
-        int per_cu = 0;
-        if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfun, kBin4Team,
-                                                         kWinWords * sizeof(uint32_t)) != hipSuccess ||
-            per_cu < 1)
-            per_cu = 1;
-        big_resident[MODE][win1] = per_cu;
+    // one window holding all N columns in every case: no window tests
+    auto kfun = P.win1 ? k_sym_big<MODE, true> : k_sym_big<MODE, false>;
+    const size_t lds = (size_t)P.win_words_max * sizeof(uint32_t);
+    {
+        PhaseTimer pt(h, PH_SYM_LONG, s, timed);
+        hipLaunchKernelGGL(kfun,
+                           dim3(grid_for(P.cap4, resident(kfun, kBin4Team, cus, kWinWords * sizeof(uint32_t)))),
+                           dim3(kBin4Team), lds, s, b.cs, b.L.b4, &b.ctl->bin_cnt[4],
+                           &b.ctl->big_next, b.L, b.cr);
     }
     {
-        PhaseTimer pt(h, PH_SYM_LONG, s);
-        hipLaunchKernelGGL(kfun, dim3(grid_for(L.cap4, (int64_t)big_resident[MODE][win1] * cus)),
-                           dim3(kBin4Team), lds, s, A, B, b.L.b4, &b.ctl->bin_cnt[4],
-                           &b.ctl->big_next, b.L, b.ctl->zacc, out);
+        PhaseTimer pt(h, PH_SYM_MERGE, s, timed);
+        hipLaunchKernelGGL((k_sym_merge<MODE>), dim3((unsigned)(2 * cus)), dim3(256), 0, s, b.cs,
+                           b.L.merge, &b.ctl->bin_cnt[5], b.L, b.cr);
     }
-    {
-        PhaseTimer pt(h, PH_SYM_MERGE, s);
-        hipLaunchKernelGGL((k_sym_merge<MODE>), dim3((unsigned)(2 * cus)), dim3(256), 0, s,
-                           b.L.merge, &b.ctl->bin_cnt[5], b.L, B.ncols, b.ctl->zacc, out);
+    PhaseTimer pt(h, PH_FINALIZE, s, timed);
+    hipLaunchKernelGGL((k_finalize<MODE>), dim3(grid_for(P.n, 1024)), dim3(kAccSlots), 0, s, b.cs,
+                       b.cr, P.n);
+}
+
+// Sets the long-row kernel's dynamic LDS limit once (before any capture).
+void prepare_kernels()
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const int bytes = (int)(kWinWords * sizeof(uint32_t));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sym_big<0, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sym_big<0, false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sym_big<1, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_sym_big<1, false>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    });
+}
+
+// The whole launch sequence of a call.  `table_on_device`: the case table is
+// already in the workspace (batches, graphs); otherwise (at most kArgCases
+// cases) k_init_args writes it from its kernel arguments.
+ssp_status launch_plan(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
+                       bool table_on_device, bool timed)
+{
+    if (table_on_device) {
+        hipLaunchKernelGGL(k_init, dim3(grid_for(P.n, 1024)), dim3(64), 0, s, b.ctl, b.cs, b.cr, P.n);
+    } else {
+        CaseArgs args;
+        std::memset(&args, 0, sizeof(args));
+        for (int c = 0; c < P.n; ++c) args.d[c] = P.cs[c];
+        hipLaunchKernelGGL(k_init_args, dim3(P.n), dim3(64), 0, s, b.ctl, b.cs, b.cr, args);
     }
-    PhaseTimer pt_fin(h, PH_FINALIZE, s);
-    hipLaunchKernelGGL((k_finalize<MODE>), dim3(1), dim3(kAccSlots), 0, s, b.ctl, st);
+    SSP_LAUNCHED(h);
+    if (P.kind == PLAN_EXACT) {
+        launch_flop<FLOP_EXACT_BIN>(h, P, b, s, timed);
+        launch_symbolic<1>(h, P, b, s, timed);
+        SSP_LAUNCHED(h);
+        return SSP_OK;
+    }
+    launch_flop<FLOP_ONLY>(h, P, b, s, timed);
+    launch_sampling(h, P, b, s, timed);
+    launch_symbolic<0>(h, P, b, s, timed);
+    if (P.kind == PLAN_PREDICT) {
+        PhaseTimer pt(h, PH_PRED_ROWS, s, timed);
+        if (P.g_rows > 0)
+            hipLaunchKernelGGL(k_pred_rows, dim3(P.g_rows), dim3(kRowsThreads), 0, s, b.cs, P.n,
+                               (const CaseRes*)b.cr);
+    } else {
+        {
+            PhaseTimer pt(h, PH_FINALIZE, s, timed);
+            hipLaunchKernelGGL(k_finalize_reference, dim3((unsigned)((P.n + 63) / 64)), dim3(64), 0,
+                               s, (const CaseDesc*)b.cs, b.cr, P.n);
+        }
+        PhaseTimer pt(h, PH_REF_ROWS, s, timed);
+        if (P.g_rows > 0)
+            hipLaunchKernelGGL(k_ref_rows, dim3(P.g_rows), dim3(kRowsThreads), 0, s, b.cs, P.n,
+                               (const CaseRes*)b.cr);
+    }
     SSP_LAUNCHED(h);
     return SSP_OK;
 }
 
-FlopArgs flop_args(const ssp_csr* A, const ssp_csr* B, const Bound& b, const Layout& L,
-                   int64_t* out, ssp_stats* st)
+// Copies a batch's case table to the workspace through the handle's pinned
+// staging buffer (reused once the previous copy from it has completed).
+ssp_status stage_table(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s)
 {
-    FlopArgs fa;
-    fa.A = to_csr(A);
-    fa.B = to_csr(B);
-    fa.out = out;
-    fa.st = st;
-    fa.ctl = b.ctl;
-    fa.L = b.L;
-    fa.tile_row = b.tile_row;
-    fa.meta = b.meta;
-    fa.ntiles = L.ntiles;
-    return fa;
-}
-
-// Merge-path tile starts and the streaming pass that leaves every row's
-// product count in rf and F in st (mode FLOP_ONLY), or bins every row for the
-// exact count (FLOP_EXACT_BIN).
-template <int MODE>
-ssp_status flop_pass(ssp_handle h, const ssp_csr* A, const ssp_csr* B, const Bound& b,
-                     const Layout& L, int64_t* out, ssp_stats* st, hipStream_t s)
-{
-    const int64_t M = A->nrows;
-    {
-        PhaseTimer pt(h, PH_TILES, s);
-        hipLaunchKernelGGL(k_tiles, dim3(grid_for((M + 255) / 256, 16LL * h->num_cus)), dim3(256),
-                           0, s, to_csr(A), L.ntiles, b.tile_row);
+    const size_t bytes = (size_t)P.n * sizeof(CaseDesc);
+    if (!h->pin_ev) SSP_HIP(h, hipEventCreateWithFlags(&h->pin_ev, hipEventDisableTiming));
+    SSP_HIP(h, hipEventSynchronize(h->pin_ev));
+    if (bytes > h->pin_bytes) {
+        if (h->pin) SSP_HIP(h, hipHostFree(h->pin));
+        h->pin = nullptr;
+        h->pin_bytes = 0;
+        SSP_HIP(h, hipHostMalloc(&h->pin, bytes, hipHostMallocDefault));
+        h->pin_bytes = bytes;
     }
-    const FlopArgs fa = flop_args(A, B, b, L, out, st);
-    const bool vec = (reinterpret_cast<uintptr_t>(A->col) & 15u) == 0 && A->nnz >= 4;
-    launch_flop<MODE>(h, fa, vec, s);
-    SSP_LAUNCHED(h);
+    std::memcpy(h->pin, P.cs.data(), bytes);
+    SSP_HIP(h, hipMemcpyAsync(b.cs, h->pin, bytes, hipMemcpyHostToDevice, s));
+    SSP_HIP(h, hipEventRecord(h->pin_ev, s));
     return SSP_OK;
 }
 
-// The sampled part: row FLOP of every row into rf, sampling and binning,
-// distinct counting of the sampled rows.  Leaves F, n_s, f*, z* in *st and
-// the divisor of f* in ctl.
-ssp_status sampled_part(ssp_handle h, const ssp_csr* A, const ssp_csr* B, ssp_sampler sampler,
-                        double rate, uint64_t seed, const Bound& b, const Layout& L,
-                        int64_t* rf, ssp_stats* st, hipStream_t s)
+// Plan, workspace, launches: the common body of every compute entry point.
+ssp_status run_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind, hipStream_t s)
 {
-    ssp_status e = flop_pass<FLOP_ONLY>(h, A, B, b, L, rf, st, s);
-    if (e != SSP_OK) return e;
-    const Csr a = to_csr(A), bb = to_csr(B);
-    const int64_t M = A->nrows;
-    {
-        PhaseTimer pt(h, PH_SAMPLE, s);
-        const bool paper = sampler == SSP_SAMPLER_PAPER;
-        const int64_t nc = paper ? paper_sample_num(M) : M;
-        const uint64_t thr = paper ? 0 : rate_threshold(rate);
-        // count, scan, write: per-group counters instead of device atomics
-        const unsigned grid = grid_for((nc + 2047) / 2048, kSampleGroups);
-        const int64_t* rfc = rf;
-        if (paper)
-            hipLaunchKernelGGL((k_sample_count<true>), dim3(grid), dim3(kSampleThreads), 0, s, a,
-                               rfc, seed, thr, nc, b.L, b.samp);
-        else
-            hipLaunchKernelGGL((k_sample_count<false>), dim3(grid), dim3(kSampleThreads), 0, s, a,
-                               rfc, seed, thr, nc, b.L, b.samp);
-        hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(kScanThreads), 0, s, b.samp, (int)grid,
-                           b.ctl, st);
-        if (paper)
-            hipLaunchKernelGGL((k_sample_write<true>), dim3(grid), dim3(kSampleThreads), 0, s, a,
-                               rfc, seed, thr, nc, B->ncols, (const SampleCounts*)b.samp, b.L);
-        else
-            hipLaunchKernelGGL((k_sample_write<false>), dim3(grid), dim3(kSampleThreads), 0, s, a,
-                               rfc, seed, thr, nc, B->ncols, (const SampleCounts*)b.samp, b.L);
-    }
-    SSP_LAUNCHED(h);
-    return launch_symbolic<0>(h, a, bb, b, L, st, nullptr, s);
+    prepare_kernels();
+    Plan P = make_plan(h, in, kind);
+    ssp_status st = ensure_workspace(h, P.total);
+    if (st != SSP_OK) return st;
+    const Bound b = bind_plan(P, h->ws);
+    const bool small = P.n <= kArgCases;
+    if (!small && (st = stage_table(h, P, b, s)) != SSP_OK) return st;
+    return launch_plan(h, P, b, s, !small, true);
 }
 
-// Few large workgroups for the per-row outputs: each adds its part of the
-// output total with one same-address atomic.
-unsigned rows_grid(ssp_handle h, int64_t M)
+CaseIn case_in(const ssp_csr* A, const ssp_csr* B, ssp_sampler sampler, double rate,
+               uint64_t seed, int64_t* out, int64_t* rf, ssp_stats* st)
 {
-    return grid_for((M + 4 * kRowsThreads - 1) / (4 * kRowsThreads), h->num_cus / 2);
+    CaseIn x;
+    x.A = to_csr(A);
+    x.B = to_csr(B);
+    x.sampler = sampler;
+    x.rate = rate;
+    x.seed = seed;
+    x.out = out;
+    x.rf = rf;
+    x.st = st;
+    return x;
 }
 
 ssp_status common_checks(ssp_handle h, const ssp_csr* A, const ssp_csr* B, ssp_sampler sampler,
@@ -524,6 +718,9 @@ ssp_status ssp_destroy(ssp_handle h)
         h->event_pool.push_back(p.b);
     }
     for (hipEvent_t e : h->event_pool) (void)hipEventDestroy(e);
+    if (h->pin_ev) (void)hipEventSynchronize(h->pin_ev);
+    if (h->pin) (void)hipHostFree(h->pin);
+    if (h->pin_ev) (void)hipEventDestroy(h->pin_ev);
     delete h;
     return st;
 }
@@ -570,29 +767,12 @@ ssp_status ssp_predict_structure_ex(ssp_handle h, const ssp_csr* A, const ssp_cs
                                     int64_t* nnz_pred, int64_t* row_flop, ssp_stats* stats,
                                     void* stream)
 {
-    ssp_status s = common_checks(h, A, B, sampler, rate, nnz_pred);
+    const ssp_status s = common_checks(h, A, B, sampler, rate, nnz_pred);
     if (s != SSP_OK) return s;
     DeviceGuard g(h->device);
     if (!g.ok()) return SSP_ERR_NO_DEVICE;
-    const int64_t M = A->nrows;
-    const int64_t nitems = sampler == SSP_SAMPLER_PAPER ? paper_sample_num(M) : M;
-    const Layout L = make_layout(nitems, M, A->nnz, row_flop == nullptr);
-    if ((s = ensure_workspace(h, L.total)) != SSP_OK) return s;
-    const Bound b = bind(h, L, B->ncols);
-    hipStream_t hs = static_cast<hipStream_t>(stream);
-    ssp_stats* st = stats ? stats : &b.ctl->stats;
-    int64_t* rf = row_flop ? row_flop : b.rowtmp;
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, hs, b.ctl, st, (uint64_t)M);
-    SSP_LAUNCHED(h);
-    if (M == 0) return SSP_OK;
-    if ((s = sampled_part(h, A, B, sampler, rate, seed, b, L, rf, st, hs)) != SSP_OK) return s;
-    {
-        PhaseTimer pt(h, PH_PRED_ROWS, hs);
-        hipLaunchKernelGGL(k_pred_rows, dim3(rows_grid(h, M)), dim3(kRowsThreads), 0, hs,
-                           (const int64_t*)rf, nnz_pred, M, b.ctl, st);
-    }
-    SSP_LAUNCHED(h);
-    return SSP_OK;
+    return run_plan(h, {case_in(A, B, sampler, rate, seed, nnz_pred, row_flop, stats)},
+                    PLAN_PREDICT, static_cast<hipStream_t>(stream));
 }
 
 ssp_status ssp_predict_structure(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
@@ -607,56 +787,139 @@ ssp_status ssp_reference_estimate(ssp_handle h, const ssp_csr* A, const ssp_csr*
                                   ssp_sampler sampler, double rate, uint64_t seed,
                                   int64_t* nnz_ref, ssp_stats* stats, void* stream)
 {
-    ssp_status s = common_checks(h, A, B, sampler, rate, nnz_ref);
+    const ssp_status s = common_checks(h, A, B, sampler, rate, nnz_ref);
     if (s != SSP_OK) return s;
     DeviceGuard g(h->device);
     if (!g.ok()) return SSP_ERR_NO_DEVICE;
-    const int64_t M = A->nrows;
-    const int64_t nitems = sampler == SSP_SAMPLER_PAPER ? paper_sample_num(M) : M;
-    const Layout L = make_layout(nitems, M, A->nnz, true);
-    if ((s = ensure_workspace(h, L.total)) != SSP_OK) return s;
-    const Bound b = bind(h, L, B->ncols);
-    hipStream_t hs = static_cast<hipStream_t>(stream);
-    ssp_stats* st = stats ? stats : &b.ctl->stats;
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, hs, b.ctl, st, (uint64_t)M);
-    SSP_LAUNCHED(h);
-    if (M == 0) return SSP_OK;
-    if ((s = sampled_part(h, A, B, sampler, rate, seed, b, L, b.rowtmp, st, hs)) != SSP_OK)
-        return s;
-    {
-        PhaseTimer pt(h, PH_FINALIZE, hs);
-        hipLaunchKernelGGL(k_finalize_reference, dim3(1), dim3(64), 0, hs, b.ctl, st,
-                           (uint64_t)M);
-    }
-    {
-        PhaseTimer pt(h, PH_REF_ROWS, hs);
-        hipLaunchKernelGGL(k_ref_rows, dim3(rows_grid(h, M)), dim3(kRowsThreads), 0, hs,
-                           (const int64_t*)b.rowtmp, nnz_ref, M, b.ctl, st);
-    }
-    SSP_LAUNCHED(h);
-    return SSP_OK;
+    return run_plan(h, {case_in(A, B, sampler, rate, seed, nnz_ref, nullptr, stats)},
+                    PLAN_REFERENCE, static_cast<hipStream_t>(stream));
 }
 
 ssp_status ssp_exact_structure(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
                                int64_t* nnz_exact, ssp_stats* stats, void* stream)
 {
-    ssp_status s = common_checks(h, A, B, SSP_SAMPLER_BERNOULLI, 0.0, nnz_exact);
+    const ssp_status s = common_checks(h, A, B, SSP_SAMPLER_BERNOULLI, 0.0, nnz_exact);
     if (s != SSP_OK) return s;
     DeviceGuard g(h->device);
     if (!g.ok()) return SSP_ERR_NO_DEVICE;
-    const int64_t M = A->nrows;
-    const Layout L = make_layout(M, M, A->nnz, false);
-    if ((s = ensure_workspace(h, L.total)) != SSP_OK) return s;
-    const Bound b = bind(h, L, B->ncols);
-    hipStream_t hs = static_cast<hipStream_t>(stream);
-    ssp_stats* st = stats ? stats : &b.ctl->stats;
-    hipLaunchKernelGGL(k_init, dim3(1), dim3(64), 0, hs, b.ctl, st, (uint64_t)M);
-    SSP_LAUNCHED(h);
-    if (M == 0) return SSP_OK;
-    if ((s = flop_pass<FLOP_EXACT_BIN>(h, A, B, b, L, nnz_exact, st, hs)) != SSP_OK) return s;
-    if ((s = launch_symbolic<1>(h, to_csr(A), to_csr(B), b, L, st, nnz_exact, hs)) != SSP_OK)
-        return s;
+    return run_plan(h, {case_in(A, B, SSP_SAMPLER_BERNOULLI, 0.0, 0, nnz_exact, nullptr, stats)},
+                    PLAN_EXACT, static_cast<hipStream_t>(stream));
+}
+
+namespace {
+ssp_status batch_inputs(ssp_handle h, int n, const ssp_case* cases, std::vector<CaseIn>& in)
+{
+    if (!h || n < 0 || (n > 0 && !cases)) return SSP_ERR_INVALID_ARG;
+    in.clear();
+    in.reserve((size_t)n);
+    for (int i = 0; i < n; ++i) {
+        const ssp_case& c = cases[i];
+        const ssp_sampler smp = (ssp_sampler)c.sampler;
+        const ssp_status s = common_checks(h, &c.A, &c.B, smp, c.sample_rate, c.nnz_pred);
+        if (s != SSP_OK) return s;
+        in.push_back(case_in(&c.A, &c.B, smp, c.sample_rate, c.seed, c.nnz_pred, c.row_flop,
+                             c.stats));
+    }
     return SSP_OK;
+}
+} // namespace
+
+ssp_status ssp_predict_batch(ssp_handle h, int n, const ssp_case* cases, void* stream)
+{
+    std::vector<CaseIn> in;
+    const ssp_status s = batch_inputs(h, n, cases, in);
+    if (s != SSP_OK) return s;
+    if (n == 0) return SSP_OK;
+    DeviceGuard g(h->device);
+    if (!g.ok()) return SSP_ERR_NO_DEVICE;
+    return run_plan(h, in, PLAN_PREDICT, static_cast<hipStream_t>(stream));
+}
+
+ssp_status ssp_batch_graph_create(ssp_handle h, int n, const ssp_case* cases,
+                                  ssp_batch_graph* out)
+{
+    if (!out) return SSP_ERR_INVALID_ARG;
+    *out = nullptr;
+    std::vector<CaseIn> in;
+    ssp_status s = batch_inputs(h, n, cases, in);
+    if (s != SSP_OK) return s;
+    if (n == 0) return SSP_ERR_INVALID_ARG;
+    DeviceGuard g(h->device);
+    if (!g.ok()) return SSP_ERR_NO_DEVICE;
+    prepare_kernels();
+    Plan P = make_plan(h, in, PLAN_PREDICT);
+    if (h->budget && P.total > h->budget) {
+        h->last_error = "graph workspace of " + std::to_string(P.total) +
+                        " bytes exceeds the budget of " + std::to_string(h->budget);
+        return SSP_ERR_BUDGET;
+    }
+    ssp_batch_graph_s* G = new (std::nothrow) ssp_batch_graph_s();
+    if (!G) return SSP_ERR_OOM;
+    G->h = h;
+    G->device = h->device;
+    G->n = n;
+    auto fail = [&](ssp_status st) {
+        if (G->exec) (void)hipGraphExecDestroy(G->exec);
+        if (G->graph) (void)hipGraphDestroy(G->graph);
+        if (G->ws) (void)hipFree(G->ws);
+        delete G;
+        return st;
+    };
+    hipError_t e = hipMalloc(&G->ws, P.total);
+    G->ws_bytes = P.total;
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        h->last_error = std::string("hipMalloc: ") + hipGetErrorString(e);
+        G->ws = nullptr;
+        return fail(SSP_ERR_OOM);
+    }
+    const Bound b = bind_plan(P, G->ws);
+    e = hipMemcpy(b.cs, P.cs.data(), (size_t)n * sizeof(CaseDesc), hipMemcpyHostToDevice);
+    if (e != hipSuccess) return fail(hip_fail(h, e, "hipMemcpy case table"));
+    hipStream_t cap = nullptr;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e != hipSuccess) return fail(hip_fail(h, e, "hipStreamCreate"));
+    e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e != hipSuccess) {
+        (void)hipStreamDestroy(cap);
+        return fail(hip_fail(h, e, "hipStreamBeginCapture"));
+    }
+    s = launch_plan(h, P, b, cap, true, false);
+    hipGraph_t graph = nullptr;
+    e = hipStreamEndCapture(cap, &graph);
+    (void)hipStreamDestroy(cap);
+    G->graph = graph;
+    if (s != SSP_OK) return fail(s);
+    if (e != hipSuccess) return fail(hip_fail(h, e, "hipStreamEndCapture"));
+    e = hipGraphInstantiate(&G->exec, G->graph, nullptr, nullptr, 0);
+    if (e != hipSuccess) return fail(hip_fail(h, e, "hipGraphInstantiate"));
+    *out = G;
+    return SSP_OK;
+}
+
+ssp_status ssp_batch_graph_launch(ssp_batch_graph g, void* stream)
+{
+    if (!g || !g->exec) return SSP_ERR_INVALID_ARG;
+    DeviceGuard dg(g->device);
+    if (!dg.ok()) return SSP_ERR_NO_DEVICE;
+    const hipError_t e = hipGraphLaunch(g->exec, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(g->h, e, "hipGraphLaunch");
+    return SSP_OK;
+}
+
+size_t ssp_batch_graph_workspace_bytes(ssp_batch_graph g) { return g ? g->ws_bytes : 0; }
+
+ssp_status ssp_batch_graph_destroy(ssp_batch_graph g)
+{
+    if (!g) return SSP_ERR_INVALID_ARG;
+    DeviceGuard dg(g->device);
+    ssp_status st = SSP_OK;
+    if (hipDeviceSynchronize() != hipSuccess) st = SSP_ERR_HIP;
+    if (g->exec) (void)hipGraphExecDestroy(g->exec);
+    if (g->graph) (void)hipGraphDestroy(g->graph);
+    if (g->ws && hipFree(g->ws) != hipSuccess) st = SSP_ERR_HIP;
+    delete g;
+    return st;
 }
 
 ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* m, int64_t* n_bad, void* stream)
