@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
-WORKLOADS = ("rmat20", "uniform4096", "stencil128", "stencil128_x_uniform")
+WORKLOADS = ("rmat20", "uniform4096", "stencil128", "stencil128_x_uniform", "sweep")
 
 
 def parse():
@@ -110,6 +110,86 @@ def long_row_mask(rf_s, ncols: int):
     return rf_s > lim
 
 
+def sweep_compare(ssp, params, reps: int = 3):
+    """Plain (one call per matrix, back to back on one stream) vs batched (one
+    ssp_predict_batch) vs graph (one launch of a captured batch) over the given
+    sweep cases; the three outputs are checked equal.  Times in ms: minimum
+    over `reps` timed runs after one warm-up."""
+    import torch
+    import workloads
+    t0 = time.time()
+    hosts = [workloads.sweep_workload(p) for p in params]
+    t_gen = time.time() - t0
+    dev = "cuda:0"
+    h = ssp.default_handle(dev)
+    devA = [ssp.DeviceCSR.from_csr(w.A, dev) for w in hosts]
+    mk = lambda: [ssp.Case(A, A, w.rate, w.seed) for A, w in zip(devA, hosts)]  # noqa: E731
+    plain, batch, graphc = mk(), mk(), mk()
+    g = ssp.BatchGraph(graphc, handle=h)
+
+    def run_plain():
+        for c in plain:
+            ssp.predict_structure(c.A, c.B, c.sample_rate, c.seed, handle=h, out=c.pred,
+                                  stats=c.stats)
+
+    runs = {"plain": run_plain, "batched": lambda: ssp.predict_batch(batch, handle=h),
+            "graph": g.launch}
+    ms = {}
+    for name, fn in runs.items():
+        fn()
+        torch.cuda.synchronize()
+        best = None
+        for _ in range(reps):
+            ta = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            dt = (time.perf_counter() - ta) * 1e3
+            best = dt if best is None else min(best, dt)
+        ms[name] = best
+    same = all(torch.equal(a.pred, b.pred) and torch.equal(a.pred, c.pred) and
+               torch.equal(a.stats, b.stats) and torch.equal(a.stats, c.stats)
+               for a, b, c in zip(plain, batch, graphc))
+    rows = sum(w.A.nrows for w in hosts)
+    nnz = sum(w.A.nnz for w in hosts)
+    stream_bytes = sum(4 * (w.A.nrows + 1) + 4 * w.A.nnz + 8 * w.A.nrows for w in hosts)
+    sym_bytes = 0
+    for c in batch:
+        st = ssp.read_stats(c.stats)
+        sym_bytes += 8 * st["n_sampled"] + 12 * st["a_sample_nnz"] + 4 * st["sample_flop"]
+    out = {"cases": len(hosts), "rows": rows, "nnz": nnz, "generate_s": round(t_gen, 1),
+           "graph_workspace_bytes": g.workspace_bytes, "outputs_identical": bool(same),
+           "algorithmic_bytes": stream_bytes + sym_bytes}
+    for name, t in ms.items():
+        out[f"{name}_ms"] = round(t, 3)
+        out[f"{name}_rows_per_s"] = round(rows / (t * 1e-3), 1)
+    out["speedup_batched_vs_plain"] = round(ms["plain"] / ms["batched"], 2)
+    out["speedup_graph_vs_plain"] = round(ms["plain"] / ms["graph"], 2)
+    out["graph_gbps_algorithmic"] = round(out["algorithmic_bytes"] / (ms["graph"] * 1e-3) / 1e9, 1)
+    g.close()
+    return out
+
+
+def main_sweep(args):
+    import torch
+    import paper_2207_13848_amd as ssp
+    import workloads
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    r = sweep_compare(ssp, workloads.sweep_cases(), reps=max(1, min(args.steps, 5)))
+    t = r["graph_ms"]
+    print(json.dumps({
+        "metric": "predicted rows/s (625-case sweep, one batched graph launch)",
+        "value": r["graph_rows_per_s"], "unit": "rows/s", "n_gpus": 1,
+        "steps": max(1, min(args.steps, 5)), "warmup": 1, "ms_per_step": t,
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "sweep625", "sizes": list(workloads.SWEEP_SIZES),
+                   "degrees": list(workloads.SWEEP_DEGREES), "structures": list(workloads.STRUCTURES),
+                   "seeds": list(workloads.SWEEP_SEEDS), "sample_rate": 0.01},
+        "sweep": r}), flush=True)
+
+
 def get_workload(name: str):
     import workloads
     return getattr(workloads, name)()
@@ -132,6 +212,10 @@ def main():
         print(json.dumps({"error": "this build runs on one GPU only: bench.py --gpus 1 "
                                    "(the multi-GPU sharding is a design note, not built)"}))
         sys.exit(2)
+
+    if args.workload == "sweep":
+        main_sweep(args)
+        return
 
     import numpy as np
     import torch
@@ -285,6 +369,11 @@ def main():
                                                   exact_np[nz])) if nz.any() else None,
         }
         result["predict_vs_exact_time"] = round(ms_per_step / result["exact_ms"], 4)
+
+    if not args.no_extras:
+        # batched vs plain on the small end of the sweep (sizes 2^12, 2^14: 250 cases)
+        import workloads
+        result["batch"] = sweep_compare(ssp, workloads.sweep_cases(sizes=(1 << 12, 1 << 14)))
 
     if not args.no_cpu_baseline:
         import oracle
