@@ -28,7 +28,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
-WORKLOADS = ("rmat20", "uniform4096", "stencil128", "stencil128_x_uniform", "sweep")
+WORKLOADS = ("rmat20", "uniform4096", "stencil128", "stencil128_x_uniform", "sweep", "serve")
 
 
 def parse():
@@ -190,6 +190,107 @@ def main_sweep(args):
         "sweep": r}), flush=True)
 
 
+def main_serve(args):
+    """Serving: Poisson arrivals (2000/s) of A.A predictions over a
+    device-resident pool of 64 matrices (rows 2^U, U ~ Uniform[10, 21],
+    structure uniform over the five generators, d uniform over 2..32, rate 1%),
+    through the continuous-batching server; then a closed-loop burst for the
+    saturation throughput.  A sample of results is checked against the same
+    prediction made alone."""
+    import numpy as np
+    import torch
+    import paper_2207_13848_amd as ssp
+    import workloads
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    rng = np.random.default_rng(8)
+    t0 = time.time()
+    pool = []
+    for k in range(64):
+        n = int(2.0 ** rng.uniform(10, 21))
+        s = workloads.STRUCTURES[int(rng.integers(5))]
+        d = int(rng.integers(2, 33))
+        pool.append(workloads.make(s, n, d, 100 + k))
+    t_gen = time.time() - t0
+    dev = "cuda:0"
+    devs = [ssp.DeviceCSR.from_csr(m, dev) for m in pool]
+    srv = ssp.Server(slots=4, slot_bytes=2 << 30, max_batch=64)
+    ids = [srv.register(d) for d in devs]
+    ring = 256
+    maxrows = max(m.nrows for m in pool)
+    outs = [torch.empty(maxrows, dtype=torch.int64, device=dev) for _ in range(ring)]
+    stats = [torch.zeros(8, dtype=torch.int64, device=dev) for _ in range(ring)]
+    torch.cuda.synchronize()
+
+    def run(n_req, lam):
+        """Submit n_req requests (Poisson at lam/s, or all at once if lam is
+        None); returns the requests and the wall time to the last completion."""
+        arr = np.cumsum(rng.exponential(1.0 / lam, n_req)) if lam else np.zeros(n_req)
+        pick = rng.integers(len(pool), size=n_req)
+        reqs = []
+        srv.reset_stats()
+        start = time.perf_counter()
+        for i in range(n_req):
+            if i >= ring:
+                srv.wait(reqs[i - ring][0], 600.0)  # the ring slot is reused
+            while time.perf_counter() - start < arr[i]:
+                pass
+            j = int(pick[i])
+            o = outs[i % ring][:pool[j].nrows]
+            t = srv.submit(ids[j], ids[j], 0.01, 5000 + i, o, stats[i % ring])
+            reqs.append((t, j, 5000 + i, i % ring))
+        for r in reqs:
+            srv.wait(r[0], 600.0)
+        wall = time.perf_counter() - start
+        return reqs, wall, srv.info()
+
+    def check(reqs):
+        ok = 0
+        for t, j, seed, slot in reqs[-min(len(reqs), 24):]:
+            p, _, st = ssp.predict_structure(devs[j], devs[j], 0.01, seed)
+            torch.cuda.synchronize()
+            ok += int(torch.equal(p, outs[slot][:pool[j].nrows]) and torch.equal(st, stats[slot]))
+        return ok, min(len(reqs), 24)
+
+    warm, _, _ = run(200, None)
+    duration = 5.0
+    lam = 2000.0
+    reqs, wall, info = run(int(lam * duration), lam)
+    ok, nchk = check(reqs)
+    rows = sum(pool[r[1]].nrows for r in reqs)
+    sat_reqs, sat_wall, sat_info = run(4000, None)
+    sat_rows = sum(pool[r[1]].nrows for r in sat_reqs)
+    srv.close()
+    print(json.dumps({
+        "metric": "served requests/s with p50/p99 latency (Poisson 2000/s, continuous batching)",
+        "value": round(len(reqs) / wall, 1), "unit": "requests/s", "n_gpus": 1,
+        "steps": len(reqs), "warmup": len(warm), "ms_per_step": round(1e3 * wall / len(reqs), 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic",
+        "config": {"workload": "serve_poisson2000", "pool": len(pool),
+                   "pool_rows_mean": float(np.mean([m.nrows for m in pool])),
+                   "pool_nnz_total": int(sum(m.nnz for m in pool)), "sample_rate": 0.01,
+                   "slots": 4, "slot_bytes": 2 << 30, "max_batch": 64, "duration_s": duration},
+        "open_loop": {"offered_per_s": lam, "requests": len(reqs), "wall_s": round(wall, 3),
+                      "rows_per_s": round(rows / wall, 1),
+                      "latency_p50_ms": round(info["latency_p50_ms"], 3),
+                      "latency_p99_ms": round(info["latency_p99_ms"], 3),
+                      "latency_mean_ms": round(info["latency_mean_ms"], 3),
+                      "latency_max_ms": round(info["latency_max_ms"], 3),
+                      "batches": info["batches"], "max_batch_seen": info["max_batch_seen"],
+                      "max_slots_busy": info["max_slots_busy"]},
+        "saturation": {"requests": len(sat_reqs), "wall_s": round(sat_wall, 3),
+                       "requests_per_s": round(len(sat_reqs) / sat_wall, 1),
+                       "rows_per_s": round(sat_rows / sat_wall, 1),
+                       "latency_p50_ms": round(sat_info["latency_p50_ms"], 3),
+                       "latency_p99_ms": round(sat_info["latency_p99_ms"], 3),
+                       "batches": sat_info["batches"],
+                       "max_batch_seen": sat_info["max_batch_seen"],
+                       "max_slots_busy": sat_info["max_slots_busy"]},
+        "results_equal_alone": f"{ok}/{nchk}", "generate_s": round(t_gen, 1)}), flush=True)
+
+
 def get_workload(name: str):
     import workloads
     return getattr(workloads, name)()
@@ -215,6 +316,9 @@ def main():
 
     if args.workload == "sweep":
         main_sweep(args)
+        return
+    if args.workload == "serve":
+        main_serve(args)
         return
 
     import numpy as np

@@ -218,6 +218,66 @@ SSP_API ssp_status ssp_batch_graph_launch(ssp_batch_graph graph, void* stream);
 SSP_API size_t ssp_batch_graph_workspace_bytes(ssp_batch_graph graph);
 SSP_API ssp_status ssp_batch_graph_destroy(ssp_batch_graph graph);
 
+/* ----------------------------------------------------------- serving */
+
+/*
+ * A request server with continuous batching over device-resident matrices.
+ * A worker thread owns `nslots` slots (a stream, a workspace of slot_bytes
+ * and a pinned staging buffer each; nslots * slot_bytes is allocated at
+ * creation and counts against the handle's HBM budget).  Submitted requests
+ * queue in arrival order; whenever a slot is free the worker admits the
+ * oldest requests whose workspaces fit the slot together (at most max_batch)
+ * and launches them as one batch (ssp_predict_batch semantics) on the slot's
+ * stream, so batches on different slots overlap on the device and requests
+ * arriving meanwhile join the next free slot.  A request's result is
+ * bit-identical to ssp_predict_structure_ex on the same inputs, alone or in
+ * any mix.  Latency is the time from submission to the worker seeing the
+ * request's batch complete.
+ *
+ *  create   : slot_bytes 0 = 1 GiB; SSP_ERR_BUDGET beyond the handle's budget.
+ *             The handle must outlive the server (the server uses its device).
+ *  register : keeps a copy of the descriptor; the arrays stay the caller's
+ *             and must stay alive and unchanged while requests use them.
+ *             Returns the matrix id in *id.
+ *  submit   : C = mats[a] . mats[b]; nnz_pred (device int64[nrows of a]) and
+ *             stats (device or NULL) must stay alive until the request is done.
+ *             Host-checkable errors return at once; SSP_ERR_BUDGET if the
+ *             request alone does not fit a slot.  Thread-safe.
+ *  poll     : SSP_OK when done, SSP_ERR_NOT_READY while queued or running,
+ *             the failure status otherwise, SSP_ERR_INVALID_ARG for an
+ *             unknown ticket.
+ *  wait     : as poll, blocking up to timeout_s seconds (< 0: no limit).
+ *  destroy  : finishes every submitted request, then frees the slots.
+ */
+typedef struct ssp_server_s* ssp_server;
+
+typedef struct {
+    int32_t a, b;          /* registered matrix ids: C = A.B               */
+    int32_t sampler;       /* ssp_sampler                                   */
+    int32_t reserved;      /* 0                                             */
+    double sample_rate;
+    uint64_t seed;
+    int64_t* nnz_pred;     /* device int64[rows of a], written              */
+    ssp_stats* stats;      /* device ssp_stats or NULL                      */
+} ssp_request;
+
+typedef struct {
+    uint64_t submitted, completed, batches, max_batch_seen, queued;
+    uint64_t max_slots_busy; /* most slots running batches at once        */
+    double elapsed_s;      /* since creation or the last reset             */
+    double latency_p50_ms, latency_p99_ms, latency_mean_ms, latency_max_ms;
+} ssp_server_stats;
+
+SSP_API ssp_status ssp_server_create(ssp_handle h, int nslots, size_t slot_bytes, int max_batch,
+                                     ssp_server* server);
+SSP_API ssp_status ssp_server_register_matrix(ssp_server s, const ssp_csr* m, int32_t* id);
+SSP_API ssp_status ssp_server_submit(ssp_server s, const ssp_request* r, uint64_t* ticket);
+SSP_API ssp_status ssp_server_poll(ssp_server s, uint64_t ticket);
+SSP_API ssp_status ssp_server_wait(ssp_server s, uint64_t ticket, double timeout_s);
+SSP_API ssp_status ssp_server_info(ssp_server s, ssp_server_stats* out);
+SSP_API ssp_status ssp_server_reset_stats(ssp_server s);
+SSP_API ssp_status ssp_server_destroy(ssp_server s);
+
 /*
  * Explicit CSR check (the compute entry points do not check contents):
  * counts the violations of rpt[0] = 0, rpt[i] <= rpt[i+1], rpt[nrows] = nnz

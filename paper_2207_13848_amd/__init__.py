@@ -281,6 +281,74 @@ class BatchGraph:
             pass
 
 
+class Server:
+    """Request server with continuous batching (ssp_server_*): register device
+    matrices, submit predictions, poll or wait by ticket."""
+
+    def __init__(self, *, handle=None, slots: int = 4, slot_bytes: int = 1 << 30,
+                 max_batch: int = 64, device=None):
+        self.handle = handle or default_handle(device)
+        self._lib = self.handle._lib
+        s = ctypes.c_void_p()
+        self.handle.check(self._lib.ssp_server_create(self.handle.ptr, int(slots), int(slot_bytes),
+                                                      int(max_batch), ctypes.byref(s)),
+                          "ssp_server_create")
+        self.ptr = s
+        self._mats = []  # keep registered matrices alive
+
+    def _check(self, status, where):
+        if status != 0:
+            raise SspError(status, where)
+
+    def register(self, M: DeviceCSR) -> int:
+        i = ctypes.c_int32()
+        c = M._c()
+        self._check(self._lib.ssp_server_register_matrix(self.ptr, ctypes.byref(c), ctypes.byref(i)),
+                    "ssp_server_register_matrix")
+        self._mats.append(M)
+        return int(i.value)
+
+    def submit(self, a: int, b: int, sample_rate: float, seed: int, out, stats=None,
+               sampler="bernoulli") -> int:
+        r = _native.SspRequest(int(a), int(b), _sampler_id(sampler), 0, float(sample_rate),
+                               int(seed) % (1 << 64), out.data_ptr() if out.numel() else 0,
+                               stats.data_ptr() if stats is not None else 0)
+        t = ctypes.c_uint64()
+        self._check(self._lib.ssp_server_submit(self.ptr, ctypes.byref(r), ctypes.byref(t)),
+                    "ssp_server_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int) -> bool:
+        st = self._lib.ssp_server_poll(self.ptr, int(ticket))
+        if st == -10:
+            return False
+        self._check(st, "ssp_server_poll")
+        return True
+
+    def wait(self, ticket: int, timeout: float = -1.0):
+        self._check(self._lib.ssp_server_wait(self.ptr, int(ticket), float(timeout)),
+                    "ssp_server_wait")
+
+    def info(self) -> dict:
+        o = _native.SspServerStats()
+        self._check(self._lib.ssp_server_info(self.ptr, ctypes.byref(o)), "ssp_server_info")
+        return {k: getattr(o, k) for k in _native.SERVER_STATS_FIELDS}
+
+    def reset_stats(self):
+        self._check(self._lib.ssp_server_reset_stats(self.ptr), "ssp_server_reset_stats")
+
+    def close(self):
+        if self.ptr:
+            self._lib.ssp_server_destroy(self.ptr)
+            self.ptr = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
 def validate_csr(M: DeviceCSR, *, handle=None, stream=None) -> int:
     """Number of CSR violations in M (synchronises)."""
     h = handle or default_handle(M.device)

@@ -27,6 +27,8 @@ EXPORTED = (
     "ssp_validate_csr", "ssp_status_string", "ssp_last_error", "ssp_version",
     "ssp_timing_enable", "ssp_timing_read", "ssp_predict_batch", "ssp_batch_graph_create",
     "ssp_batch_graph_launch", "ssp_batch_graph_workspace_bytes", "ssp_batch_graph_destroy",
+    "ssp_server_create", "ssp_server_register_matrix", "ssp_server_submit", "ssp_server_poll",
+    "ssp_server_wait", "ssp_server_info", "ssp_server_reset_stats", "ssp_server_destroy",
 )
 
 
@@ -40,6 +42,23 @@ class SspCase(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("sample_rate", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("nnz_pred", ctypes.c_void_p),
                 ("row_flop", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+
+
+class SspRequest(ctypes.Structure):
+    _fields_ = [("a", ctypes.c_int32), ("b", ctypes.c_int32), ("sampler", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("sample_rate", ctypes.c_double),
+                ("seed", ctypes.c_uint64), ("nnz_pred", ctypes.c_void_p),
+                ("stats", ctypes.c_void_p)]
+
+
+SERVER_STATS_FIELDS = ("submitted", "completed", "batches", "max_batch_seen", "queued",
+                       "max_slots_busy", "elapsed_s", "latency_p50_ms", "latency_p99_ms",
+                       "latency_mean_ms", "latency_max_ms")
+
+
+class SspServerStats(ctypes.Structure):
+    _fields_ = ([(n, ctypes.c_uint64) for n in SERVER_STATS_FIELDS[:6]] +
+                [(n, ctypes.c_double) for n in SERVER_STATS_FIELDS[6:]])
 
 
 STATS_FIELDS = ("total_flop", "n_sampled", "sample_flop", "sample_nnz", "out_sum", "nrows",
@@ -106,6 +125,15 @@ def load():
     lib.ssp_batch_graph_workspace_bytes.argtypes = [vp]
     lib.ssp_batch_graph_workspace_bytes.restype = ctypes.c_size_t
     lib.ssp_batch_graph_destroy.argtypes = [vp]
+    u64 = ctypes.c_uint64
+    lib.ssp_server_create.argtypes = [vp, cint, ctypes.c_size_t, cint, ctypes.POINTER(vp)]
+    lib.ssp_server_register_matrix.argtypes = [vp, csr_p, ctypes.POINTER(ctypes.c_int32)]
+    lib.ssp_server_submit.argtypes = [vp, ctypes.POINTER(SspRequest), ctypes.POINTER(u64)]
+    lib.ssp_server_poll.argtypes = [vp, u64]
+    lib.ssp_server_wait.argtypes = [vp, u64, dbl]
+    lib.ssp_server_info.argtypes = [vp, ctypes.POINTER(SspServerStats)]
+    lib.ssp_server_reset_stats.argtypes = [vp]
+    lib.ssp_server_destroy.argtypes = [vp]
     lib.ssp_version.argtypes = []
     lib.ssp_version.restype = ctypes.c_char_p
     _lib = lib

@@ -939,3 +939,5 @@ ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* m, int64_t* n_bad, void
 }
 
 } // extern "C"
+
+#include "ssp_server.hpp"
