@@ -218,6 +218,55 @@ SSP_API ssp_status ssp_batch_graph_launch(ssp_batch_graph graph, void* stream);
 SSP_API size_t ssp_batch_graph_workspace_bytes(ssp_batch_graph graph);
 SSP_API ssp_status ssp_batch_graph_destroy(ssp_batch_graph graph);
 
+/* ------------------------------------------------------------ tuning */
+
+/*
+ * Launch parameters of the distinct-count stage, per handle (a server copies
+ * its handle's at creation).  Outputs never depend on them (every count is
+ * exact); only speed does.
+ *   bin_max[3]  : rows of up to bin_max[0] products are counted by one
+ *                 wavefront each, up to bin_max[1] by 256 threads, up to
+ *                 bin_max[2] by 512 threads, longer ones by the 1024-thread
+ *                 long-row kernel.  Defaults 128, 1024, 8192.
+ *   hash_mult   : LDS hash tables hold at least hash_mult times a row's
+ *                 distinct bound (2, 4 or 8; default 2).  Limits:
+ *                 bin_max[0..2] * hash_mult <= 256, 2048, 16384.
+ *   long_len    : the long-row kernel walks B rows of at least long_len
+ *                 columns in 256-column units by wavefront, shorter ones
+ *                 flattened over the workgroup (8..1024; default 32).
+ *   big3        : 1 (default): when one 2^20-column bitmap covers all of B's
+ *                 columns but bin 3 would hash, bin-3 rows go to the long-row
+ *                 kernel; 0: never.
+ *   split_target: long rows above this many products are split into parts
+ *                 (2^12..2^40; default 2^17).
+ */
+typedef struct {
+    uint32_t bin_max[3];
+    uint32_t hash_mult;
+    uint32_t long_len;
+    int32_t big3;
+    uint64_t split_target;
+} ssp_tuning;
+
+/* Defaults, current value, and change (SSP_ERR_INVALID_ARG outside the limits). */
+SSP_API void ssp_default_tuning(ssp_tuning* t);
+SSP_API ssp_status ssp_get_tuning(ssp_handle h, ssp_tuning* t);
+SSP_API ssp_status ssp_set_tuning(ssp_handle h, const ssp_tuning* t);
+
+/*
+ * Picks the tuning for a representative batch (n >= 1 cases, as for
+ * ssp_predict_batch) by coordinate descent from the handle's current tuning:
+ * each parameter in turn is tried at a few values, every candidate timed as
+ * the mean of `reps` batch calls (HIP events on `stream`, after a warm-up);
+ * a change is kept when it is at least 2% faster.  Sets the handle's tuning
+ * to the result and returns it in *chosen, with its time and the default
+ * tuning's time in *best_ms and *default_ms (either may be NULL).  The cases'
+ * outputs are written by every trial.  Synchronises with the device.
+ */
+SSP_API ssp_status ssp_autotune(ssp_handle h, int n, const ssp_case* cases, int reps,
+                                ssp_tuning* chosen, double* best_ms, double* default_ms,
+                                void* stream);
+
 /* ----------------------------------------------------------- serving */
 
 /*

@@ -281,6 +281,48 @@ class BatchGraph:
             pass
 
 
+def default_tuning() -> dict:
+    """The library's default tuning (ssp_default_tuning) as a dict."""
+    t = _native.SspTuning()
+    _native.load().ssp_default_tuning(ctypes.byref(t))
+    return t.as_dict()
+
+
+def _tuning_struct(d: dict) -> "_native.SspTuning":
+    t = _native.SspTuning()
+    t.bin_max[:] = [int(x) for x in d["bin_max"]]
+    t.hash_mult, t.long_len, t.big3 = int(d["hash_mult"]), int(d["long_len"]), int(d["big3"])
+    t.split_target = int(d["split_target"])
+    return t
+
+
+def get_tuning(*, handle=None, device=None) -> dict:
+    h = handle or default_handle(device)
+    t = _native.SspTuning()
+    h.check(h._lib.ssp_get_tuning(h.ptr, ctypes.byref(t)), "ssp_get_tuning")
+    return t.as_dict()
+
+
+def set_tuning(tuning: dict, *, handle=None, device=None):
+    h = handle or default_handle(device)
+    t = _tuning_struct(tuning)
+    h.check(h._lib.ssp_set_tuning(h.ptr, ctypes.byref(t)), "ssp_set_tuning")
+
+
+def autotune(cases, *, reps: int = 3, handle=None, stream=None) -> dict:
+    """Tune the handle on a representative batch (ssp_autotune); returns
+    {"tuning": ..., "best_ms": ..., "default_ms": ...}."""
+    cases = list(cases)
+    h = handle or default_handle(cases[0].A.device)
+    arr = _case_array(cases)
+    t = _native.SspTuning()
+    best, dflt = ctypes.c_double(), ctypes.c_double()
+    h.check(h._lib.ssp_autotune(h.ptr, len(cases), arr, int(reps), ctypes.byref(t),
+                                ctypes.byref(best), ctypes.byref(dflt), _stream_ptr(stream)),
+            "ssp_autotune")
+    return {"tuning": t.as_dict(), "best_ms": best.value, "default_ms": dflt.value}
+
+
 class Server:
     """Request server with continuous batching (ssp_server_*): register device
     matrices, submit predictions, poll or wait by ticket."""

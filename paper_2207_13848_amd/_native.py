@@ -29,6 +29,7 @@ EXPORTED = (
     "ssp_batch_graph_launch", "ssp_batch_graph_workspace_bytes", "ssp_batch_graph_destroy",
     "ssp_server_create", "ssp_server_register_matrix", "ssp_server_submit", "ssp_server_poll",
     "ssp_server_wait", "ssp_server_info", "ssp_server_reset_stats", "ssp_server_destroy",
+    "ssp_default_tuning", "ssp_get_tuning", "ssp_set_tuning", "ssp_autotune",
 )
 
 
@@ -42,6 +43,16 @@ class SspCase(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("sample_rate", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("nnz_pred", ctypes.c_void_p),
                 ("row_flop", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+
+
+class SspTuning(ctypes.Structure):
+    _fields_ = [("bin_max", ctypes.c_uint32 * 3), ("hash_mult", ctypes.c_uint32),
+                ("long_len", ctypes.c_uint32), ("big3", ctypes.c_int32),
+                ("split_target", ctypes.c_uint64)]
+
+    def as_dict(self) -> dict:
+        return {"bin_max": list(self.bin_max), "hash_mult": self.hash_mult,
+                "long_len": self.long_len, "big3": self.big3, "split_target": self.split_target}
 
 
 class SspRequest(ctypes.Structure):
@@ -134,6 +145,13 @@ def load():
     lib.ssp_server_info.argtypes = [vp, ctypes.POINTER(SspServerStats)]
     lib.ssp_server_reset_stats.argtypes = [vp]
     lib.ssp_server_destroy.argtypes = [vp]
+    tun_p = ctypes.POINTER(SspTuning)
+    lib.ssp_default_tuning.argtypes = [tun_p]
+    lib.ssp_default_tuning.restype = None
+    lib.ssp_get_tuning.argtypes = [vp, tun_p]
+    lib.ssp_set_tuning.argtypes = [vp, tun_p]
+    lib.ssp_autotune.argtypes = [vp, cint, case_p, cint, tun_p, ctypes.POINTER(dbl),
+                                 ctypes.POINTER(dbl), vp]
     lib.ssp_version.argtypes = []
     lib.ssp_version.restype = ctypes.c_char_p
     _lib = lib

@@ -14,13 +14,16 @@ namespace ssp {
 //   bin 4: more                 -> 1024 threads, LDS bitmap per column window;
 //                                  rows above kSplitTarget products are cut into
 //                                  parts whose bitmaps a merge kernel ORs
+// Defaults of the bin limits (tunable, see ssp_tuning); a bin's limit times
+// the hash-table multiplier may not exceed its table (kBin*Words).
 constexpr uint64_t kBin1Max = 128, kBin2Max = 1024, kBin3Max = 8192;
 constexpr int kBin1Words = 256, kBin2Words = 2048, kBin3Words = 16384;
 constexpr int kBin1Team = 64, kBin2Team = 256, kBin3Team = 512, kBin4Team = 1024;
 
 // Bin-4 bitmap window: at most 32768 words = 2^20 columns = 128 KiB of LDS.
 constexpr int kWinWords = 32768;
-constexpr uint64_t kSplitTarget = 1ull << 17; // products per part of a split row
+constexpr uint64_t kSplitTarget = 1ull << 17; // products per part of a split row (default)
+constexpr uint32_t kLongLenDefault = 32;      // B rows walked in units by the long-row kernel
 constexpr int kMaxParts = 64;
 constexpr int kMaxPartWindows = 1024;         // global part bitmaps of kWinWords words
 constexpr int kMaxSplitWindows = 4;           // rows needing more windows are not split
@@ -66,7 +69,12 @@ struct CaseDesc {
     int32_t merge_per_row;  // merge items of one split row
     int32_t paper;       // the paper's fixed-count sampler
     int32_t wg_tiles, wg_flop, wg_fixup, wg_rows;
-    int32_t pad[3];
+    // tuning (the same for every case of a call)
+    uint32_t bin_max[3];    // product limits of bins 1..3
+    uint32_t hash_mult;     // hash tables hold at least hash_mult x the distinct bound
+    uint32_t long_len;      // long-row kernel: B rows of at least this many columns go in units
+    uint32_t pad;
+    uint64_t split_target;  // products per part of a split long row
 };
 
 // Per-case results written by the kernels.

@@ -118,9 +118,9 @@ __global__ __launch_bounds__(64) void k_init_args(Ctl* ctl, CaseDesc* __restrict
 
 // ------------------------------------------------------------- binning
 
-__device__ __forceinline__ int bin_of(uint64_t rf)
+__device__ __forceinline__ int bin_of(uint64_t rf, const uint32_t (&lim)[3])
 {
-    return rf == 0 ? 0 : rf <= kBin1Max ? 1 : rf <= kBin2Max ? 2 : rf <= kBin3Max ? 3 : 4;
+    return rf == 0 ? 0 : rf <= lim[0] ? 1 : rf <= lim[1] ? 2 : rf <= lim[2] ? 3 : 4;
 }
 
 // Bin of a row for the kernels: bin-3 rows go to the long-row kernel when all
@@ -128,7 +128,7 @@ __device__ __forceinline__ int bin_of(uint64_t rf)
 // would hash); the bitmap kernel then counts them far faster.
 __device__ __forceinline__ int bin_route(uint64_t rf, const CaseDesc& cd)
 {
-    const int b = bin_of(rf);
+    const int b = bin_of(rf, cd.bin_max);
     return (b == 3 && cd.big3) ? 4 : b;
 }
 
@@ -166,10 +166,11 @@ __device__ inline void append_big(int32_t row, uint64_t rf, int32_t e0, int32_t 
 {
     const int64_t alen = (int64_t)e1 - e0;
     int32_t nparts = 1, slot = -1;
-    if (rf > kSplitTarget && cd.nwin <= kMaxSplitWindows && alen > 1 &&
+    const uint64_t T = cd.split_target;
+    if (rf > T && cd.nwin <= kMaxSplitWindows && alen > 1 &&
         __hip_atomic_load(&ctl->pw_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
             (uint32_t)kMaxPartWindows) {  // (bounds the counter: it cannot wrap)
-        uint64_t want = (rf + kSplitTarget - 1) / kSplitTarget;
+        uint64_t want = (rf + T - 1) / T;
         if (want > (uint64_t)kMaxParts) want = kMaxParts;
         if (want > (uint64_t)alen) want = (uint64_t)alen;
         const uint32_t need = (uint32_t)want * (uint32_t)cd.nwin;
@@ -277,6 +278,8 @@ struct SamplerArgs {
     uint64_t seed, thresh;
     int64_t ncand;
     int32_t paper, nwin, big3, merge_per_row;
+    uint32_t bin_max[3];
+    uint64_t split_target;
 };
 
 __device__ __forceinline__ SamplerArgs sampler_args(const CaseDesc& cd)
@@ -291,6 +294,10 @@ __device__ __forceinline__ SamplerArgs sampler_args(const CaseDesc& cd)
     a.nwin = cd.nwin;
     a.big3 = cd.big3;
     a.merge_per_row = cd.merge_per_row;
+    a.bin_max[0] = cd.bin_max[0];
+    a.bin_max[1] = cd.bin_max[1];
+    a.bin_max[2] = cd.bin_max[2];
+    a.split_target = cd.split_target;
     return a;
 }
 
@@ -332,11 +339,11 @@ __device__ __forceinline__ SampledRow classify_row(int64_t g, const SamplerArgs&
     r.rf = (uint64_t)a.rf[g];
     r.e0 = a.A.rpt[g];
     r.e1 = a.A.rpt[g + 1];
-    const int b = bin_of(r.rf);
+    const int b = bin_of(r.rf, a.bin_max);
     r.bin = (b == 3 && a.big3) ? 4 : b;
     const int64_t alen = (int64_t)r.e1 - r.e0;
-    if (r.bin == 4 && r.rf > kSplitTarget && a.nwin <= kMaxSplitWindows && alen > 1) {
-        uint64_t want = (r.rf + kSplitTarget - 1) / kSplitTarget;
+    if (r.bin == 4 && r.rf > a.split_target && a.nwin <= kMaxSplitWindows && alen > 1) {
+        uint64_t want = (r.rf + a.split_target - 1) / a.split_target;
         if (want > (uint64_t)kMaxParts) want = kMaxParts;
         if (want > (uint64_t)alen) want = (uint64_t)alen;
         r.want = (uint32_t)want;
@@ -619,7 +626,8 @@ __global__ __launch_bounds__(TEAM) void k_sym(const CaseDesc* __restrict__ cs,
         const int64_t N = B.ncols;
         const uint32_t bound = (uint32_t)((int64_t)item.rf < N ? (int64_t)item.rf : N);
         uint32_t tsize = 64;
-        while (tsize < 2u * bound) tsize <<= 1;
+        const uint32_t mult = cs[zc].hash_mult;
+        while (tsize < mult * bound && tsize < (uint32_t)WORDS) tsize <<= 1;
         const bool bitmap = N <= 32 * (int64_t)tsize;
         const uint32_t words = bitmap ? (uint32_t)((N + 31) / 32) : tsize;
         const int lg = __builtin_ctz(tsize);
@@ -693,7 +701,6 @@ __global__ __launch_bounds__(TEAM) void k_sym(const CaseDesc* __restrict__ cs,
 // flattened (owner by binary search in LDS) and shared out over the whole
 // workgroup.  An unsplit item counts its bits; a part of a split row stores
 // its window bitmap to global scratch for k_sym_merge.
-constexpr uint32_t kLongLen = 32;
 constexpr uint32_t kUnitCols = 4 * kWave;
 
 __device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
@@ -740,6 +747,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
         const int64_t N = B.ncols;
         const int32_t nwin = cs[zc].nwin;
         const int64_t wcols_full = (int64_t)cs[zc].win_words * 32;
+        const uint32_t long_len = cs[zc].long_len;  // >= 8: a long row has a full 16-byte group
         // entries e0, e0 + P, e0 + 2P, ... below e_hi (P = 1 unless split)
         const int32_t e0 = item.e_lo + item.part, P = item.nparts;
         const int64_t cnt = item.e_hi > e0 ? ((int64_t)item.e_hi - e0 + P - 1) / P : 0;
@@ -758,7 +766,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
                 const int32_t k = A.col[e0 + (int32_t)((live ? i : cnt - 1) * P)];
                 const int32_t b0 = B.rpt[k];
                 const uint32_t len = live ? (uint32_t)(B.rpt[k + 1] - b0) : 0u;
-                const bool lng = len >= kLongLen, shrt = !lng && len != 0;
+                const bool lng = len >= long_len, shrt = !lng && len != 0;
                 // short products (bits 0..19), short entries (20..39), long entries (40..)
                 const uint64_t packed = (shrt ? (uint64_t)len | (1ull << 20) : 0ull) |
                                         (lng ? (1ull << 40) : 0ull);

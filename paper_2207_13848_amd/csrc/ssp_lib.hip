@@ -40,7 +40,42 @@ struct EventPair {
 };
 } // namespace
 
+namespace {
+ssp_tuning default_tuning()
+{
+    ssp_tuning t;
+    std::memset(&t, 0, sizeof(t));
+    t.bin_max[0] = (uint32_t)ssp::kBin1Max;
+    t.bin_max[1] = (uint32_t)ssp::kBin2Max;
+    t.bin_max[2] = (uint32_t)ssp::kBin3Max;
+    t.hash_mult = 2;
+    t.long_len = ssp::kLongLenDefault;
+    t.big3 = 1;
+    t.split_target = ssp::kSplitTarget;
+    return t;
+}
+
+// The limits the kernels rely on: a bin's hash table holds hash_mult x its
+// limit, a long B row has a whole 16-byte group, short products of a chunk
+// fit a 20-bit field.
+bool tuning_valid(const ssp_tuning& t)
+{
+    const uint32_t m = t.hash_mult;
+    if (m != 2 && m != 4 && m != 8) return false;
+    if (t.bin_max[0] < 1 || t.bin_max[0] > t.bin_max[1] || t.bin_max[1] > t.bin_max[2]) return false;
+    if ((uint64_t)t.bin_max[0] * m > (uint64_t)ssp::kBin1Words ||
+        (uint64_t)t.bin_max[1] * m > (uint64_t)ssp::kBin2Words ||
+        (uint64_t)t.bin_max[2] * m > (uint64_t)ssp::kBin3Words)
+        return false;
+    if (t.long_len < 8 || t.long_len > 1024) return false;
+    if (t.big3 != 0 && t.big3 != 1) return false;
+    if (t.split_target < (1ull << 12) || t.split_target > (1ull << 40)) return false;
+    return true;
+}
+} // namespace
+
 struct ssp_context {
+    ssp_tuning tuning = default_tuning();
     int device = 0;
     size_t budget = 0;
     void* ws = nullptr;
@@ -339,7 +374,14 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind)
         window_shape(N, &d.win_words, &d.nwin);
         // bin 3 would hash (its table as a bitmap covers fewer than N columns)
         // while one bitmap window covers all N: those rows go to the long-row kernel
-        d.big3 = (d.nwin == 1 && N > 32LL * kBin3Words) ? 1 : 0;
+        const ssp_tuning& tu = h->tuning;
+        d.big3 = (tu.big3 && d.nwin == 1 && N > 32LL * kBin3Words) ? 1 : 0;
+        d.bin_max[0] = tu.bin_max[0];
+        d.bin_max[1] = tu.bin_max[1];
+        d.bin_max[2] = tu.bin_max[2];
+        d.hash_mult = tu.hash_mult;
+        d.long_len = tu.long_len;
+        d.split_target = tu.split_target;
         int32_t mpr = 0;  // merge items of a split row: slices of every window
         for (int32_t w = 0; w < d.nwin; ++w) {
             const int64_t cols = std::min<int64_t>(N - (int64_t)w * d.win_words * 32,
@@ -920,6 +962,113 @@ ssp_status ssp_batch_graph_destroy(ssp_batch_graph g)
     if (g->ws && hipFree(g->ws) != hipSuccess) st = SSP_ERR_HIP;
     delete g;
     return st;
+}
+
+void ssp_default_tuning(ssp_tuning* t)
+{
+    if (t) *t = default_tuning();
+}
+
+ssp_status ssp_get_tuning(ssp_handle h, ssp_tuning* t)
+{
+    if (!h || !t) return SSP_ERR_INVALID_ARG;
+    *t = h->tuning;
+    return SSP_OK;
+}
+
+ssp_status ssp_set_tuning(ssp_handle h, const ssp_tuning* t)
+{
+    if (!h || !t || !tuning_valid(*t)) return SSP_ERR_INVALID_ARG;
+    h->tuning = *t;
+    return SSP_OK;
+}
+
+ssp_status ssp_autotune(ssp_handle h, int n, const ssp_case* cases, int reps,
+                        ssp_tuning* chosen, double* best_ms, double* default_ms, void* stream)
+{
+    if (reps < 1 || n < 1) return SSP_ERR_INVALID_ARG;
+    std::vector<CaseIn> in;
+    ssp_status s = batch_inputs(h, n, cases, in);
+    if (s != SSP_OK) return s;
+    DeviceGuard g(h->device);
+    if (!g.ok()) return SSP_ERR_NO_DEVICE;
+    hipStream_t hs = static_cast<hipStream_t>(stream);
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    SSP_HIP(h, hipEventCreate(&e0));
+    if (hipEventCreate(&e1) != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return SSP_ERR_HIP;
+    }
+    const bool was_timing = h->timing;
+    h->timing = false;
+    const ssp_tuning start = h->tuning;
+    auto measure = [&](const ssp_tuning& t, double* ms) -> ssp_status {
+        h->tuning = t;
+        ssp_status st = run_plan(h, in, PLAN_PREDICT, hs);  // warm-up (and workspace)
+        if (st != SSP_OK) return st;
+        if (hipEventRecord(e0, hs) != hipSuccess) return SSP_ERR_HIP;
+        for (int r = 0; r < reps; ++r)
+            if ((st = run_plan(h, in, PLAN_PREDICT, hs)) != SSP_OK) return st;
+        if (hipEventRecord(e1, hs) != hipSuccess || hipEventSynchronize(e1) != hipSuccess)
+            return SSP_ERR_HIP;
+        float t_ms = 0.f;
+        if (hipEventElapsedTime(&t_ms, e0, e1) != hipSuccess) return SSP_ERR_HIP;
+        *ms = (double)t_ms / reps;
+        return SSP_OK;
+    };
+    ssp_tuning best = start;
+    double best_t = 0, def_t = 0;
+    s = measure(default_tuning(), &def_t);
+    if (s == SSP_OK) s = measure(best, &best_t);
+    // coordinate descent over the parameters, a few values each
+    const uint64_t splits[] = {1ull << 15, 1ull << 16, 1ull << 17, 1ull << 18, 1ull << 19};
+    const uint32_t longs[] = {16, 32, 64, 128};
+    const uint32_t bins[][4] = {{128, 1024, 8192, 2}, {64, 512, 4096, 4}, {64, 512, 8192, 2},
+                                {32, 256, 4096, 2},  {128, 512, 4096, 2}};
+    auto consider = [&](ssp_tuning t) {
+        if (s != SSP_OK || !tuning_valid(t) || std::memcmp(&t, &best, sizeof(t)) == 0) return;
+        double ms = 0;
+        s = measure(t, &ms);
+        if (s == SSP_OK && ms < 0.98 * best_t) {
+            best = t;
+            best_t = ms;
+        }
+    };
+    for (uint64_t v : splits) {
+        ssp_tuning t = best;
+        t.split_target = v;
+        consider(t);
+    }
+    for (uint32_t v : longs) {
+        ssp_tuning t = best;
+        t.long_len = v;
+        consider(t);
+    }
+    for (int v = 0; v <= 1; ++v) {
+        ssp_tuning t = best;
+        t.big3 = v;
+        consider(t);
+    }
+    for (const auto& b : bins) {
+        ssp_tuning t = best;
+        t.bin_max[0] = b[0];
+        t.bin_max[1] = b[1];
+        t.bin_max[2] = b[2];
+        t.hash_mult = b[3];
+        consider(t);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    h->timing = was_timing;
+    if (s != SSP_OK) {
+        h->tuning = start;
+        return s;
+    }
+    h->tuning = best;
+    if (chosen) *chosen = best;
+    if (best_ms) *best_ms = best_t;
+    if (default_ms) *default_ms = def_t;
+    return SSP_OK;
 }
 
 ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* m, int64_t* n_bad, void* stream)

@@ -207,6 +207,7 @@ ssp_status ssp_server_create(ssp_handle h, int nslots, size_t slot_bytes, int ma
     if (!S) return SSP_ERR_OOM;
     S->ctx.device = h->device;
     S->ctx.num_cus = h->num_cus;
+    S->ctx.tuning = h->tuning;
     S->device = h->device;
     S->slot_bytes = slot_bytes;
     S->max_batch = max_batch;

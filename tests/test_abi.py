@@ -94,3 +94,9 @@ def test_product_path_does_not_touch_the_oracle():
                 text = open(os.path.join(dirpath, f)).read()
                 assert "oracle" not in text.lower(), f"{f} mentions the oracle"
                 assert "workloads" not in text, f"{f} imports the input generators"
+
+
+def test_default_tuning_matches_the_documented_defaults():
+    import paper_2207_13848_amd as ssp
+    assert ssp.default_tuning() == {"bin_max": [128, 1024, 8192], "hash_mult": 2, "long_len": 32,
+                                    "big3": 1, "split_target": 1 << 17}
