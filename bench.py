@@ -28,7 +28,8 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
-WORKLOADS = ("rmat20", "uniform4096", "stencil128", "stencil128_x_uniform", "sweep", "serve")
+WORKLOADS = ("rmat20", "uniform4096", "stencil128", "stencil128_x_uniform", "sweep", "serve",
+             "accuracy")
 
 
 def parse():
@@ -291,6 +292,78 @@ def main_serve(args):
         "results_equal_alone": f"{ok}/{nchk}", "generate_s": round(t_gen, 1)}), flush=True)
 
 
+def main_accuracy(args):
+    """Accuracy over the 625-case sweep (Sec. VI-A's analysis): per case the
+    proposed prediction (Z2* = F z*/f*), the reference design (Z1* = z* M/n_s)
+    and the exact total Z, all on the GPU, with the Bernoulli sampler at 1% and
+    the paper's fixed-count sampler; errors eps = estimate / Z - 1, with
+    eps_f = F*/F - 1 for F* = f* M / n_s (Eq. (5): (1+eps2)(1+epsf) = 1+eps1)."""
+    import numpy as np
+    import torch
+    import paper_2207_13848_amd as ssp
+    import workloads
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    dev = "cuda:0"
+    rows = []
+    t0 = time.time()
+    for p in workloads.sweep_cases():
+        w = workloads.sweep_workload(p)
+        A = ssp.DeviceCSR.from_csr(w.A, dev)
+        ex, exs = ssp.exact_structure(A, A)
+        out = {"structure": p[0], "n": p[1], "d": p[2], "seed": p[3]}
+        for smp in ("bernoulli", "paper"):
+            _, _, st = ssp.predict_structure(A, A, w.rate, w.seed, sampler=smp)
+            _, rst = ssp.reference_estimate(A, A, w.rate, w.seed, sampler=smp)
+            s_, r_ = ssp.read_stats(st), ssp.read_stats(rst)
+            out[smp] = (s_, r_)
+        e = ssp.read_stats(exs)
+        out["Z"], out["F"] = e["out_sum"], e["total_flop"]
+        rows.append(out)
+        del A
+    torch.cuda.synchronize()
+    t_run = time.time() - t0
+
+    def summarise(smp):
+        recs, excluded = [], 0
+        for r in rows:
+            s_ = r[smp][0]
+            Z, F, M = r["Z"], r["F"], r["n"]
+            ns, fs, zs = s_["n_sampled"], s_["sample_flop"], s_["sample_nnz"]
+            if Z == 0 or ns == 0 or fs == 0:
+                excluded += 1
+                continue
+            recs.append((r["structure"], zs * M / ns / Z - 1, F * zs / fs / Z - 1,
+                         fs * M / ns / F - 1, s_["out_sum"] / Z - 1))
+        st = np.array([x[0] for x in recs])
+        e1, e2, ef, ea = (np.array([x[k] for x in recs]) for k in (1, 2, 3, 4))
+        out = {"cases": int(len(recs)), "excluded": excluded,
+               "mean_abs_eps1": float(np.mean(np.abs(e1))), "worst_abs_eps1": float(np.max(np.abs(e1))),
+               "mean_abs_eps2": float(np.mean(np.abs(e2))), "worst_abs_eps2": float(np.max(np.abs(e2))),
+               "mean_abs_epsf": float(np.mean(np.abs(ef))), "worst_abs_epsf": float(np.max(np.abs(ef))),
+               "mean_abs_eps2_alloc": float(np.mean(np.abs(ea))),
+               "corr_eps1_epsf": float(np.corrcoef(e1, ef)[0, 1]),
+               "frac_abs_eps2_lt_abs_eps1": float(np.mean(np.abs(e2) < np.abs(e1))),
+               "frac_same_sign_eps1_epsf": float(np.mean(np.sign(e1) == np.sign(ef))),
+               "by_structure": {}}
+        for sname in workloads.STRUCTURES:
+            m = st == sname
+            if m.any():
+                out["by_structure"][sname] = {
+                    "mean_abs_eps1": float(np.mean(np.abs(e1[m]))),
+                    "mean_abs_eps2": float(np.mean(np.abs(e2[m]))),
+                    "worst_abs_eps2": float(np.max(np.abs(e2[m])))}
+        return out
+
+    print(json.dumps({"study": "accuracy over the 625-case sweep", "run_s": round(t_run, 1),
+                      "bernoulli_1pct": summarise("bernoulli"),
+                      "paper_sampler": summarise("paper"),
+                      "paper_reports": {"mean_abs_eps1": 0.0812, "mean_abs_eps2": 0.0156,
+                                        "worst_abs_eps1": 1.58, "worst_abs_eps2": 0.25}}),
+          flush=True)
+
+
 def get_workload(name: str):
     import workloads
     return getattr(workloads, name)()
@@ -319,6 +392,9 @@ def main():
         return
     if args.workload == "serve":
         main_serve(args)
+        return
+    if args.workload == "accuracy":
+        main_accuracy(args)
         return
 
     import numpy as np
