@@ -57,9 +57,8 @@ struct CaseDesc {
     ssp_stats* st;       // statistics (the caller's, or the case's workspace slot)
     uint64_t seed, thresh;
     int64_t ncand;       // sampling candidates: rows (Bernoulli) or draws (paper)
-    int64_t tile_base;   // first entry of this case in the tile-start array
-    int64_t meta_base;   // first entry in the tile metadata
-    int64_t ntiles;      // merge-path tiles of A (at least 1)
+    int64_t tile_base;   // first global tile of this case (tiles numbered case after case)
+    int64_t ntiles;      // merge-path tiles of A (0 when A has no rows)
     int64_t group_base;  // first sampling group of this case
     int64_t group_size;  // candidates per sampling group (a multiple of 256)
     int64_t ngroups;
@@ -68,7 +67,7 @@ struct CaseDesc {
     int32_t big3;        // bin-3 rows go to the long-row kernel
     int32_t merge_per_row;  // merge items of one split row
     int32_t paper;       // the paper's fixed-count sampler
-    int32_t wg_tiles, wg_flop, wg_fixup, wg_rows;
+    int32_t wg_tiles, wg_rows;
     // tuning (the same for every case of a call)
     uint32_t bin_max[3];    // product limits of bins 1..3
     uint32_t hash_mult;     // hash tables hold at least hash_mult x the distinct bound

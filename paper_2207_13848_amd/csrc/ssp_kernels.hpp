@@ -246,25 +246,27 @@ __device__ inline void append_row(int32_t row, uint64_t rf, int32_t e0, int32_t 
 
 // ------------------------------------------------------------ k_tiles
 
-// Merge-path partition of the streaming FLOP pass: tile b starts in row g
-// when its first item b * kFlopTile lies in [rpt[g] + g, rpt[g+1] + g + 1),
-// the span of row g's entries and end marker.  tile_row[ntiles] = M.
+// Merge-path partition of the streaming FLOP pass: tile b of a case starts in
+// row g when its first item b * kFlopTile lies in [rpt[g] + g, rpt[g+1] + g + 1),
+// the span of row g's entries and end marker.  Writes the start row and the
+// case of every global tile (tiles numbered case after case).
 __global__ __launch_bounds__(256) void k_tiles(const CaseDesc* __restrict__ cs, int n,
-                                              int32_t* __restrict__ tile_row_all)
+                                              int32_t* __restrict__ tile_row,
+                                              int32_t* __restrict__ tile_case)
 {
     const int c = case_of_wg<&CaseDesc::wg_tiles>(cs, n, blockIdx.x);
     const int64_t bl = (int64_t)blockIdx.x - cs[c].wg_tiles;
     const int64_t G = wgs_of_case<&CaseDesc::wg_tiles>(cs, n, c);
     const Csr A = cs[c].A;
-    const int64_t M = A.nrows, ntiles = cs[c].ntiles;
-    int32_t* __restrict__ tile_row = tile_row_all + cs[c].tile_base;
+    const int64_t M = A.nrows, ntiles = cs[c].ntiles, base = cs[c].tile_base;
     const int64_t stride = G * 256;
     for (int64_t g = bl * 256 + threadIdx.x; g < M; g += stride) {
         const int64_t f0 = (int64_t)A.rpt[g] + g, f1 = (int64_t)A.rpt[g + 1] + g + 1;
-        for (int64_t b = (f0 + kFlopTile - 1) / kFlopTile; b * kFlopTile < f1 && b < ntiles; ++b)
-            tile_row[b] = (int32_t)g;
+        for (int64_t b = (f0 + kFlopTile - 1) / kFlopTile; b * kFlopTile < f1 && b < ntiles; ++b) {
+            tile_row[base + b] = (int32_t)g;
+            tile_case[base + b] = c;
+        }
     }
-    if (bl == 0 && threadIdx.x == 0) tile_row[ntiles] = (int32_t)M;
 }
 
 // --------------------------------------------------------- sampling
@@ -1057,69 +1059,48 @@ __global__ void k_finalize_reference(const CaseDesc* __restrict__ cs, CaseRes* _
 
 enum { FLOP_ONLY = 1, FLOP_EXACT_BIN = 2 };
 
-struct FlopArgs {
-    Csr A, B;
-    int64_t* out;      // ONLY: row flop; EXACT_BIN: nnz_exact (0 for rows of bins 0 and 4)
-    Ctl* ctl;
-    BinLists L;
-    const int32_t* tile_row; // first row of every tile, tile_row[ntiles] = M
-    TileMeta* meta;
-    int64_t ntiles;
-    const CaseDesc* cd;      // the case (window shape, for binning)
-    int32_t ci;
-};
-
-// The streaming-pass arguments of case c.
+// Output of one finished row of case c: its product count, or its bin.
 template <int MODE>
-__device__ __forceinline__ FlopArgs flop_args(const CaseDesc* __restrict__ cs, int c,
-                                              int32_t* tile_row_all, TileMeta* meta_all,
-                                              Ctl* ctl, const BinLists& L)
-{
-    FlopArgs a;
-    a.A = cs[c].A;
-    a.B = cs[c].B;
-    a.out = MODE == FLOP_ONLY ? cs[c].rf : cs[c].out;
-    a.ctl = ctl;
-    a.L = L;
-    a.tile_row = tile_row_all + cs[c].tile_base;
-    a.meta = meta_all + cs[c].meta_base;
-    a.ntiles = cs[c].ntiles;
-    a.cd = cs + c;
-    a.ci = c;
-    return a;
-}
-
-// Output of one finished row: its product count, or its bin.
-template <int MODE>
-__device__ __forceinline__ void emit_row(const FlopArgs& a, int64_t row, uint64_t rf)
+__device__ __forceinline__ void emit_row(const CaseDesc* __restrict__ cs, int c, int64_t row,
+                                         uint64_t rf, Ctl* ctl, const BinLists& L)
 {
     if (MODE == FLOP_ONLY) {
-        a.out[row] = (int64_t)rf;
+        cs[c].rf[row] = (int64_t)rf;
     } else {
-        const int b = bin_route(rf, *a.cd);
-        if (b == 0 || b == 4) a.out[row] = 0;
-        if (b != 0)
-            append_row((int32_t)row, rf, a.A.rpt[row], a.A.rpt[row + 1], a.ci, *a.cd, a.ctl, a.L);
+        const CaseDesc& cd = cs[c];
+        const int b = bin_route(rf, cd);
+        if (b == 0 || b == 4) cd.out[row] = 0;
+        if (b != 0) append_row((int32_t)row, rf, cd.A.rpt[row], cd.A.rpt[row + 1], c, cd, ctl, L);
     }
 }
 
-// Merge-path tile b covers the items [b T, (b+1) T) of the sequence that
-// interleaves A's entries with one end marker per row (Merrill & Garland,
-// SC16), so every tile has at most T = kFlopTile rows + entries whatever the
-// row lengths.  A tile's entries are loaded with two 16-byte loads per thread
-// (each load instruction fully coalesced, non-temporal so the stream does not
-// evict B's row pointers from L2) and each contributes the length of the B row
-// it names (one 8-byte gather).  An exclusive scan of these lengths gives the
-// running product count at every row boundary, and a row's count is the
-// difference of its two boundaries.  Rows that begin in an earlier tile or end
-// in a later one leave their partial counts in the tile's metadata for
-// k_flop_fixup.
+// Merge-path tile b of a case covers the items [b T, (b+1) T) of the sequence
+// that interleaves A's entries with one end marker per row (Merrill &
+// Garland, SC16), so every tile has at most T = kFlopTile rows + entries
+// whatever the row lengths.  A tile's entries are loaded with two 16-byte
+// loads per thread (each load instruction fully coalesced, non-temporal so the
+// stream does not evict B's row pointers from L2) and each contributes the
+// length of the B row it names (one 8-byte gather).  An exclusive scan of
+// these lengths gives the running product count at every row boundary, and a
+// row's count is the difference of its two boundaries.  Rows that begin in an
+// earlier tile or end in a later one leave their partial counts in the tile's
+// metadata for k_flop_fixup.
 //
-// The kernel is persistent: workgroup g takes tiles g, g + G, g + 2G, ...
-// and software-pipelines them.  While tile b's gathers are in flight it
-// issues the loads of tile b + G, and the tile starts of b + 2G are read one
-// tile further ahead.
+// Tiles are numbered case after case (global tile g belongs to case
+// tile_case[g]).  The kernel is persistent: workgroup w takes the global tiles
+// w, w + G, w + 2G, ..., so at any time the device works on one or two
+// neighbouring cases and their B row pointers stay in L2 (a batch that gave
+// every case its own workgroups at once would gather from all of them
+// together).  It software-pipelines its tiles: while tile g's gathers are in
+// flight it issues the loads of tile g + G, and the starts of the tiles after
+// that are staged in LDS.
 struct FlopTileRegs {
+    int64_t g;        // global tile
+    int32_t c;        // its case
+    const int32_t* Arpt;
+    const int32_t* Brpt;
+    int64_t* out;
+    int64_t M, nnzA;
     int64_t i0, i1, j0, j1, a0;
     int4 col[2];   // as loaded; shifted by sh[q] positions when the load was clamped
     int32_t sh[2];
@@ -1137,16 +1118,27 @@ __device__ __forceinline__ int32_t quad_at(int32_t w0, int32_t w1, int32_t w2, i
     return (w0 & m0) | (w1 & m1) | (w2 & m2) | (w3 & m3);
 }
 
-template <bool VEC>
-__device__ __forceinline__ void flop_issue_tile(const FlopArgs& a, int64_t b, int64_t i0,
-                                                int64_t i1, FlopTileRegs& R)
+// Issues the loads of global tile g of case c, whose rows are [i0, i1].
+template <int MODE, bool VEC>
+__device__ __forceinline__ void flop_issue_tile(const CaseDesc* __restrict__ cs, int64_t g, int c,
+                                                int64_t i0, int64_t i1, FlopTileRegs& R)
 {
     constexpr int NT = kFlopThreads, HALF = kFlopChunk / 2, NRP = kFlopTile / kFlopThreads + 1;
     const int t = threadIdx.x;
-    const int64_t M = a.A.nrows, nnzA = a.A.nnz;
-    const int64_t d0 = b * kFlopTile;
-    const int64_t d1 = (d0 + kFlopTile) < (M + nnzA) ? (d0 + kFlopTile) : (M + nnzA);
     // the tile scalars are uniform: keep them in scalar registers
+    c = __builtin_amdgcn_readfirstlane(c);
+    const CaseDesc& cd = cs[c];
+    R.g = g;
+    R.c = c;
+    R.Arpt = cd.A.rpt;
+    R.Brpt = cd.B.rpt;
+    R.out = MODE == FLOP_ONLY ? cd.rf : cd.out;
+    const int32_t* Acol = cd.A.col;
+    const int64_t M = cd.A.nrows, nnzA = cd.A.nnz;
+    R.M = M;
+    R.nnzA = nnzA;
+    const int64_t d0 = (g - cd.tile_base) * kFlopTile;
+    const int64_t d1 = (d0 + kFlopTile) < (M + nnzA) ? (d0 + kFlopTile) : (M + nnzA);
     i0 = (int64_t)__builtin_amdgcn_readfirstlane((int)i0);
     i1 = (int64_t)__builtin_amdgcn_readfirstlane((int)i1);
     R.i0 = i0;
@@ -1159,7 +1151,7 @@ __device__ __forceinline__ void flop_issue_tile(const FlopArgs& a, int64_t b, in
 #pragma unroll
     for (int u = 0; u < NRP; ++u) {
         const int k = t + u * NT;
-        R.rp[u] = a.A.rpt[i0 + (k < nb ? k : nb - 1)];
+        R.rp[u] = R.Arpt[i0 + (k < nb ? k : nb - 1)];
     }
     // Loads are unconditional from clamped in-range addresses (masked later):
     // a load under a lane condition becomes a branch, and loads in separate
@@ -1171,7 +1163,7 @@ __device__ __forceinline__ void flop_issue_tile(const FlopArgs& a, int64_t b, in
         if (VEC) {
             typedef int v4i __attribute__((ext_vector_type(4)));
             const int64_t pl = (p + 3 < nnzA) ? p : nnzA - 4; // 4-byte aligned when clamped
-            const v4i w = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(a.A.col + pl));
+            const v4i w = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(Acol + pl));
             v = make_int4(w.x, w.y, w.z, w.w);
             // positions >= nnz(A) are masked anyway; cap the shift so quad_at stays in range
             const int64_t sh = p - pl;
@@ -1181,24 +1173,34 @@ __device__ __forceinline__ void flop_issue_tile(const FlopArgs& a, int64_t b, in
             v = make_int4(0, 0, 0, 0);
             if (nnzA > 0) {  // A may have no entries (and no column array) at all
                 const int64_t last = nnzA - 1;
-                v.x = a.A.col[(p + 0) < last ? (p + 0) : last];
-                v.y = a.A.col[(p + 1) < last ? (p + 1) : last];
-                v.z = a.A.col[(p + 2) < last ? (p + 2) : last];
-                v.w = a.A.col[(p + 3) < last ? (p + 3) : last];
+                v.x = Acol[(p + 0) < last ? (p + 0) : last];
+                v.y = Acol[(p + 1) < last ? (p + 1) : last];
+                v.z = Acol[(p + 2) < last ? (p + 2) : last];
+                v.w = Acol[(p + 3) < last ? (p + 3) : last];
             }
         }
         R.col[q] = v;
     }
 }
 
+// Start row of the tile after global tile g (the case's M after its last tile).
+__device__ __forceinline__ int32_t tile_end_row(const CaseDesc* __restrict__ cs,
+                                                const int32_t* __restrict__ tile_row,
+                                                const int32_t* __restrict__ tile_case,
+                                                int64_t ntiles_all, int64_t g)
+{
+    const int c = tile_case[g];
+    return (g + 1 < ntiles_all && tile_case[g + 1] == c) ? tile_row[g + 1]
+                                                         : (int32_t)cs[c].A.nrows;
+}
+
 template <int MODE, bool VEC>
-__global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restrict__ cs, int n,
-                                                      int32_t* tile_row_all, TileMeta* meta_all,
+__global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restrict__ cs,
+                                                      const int32_t* __restrict__ tile_row,
+                                                      const int32_t* __restrict__ tile_case,
+                                                      int64_t ntiles_all, TileMeta* meta,
                                                       Ctl* ctl, BinLists L)
 {
-    // the case of this workgroup, and its rank among the case's workgroups
-    const int c = case_of_wg<&CaseDesc::wg_flop>(cs, n, blockIdx.x);
-    const FlopArgs a = flop_args<MODE>(cs, c, tile_row_all, meta_all, ctl, L);
     constexpr int NT = kFlopThreads, CH = kFlopChunk, HALF = CH / 2;
     constexpr int T = (int)kFlopTile, NRP = kFlopTile / kFlopThreads + 1;
     __shared__ int32_t s_bnd[T + 2];
@@ -1207,30 +1209,28 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restric
     __shared__ uint64_t s_w[2 * (NT / kWave)];
 
     const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
-    const int64_t M = a.A.nrows;
-    const int64_t G = wgs_of_case<&CaseDesc::wg_flop>(cs, n, c), ntiles = a.ntiles;
-    const int32_t* __restrict__ Brpt = a.B.rpt;
+    const int64_t G = gridDim.x;
 
-    // The tile starts of this workgroup's tiles are staged in LDS, kTrow at a
-    // time: reading them from LDS does not wait on the vector loads in flight.
+    // Start row, case and end row of this workgroup's tiles, staged in LDS
+    // kTrow at a time: reading them from LDS does not wait on the vector loads
+    // in flight.  Past the last tile: the last tile's case with an empty row
+    // range at its M, so the loads of the pipeline's extra issue stay in range.
     constexpr int kTrow = 64;
-    __shared__ int32_t s_trow[kTrow + 1];
-    int64_t b = (int64_t)blockIdx.x - cs[c].wg_flop;
-    if (b >= ntiles) return;
-    auto stage_trow = [&](int64_t bfirst) {  // tiles bfirst + k G, k < kTrow
+    __shared__ int32_t s_trow[kTrow + 1], s_tcase[kTrow + 1], s_next[kTrow + 1];
+    int64_t b = blockIdx.x;
+    if (b >= ntiles_all) return;
+    auto stage_all = [&](int64_t bfirst) {  // tiles bfirst + k G, k <= kTrow
         for (int k = t; k <= kTrow; k += NT) {
             const int64_t bk = bfirst + (int64_t)k * G;
-            s_trow[k] = bk <= ntiles ? a.tile_row[bk] : (int32_t)M;
-        }
-    };
-    // tile_row[b + 1] is the start of the tile after b, i.e. of a tile of
-    // another workgroup; it is staged alongside as s_next[k]
-    __shared__ int32_t s_next[kTrow + 1];
-    auto stage_all = [&](int64_t bfirst) {
-        stage_trow(bfirst);
-        for (int k = t; k <= kTrow; k += NT) {
-            const int64_t bk = bfirst + (int64_t)k * G;
-            s_next[k] = bk < ntiles ? a.tile_row[bk + 1] : (int32_t)M;
+            if (bk < ntiles_all) {
+                s_trow[k] = tile_row[bk];
+                s_tcase[k] = tile_case[bk];
+                s_next[k] = tile_end_row(cs, tile_row, tile_case, ntiles_all, bk);
+            } else {
+                const int cl = tile_case[ntiles_all - 1];
+                s_tcase[k] = cl;
+                s_trow[k] = s_next[k] = (int32_t)cs[cl].A.nrows;
+            }
         }
         __syncthreads();
     };
@@ -1238,11 +1238,13 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restric
     stage_all(stage_base);
     int kk = 0;  // index of tile b in the staged window
     FlopTileRegs cur, nxt;
-    flop_issue_tile<VEC>(a, b, s_trow[0], s_next[0], cur);
+    flop_issue_tile<MODE, VEC>(cs, b, s_tcase[0], s_trow[0], s_next[0], cur);
     for (;;) {
         const int64_t bn = b + G;
         // 1. gathers of the current tile
         const int64_t i0 = cur.i0, i1 = cur.i1, j0 = cur.j0, j1 = cur.j1, a0 = cur.a0;
+        const int64_t M = cur.M;
+        const int32_t* __restrict__ Brpt = cur.Brpt;
         uint32_t x[8];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -1256,14 +1258,13 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restric
                 uint32_t len = 0;
                 // row 0 of B when masked; with no entries at all (then K may be
                 // 0 and B's row pointers hold one value) nothing is read
-                if (VEC || a.A.nnz > 0) len = csr_row_len(Brpt, in ? cc : 0);
+                if (VEC || cur.nnzA > 0) len = csr_row_len(Brpt, in ? cc : 0);
                 x[4 * q + l] = in ? len : 0u;
             }
         }
         // 2. loads of the next tile, unconditionally (a branch here would make
-        //    the compiler drain every load in flight at its join); past the
-        //    last tile the staged starts are M and the loads clamp in range
-        flop_issue_tile<VEC>(a, bn, s_trow[kk + 1], s_next[kk + 1], nxt);
+        //    the compiler drain every load in flight at its join)
+        flop_issue_tile<MODE, VEC>(cs, bn, s_tcase[kk + 1], s_trow[kk + 1], s_next[kk + 1], nxt);
         // 3. the current tile
         const int64_t rlast = i1 < M ? i1 : M - 1;
         const int nb = (int)(rlast - i0 + 2);
@@ -1334,24 +1335,25 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restric
                     const int64_t st_ = rs > j0 ? rs : j0;
                     const int64_t en = re < j1 ? re : j1;
                     sum = prefix(en) - prefix(st_);
-                    if (rs < j0) a.meta[b].head = sum;
-                    else if (open) a.meta[b].carry = sum;
+                    if (rs < j0) meta[cur.g].head = sum;
+                    else if (open) meta[cur.g].carry = sum;
                     else emit = true;
                 }
             }
             if (MODE == FLOP_EXACT_BIN) {
-                const int bn_ = emit ? bin_route(sum, *a.cd) : 0;
-                append_small_bins(bn_, (int32_t)r, sum, a.ci, a.ctl, a.L);
-                if (emit && (bn_ == 0 || bn_ == 4)) a.out[r] = 0;
+                const CaseDesc& cd = cs[cur.c];
+                const int bn_ = emit ? bin_route(sum, cd) : 0;
+                append_small_bins(bn_, (int32_t)r, sum, cur.c, ctl, L);
+                if (emit && (bn_ == 0 || bn_ == 4)) cur.out[r] = 0;
                 if (emit && bn_ == 4)
-                    append_big((int32_t)r, sum, s_bnd[k], s_bnd[k + 1], a.ci, *a.cd, a.ctl, a.L);
+                    append_big((int32_t)r, sum, s_bnd[k], s_bnd[k + 1], cur.c, cd, ctl, L);
             } else if (emit) {
-                __builtin_nontemporal_store((int64_t)sum, a.out + r);
+                __builtin_nontemporal_store((int64_t)sum, cur.out + r);
             }
         }
-        if (t == 0) a.meta[b].fsum = tile_total;
+        if (t == 0) meta[cur.g].fsum = tile_total;
         __syncthreads();  // s_bnd, s_x and the prefixes are rewritten for the next tile
-        if (bn >= ntiles) break;
+        if (bn >= ntiles_all) break;
         b = bn;
         cur = nxt;
         if (++kk == kTrow) {  // restage; k = 0..kTrow are staged, so kk + 1 always is
@@ -1363,40 +1365,47 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restric
     }
 }
 
-// One thread per tile: a row that begins in tile b and goes on (its partial
-// is b's carry) collects the heads of the following tiles until the tile
-// holding its end marker, then gets its output.  Adds the case's F.
+// One thread per global tile: a row that begins in tile g and goes on (its
+// partial is g's carry) collects the heads of the case's following tiles until
+// the tile holding its end marker, then gets its output.  Adds each case's F:
+// one atomic for the workgroup's first case, one per tile of any other case.
 template <int MODE>
-__global__ __launch_bounds__(256) void k_flop_fixup(const CaseDesc* __restrict__ cs, int n,
-                                                   int32_t* tile_row_all, TileMeta* meta_all,
+__global__ __launch_bounds__(256) void k_flop_fixup(const CaseDesc* __restrict__ cs,
+                                                   const int32_t* __restrict__ tile_row,
+                                                   const int32_t* __restrict__ tile_case,
+                                                   int64_t ntiles_all, const TileMeta* meta,
                                                    Ctl* ctl, BinLists L)
 {
     __shared__ uint64_t s_red[256 / kWave + 1];
-    const int c = case_of_wg<&CaseDesc::wg_fixup>(cs, n, blockIdx.x);
-    const FlopArgs a = flop_args<MODE>(cs, c, tile_row_all, meta_all, ctl, L);
-    const int64_t b = ((int64_t)blockIdx.x - cs[c].wg_fixup) * 256 + threadIdx.x;
-    const int64_t M = a.A.nrows, nnzA = a.A.nnz;
+    const int64_t g = (int64_t)blockIdx.x * 256 + threadIdx.x;
+    const int64_t g_first = (int64_t)blockIdx.x * 256;
+    const int c0 = tile_case[g_first];  // (the grid covers ntiles_all, so g_first is a tile)
     uint64_t F = 0;
-    if (b < a.ntiles) {
-        F = a.meta[b].fsum;
-        const int64_t d0 = b * kFlopTile;
+    if (g < ntiles_all) {
+        const int c = tile_case[g];
+        const CaseDesc& cd = cs[c];
+        const int64_t M = cd.A.nrows, nnzA = cd.A.nnz;
+        const int64_t last = cd.tile_base + cd.ntiles;  // one past the case's last tile
+        const int64_t d0 = (g - cd.tile_base) * kFlopTile;
         const int64_t d1 = (d0 + kFlopTile) < (M + nnzA) ? (d0 + kFlopTile) : (M + nnzA);
-        const int64_t i1 = a.tile_row[b + 1];
-        const int64_t j0 = d0 - a.tile_row[b], j1 = d1 - i1;
+        const int64_t i1 = tile_end_row(cs, tile_row, tile_case, ntiles_all, g);
+        const int64_t j0 = d0 - tile_row[g], j1 = d1 - i1;
         if (i1 < M) {
-            const int64_t rs = a.A.rpt[i1];
+            const int64_t rs = cd.A.rpt[i1];
             if (rs >= j0 && rs < j1) {
-                uint64_t total = a.meta[b].carry;
-                for (int64_t bb = b + 1; bb < a.ntiles; ++bb) {
-                    total += a.meta[bb].head;
-                    if (a.tile_row[bb + 1] > i1) break;
+                uint64_t total = meta[g].carry;
+                for (int64_t bb = g + 1; bb < last; ++bb) {
+                    total += meta[bb].head;
+                    if (tile_end_row(cs, tile_row, tile_case, ntiles_all, bb) > i1) break;
                 }
-                emit_row<MODE>(a, i1, total);
+                emit_row<MODE>(cs, c, i1, total, ctl, L);
             }
         }
+        if (c == c0) F = meta[g].fsum;
+        else if (meta[g].fsum) atomicAdd(as_ull(&cd.st->total_flop), (ull)meta[g].fsum);
     }
     const uint64_t Fs = block_sum<256, uint64_t>(F, s_red);
-    if (threadIdx.x == 0 && Fs) atomicAdd(as_ull(&cs[c].st->total_flop), (ull)Fs);
+    if (threadIdx.x == 0 && Fs) atomicAdd(as_ull(&cs[c0].st->total_flop), (ull)Fs);
 }
 
 // ------------------------------------------------------ prediction rows

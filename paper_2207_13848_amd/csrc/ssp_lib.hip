@@ -279,12 +279,12 @@ struct Plan {
     std::vector<CaseDesc> cs;
     std::vector<int64_t> rf_off;   // workspace row-FLOP offset per case, -1 = caller's
     std::vector<int> st_slot;      // workspace stats slot per case, -1 = caller's
-    int64_t cap13 = 1, cap4 = 1, cap5 = 1, ngroups = 0, tiles = 0, meta = 0, rowtmp = 0;
+    int64_t cap13 = 1, cap4 = 1, cap5 = 1, ngroups = 0, tiles = 0, rowtmp = 0;
     int32_t g_tiles = 0, g_flop = 0, g_fixup = 0, g_rows = 0;
     int32_t win_words_max = 4;
     bool win1 = true, vec = true;
     size_t o_ctl = 0, o_scratch = 0, o_b1 = 0, o_b2 = 0, o_b3 = 0, o_b4 = 0, o_merge = 0,
-           o_tiles = 0, o_meta = 0, o_samp = 0, o_cases = 0, o_res = 0, o_stats = 0,
+           o_tiles = 0, o_tcase = 0, o_meta = 0, o_samp = 0, o_cases = 0, o_res = 0, o_stats = 0,
            o_rowtmp = 0, total = 0;
 };
 
@@ -391,9 +391,7 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind)
         d.merge_per_row = mpr;
         d.ntiles = M > 0 ? flop_tiles(M, nnz) : 0;
         d.tile_base = P.tiles;
-        P.tiles += M > 0 ? d.ntiles + 1 : 0;
-        d.meta_base = P.meta;
-        P.meta += d.ntiles;
+        P.tiles += d.ntiles;
         if (!x.rf && kind != PLAN_EXACT) {
             P.rf_off[c] = P.rowtmp;
             P.rowtmp += M;
@@ -420,18 +418,12 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind)
     auto T = [&](int c) { return P.cs[c].ntiles; };
     P.g_tiles = share_wgs(n, 16LL * cus, Mof, [&](int c) { return (Mof(c) + 255) / 256; }, f);
     for (int c = 0; c < n; ++c) P.cs[c].wg_tiles = f[c];
+    (void)T;
+    // the streaming pass walks all tiles, case after case, with one persistent grid
     const int64_t rflop = P.vec ? resident(k_flop<FLOP_ONLY, true>, kFlopThreads, cus)
                                 : resident(k_flop<FLOP_ONLY, false>, kFlopThreads, cus);
-    P.g_flop = share_wgs(n, rflop, T, T, f);
-    for (int c = 0; c < n; ++c) P.cs[c].wg_flop = f[c];
-    {
-        int64_t g = 0;
-        for (int c = 0; c < n; ++c) {
-            P.cs[c].wg_fixup = (int32_t)g;
-            g += (P.cs[c].ntiles + 255) / 256;
-        }
-        P.g_fixup = (int32_t)g;
-    }
+    P.g_flop = (int32_t)std::min<int64_t>(rflop, P.tiles);
+    P.g_fixup = (int32_t)((P.tiles + 255) / 256);
     P.g_rows = share_wgs(n, std::max(1, cus / 2), Mof,
                          [&](int c) { return (Mof(c) + 4 * kRowsThreads - 1) / (4 * kRowsThreads); }, f);
     for (int c = 0; c < n; ++c) P.cs[c].wg_rows = f[c];
@@ -451,7 +443,8 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind)
     P.o_b4 = o;      o = align256(o + (size_t)P.cap4 * sizeof(BigItem));
     P.o_merge = o;   o = align256(o + (size_t)P.cap5 * sizeof(MergeItem));
     P.o_tiles = o;   o = align256(o + (size_t)std::max<int64_t>(P.tiles, 1) * sizeof(int32_t));
-    P.o_meta = o;    o = align256(o + (size_t)std::max<int64_t>(P.meta, 1) * sizeof(TileMeta));
+    P.o_tcase = o;   o = align256(o + (size_t)std::max<int64_t>(P.tiles, 1) * sizeof(int32_t));
+    P.o_meta = o;    o = align256(o + (size_t)std::max<int64_t>(P.tiles, 1) * sizeof(TileMeta));
     P.o_samp = o;    o = align256(o + (size_t)std::max<int64_t>(P.ngroups, 1) * sizeof(SampleCounts));
     P.o_cases = o;   o = align256(o + (size_t)n * sizeof(CaseDesc));
     P.o_res = o;     o = align256(o + (size_t)n * sizeof(CaseRes));
@@ -467,6 +460,7 @@ struct Bound {
     Ctl* ctl;
     BinLists L;
     int32_t* tile_row;
+    int32_t* tile_case;
     TileMeta* meta;
     SampleCounts* samp;
     CaseDesc* cs;
@@ -485,6 +479,7 @@ Bound bind_plan(Plan& P, void* ws)
     b.L.merge = reinterpret_cast<MergeItem*>(base + P.o_merge);
     b.L.scratch = reinterpret_cast<uint32_t*>(base + P.o_scratch);
     b.tile_row = reinterpret_cast<int32_t*>(base + P.o_tiles);
+    b.tile_case = reinterpret_cast<int32_t*>(base + P.o_tcase);
     b.meta = reinterpret_cast<TileMeta*>(base + P.o_meta);
     b.samp = reinterpret_cast<SampleCounts*>(base + P.o_samp);
     b.cs = reinterpret_cast<CaseDesc*>(base + P.o_cases);
@@ -506,21 +501,25 @@ void launch_flop(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s, boo
     {
         PhaseTimer pt(h, PH_TILES, s, timed);
         if (P.g_tiles > 0)
-            hipLaunchKernelGGL(k_tiles, dim3(P.g_tiles), dim3(256), 0, s, b.cs, P.n, b.tile_row);
+            hipLaunchKernelGGL(k_tiles, dim3(P.g_tiles), dim3(256), 0, s, b.cs, P.n, b.tile_row,
+                               b.tile_case);
     }
     if (P.g_flop > 0) {
         PhaseTimer pt(h, PH_FLOP, s, timed);
         if (P.vec)
             hipLaunchKernelGGL((k_flop<MODE, true>), dim3(P.g_flop), dim3(kFlopThreads), 0, s, b.cs,
-                               P.n, b.tile_row, b.meta, b.ctl, b.L);
+                               (const int32_t*)b.tile_row, (const int32_t*)b.tile_case, P.tiles,
+                               b.meta, b.ctl, b.L);
         else
-            hipLaunchKernelGGL((k_flop<MODE, false>), dim3(P.g_flop), dim3(kFlopThreads), 0, s, b.cs,
-                               P.n, b.tile_row, b.meta, b.ctl, b.L);
+            hipLaunchKernelGGL((k_flop<MODE, false>), dim3(P.g_flop), dim3(kFlopThreads), 0, s,
+                               b.cs, (const int32_t*)b.tile_row, (const int32_t*)b.tile_case,
+                               P.tiles, b.meta, b.ctl, b.L);
     }
     PhaseTimer pt(h, PH_FLOP_FIXUP, s, timed);
     if (P.g_fixup > 0)
-        hipLaunchKernelGGL((k_flop_fixup<MODE>), dim3(P.g_fixup), dim3(256), 0, s, b.cs, P.n,
-                           b.tile_row, b.meta, b.ctl, b.L);
+        hipLaunchKernelGGL((k_flop_fixup<MODE>), dim3(P.g_fixup), dim3(256), 0, s, b.cs,
+                           (const int32_t*)b.tile_row, (const int32_t*)b.tile_case, P.tiles,
+                           (const TileMeta*)b.meta, b.ctl, b.L);
 }
 
 void launch_sampling(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s, bool timed)
