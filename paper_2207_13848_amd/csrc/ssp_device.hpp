@@ -356,13 +356,26 @@ __device__ __forceinline__ void lane_bitmap_insert_all(uint32_t* bm, const uint3
     }
 }
 
+// Global-memory pointers (device code): see ssp_internal.hpp.
+#ifndef SSP_GLOBAL
+#ifdef __HIP_DEVICE_COMPILE__
+#define SSP_GLOBAL __attribute__((address_space(1)))
+#else
+#define SSP_GLOBAL
+#endif
+#endif
+
+// 8- and 16-byte vectors of int32 at 4-byte alignment, for wide loads of
+// CSR arrays at any entry
+typedef int32_t i32x2u __attribute__((ext_vector_type(2), aligned(4)));
+typedef int32_t i32x4u __attribute__((ext_vector_type(4), aligned(4)));
+
 // Length of row k of a CSR matrix from its row pointers: one 8-byte read
-// of rpt[k], rpt[k+1] (4-byte aligned).
-__device__ __forceinline__ uint32_t csr_row_len(const int32_t* __restrict__ rpt, int32_t k)
+// of rpt[k], rpt[k+1].
+__device__ __forceinline__ uint32_t csr_row_len(const SSP_GLOBAL int32_t* __restrict__ rpt,
+                                                int32_t k)
 {
-    typedef int32_t i32x2 __attribute__((ext_vector_type(2)));
-    i32x2 v;
-    __builtin_memcpy(&v, rpt + k, sizeof(v));
+    const i32x2u v = *(const SSP_GLOBAL i32x2u*)(rpt + k);
     return (uint32_t)(v.y - v.x);
 }
 

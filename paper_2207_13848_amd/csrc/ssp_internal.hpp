@@ -40,9 +40,22 @@ constexpr int64_t kFlopTile = 2040;
 // serialise, atomics on distinct addresses do not.  k_finalize sums them.
 constexpr int kAccSlots = 64;
 
+// Device code sees the arrays of a case as global-memory pointers.  Read from
+// the case table (itself in global memory) they would otherwise be generic to
+// the compiler, which then emits flat accesses; a flat load counts against the
+// LDS counter as well, so every wait for an LDS result would also wait for it.
+// The host sees plain pointers of the same size.
+#ifndef SSP_GLOBAL
+#ifdef __HIP_DEVICE_COMPILE__
+#define SSP_GLOBAL __attribute__((address_space(1)))
+#else
+#define SSP_GLOBAL
+#endif
+#endif
+
 struct Csr {
-    const int32_t* rpt;
-    const int32_t* col;
+    const SSP_GLOBAL int32_t* rpt;
+    const SSP_GLOBAL int32_t* col;
     int64_t nrows, ncols, nnz;
 };
 
@@ -52,8 +65,8 @@ struct Csr {
 // case index an item carries.
 struct CaseDesc {
     Csr A, B;
-    int64_t* out;        // per-row output (prediction, reference or exact counts)
-    int64_t* rf;         // per-row FLOP (the caller's array or workspace)
+    SSP_GLOBAL int64_t* out;  // per-row output (prediction, reference or exact counts)
+    SSP_GLOBAL int64_t* rf;   // per-row FLOP (the caller's array or workspace)
     ssp_stats* st;       // statistics (the caller's, or the case's workspace slot)
     uint64_t seed, thresh;
     int64_t ncand;       // sampling candidates: rows (Bernoulli) or draws (paper)
@@ -89,7 +102,8 @@ struct CaseRes {
 // Control block at the start of the workspace (device memory): the shared
 // lists of a call and their counters.
 struct Ctl {
-    uint32_t bin_cnt[8];  // items in bins 1..4 (index = bin), merge items at 5
+    uint32_t bin_cnt[8];  // items in bins 1..4 (index = bin; bin 4: the heavy items),
+                          // merge items at 5, light bin-4 items at 6
     uint32_t pw_ctr;      // part windows handed out (exact path)
     uint32_t big_next;    // work queue of the long-row kernel
     uint32_t pad[22];
@@ -124,15 +138,21 @@ struct MergeItem {  // one slice of one window of a split row
 // Per-group counters of the sampling passes.  k_sample_count writes
 //   c[0..2] rows of bins 1..3, c[3] rows of bin 4, c[4] bin-4 items if its
 //   split-eligible rows are split, c[5] their merge items, c[6] part windows
-//   they request; ns, fs, as: sampled rows, their products, their A entries;
+//   they request, c[7] the case; ns, fs, as: sampled rows, their products,
+//   their A entries; ne: split-eligible rows; nh: heavy bin-4 rows (above a
+//   quarter of the split target; the eligible rows among them);
 // k_sample_scan rewrites them in place as
-//   c[0..2] offsets in bins 1..3, c[3] offset in bin 4, c[4] offset in the
-//   merge list, c[5] first part window, c[6] 1 if the rows are split;
+//   c[0..2] offsets in bins 1..3, c[3] offset among the heavy bin-4 items,
+//   c[4] offset in the merge list, c[5] first part window, c[6] 1 if the rows
+//   are split, ne: offset among the light bin-4 items;
 //   ns, fs, as: inclusive prefixes over all groups of the call.
 struct SampleCounts {
     uint32_t c[8];
-    uint64_t ns, fs, as, pad;
+    uint64_t ns, fs, as;
+    uint32_t ne, nh;
 };
+// Bin-4 rows above split_target >> kHeavyShift products are heavy.
+constexpr int kHeavyShift = 2;
 constexpr int kSampleTarget = 8192; // sampling groups of a call, about (at least 1 per case)
 
 struct TileMeta {   // per streaming tile

@@ -30,7 +30,19 @@ struct BinLists {
     BigItem* b4;
     MergeItem* merge;
     uint32_t* scratch; // kMaxPartWindows windows of kWinWords words
+    // Bin 4 holds its heavy items from the front (parts of split rows, and
+    // rows above a quarter of the split target) and the light ones from the
+    // back (light item i at cap4 - 1 - i): the long-row kernel takes the
+    // heavy ones first, so the last items taken are short.
+    uint32_t cap4;
 };
+
+// Queue position k of the long-row kernel -> bin-4 list index, given the
+// count of heavy items.
+__device__ __forceinline__ uint32_t big_index(uint32_t k, uint32_t nheavy, uint32_t cap4)
+{
+    return k < nheavy ? k : cap4 - 1u - (k - nheavy);
+}
 
 // The case of workgroup `wg` in a grid whose workgroups serve one case each:
 // the last case whose first workgroup (field F) is at or before wg.
@@ -180,7 +192,9 @@ __device__ inline void append_big(int32_t row, uint64_t rf, int32_t e0, int32_t 
             nparts = (int32_t)want;
         }
     }
-    const uint32_t base = atomicAdd(&ctl->bin_cnt[4], (uint32_t)nparts);
+    const bool heavy = nparts > 1 || rf > (T >> kHeavyShift);
+    const uint32_t base = heavy ? atomicAdd(&ctl->bin_cnt[4], (uint32_t)nparts)
+                                : L.cap4 - 1u - atomicAdd(&ctl->bin_cnt[6], 1u);
     for (int32_t p = 0; p < nparts; ++p) {
         BigItem it;
         it.row = row;
@@ -276,7 +290,7 @@ constexpr int kSampleThreads = 256;
 // Sampler parameters of a case, in registers.
 struct SamplerArgs {
     Csr A;
-    const int64_t* rf;
+    const SSP_GLOBAL int64_t* rf;
     uint64_t seed, thresh;
     int64_t ncand;
     int32_t paper, nwin, big3, merge_per_row;
@@ -326,6 +340,7 @@ struct SampledRow {
     int bin;
     uint32_t want;  // parts when split (1 unless eligible)
     bool elig;
+    bool heavy;     // bin 4 above split_target >> kHeavyShift (eligible rows are)
 };
 
 __device__ __forceinline__ SampledRow classify_row(int64_t g, const SamplerArgs& a)
@@ -337,6 +352,7 @@ __device__ __forceinline__ SampledRow classify_row(int64_t g, const SamplerArgs&
     r.bin = 0;
     r.want = 1;
     r.elig = false;
+    r.heavy = false;
     if (g < 0) return r;
     r.rf = (uint64_t)a.rf[g];
     r.e0 = a.A.rpt[g];
@@ -344,6 +360,7 @@ __device__ __forceinline__ SampledRow classify_row(int64_t g, const SamplerArgs&
     const int b = bin_of(r.rf, a.bin_max);
     r.bin = (b == 3 && a.big3) ? 4 : b;
     const int64_t alen = (int64_t)r.e1 - r.e0;
+    r.heavy = r.bin == 4 && r.rf > (a.split_target >> kHeavyShift);
     if (r.bin == 4 && r.rf > a.split_target && a.nwin <= kMaxSplitWindows && alen > 1) {
         uint64_t want = (r.rf + a.split_target - 1) / a.split_target;
         if (want > (uint64_t)kMaxParts) want = kMaxParts;
@@ -391,6 +408,7 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc*
     const SamplerArgs a = sampler_args(cs[gr.c]);
     uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
     uint64_t ns = 0, fs = 0, as = 0;
+    uint32_t ne = 0, nh = 0;
     for (int64_t i = gr.lo + threadIdx.x; i < gr.hi; i += NT) {
         const SampledRow r = classify_row(candidate_row(i, a), a);
         if (r.g < 0) continue;
@@ -403,7 +421,9 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc*
         if (r.bin == 4) {
             c[3] += 1;
             c[4] += r.want;
+            nh += r.heavy;
             if (r.elig) {
+                ne += 1;
                 c[5] += (uint32_t)a.merge_per_row;
                 c[6] += r.want * (uint32_t)a.nwin;
             }
@@ -415,6 +435,8 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc*
     const uint64_t Ns = block_sum<NT, uint64_t>(ns, s_red);
     const uint64_t Fs = block_sum<NT, uint64_t>(fs, s_red);
     const uint64_t As = block_sum<NT, uint64_t>(as, s_red);
+    const uint32_t Ne = (uint32_t)block_sum<NT, uint64_t>(ne, s_red);
+    const uint32_t Nh = (uint32_t)block_sum<NT, uint64_t>(nh, s_red);
     if (threadIdx.x == 0) {
         SampleCounts o;
 #pragma unroll
@@ -423,7 +445,8 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc*
         o.ns = Ns;
         o.fs = Fs;
         o.as = As;
-        o.pad = 0;
+        o.ne = Ne;
+        o.nh = Nh;
         cnt[blockIdx.x] = o;
     }
 }
@@ -444,22 +467,27 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
     __shared__ uint64_t s_red[NT / kWave + 1];
     __shared__ uint64_t s_e[3][NT];  // exclusive prefixes of ns, fs, as in the chunk
     const int t = threadIdx.x;
-    uint64_t k01 = 0, k2w = 0, k4m = 0;  // carries, two u32 fields each
+    uint64_t k01 = 0, k2w = 0, k4 = 0, km = 0;  // carries (k01, k2w, k4: two u32 fields)
     for (int64_t g0 = 0; g0 < ngroups; g0 += NT) {
         const int64_t g = g0 + t;
         SampleCounts x{};
         if (g < ngroups) x = cnt[g];
-        uint64_t t01, t2w, t4m, tns, tfs, tas;
+        uint64_t t01, t2w, tns, tfs, tas;
         const uint64_t p01 = k01 + block_excl_scan<NT, uint64_t>(
                                        (uint64_t)x.c[0] | ((uint64_t)x.c[1] << 32), s_red, &t01);
         const uint64_t p2w = k2w + block_excl_scan<NT, uint64_t>(
                                        (uint64_t)x.c[2] | ((uint64_t)x.c[6] << 32), s_red, &t2w);
         const uint32_t wpre = (uint32_t)(p2w >> 32);
         const bool split = x.c[6] != 0 && (uint64_t)wpre + x.c[6] <= (uint64_t)kMaxPartWindows;
-        const uint32_t n4 = split ? x.c[4] : x.c[3];
+        // bin 4: heavy items (front: parts of split rows, heavy unsplit rows)
+        // and light rows (back); eligible rows are heavy
+        const uint32_t nf = split ? x.c[4] - x.c[3] + x.nh : x.nh;
+        const uint32_t nb = x.c[3] - x.nh;
         const uint32_t nm = split ? x.c[5] : 0u;
-        const uint64_t p4m =
-            k4m + block_excl_scan<NT, uint64_t>((uint64_t)n4 | ((uint64_t)nm << 32), s_red, &t4m);
+        uint64_t t4, tm;
+        const uint64_t p4 =
+            k4 + block_excl_scan<NT, uint64_t>((uint64_t)nf | ((uint64_t)nb << 32), s_red, &t4);
+        const uint64_t pm = km + block_excl_scan<NT, uint64_t>((uint64_t)nm, s_red, &tm);
         const uint64_t ens = block_excl_scan<NT, uint64_t>(x.ns, s_red, &tns);
         const uint64_t efs = block_excl_scan<NT, uint64_t>(x.fs, s_red, &tfs);
         const uint64_t eas = block_excl_scan<NT, uint64_t>(x.as, s_red, &tas);
@@ -472,10 +500,11 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
             o.c[0] = (uint32_t)p01;
             o.c[1] = (uint32_t)(p01 >> 32);
             o.c[2] = (uint32_t)p2w;
-            o.c[3] = (uint32_t)p4m;
-            o.c[4] = (uint32_t)(p4m >> 32);
+            o.c[3] = (uint32_t)p4;
+            o.c[4] = (uint32_t)pm;
             o.c[5] = wpre;
             o.c[6] = split ? 1u : 0u;
+            o.ne = (uint32_t)(p4 >> 32);
             cnt[g] = o;
             // the last group of its case in this chunk adds the case's part
             const int c = (int)x.c[7];
@@ -494,14 +523,16 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
         __syncthreads();  // s_e is rewritten by the next chunk
         k01 += t01;
         k2w += t2w;
-        k4m += t4m;
+        k4 += t4;
+        km += tm;
     }
     if (t == 0) {
         ctl->bin_cnt[1] = (uint32_t)k01;
         ctl->bin_cnt[2] = (uint32_t)(k01 >> 32);
         ctl->bin_cnt[3] = (uint32_t)k2w;
-        ctl->bin_cnt[4] = (uint32_t)k4m;
-        ctl->bin_cnt[5] = (uint32_t)(k4m >> 32);
+        ctl->bin_cnt[4] = (uint32_t)k4;
+        ctl->bin_cnt[5] = (uint32_t)km;
+        ctl->bin_cnt[6] = (uint32_t)(k4 >> 32);
     }
 }
 
@@ -521,19 +552,23 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_write(const CaseDesc*
     const SampleCounts o = cnt[blockIdx.x];
     const bool split = o.c[6] != 0;
     uint32_t off1 = o.c[0], off2 = o.c[1], off3 = o.c[2], off4 = o.c[3], offm = o.c[4],
-             offw = o.c[5];
+             offw = o.c[5], offb = o.ne;
     for (int64_t i0 = gr.lo; i0 < gr.hi; i0 += NT) {  // same trip count in every lane (scans)
         const int64_t i = i0 + t;
         const SampledRow r = classify_row(i < gr.hi ? candidate_row(i, a) : -1, a);
         const bool sp = split && r.elig;
         const uint32_t n4 = r.bin == 4 ? (sp ? r.want : 1u) : 0u;
+        const uint32_t nf = r.heavy ? n4 : 0u, nb = r.bin == 4 && !r.heavy ? 1u : 0u;
         const uint32_t nm = sp ? (uint32_t)a.merge_per_row : 0u;
         const uint32_t nw = sp ? r.want * (uint32_t)a.nwin : 0u;
         uint64_t t01, t34, tmw;
+        // bins 1, 2 and light bin-4 rows in 21-bit fields (at most NT each)
+        static_assert(NT < (1 << 21), "21-bit scan fields");
         const uint64_t p01 = block_excl_scan<NT, uint64_t>(
-            (uint64_t)(r.bin == 1) | ((uint64_t)(r.bin == 2) << 32), s_red, &t01);
+            (uint64_t)(r.bin == 1) | ((uint64_t)(r.bin == 2) << 21) | ((uint64_t)nb << 42), s_red,
+            &t01);
         const uint64_t p34 = block_excl_scan<NT, uint64_t>(
-            (uint64_t)(r.bin == 3) | ((uint64_t)n4 << 32), s_red, &t34);
+            (uint64_t)(r.bin == 3) | ((uint64_t)nf << 32), s_red, &t34);
         const uint64_t pmw = block_excl_scan<NT, uint64_t>((uint64_t)nm | ((uint64_t)nw << 32),
                                                            s_red, &tmw);
         if (r.bin >= 1 && r.bin <= 3) {
@@ -542,11 +577,12 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_write(const CaseDesc*
             it.rf = (uint32_t)r.rf;
             it.cs = gr.c;
             it.pad = 0;
-            if (r.bin == 1) L.b1[off1 + (uint32_t)p01] = it;
-            else if (r.bin == 2) L.b2[off2 + (uint32_t)(p01 >> 32)] = it;
+            if (r.bin == 1) L.b1[off1 + (uint32_t)(p01 & 0x1FFFFF)] = it;
+            else if (r.bin == 2) L.b2[off2 + (uint32_t)((p01 >> 21) & 0x1FFFFF)] = it;
             else L.b3[off3 + (uint32_t)p34] = it;
         } else if (r.bin == 4) {
-            const uint32_t base = off4 + (uint32_t)(p34 >> 32);
+            const uint32_t base = r.heavy ? off4 + (uint32_t)(p34 >> 32)
+                                          : L.cap4 - 1u - (offb + (uint32_t)(p01 >> 42));
             const int32_t slot = sp ? (int32_t)(offw + (uint32_t)(pmw >> 32)) : -1;
             for (uint32_t p = 0; p < n4; ++p) {
                 BigItem it;
@@ -563,8 +599,9 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_write(const CaseDesc*
             if (sp) write_merge_items(L.merge + offm + (uint32_t)pmw, (int32_t)r.g, slot,
                                       (int32_t)n4, gr.c, cs[gr.c]);
         }
-        off1 += (uint32_t)t01;
-        off2 += (uint32_t)(t01 >> 32);
+        off1 += (uint32_t)(t01 & 0x1FFFFF);
+        off2 += (uint32_t)((t01 >> 21) & 0x1FFFFF);
+        offb += (uint32_t)(t01 >> 42);
         off3 += (uint32_t)t34;
         off4 += (uint32_t)(t34 >> 32);
         offm += (uint32_t)tmw;
@@ -728,18 +765,20 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
     __shared__ uint64_t s_start[TEAM]; // short: first product; long: first unit
     __shared__ uint64_t s_red[TEAM / kWave + 1];
     __shared__ uint32_t s_it;
-    const uint32_t n = *count;
+    const uint32_t nheavy = count[0], n = nheavy + count[2];  // heavy, light items
     const int t = threadIdx.x, lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(t / kWave);
     int zc = -1;  // case of zsum
     uint64_t zsum = 0;
-    for (;;) {  // work queue: items are taken one at a time as workgroups free up
-        if (t == 0) s_it = atomicAdd(next, 1u);
-        __syncthreads();
-        const uint32_t it = s_it;
-        __syncthreads();
+    // Work queue: items are taken one at a time as workgroups free up; the
+    // ticket of the next item is taken as the last pass over the current one
+    // begins.
+    if (t == 0) s_it = atomicAdd(next, 1u);
+    __syncthreads();
+    uint32_t it = __builtin_amdgcn_readfirstlane(s_it);
+    for (;;) {
         if (it >= n) break;
-        const BigItem item = items[it];
+        const BigItem item = items[big_index(it, nheavy, L.cap4)];
         if (item.cs != zc) {
             if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
             zsum = 0;
@@ -826,7 +865,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
                     auto issue = [&](i32x4& v, bool& ok) {
                         const uint32_t base = ui * kUnitCols + 4u * lane;
                         const uint32_t off = base < elen - 4u ? base : elen - 4u;
-                        __builtin_memcpy(&v, B.col + eb0 + off, sizeof(v));
+                        v = *(const SSP_GLOBAL i32x4u*)(B.col + eb0 + off);
                         ok = base < elen;
                         __builtin_amdgcn_sched_barrier(0);  // keep the load ahead of the inserts
                     };
@@ -892,6 +931,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
                 }
                 __syncthreads();
             }
+            if (w == nwin - 1 && t == 0) s_it = atomicAdd(next, 1u);  // read after the barrier below
             // 16-byte LDS reads, eight issued before any is used (a loop of
             // single reads would wait on each)
             constexpr int UR = 8;
@@ -932,6 +972,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
             zsum += total;
             if (MODE == 1) atomicAdd(reinterpret_cast<ull*>(&cs[zc].out[item.row]), (ull)total);
         }
+        it = __builtin_amdgcn_readfirstlane(s_it);
     }
     if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
 }
@@ -1097,9 +1138,9 @@ __device__ __forceinline__ void emit_row(const CaseDesc* __restrict__ cs, int c,
 struct FlopTileRegs {
     int64_t g;        // global tile
     int32_t c;        // its case
-    const int32_t* Arpt;
-    const int32_t* Brpt;
-    int64_t* out;
+    const SSP_GLOBAL int32_t* Arpt;
+    const SSP_GLOBAL int32_t* Brpt;
+    SSP_GLOBAL int64_t* out;
     int64_t M, nnzA;
     int64_t i0, i1, j0, j1, a0;
     int4 col[2];   // as loaded; shifted by sh[q] positions when the load was clamped
@@ -1133,7 +1174,7 @@ __device__ __forceinline__ void flop_issue_tile(const CaseDesc* __restrict__ cs,
     R.Arpt = cd.A.rpt;
     R.Brpt = cd.B.rpt;
     R.out = MODE == FLOP_ONLY ? cd.rf : cd.out;
-    const int32_t* Acol = cd.A.col;
+    const SSP_GLOBAL int32_t* Acol = cd.A.col;
     const int64_t M = cd.A.nrows, nnzA = cd.A.nnz;
     R.M = M;
     R.nnzA = nnzA;
@@ -1244,7 +1285,7 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restric
         // 1. gathers of the current tile
         const int64_t i0 = cur.i0, i1 = cur.i1, j0 = cur.j0, j1 = cur.j1, a0 = cur.a0;
         const int64_t M = cur.M;
-        const int32_t* __restrict__ Brpt = cur.Brpt;
+        const SSP_GLOBAL int32_t* __restrict__ Brpt = cur.Brpt;
         uint32_t x[8];
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
@@ -1422,8 +1463,8 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __re
     const int c = case_of_wg<&CaseDesc::wg_rows>(cs, n, blockIdx.x);
     const int64_t bl = (int64_t)blockIdx.x - cs[c].wg_rows;
     const int64_t G = wgs_of_case<&CaseDesc::wg_rows>(cs, n, c);
-    const int64_t* __restrict__ rf_in = cs[c].rf;
-    int64_t* __restrict__ out = cs[c].out;
+    const SSP_GLOBAL int64_t* __restrict__ rf_in = cs[c].rf;
+    SSP_GLOBAL int64_t* __restrict__ out = cs[c].out;
     const int64_t M = cs[c].A.nrows;
     ssp_stats* st = cs[c].st;
     const uint32_t fallback = cr[c].fallback;
@@ -1467,8 +1508,8 @@ __global__ __launch_bounds__(kRowsThreads) void k_ref_rows(const CaseDesc* __res
     const int c = case_of_wg<&CaseDesc::wg_rows>(cs, n, blockIdx.x);
     const int64_t bl = (int64_t)blockIdx.x - cs[c].wg_rows;
     const int64_t G = wgs_of_case<&CaseDesc::wg_rows>(cs, n, c);
-    const int64_t* __restrict__ rf_in = cs[c].rf;
-    int64_t* __restrict__ out = cs[c].out;
+    const SSP_GLOBAL int64_t* __restrict__ rf_in = cs[c].rf;
+    SSP_GLOBAL int64_t* __restrict__ out = cs[c].out;
     const int64_t M = cs[c].A.nrows;
     ssp_stats* st = cs[c].st;
     const uint32_t fallback = cr[c].fallback;

@@ -204,8 +204,8 @@ ssp_status check_pair(const ssp_csr* A, const ssp_csr* B)
 Csr to_csr(const ssp_csr* m)
 {
     Csr c;
-    c.rpt = m->rpt;
-    c.col = m->col;
+    c.rpt = (decltype(c.rpt))m->rpt;
+    c.col = (decltype(c.col))m->col;
     c.nrows = m->nrows;
     c.ncols = m->ncols;
     c.nnz = m->nnz;
@@ -364,8 +364,8 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind)
         const int64_t M = x.A.nrows, nnz = x.A.nnz, N = x.B.ncols;
         d.A = x.A;
         d.B = x.B;
-        d.out = x.out;
-        d.rf = x.rf;
+        d.out = (decltype(d.out))x.out;
+        d.rf = (decltype(d.rf))x.rf;
         d.st = x.st;
         d.seed = x.seed;
         d.paper = x.sampler == SSP_SAMPLER_PAPER ? 1 : 0;
@@ -478,6 +478,7 @@ Bound bind_plan(Plan& P, void* ws)
     b.L.b4 = reinterpret_cast<BigItem*>(base + P.o_b4);
     b.L.merge = reinterpret_cast<MergeItem*>(base + P.o_merge);
     b.L.scratch = reinterpret_cast<uint32_t*>(base + P.o_scratch);
+    b.L.cap4 = (uint32_t)P.cap4;
     b.tile_row = reinterpret_cast<int32_t*>(base + P.o_tiles);
     b.tile_case = reinterpret_cast<int32_t*>(base + P.o_tcase);
     b.meta = reinterpret_cast<TileMeta*>(base + P.o_meta);
@@ -487,7 +488,7 @@ Bound bind_plan(Plan& P, void* ws)
     ssp_stats* stats = reinterpret_cast<ssp_stats*>(base + P.o_stats);
     int64_t* rowtmp = reinterpret_cast<int64_t*>(base + P.o_rowtmp);
     for (int c = 0; c < P.n; ++c) {
-        if (P.rf_off[c] >= 0) P.cs[c].rf = rowtmp + P.rf_off[c];
+        if (P.rf_off[c] >= 0) P.cs[c].rf = (decltype(P.cs[c].rf))(rowtmp + P.rf_off[c]);
         if (P.st_slot[c] >= 0) P.cs[c].st = stats + P.st_slot[c];
     }
     return b;
