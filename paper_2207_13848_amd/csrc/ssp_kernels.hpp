@@ -395,6 +395,34 @@ __device__ __forceinline__ GroupRange group_range(const CaseDesc* __restrict__ c
     return r;
 }
 
+// The sampled rows of a group, a round of NT * kCandPerThread candidates at a
+// time, in candidate order: thread t draws candidates base + 8t .. base + 8t
+// + 7 and a workgroup scan places the sampled ones in `rows` (LDS).  With a
+// sparse sample a round yields few rows, and the per-row work of the passes
+// (scans included) runs over those, not over every candidate.  Returns the
+// count (uniform); ends with a barrier.
+constexpr int kCandPerThread = 8;
+template <int NT>
+__device__ __forceinline__ int gather_sampled(int64_t base, int64_t hi, const SamplerArgs& a,
+                                              int64_t* rows, uint64_t* s_red)
+{
+    int64_t g[kCandPerThread];
+    uint32_t n = 0;
+#pragma unroll
+    for (int u = 0; u < kCandPerThread; ++u) {
+        const int64_t i = base + (int64_t)threadIdx.x * kCandPerThread + u;
+        g[u] = i < hi ? candidate_row(i, a) : -1;
+        n += g[u] >= 0 ? 1u : 0u;
+    }
+    uint64_t tot;
+    uint32_t pos = (uint32_t)block_excl_scan<NT, uint64_t>(n, s_red, &tot);
+#pragma unroll
+    for (int u = 0; u < kCandPerThread; ++u)
+        if (g[u] >= 0) rows[pos++] = g[u];
+    __syncthreads();
+    return (int)tot;
+}
+
 // Pass 1: per group, the counts of SampleCounts and the sums of n_s, f* and
 // the sample's A entries.  No atomics: the passes hand over per-group
 // counters (same-address device atomics serialise on this part).
@@ -404,28 +432,31 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc*
 {
     constexpr int NT = kSampleThreads;
     __shared__ uint64_t s_red[NT / kWave + 1];
+    __shared__ int64_t s_rows[NT * kCandPerThread];
     const GroupRange gr = group_range(cs, n, blockIdx.x);
     const SamplerArgs a = sampler_args(cs[gr.c]);
     uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
     uint64_t ns = 0, fs = 0, as = 0;
     uint32_t ne = 0, nh = 0;
-    for (int64_t i = gr.lo + threadIdx.x; i < gr.hi; i += NT) {
-        const SampledRow r = classify_row(candidate_row(i, a), a);
-        if (r.g < 0) continue;
-        ns += 1;
-        fs += r.rf;
-        as += (uint64_t)(r.e1 - r.e0);
-        c[0] += r.bin == 1;  // (selects, not an index: c stays in registers)
-        c[1] += r.bin == 2;
-        c[2] += r.bin == 3;
-        if (r.bin == 4) {
-            c[3] += 1;
-            c[4] += r.want;
-            nh += r.heavy;
-            if (r.elig) {
-                ne += 1;
-                c[5] += (uint32_t)a.merge_per_row;
-                c[6] += r.want * (uint32_t)a.nwin;
+    for (int64_t base = gr.lo; base < gr.hi; base += NT * kCandPerThread) {
+        const int nr = gather_sampled<NT>(base, gr.hi, a, s_rows, s_red);
+        for (int k = threadIdx.x; k < nr; k += NT) {
+            const SampledRow r = classify_row(s_rows[k], a);
+            ns += 1;
+            fs += r.rf;
+            as += (uint64_t)(r.e1 - r.e0);
+            c[0] += r.bin == 1;  // (selects, not an index: c stays in registers)
+            c[1] += r.bin == 2;
+            c[2] += r.bin == 3;
+            if (r.bin == 4) {
+                c[3] += 1;
+                c[4] += r.want;
+                nh += r.heavy;
+                if (r.elig) {
+                    ne += 1;
+                    c[5] += (uint32_t)a.merge_per_row;
+                    c[6] += r.want * (uint32_t)a.nwin;
+                }
             }
         }
     }
@@ -545,6 +576,7 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_write(const CaseDesc*
 {
     constexpr int NT = kSampleThreads;
     __shared__ uint64_t s_red[NT / kWave + 1];
+    __shared__ int64_t s_rows[NT * kCandPerThread];
     const int t = threadIdx.x;
     const GroupRange gr = group_range(cs, n, blockIdx.x);
     if (gr.lo >= gr.hi) return;  // (uniform over the workgroup)
@@ -553,59 +585,61 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_write(const CaseDesc*
     const bool split = o.c[6] != 0;
     uint32_t off1 = o.c[0], off2 = o.c[1], off3 = o.c[2], off4 = o.c[3], offm = o.c[4],
              offw = o.c[5], offb = o.ne;
-    for (int64_t i0 = gr.lo; i0 < gr.hi; i0 += NT) {  // same trip count in every lane (scans)
-        const int64_t i = i0 + t;
-        const SampledRow r = classify_row(i < gr.hi ? candidate_row(i, a) : -1, a);
-        const bool sp = split && r.elig;
-        const uint32_t n4 = r.bin == 4 ? (sp ? r.want : 1u) : 0u;
-        const uint32_t nf = r.heavy ? n4 : 0u, nb = r.bin == 4 && !r.heavy ? 1u : 0u;
-        const uint32_t nm = sp ? (uint32_t)a.merge_per_row : 0u;
-        const uint32_t nw = sp ? r.want * (uint32_t)a.nwin : 0u;
-        uint64_t t01, t34, tmw;
-        // bins 1, 2 and light bin-4 rows in 21-bit fields (at most NT each)
-        static_assert(NT < (1 << 21), "21-bit scan fields");
-        const uint64_t p01 = block_excl_scan<NT, uint64_t>(
-            (uint64_t)(r.bin == 1) | ((uint64_t)(r.bin == 2) << 21) | ((uint64_t)nb << 42), s_red,
-            &t01);
-        const uint64_t p34 = block_excl_scan<NT, uint64_t>(
-            (uint64_t)(r.bin == 3) | ((uint64_t)nf << 32), s_red, &t34);
-        const uint64_t pmw = block_excl_scan<NT, uint64_t>((uint64_t)nm | ((uint64_t)nw << 32),
-                                                           s_red, &tmw);
-        if (r.bin >= 1 && r.bin <= 3) {
-            BinItem it;
-            it.row = (int32_t)r.g;
-            it.rf = (uint32_t)r.rf;
-            it.cs = gr.c;
-            it.pad = 0;
-            if (r.bin == 1) L.b1[off1 + (uint32_t)(p01 & 0x1FFFFF)] = it;
-            else if (r.bin == 2) L.b2[off2 + (uint32_t)((p01 >> 21) & 0x1FFFFF)] = it;
-            else L.b3[off3 + (uint32_t)p34] = it;
-        } else if (r.bin == 4) {
-            const uint32_t base = r.heavy ? off4 + (uint32_t)(p34 >> 32)
-                                          : L.cap4 - 1u - (offb + (uint32_t)(p01 >> 42));
-            const int32_t slot = sp ? (int32_t)(offw + (uint32_t)(pmw >> 32)) : -1;
-            for (uint32_t p = 0; p < n4; ++p) {
-                BigItem it;
+    for (int64_t base = gr.lo; base < gr.hi; base += NT * kCandPerThread) {
+        const int nr = gather_sampled<NT>(base, gr.hi, a, s_rows, s_red);
+        for (int k0 = 0; k0 < nr; k0 += NT) {  // same trip count in every lane (scans)
+            const SampledRow r = classify_row(k0 + t < nr ? s_rows[k0 + t] : -1, a);
+            const bool sp = split && r.elig;
+            const uint32_t n4 = r.bin == 4 ? (sp ? r.want : 1u) : 0u;
+            const uint32_t nf = r.heavy ? n4 : 0u, nb = r.bin == 4 && !r.heavy ? 1u : 0u;
+            const uint32_t nm = sp ? (uint32_t)a.merge_per_row : 0u;
+            const uint32_t nw = sp ? r.want * (uint32_t)a.nwin : 0u;
+            uint64_t t01, t34, tmw;
+            // bins 1, 2 and light bin-4 rows in 21-bit fields (at most NT each)
+            static_assert(NT < (1 << 21), "21-bit scan fields");
+            const uint64_t f01 =
+                (uint64_t)(r.bin == 1) | ((uint64_t)(r.bin == 2) << 21) | ((uint64_t)nb << 42);
+            const uint64_t p01 = block_excl_scan<NT, uint64_t>(f01, s_red, &t01);
+            const uint64_t p34 = block_excl_scan<NT, uint64_t>(
+                (uint64_t)(r.bin == 3) | ((uint64_t)nf << 32), s_red, &t34);
+            const uint64_t pmw = block_excl_scan<NT, uint64_t>((uint64_t)nm | ((uint64_t)nw << 32),
+                                                               s_red, &tmw);
+            if (r.bin >= 1 && r.bin <= 3) {
+                BinItem it;
                 it.row = (int32_t)r.g;
-                it.slot = slot;
-                it.part = (int32_t)p;
-                it.nparts = (int32_t)n4;
-                it.e_lo = r.e0;
-                it.e_hi = r.e1;
+                it.rf = (uint32_t)r.rf;
                 it.cs = gr.c;
                 it.pad = 0;
-                L.b4[base + p] = it;
+                if (r.bin == 1) L.b1[off1 + (uint32_t)(p01 & 0x1FFFFF)] = it;
+                else if (r.bin == 2) L.b2[off2 + (uint32_t)((p01 >> 21) & 0x1FFFFF)] = it;
+                else L.b3[off3 + (uint32_t)p34] = it;
+            } else if (r.bin == 4) {
+                const uint32_t at = r.heavy ? off4 + (uint32_t)(p34 >> 32)
+                                            : L.cap4 - 1u - (offb + (uint32_t)(p01 >> 42));
+                const int32_t slot = sp ? (int32_t)(offw + (uint32_t)(pmw >> 32)) : -1;
+                for (uint32_t p = 0; p < n4; ++p) {
+                    BigItem it;
+                    it.row = (int32_t)r.g;
+                    it.slot = slot;
+                    it.part = (int32_t)p;
+                    it.nparts = (int32_t)n4;
+                    it.e_lo = r.e0;
+                    it.e_hi = r.e1;
+                    it.cs = gr.c;
+                    it.pad = 0;
+                    L.b4[at + p] = it;
+                }
+                if (sp) write_merge_items(L.merge + offm + (uint32_t)pmw, (int32_t)r.g, slot,
+                                          (int32_t)n4, gr.c, cs[gr.c]);
             }
-            if (sp) write_merge_items(L.merge + offm + (uint32_t)pmw, (int32_t)r.g, slot,
-                                      (int32_t)n4, gr.c, cs[gr.c]);
+            off1 += (uint32_t)(t01 & 0x1FFFFF);
+            off2 += (uint32_t)((t01 >> 21) & 0x1FFFFF);
+            offb += (uint32_t)(t01 >> 42);
+            off3 += (uint32_t)t34;
+            off4 += (uint32_t)(t34 >> 32);
+            offm += (uint32_t)tmw;
+            offw += (uint32_t)(tmw >> 32);
         }
-        off1 += (uint32_t)(t01 & 0x1FFFFF);
-        off2 += (uint32_t)((t01 >> 21) & 0x1FFFFF);
-        offb += (uint32_t)(t01 >> 42);
-        off3 += (uint32_t)t34;
-        off4 += (uint32_t)(t34 >> 32);
-        offm += (uint32_t)tmw;
-        offw += (uint32_t)(tmw >> 32);
     }
 }
 
