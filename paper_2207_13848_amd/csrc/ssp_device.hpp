@@ -169,48 +169,114 @@ __device__ inline u128 u128_ceil_div(u128 n, u128 d)
 
 __device__ __forceinline__ int lane_id() { return threadIdx.x & (kWave - 1); }
 
+// Lane shifts by DPP: VALU data movement, which (unlike __shfl_*, a
+// ds_bpermute through the LDS crossbar) takes no LDS bandwidth from the other
+// waves of the workgroup.  Lanes whose source lies outside the row read 0
+// (bound_ctrl); lanes of rows left out by ROW_MASK get 0 (the `old` value).
+// Every lane of the wave must be active.
+template <int CTRL, int ROW_MASK>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t v)
+{
+    return (uint32_t)__builtin_amdgcn_update_dpp(0, (int)v, CTRL, ROW_MASK, 0xf, true);
+}
+
+template <int CTRL, int ROW_MASK, typename T>
+__device__ __forceinline__ T dpp_shift(T v)
+{
+    static_assert(sizeof(T) == 4 || sizeof(T) == 8, "32- or 64-bit lanes");
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = (uint64_t)v;
+        const uint32_t lo = dpp_u32<CTRL, ROW_MASK>((uint32_t)u);
+        const uint32_t hi = dpp_u32<CTRL, ROW_MASK>((uint32_t)(u >> 32));
+        return (T)(((uint64_t)hi << 32) | lo);
+    } else {
+        return (T)dpp_u32<CTRL, ROW_MASK>((uint32_t)v);
+    }
+}
+
+// Inclusive scan over the 64 lanes: shifts by 1, 2, 4, 8 within each row of
+// 16 lanes (row_shr), then the last lane of rows 0 and 2 added to rows 1 and
+// 3 (row_bcast:15), then lane 31 added to rows 2 and 3 (row_bcast:31).
+template <typename T>
+__device__ __forceinline__ T wave_incl_scan(T x)
+{
+    x += dpp_shift<0x111, 0xf>(x);
+    x += dpp_shift<0x112, 0xf>(x);
+    x += dpp_shift<0x114, 0xf>(x);
+    x += dpp_shift<0x118, 0xf>(x);
+    x += dpp_shift<0x142, 0xa>(x);
+    x += dpp_shift<0x143, 0xc>(x);
+    return x;
+}
+
+// Value of lane 63, in every lane.
+template <typename T>
+__device__ __forceinline__ T lane63(T v)
+{
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = (uint64_t)v;
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, kWave - 1);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), kWave - 1);
+        return (T)(((uint64_t)hi << 32) | lo);
+    } else {
+        return (T)__builtin_amdgcn_readlane((uint32_t)v, kWave - 1);
+    }
+}
+
+// Sum over the wave, returned to every lane.
 template <typename T>
 __device__ __forceinline__ T wave_sum(T v)
 {
-#pragma unroll
-    for (int o = kWave / 2; o > 0; o >>= 1) v += __shfl_xor(v, o, kWave);
-    return v;
+    return lane63(wave_incl_scan(v));
 }
 
+// Value of lane `l` (wave-uniform), in every lane.
 template <typename T>
-__device__ __forceinline__ T wave_incl_scan(T v)
+__device__ __forceinline__ T lane_value(T v, int l)
 {
-    const int lane = lane_id();
-#pragma unroll
-    for (int o = 1; o < kWave; o <<= 1) {
-        const T u = __shfl_up(v, o, kWave);
-        if (lane >= o) v += u;
+    if constexpr (sizeof(T) == 8) {
+        const uint64_t u = (uint64_t)v;
+        const uint32_t lo = __builtin_amdgcn_readlane((uint32_t)u, l);
+        const uint32_t hi = __builtin_amdgcn_readlane((uint32_t)(u >> 32), l);
+        return (T)(((uint64_t)hi << 32) | lo);
+    } else {
+        return (T)__builtin_amdgcn_readlane((uint32_t)v, l);
     }
-    return v;
 }
 
-// Exclusive scan over the workgroup (NT threads, a multiple of 64).  `sm`
-// needs NT/64 entries.  Ends with a barrier so `sm` can be reused.
+// Inclusive scan of the wave totals staged in sm[0..NW): lane w < NW holds
+// the prefix through wave w (one row of 16 lanes, row_shr steps).
+template <int NW, typename T>
+__device__ __forceinline__ T scan_wave_totals(const T* sm)
+{
+    static_assert(NW >= 1 && NW <= 16, "wave totals within one row of 16 lanes");
+    const int lane = lane_id();
+    T x = lane < NW ? sm[lane] : T(0);
+    x += dpp_shift<0x111, 0xf>(x);
+    x += dpp_shift<0x112, 0xf>(x);
+    x += dpp_shift<0x114, 0xf>(x);
+    x += dpp_shift<0x118, 0xf>(x);
+    return x;
+}
+
+// Exclusive scan over the workgroup (NT threads, a multiple of 64, at most
+// 1024).  `sm` needs NT/64 entries.  Ends with a barrier so `sm` can be reused.
 template <int NT, typename T>
 __device__ __forceinline__ T block_excl_scan(T v, T* sm, T* total)
 {
     const T inc = wave_incl_scan(v);
     if constexpr (NT == kWave) {
-        *total = __shfl(inc, kWave - 1, kWave);
+        *total = lane63(inc);
         return inc - v;
     } else {
-        const int wid = threadIdx.x / kWave;
+        constexpr int NW = NT / kWave;
+        const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
         if (lane_id() == kWave - 1) sm[wid] = inc;
         __syncthreads();
-        T pre = 0, tot = 0;
-#pragma unroll
-        for (int w = 0; w < NT / kWave; ++w) {
-            const T x = sm[w];
-            pre += (w < wid) ? x : T(0);
-            tot += x;
-        }
+        const T x = scan_wave_totals<NW>(sm);
+        const T pre = wid > 0 ? lane_value(x, wid - 1) : T(0);
+        *total = lane_value(x, NW - 1);
         __syncthreads();
-        *total = tot;
         return pre + inc - v;
     }
 }
@@ -223,12 +289,11 @@ __device__ __forceinline__ T block_sum(T v, T* sm)
     if constexpr (NT == kWave) {
         return v;
     } else {
-        const int wid = threadIdx.x / kWave;
+        constexpr int NW = NT / kWave;
+        const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
         if (lane_id() == 0) sm[wid] = v;
         __syncthreads();
-        T tot = 0;
-#pragma unroll
-        for (int w = 0; w < NT / kWave; ++w) tot += sm[w];
+        const T tot = lane_value(scan_wave_totals<NW>(sm), NW - 1);
         __syncthreads();
         return tot;
     }

@@ -799,20 +799,43 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
     __shared__ uint64_t s_start[TEAM]; // short: first product; long: first unit
     __shared__ uint64_t s_red[TEAM / kWave + 1];
     __shared__ uint32_t s_it;
+    // the next item, taken ahead by wave 0: ticket, descriptor, and the B row
+    // bounds of the entries of its first chunk
+    __shared__ uint32_t s_nt;
+    __shared__ int32_t s_nx[8];
+    __shared__ int32_t s_nb0[TEAM], s_nb1[TEAM];
+    static_assert(sizeof(BigItem) == sizeof(s_nx), "descriptor words");
     const uint32_t nheavy = count[0], n = nheavy + count[2];  // heavy, light items
+    const uint32_t near_end = 2u * gridDim.x;
     const int t = threadIdx.x, lane = lane_id();
     const int wave = __builtin_amdgcn_readfirstlane(t / kWave);
     int zc = -1;  // case of zsum
     uint64_t zsum = 0;
-    // Work queue: items are taken one at a time as workgroups free up; the
-    // ticket of the next item is taken as the last pass over the current one
-    // begins.
+    // Work queue.  Far from its end, wave 0 takes the ticket of the next item
+    // during the first chunk of the current one and stages what the next
+    // item's first chunk reads (its other waves meanwhile take the chunk's
+    // long entries), so an item does not begin on a chain of dependent global
+    // loads.  Near the end (fewer than two items per workgroup left) the
+    // ticket is taken as the last pass over the current item begins, so no
+    // item waits on a busy workgroup while another is idle.
     if (t == 0) s_it = atomicAdd(next, 1u);
     __syncthreads();
     uint32_t it = __builtin_amdgcn_readfirstlane(s_it);
+    bool staged = false;  // item `it` is staged in s_nx, s_nb0, s_nb1
     for (;;) {
         if (it >= n) break;
-        const BigItem item = items[big_index(it, nheavy, L.cap4)];
+        BigItem item;
+        if (staged) {
+            item.row = __builtin_amdgcn_readfirstlane(s_nx[0]);
+            item.slot = __builtin_amdgcn_readfirstlane(s_nx[1]);
+            item.part = __builtin_amdgcn_readfirstlane(s_nx[2]);
+            item.nparts = __builtin_amdgcn_readfirstlane(s_nx[3]);
+            item.e_lo = __builtin_amdgcn_readfirstlane(s_nx[4]);
+            item.e_hi = __builtin_amdgcn_readfirstlane(s_nx[5]);
+            item.cs = __builtin_amdgcn_readfirstlane(s_nx[6]);
+        } else {
+            item = items[big_index(it, nheavy, L.cap4)];
+        }
         if (item.cs != zc) {
             if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
             zsum = 0;
@@ -826,6 +849,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
         // entries e0, e0 + P, e0 + 2P, ... below e_hi (P = 1 unless split)
         const int32_t e0 = item.e_lo + item.part, P = item.nparts;
         const int64_t cnt = item.e_hi > e0 ? ((int64_t)item.e_hi - e0 + P - 1) / P : 0;
+        const bool ahead = it + near_end < n && cnt > 0;  // wave 0 stages the next item
         uint64_t total = 0;
         for (int w = 0; w < nwin; ++w) {
             const int64_t c_lo = w * wcols_full;
@@ -838,9 +862,17 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
             for (int64_t i0 = 0; i0 < cnt; i0 += TEAM) {
                 const int64_t i = i0 + t;
                 const bool live = i < cnt;
-                const int32_t k = A.col[e0 + (int32_t)((live ? i : cnt - 1) * P)];
-                const int32_t b0 = B.rpt[k];
-                const uint32_t len = live ? (uint32_t)(B.rpt[k + 1] - b0) : 0u;
+                const bool first = w == 0 && i0 == 0;
+                int32_t b0, b1;
+                if (staged && first) {
+                    b0 = s_nb0[t];
+                    b1 = s_nb1[t];
+                } else {
+                    const int32_t k = A.col[e0 + (int32_t)((live ? i : cnt - 1) * P)];
+                    b0 = B.rpt[k];
+                    b1 = B.rpt[k + 1];
+                }
+                const uint32_t len = live ? (uint32_t)(b1 - b0) : 0u;
                 const bool lng = len >= long_len, shrt = !lng && len != 0;
                 // short products (bits 0..19), short entries (20..39), long entries (40..)
                 const uint64_t packed = (shrt ? (uint64_t)len | (1ull << 20) : 0ull) |
@@ -865,10 +897,46 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
                 utot = uniform_u64(utot);
                 const uint32_t nsp = (uint32_t)(ptot & 0xFFFFF);
                 const int nse = (int)((ptot >> 20) & 0xFFFFF), nle = (int)(ptot >> 40);
-                // long entries: units [ub, ue) of this wave
-                const uint64_t ub = utot * (uint64_t)wave / NWAVE;
-                const uint64_t ue = utot * (uint64_t)(wave + 1) / NWAVE;
-                if (ub < ue) {
+                // long entries: units [ub, ue) of this wave (wave 0 stages the
+                // next item instead, during the first chunk of an `ahead` item)
+                const bool stage = ahead && first;
+                const int nwv = stage ? NWAVE - 1 : NWAVE, wv = stage ? wave - 1 : wave;
+                const uint64_t ub = wv < 0 ? 0 : utot * (uint64_t)wv / nwv;
+                const uint64_t ue = wv < 0 ? 0 : utot * (uint64_t)(wv + 1) / nwv;
+                if (stage && wave == 0) {
+                    uint32_t j = 0;
+                    if (lane == 0) j = atomicAdd(next, 1u);
+                    j = __builtin_amdgcn_readfirstlane(j);
+                    if (lane == 0) s_nt = j;
+                    if (j < n) {
+                        const BigItem nx = items[big_index(j, nheavy, L.cap4)];
+                        if (lane < 8) s_nx[lane] = reinterpret_cast<const int32_t*>(&nx)[lane];
+                        const Csr A2 = cs[nx.cs].A, B2 = cs[nx.cs].B;
+                        const int32_t ne0 = nx.e_lo + nx.part, nP = nx.nparts;
+                        const int64_t ncnt =
+                            nx.e_hi > ne0 ? ((int64_t)nx.e_hi - ne0 + nP - 1) / nP : 0;
+                        const int m = (int)(ncnt < TEAM ? ncnt : TEAM);
+                        // eight entries per lane in flight at a time
+                        constexpr int PER = 8;
+                        for (int q0 = 0; q0 < m; q0 += PER * kWave) {
+                            int32_t kk[PER];
+#pragma unroll
+                            for (int u = 0; u < PER; ++u) {
+                                const int q = q0 + lane + u * kWave;
+                                kk[u] = A2.col[ne0 + (q < m ? q : m - 1) * nP];
+                            }
+#pragma unroll
+                            for (int u = 0; u < PER; ++u) {
+                                const int q = q0 + lane + u * kWave;
+                                const i32x2u v = *(const SSP_GLOBAL i32x2u*)(B2.rpt + kk[u]);
+                                if (q < m) {
+                                    s_nb0[q] = v.x;
+                                    s_nb1[q] = v.y;
+                                }
+                            }
+                        }
+                    }
+                } else if (ub < ue) {
                     // owner of unit ub: the last long entry starting at or before it
                     int lo = 0, hi = nle;
                     while (hi - lo > 1) {
@@ -965,7 +1033,8 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
                 }
                 __syncthreads();
             }
-            if (w == nwin - 1 && t == 0) s_it = atomicAdd(next, 1u);  // read after the barrier below
+            if (w == nwin - 1 && !ahead && t == 0)
+                s_it = atomicAdd(next, 1u);  // read after the barrier below
             // 16-byte LDS reads, eight issued before any is used (a loop of
             // single reads would wait on each)
             constexpr int UR = 8;
@@ -1006,7 +1075,8 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
             zsum += total;
             if (MODE == 1) atomicAdd(reinterpret_cast<ull*>(&cs[zc].out[item.row]), (ull)total);
         }
-        it = __builtin_amdgcn_readfirstlane(s_it);
+        it = __builtin_amdgcn_readfirstlane(ahead ? s_nt : s_it);
+        staged = ahead && it < n;
     }
     if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
 }
@@ -1357,15 +1427,7 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restric
             s1 += x[4 + l];
         }
         // exclusive scans of the two halves, in lockstep
-        uint64_t i0s = s0, i1s = s1;
-#pragma unroll
-        for (int o = 1; o < kWave; o <<= 1) {
-            const uint64_t u0 = __shfl_up(i0s, o, kWave), u1 = __shfl_up(i1s, o, kWave);
-            if (lane >= o) {
-                i0s += u0;
-                i1s += u1;
-            }
-        }
+        const uint64_t i0s = wave_incl_scan(s0), i1s = wave_incl_scan(s1);
         if (lane == kWave - 1) {
             s_w[wid] = i0s;
             s_w[NT / kWave + wid] = i1s;
