@@ -281,6 +281,28 @@ __device__ __forceinline__ T block_excl_scan(T v, T* sm, T* total)
     }
 }
 
+// Two exclusive scans over the workgroup in one pass (one pair of barriers).
+// `sm` needs 2 NT/64 entries.  Ends with a barrier so `sm` can be reused.
+template <int NT, typename T>
+__device__ __forceinline__ void block_excl_scan2(T a, T b, T* sm, T* ea, T* eb, T* ta, T* tb)
+{
+    static_assert(NT > kWave, "workgroup of several waves");
+    constexpr int NW = NT / kWave;
+    const T ia = wave_incl_scan(a), ib = wave_incl_scan(b);
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (lane_id() == kWave - 1) {
+        sm[wid] = ia;
+        sm[NW + wid] = ib;
+    }
+    __syncthreads();
+    const T xa = scan_wave_totals<NW>(sm), xb = scan_wave_totals<NW>(sm + NW);
+    *ea = (wid > 0 ? lane_value(xa, wid - 1) : T(0)) + ia - a;
+    *eb = (wid > 0 ? lane_value(xb, wid - 1) : T(0)) + ib - b;
+    *ta = lane_value(xa, NW - 1);
+    *tb = lane_value(xb, NW - 1);
+    __syncthreads();
+}
+
 // Sum over the workgroup, returned to every thread.  `sm` needs NT/64 entries.
 template <int NT, typename T>
 __device__ __forceinline__ T block_sum(T v, T* sm)

@@ -797,7 +797,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
     __shared__ int32_t s_b0[TEAM];
     __shared__ uint32_t s_len[TEAM];
     __shared__ uint64_t s_start[TEAM]; // short: first product; long: first unit
-    __shared__ uint64_t s_red[TEAM / kWave + 1];
+    __shared__ uint64_t s_red[2 * (TEAM / kWave)];
     __shared__ uint32_t s_it;
     // the next item, taken ahead by wave 0: ticket, descriptor, and the B row
     // bounds of the entries of its first chunk
@@ -878,9 +878,8 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
                 const uint64_t packed = (shrt ? (uint64_t)len | (1ull << 20) : 0ull) |
                                         (lng ? (1ull << 40) : 0ull);
                 const uint64_t nunits = lng ? (len + kUnitCols - 1) / kUnitCols : 0u;
-                uint64_t ptot, utot;
-                const uint64_t pk = block_excl_scan<TEAM, uint64_t>(packed, s_red, &ptot);
-                const uint64_t uk = block_excl_scan<TEAM, uint64_t>(nunits, s_red, &utot);
+                uint64_t pk, uk, ptot, utot;
+                block_excl_scan2<TEAM, uint64_t>(packed, nunits, s_red, &pk, &uk, &ptot, &utot);
                 if (shrt) {
                     const int i = (int)((pk >> 20) & 0xFFFFF);
                     s_b0[i] = b0;
@@ -1550,12 +1549,16 @@ __global__ __launch_bounds__(256) void k_flop_fixup(const CaseDesc* __restrict__
 constexpr int kRowsThreads = 1024;
 
 // nnz_pred[i] = ceil(rf_i z* / f*) (Eq. 3 per row), rf_i when the sample has
-// no products.  Grid-stride with few workgroups: each adds its part of the
-// output total with one atomic.
+// no products.  Grid-stride with few workgroups (at least one per case, rows
+// or not): each adds its part of the output total with one atomic.  Every
+// workgroup first sums its case's distinct-count slots into z* and derives
+// the divisor of f*; the case's first workgroup records z* and the
+// empty-sample flag in the statistics.
 __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __restrict__ cs, int n,
                                                             const CaseRes* __restrict__ cr)
 {
     __shared__ uint64_t s_red[kRowsThreads / kWave + 1];
+    __shared__ uint64_t s_z;
     const int c = case_of_wg<&CaseDesc::wg_rows>(cs, n, blockIdx.x);
     const int64_t bl = (int64_t)blockIdx.x - cs[c].wg_rows;
     const int64_t G = wgs_of_case<&CaseDesc::wg_rows>(cs, n, c);
@@ -1563,12 +1566,20 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __re
     SSP_GLOBAL int64_t* __restrict__ out = cs[c].out;
     const int64_t M = cs[c].A.nrows;
     ssp_stats* st = cs[c].st;
-    const uint32_t fallback = cr[c].fallback;
-    Divisor D;
-    D.dn = cr[c].div_dn;
-    D.v = cr[c].div_v;
-    D.shift = cr[c].div_shift;
-    const uint64_t zs = st->sample_nnz;
+    static_assert(kAccSlots == kWave, "one slot per lane of wave 0");
+    if (threadIdx.x < kWave) {
+        const uint64_t z = wave_sum(cr[c].zacc[threadIdx.x]);
+        if (threadIdx.x == 0) s_z = z;
+    }
+    __syncthreads();
+    const uint64_t zs = s_z, fs = st->sample_flop;
+    const bool fallback = fs == 0;
+    Divisor D{};
+    if (!fallback) D = make_divisor(fs);
+    if (bl == 0 && threadIdx.x == 0) {
+        st->sample_nnz = zs;
+        if (fallback) atomicOr(as_ull(&st->flags), (ull)SSP_FLAG_EMPTY_SAMPLE);
+    }
     uint64_t osum = 0;
     constexpr int U = 4;  // rows per thread and step, loaded together
     const int64_t stride = G * kRowsThreads * U;

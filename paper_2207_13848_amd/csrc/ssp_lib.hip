@@ -424,8 +424,13 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind)
                                 : resident(k_flop<FLOP_ONLY, false>, kFlopThreads, cus);
     P.g_flop = (int32_t)std::min<int64_t>(rflop, P.tiles);
     P.g_fixup = (int32_t)((P.tiles + 255) / 256);
-    P.g_rows = share_wgs(n, std::max(1, cus / 2), Mof,
-                         [&](int c) { return (Mof(c) + 4 * kRowsThreads - 1) / (4 * kRowsThreads); }, f);
+    // (every case gets a workgroup of the row kernels, rows or not: the
+    // prediction kernel also finishes the case's statistics)
+    auto rows_work = [&](int c) { return std::max<int64_t>(Mof(c), 1); };
+    auto rows_cap = [&](int c) {
+        return std::max<int64_t>(1, (Mof(c) + 4 * kRowsThreads - 1) / (4 * kRowsThreads));
+    };
+    P.g_rows = share_wgs(n, std::max(1, cus / 2), rows_work, rows_cap, f);
     for (int c = 0; c < n; ++c) P.cs[c].wg_rows = f[c];
     // list capacities
     int64_t sumM = 0;
@@ -540,7 +545,8 @@ void launch_sampling(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
 // per-case finalize (sizes of the lists are device-side; the grids are upper
 // bounds and every kernel walks its list grid-stride or by work queue).
 template <int MODE>
-void launch_symbolic(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s, bool timed)
+void launch_symbolic(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s, bool timed,
+                     bool finalize)
 {
     const int cus = h->num_cus;
     const int64_t nitems = P.cap13;
@@ -573,6 +579,7 @@ void launch_symbolic(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
         hipLaunchKernelGGL((k_sym_merge<MODE>), dim3((unsigned)(2 * cus)), dim3(256), 0, s, b.cs,
                            b.L.merge, &b.ctl->bin_cnt[5], b.L, b.cr);
     }
+    if (!finalize) return;  // (the prediction kernel sums z* itself)
     PhaseTimer pt(h, PH_FINALIZE, s, timed);
     hipLaunchKernelGGL((k_finalize<MODE>), dim3(grid_for(P.n, 1024)), dim3(kAccSlots), 0, s, b.cs,
                        b.cr, P.n);
@@ -612,13 +619,13 @@ ssp_status launch_plan(ssp_handle h, const Plan& P, const Bound& b, hipStream_t 
     SSP_LAUNCHED(h);
     if (P.kind == PLAN_EXACT) {
         launch_flop<FLOP_EXACT_BIN>(h, P, b, s, timed);
-        launch_symbolic<1>(h, P, b, s, timed);
+        launch_symbolic<1>(h, P, b, s, timed, true);
         SSP_LAUNCHED(h);
         return SSP_OK;
     }
     launch_flop<FLOP_ONLY>(h, P, b, s, timed);
     launch_sampling(h, P, b, s, timed);
-    launch_symbolic<0>(h, P, b, s, timed);
+    launch_symbolic<0>(h, P, b, s, timed, P.kind != PLAN_PREDICT);
     if (P.kind == PLAN_PREDICT) {
         PhaseTimer pt(h, PH_PRED_ROWS, s, timed);
         if (P.g_rows > 0)
