@@ -67,6 +67,14 @@ __device__ __forceinline__ int32_t wgs_of_case(const CaseDesc* __restrict__ cs, 
 
 typedef unsigned long long ull;
 
+// A wave-uniform 64-bit value in scalar registers.
+__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
+{
+    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
+    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
+    return ((uint64_t)hi << 32) | lo;
+}
+
 __device__ __forceinline__ ull* as_ull(uint64_t* p) { return reinterpret_cast<ull*>(p); }
 
 // ---------------------------------------------------------------- init
@@ -770,18 +778,13 @@ __global__ __launch_bounds__(TEAM) void k_sym(const CaseDesc* __restrict__ cs,
 // a time.  Those naming a B row of at least kLongLen columns are cut into
 // units of kUnitCols columns; every wave walks its own contiguous range of the
 // chunk's units, lane l reading columns [4l, 4l + 4) of a unit with one
-// 16-byte load, two units ahead of the inserts.  The short B rows are
+// 16-byte load, kUnitsInFlight - 1 units ahead of the inserts.  The short B rows are
 // flattened (owner by binary search in LDS) and shared out over the whole
 // workgroup.  An unsplit item counts its bits; a part of a split row stores
 // its window bitmap to global scratch for k_sym_merge.
 constexpr uint32_t kUnitCols = 4 * kWave;
+constexpr int kUnitsInFlight = 4;  // 16-byte loads in flight per lane in the unit loop
 
-__device__ __forceinline__ uint64_t uniform_u64(uint64_t x)
-{
-    const uint32_t lo = __builtin_amdgcn_readfirstlane((uint32_t)x);
-    const uint32_t hi = __builtin_amdgcn_readfirstlane((uint32_t)(x >> 32));
-    return ((uint64_t)hi << 32) | lo;
-}
 
 template <int MODE, bool WIN1>
 __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restrict__ cs,
@@ -958,11 +961,12 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
                     load_entry();
                     ui = (uint32_t)(ub - uniform_u64(s_start[TEAM - 1 - r]));
                     uint32_t left = (uint32_t)(ue - ub);  // < 2^29: per-wave share
-                    // Three units in flight in registers of fixed roles (the loop is
-                    // unrolled by three so no loaded register is moved before use,
-                    // which would make the compiler wait for every load).
-                    i32x4 va, vb, vc;
-                    bool oa, ob, oc;
+                    // kUnitsInFlight units in flight in registers of fixed roles (the
+                    // loop is unrolled by that depth so no loaded register is moved
+                    // before use, which would make the compiler wait for every load).
+                    constexpr int D = kUnitsInFlight;
+                    i32x4 v[D];
+                    bool ok[D];
                     auto issue = [&](i32x4& v, bool& ok) {
                         const uint32_t base = ui * kUnitCols + 4u * lane;
                         const uint32_t off = base < elen - 4u ? base : elen - 4u;
@@ -994,19 +998,18 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
                         }
                     };
                     const uint32_t n = left;
-                    issue(va, oa);
-                    advance();
-                    issue(vb, ob);
-                    for (uint32_t u = 0; u < n; u += 3) {
-                        advance();
-                        issue(vc, oc);
-                        insert(va, oa);
-                        advance();
-                        issue(va, oa);
-                        if (u + 1 < n) insert(vb, ob);
-                        advance();
-                        issue(vb, ob);
-                        if (u + 2 < n) insert(vc, oc);
+#pragma unroll
+                    for (int k = 0; k < D - 1; ++k) {  // units 0 .. D-2
+                        if (k) advance();
+                        issue(v[k], ok[k]);
+                    }
+                    for (uint32_t u = 0; u < n; u += D) {
+#pragma unroll
+                        for (int k = 0; k < D; ++k) {  // issue unit u+k+D-1, insert unit u+k
+                            advance();
+                            issue(v[(k + D - 1) % D], ok[(k + D - 1) % D]);
+                            if (k == 0 || u + k < n) insert(v[k], ok[k]);
+                        }
                     }
                 }
                 // short entries: products flattened over the workgroup
@@ -1292,10 +1295,13 @@ __device__ __forceinline__ void flop_issue_tile(const CaseDesc* __restrict__ cs,
     R.a0 = R.j0 & ~(int64_t)3;
     const int64_t rlast = i1 < M ? i1 : M - 1;
     const int nb = (int)(rlast - i0 + 2);
+    // only the loads the tile's rows need (nb is uniform: whole instructions
+    // are skipped, which spares the address units most of them on tiles of
+    // long rows)
 #pragma unroll
     for (int u = 0; u < NRP; ++u) {
         const int k = t + u * NT;
-        R.rp[u] = R.Arpt[i0 + (k < nb ? k : nb - 1)];
+        if (u == 0 || u * NT < nb) R.rp[u] = R.Arpt[i0 + (k < nb ? k : nb - 1)];
     }
     // Loads are unconditional from clamped in-range addresses (masked later):
     // a load under a lane condition becomes a branch, and loads in separate
@@ -1415,7 +1421,7 @@ __global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restric
 #pragma unroll
         for (int u = 0; u < NRP; ++u) {
             const int k = t + u * NT;
-            if (k < nb) s_bnd[k] = cur.rp[u];
+            if (u * NT < nb && k < nb) s_bnd[k] = cur.rp[u];
         }
         uint64_t s0 = 0, s1 = 0;
 #pragma unroll
@@ -1567,12 +1573,29 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __re
     const int64_t M = cs[c].A.nrows;
     ssp_stats* st = cs[c].st;
     static_assert(kAccSlots == kWave, "one slot per lane of wave 0");
+    // Loads issued at once: the case's f*, its distinct-count slots, and the
+    // first step's row products (none of them waits on another).
+    const uint64_t fs_ld = st->sample_flop;
+    const uint64_t z_ld = threadIdx.x < kWave ? cr[c].zacc[threadIdx.x] : 0;
+    constexpr int U = 8;  // rows per thread and step, loaded together
+    const int64_t stride = G * kRowsThreads * U;
+    uint64_t rf[U];
+    auto load_rows = [&](int64_t i0) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const int64_t i = i0 + u * kRowsThreads;
+            rf[u] = i < M ? (uint64_t)__builtin_nontemporal_load(rf_in + i) : 0;
+        }
+    };
+    const int64_t first = bl * kRowsThreads * U + threadIdx.x;
+    load_rows(first);
     if (threadIdx.x < kWave) {
-        const uint64_t z = wave_sum(cr[c].zacc[threadIdx.x]);
+        const uint64_t z = wave_sum(z_ld);
         if (threadIdx.x == 0) s_z = z;
     }
     __syncthreads();
-    const uint64_t zs = s_z, fs = st->sample_flop;
+    // (uniform values: the divisor's reciprocal loop runs on the scalar unit)
+    const uint64_t zs = uniform_u64(s_z), fs = uniform_u64(fs_ld);
     const bool fallback = fs == 0;
     Divisor D{};
     if (!fallback) D = make_divisor(fs);
@@ -1581,15 +1604,8 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __re
         if (fallback) atomicOr(as_ull(&st->flags), (ull)SSP_FLAG_EMPTY_SAMPLE);
     }
     uint64_t osum = 0;
-    constexpr int U = 4;  // rows per thread and step, loaded together
-    const int64_t stride = G * kRowsThreads * U;
-    for (int64_t i0 = bl * kRowsThreads * U + threadIdx.x; i0 < M; i0 += stride) {
-        uint64_t rf[U];
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            const int64_t i = i0 + u * kRowsThreads;
-            rf[u] = (uint64_t)__builtin_nontemporal_load(rf_in + (i < M ? i : M - 1));
-        }
+    for (int64_t i0 = first; i0 < M; i0 += stride) {
+        if (i0 != first) load_rows(i0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             const int64_t i = i0 + u * kRowsThreads;

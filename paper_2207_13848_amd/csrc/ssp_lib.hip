@@ -428,7 +428,7 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind)
     // prediction kernel also finishes the case's statistics)
     auto rows_work = [&](int c) { return std::max<int64_t>(Mof(c), 1); };
     auto rows_cap = [&](int c) {
-        return std::max<int64_t>(1, (Mof(c) + 4 * kRowsThreads - 1) / (4 * kRowsThreads));
+        return std::max<int64_t>(1, (Mof(c) + 8 * kRowsThreads - 1) / (8 * kRowsThreads));
     };
     P.g_rows = share_wgs(n, std::max(1, cus / 2), rows_work, rows_cap, f);
     for (int c = 0; c < n; ++c) P.cs[c].wg_rows = f[c];
