@@ -25,7 +25,10 @@ constexpr int kWinWords = 32768;
 constexpr uint64_t kSplitTarget = 1ull << 17; // products per part of a split row (default)
 constexpr uint32_t kLongLenDefault = 32;      // B rows walked in units by the long-row kernel
 constexpr int kMaxParts = 64;
-constexpr int kMaxPartWindows = 1024;         // global part bitmaps of kWinWords words
+// Global part bitmaps of kWinWords words: a call holds kPartWindowsBase, a
+// batch kPartWindowsBase per 32 cases up to kPartWindowsMax.
+constexpr int kPartWindowsBase = 1024;
+constexpr int kPartWindowsMax = 8192;
 constexpr int kMaxSplitWindows = 4;           // rows needing more windows are not split
 constexpr int kMergeSlice = 1024;             // words per merge item
 
@@ -106,7 +109,8 @@ struct Ctl {
                           // merge items at 5, light bin-4 items at 6
     uint32_t pw_ctr;      // part windows handed out (exact path)
     uint32_t big_next;    // work queue of the long-row kernel
-    uint32_t pad[22];
+    uint32_t split_level; // the call's split level (sampling passes)
+    uint32_t pad[21];
 };
 
 struct BinItem {  // bins 1..3
@@ -135,24 +139,28 @@ struct MergeItem {  // one slice of one window of a split row
     int32_t cs;     // case
 };
 
-// Per-group counters of the sampling passes.  k_sample_count writes
-//   c[0..2] rows of bins 1..3, c[3] rows of bin 4, c[4] bin-4 items if its
-//   split-eligible rows are split, c[5] their merge items, c[6] part windows
-//   they request, c[7] the case; ns, fs, as: sampled rows, their products,
-//   their A entries; ne: split-eligible rows; nh: heavy bin-4 rows (above a
-//   quarter of the split target; the eligible rows among them);
-// k_sample_scan rewrites them in place as
-//   c[0..2] offsets in bins 1..3, c[3] offset among the heavy bin-4 items,
-//   c[4] offset in the merge list, c[5] first part window, c[6] 1 if the rows
-//   are split, ne: offset among the light bin-4 items;
-//   ns, fs, as: inclusive prefixes over all groups of the call.
-struct SampleCounts {
-    uint32_t c[8];
-    uint64_t ns, fs, as;
-    uint32_t ne, nh;
-};
-// Bin-4 rows above split_target >> kHeavyShift products are heavy.
+// Split levels: a call splits its eligible long rows at split_target << L,
+// L the smallest level whose part windows all fit the scratch (the last level
+// when none does; then a group's rows are split while the windows requested up
+// to and including the group fit).  Rows above a quarter of the level's
+// target are heavy.
+constexpr int kSplitLevels = 4;
 constexpr int kHeavyShift = 2;
+
+// Per-group counters of the sampling passes.  k_sample_count writes the
+// counts, k_sample_scan the offsets (and turns ns, fs, as into inclusive
+// prefixes over all groups of the call).
+struct SampleCounts {
+    uint32_t n1, n2, n3, n4;   // sampled rows in bins 1..3 and bin 4
+    uint32_t cs;               // case
+    uint32_t split;            // (scan) 1 if the group's eligible rows are split
+    uint32_t lv[kSplitLevels][4];  // per level: bin-4 items, part windows, eligible rows, heavy rows
+    uint32_t o1, o2, o3;       // (scan) offsets in bins 1..3
+    uint32_t oh, ol;           // (scan) offsets among the heavy and the light bin-4 items
+    uint32_t om, ow;           // (scan) offset in the merge list, first part window
+    uint32_t pad;
+    uint64_t ns, fs, as;       // sampled rows, their products, their A entries
+};
 constexpr int kSampleTarget = 8192; // sampling groups of a call, about (at least 1 per case)
 
 struct TileMeta {   // per streaming tile

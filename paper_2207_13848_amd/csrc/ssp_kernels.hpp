@@ -29,12 +29,13 @@ struct BinLists {
     BinItem* b3;
     BigItem* b4;
     MergeItem* merge;
-    uint32_t* scratch; // kMaxPartWindows windows of kWinWords words
+    uint32_t* scratch; // part_windows windows of kWinWords words
     // Bin 4 holds its heavy items from the front (parts of split rows, and
     // rows above a quarter of the split target) and the light ones from the
     // back (light item i at cap4 - 1 - i): the long-row kernel takes the
     // heavy ones first, so the last items taken are short.
     uint32_t cap4;
+    uint32_t part_windows;  // windows in scratch (the call's budget of split-row parts)
 };
 
 // Queue position k of the long-row kernel -> bin-4 list index, given the
@@ -189,13 +190,13 @@ __device__ inline void append_big(int32_t row, uint64_t rf, int32_t e0, int32_t 
     const uint64_t T = cd.split_target;
     if (rf > T && cd.nwin <= kMaxSplitWindows && alen > 1 &&
         __hip_atomic_load(&ctl->pw_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
-            (uint32_t)kMaxPartWindows) {  // (bounds the counter: it cannot wrap)
+            L.part_windows) {  // (bounds the counter: it cannot wrap)
         uint64_t want = (rf + T - 1) / T;
         if (want > (uint64_t)kMaxParts) want = kMaxParts;
         if (want > (uint64_t)alen) want = (uint64_t)alen;
         const uint32_t need = (uint32_t)want * (uint32_t)cd.nwin;
         const uint32_t s = atomicAdd(&ctl->pw_ctr, need);
-        if (s + need <= (uint32_t)kMaxPartWindows) {
+        if (s + need <= L.part_windows) {
             slot = (int32_t)s;
             nparts = (int32_t)want;
         }
@@ -346,9 +347,6 @@ struct SampledRow {
     uint64_t rf;
     int32_t e0, e1;
     int bin;
-    uint32_t want;  // parts when split (1 unless eligible)
-    bool elig;
-    bool heavy;     // bin 4 above split_target >> kHeavyShift (eligible rows are)
 };
 
 __device__ __forceinline__ SampledRow classify_row(int64_t g, const SamplerArgs& a)
@@ -358,25 +356,39 @@ __device__ __forceinline__ SampledRow classify_row(int64_t g, const SamplerArgs&
     r.rf = 0;
     r.e0 = r.e1 = 0;
     r.bin = 0;
-    r.want = 1;
-    r.elig = false;
-    r.heavy = false;
     if (g < 0) return r;
     r.rf = (uint64_t)a.rf[g];
     r.e0 = a.A.rpt[g];
     r.e1 = a.A.rpt[g + 1];
     const int b = bin_of(r.rf, a.bin_max);
     r.bin = (b == 3 && a.big3) ? 4 : b;
+    return r;
+}
+
+// How a bin-4 row splits at split level `lv`: eligible rows (above the
+// level's target, windows few enough, at least two entries) want one part
+// per target's worth of products, at most kMaxParts and one per entry; rows
+// above a quarter of the target are heavy (eligible rows are).
+struct SplitInfo {
+    uint32_t want;  // parts when split (1 unless eligible)
+    bool elig, heavy;
+};
+
+__device__ __forceinline__ SplitInfo split_info(const SampledRow& r, const SamplerArgs& a, int lv)
+{
+    SplitInfo si{1u, false, false};
+    if (r.bin != 4) return si;
+    const uint64_t T = a.split_target << lv;
+    si.heavy = r.rf > (T >> kHeavyShift);
     const int64_t alen = (int64_t)r.e1 - r.e0;
-    r.heavy = r.bin == 4 && r.rf > (a.split_target >> kHeavyShift);
-    if (r.bin == 4 && r.rf > a.split_target && a.nwin <= kMaxSplitWindows && alen > 1) {
-        uint64_t want = (r.rf + a.split_target - 1) / a.split_target;
+    if (r.rf > T && a.nwin <= kMaxSplitWindows && alen > 1) {
+        uint64_t want = (r.rf + T - 1) / T;
         if (want > (uint64_t)kMaxParts) want = kMaxParts;
         if (want > (uint64_t)alen) want = (uint64_t)alen;
-        r.want = (uint32_t)want;
-        r.elig = true;
+        si.want = (uint32_t)want;
+        si.elig = true;
     }
-    return r;
+    return si;
 }
 
 // The case of sampling group `grp` (groups of a case are consecutive) and
@@ -431,21 +443,25 @@ __device__ __forceinline__ int gather_sampled(int64_t base, int64_t hi, const Sa
     return (int)tot;
 }
 
-// Pass 1: per group, the counts of SampleCounts and the sums of n_s, f* and
-// the sample's A entries.  No atomics: the passes hand over per-group
-// counters (same-address device atomics serialise on this part).
+// Pass 1: per group, the counts of SampleCounts (at every split level) and
+// the sums of n_s, f* and the sample's A entries.  No atomics: the passes
+// hand over per-group counters (same-address device atomics serialise on
+// this part).
 __global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc* __restrict__ cs,
                                                                 int n,
                                                                 SampleCounts* __restrict__ cnt)
 {
-    constexpr int NT = kSampleThreads;
+    constexpr int NT = kSampleThreads, NC = 4 + 4 * kSplitLevels;
     __shared__ uint64_t s_red[NT / kWave + 1];
+    __shared__ uint32_t s_tot[NT / kWave][NC];
     __shared__ int64_t s_rows[NT * kCandPerThread];
     const GroupRange gr = group_range(cs, n, blockIdx.x);
     const SamplerArgs a = sampler_args(cs[gr.c]);
-    uint32_t c[7] = {0, 0, 0, 0, 0, 0, 0};
+    // c[0..3]: rows of bins 1..4; c[4 + 4 lv + j]: SampleCounts::lv[lv][j]
+    uint32_t c[NC];
+#pragma unroll
+    for (int k = 0; k < NC; ++k) c[k] = 0;
     uint64_t ns = 0, fs = 0, as = 0;
-    uint32_t ne = 0, nh = 0;
     for (int64_t base = gr.lo; base < gr.hi; base += NT * kCandPerThread) {
         const int nr = gather_sampled<NT>(base, gr.hi, a, s_rows, s_red);
         for (int k = threadIdx.x; k < nr; k += NT) {
@@ -456,43 +472,52 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc*
             c[0] += r.bin == 1;  // (selects, not an index: c stays in registers)
             c[1] += r.bin == 2;
             c[2] += r.bin == 3;
-            if (r.bin == 4) {
-                c[3] += 1;
-                c[4] += r.want;
-                nh += r.heavy;
-                if (r.elig) {
-                    ne += 1;
-                    c[5] += (uint32_t)a.merge_per_row;
-                    c[6] += r.want * (uint32_t)a.nwin;
-                }
+            c[3] += r.bin == 4;
+#pragma unroll
+            for (int lv = 0; lv < kSplitLevels; ++lv) {
+                const SplitInfo si = split_info(r, a, lv);
+                c[4 + 4 * lv + 0] += r.bin == 4 ? si.want : 0u;
+                c[4 + 4 * lv + 1] += si.elig ? si.want * (uint32_t)a.nwin : 0u;
+                c[4 + 4 * lv + 2] += si.elig ? 1u : 0u;
+                c[4 + 4 * lv + 3] += si.heavy ? 1u : 0u;
             }
         }
     }
-    uint32_t tot[7];
+    // the NC counts: wave sums, then one barrier and a column sum per count
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
 #pragma unroll
-    for (int k = 0; k < 7; ++k) tot[k] = (uint32_t)block_sum<NT, uint64_t>(c[k], s_red);
-    const uint64_t Ns = block_sum<NT, uint64_t>(ns, s_red);
+    for (int k = 0; k < NC; ++k) {
+        const uint32_t v = wave_sum(c[k]);
+        if (lane_id() == 0) s_tot[wid][k] = v;
+    }
+    const uint64_t Ns = block_sum<NT, uint64_t>(ns, s_red);  // (its barrier covers s_tot)
     const uint64_t Fs = block_sum<NT, uint64_t>(fs, s_red);
     const uint64_t As = block_sum<NT, uint64_t>(as, s_red);
-    const uint32_t Ne = (uint32_t)block_sum<NT, uint64_t>(ne, s_red);
-    const uint32_t Nh = (uint32_t)block_sum<NT, uint64_t>(nh, s_red);
-    if (threadIdx.x == 0) {
-        SampleCounts o;
+    SampleCounts* o = &cnt[blockIdx.x];
+    if (threadIdx.x < NC) {
+        uint32_t v = 0;
 #pragma unroll
-        for (int k = 0; k < 7; ++k) o.c[k] = tot[k];
-        o.c[7] = (uint32_t)gr.c;
-        o.ns = Ns;
-        o.fs = Fs;
-        o.as = As;
-        o.ne = Ne;
-        o.nh = Nh;
-        cnt[blockIdx.x] = o;
+        for (int w = 0; w < NT / kWave; ++w) v += s_tot[w][threadIdx.x];
+        const int k = threadIdx.x;
+        if (k == 0) o->n1 = v;
+        else if (k == 1) o->n2 = v;
+        else if (k == 2) o->n3 = v;
+        else if (k == 3) o->n4 = v;
+        else o->lv[(k - 4) / 4][(k - 4) % 4] = v;
+    }
+    if (threadIdx.x == 0) {
+        o->cs = (uint32_t)gr.c;
+        o->ns = Ns;
+        o->fs = Fs;
+        o->as = As;
     }
 }
 
-// Pass 2, one workgroup, the groups taken kScanThreads at a time: exclusive
-// offsets of every group in every list, the split decision (a group's
-// eligible rows are split when all part windows requested up to and
+// Pass 2, one workgroup, the groups taken kScanThreads at a time.  First the
+// call's split level: the part windows every level requests over all groups;
+// the smallest level whose windows fit the scratch.  Then the exclusive
+// offsets of every group in every list at that level, the split decision (a
+// group's eligible rows are split when all part windows requested up to and
 // including the group fit the scratch), the list sizes, and per case n_s, f*
 // and the sample's A entries (one atomic per case and chunk of groups).
 constexpr int kScanThreads = 512;
@@ -500,29 +525,58 @@ constexpr int kScanThreads = 512;
 __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __restrict__ cnt,
                                                              int64_t ngroups,
                                                              const CaseDesc* __restrict__ cs,
-                                                             Ctl* ctl)
+                                                             Ctl* ctl, uint32_t budget)
 {
     constexpr int NT = kScanThreads;
     __shared__ uint64_t s_red[NT / kWave + 1];
     __shared__ uint64_t s_e[3][NT];  // exclusive prefixes of ns, fs, as in the chunk
     const int t = threadIdx.x;
+    uint64_t wsum[kSplitLevels] = {};
+    for (int64_t g = t; g < ngroups; g += NT) {
+#pragma unroll
+        for (int lv = 0; lv < kSplitLevels; ++lv) wsum[lv] += cnt[g].lv[lv][1];
+    }
+    int L = kSplitLevels - 1;
+#pragma unroll
+    for (int lv = kSplitLevels - 1; lv >= 0; --lv)
+        if (block_sum<NT, uint64_t>(wsum[lv], s_red) <= (uint64_t)budget) L = lv;
     uint64_t k01 = 0, k2w = 0, k4 = 0, km = 0;  // carries (k01, k2w, k4: two u32 fields)
     for (int64_t g0 = 0; g0 < ngroups; g0 += NT) {
         const int64_t g = g0 + t;
-        SampleCounts x{};
-        if (g < ngroups) x = cnt[g];
+        // (fields read one by one: the level index is dynamic, a struct copy
+        // indexed by it would live in scratch)
+        struct {
+            uint32_t n1, n2, n3, n4, cs;
+            uint64_t ns, fs, as;
+        } x{};
+        uint32_t items = 0, wins = 0, ne = 0, nh = 0;
+        if (g < ngroups) {
+            const SampleCounts& y = cnt[g];
+            x.n1 = y.n1;
+            x.n2 = y.n2;
+            x.n3 = y.n3;
+            x.n4 = y.n4;
+            x.cs = y.cs;
+            x.ns = y.ns;
+            x.fs = y.fs;
+            x.as = y.as;
+            items = y.lv[L][0];
+            wins = y.lv[L][1];
+            ne = y.lv[L][2];
+            nh = y.lv[L][3];
+        }
         uint64_t t01, t2w, tns, tfs, tas;
         const uint64_t p01 = k01 + block_excl_scan<NT, uint64_t>(
-                                       (uint64_t)x.c[0] | ((uint64_t)x.c[1] << 32), s_red, &t01);
+                                       (uint64_t)x.n1 | ((uint64_t)x.n2 << 32), s_red, &t01);
         const uint64_t p2w = k2w + block_excl_scan<NT, uint64_t>(
-                                       (uint64_t)x.c[2] | ((uint64_t)x.c[6] << 32), s_red, &t2w);
+                                       (uint64_t)x.n3 | ((uint64_t)wins << 32), s_red, &t2w);
         const uint32_t wpre = (uint32_t)(p2w >> 32);
-        const bool split = x.c[6] != 0 && (uint64_t)wpre + x.c[6] <= (uint64_t)kMaxPartWindows;
+        const bool split = wins != 0 && (uint64_t)wpre + wins <= (uint64_t)budget;
         // bin 4: heavy items (front: parts of split rows, heavy unsplit rows)
         // and light rows (back); eligible rows are heavy
-        const uint32_t nf = split ? x.c[4] - x.c[3] + x.nh : x.nh;
-        const uint32_t nb = x.c[3] - x.nh;
-        const uint32_t nm = split ? x.c[5] : 0u;
+        const uint32_t nf = split ? items - x.n4 + nh : nh;
+        const uint32_t nb = x.n4 - nh;
+        const uint32_t nm = split ? ne * (uint32_t)cs[x.cs].merge_per_row : 0u;
         uint64_t t4, tm;
         const uint64_t p4 =
             k4 + block_excl_scan<NT, uint64_t>((uint64_t)nf | ((uint64_t)nb << 32), s_red, &t4);
@@ -535,18 +589,17 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
         s_e[2][t] = eas;
         __syncthreads();
         if (g < ngroups) {
-            SampleCounts o = x;
-            o.c[0] = (uint32_t)p01;
-            o.c[1] = (uint32_t)(p01 >> 32);
-            o.c[2] = (uint32_t)p2w;
-            o.c[3] = (uint32_t)p4;
-            o.c[4] = (uint32_t)pm;
-            o.c[5] = wpre;
-            o.c[6] = split ? 1u : 0u;
-            o.ne = (uint32_t)(p4 >> 32);
-            cnt[g] = o;
+            SampleCounts* o = &cnt[g];
+            o->o1 = (uint32_t)p01;
+            o->o2 = (uint32_t)(p01 >> 32);
+            o->o3 = (uint32_t)p2w;
+            o->oh = (uint32_t)p4;
+            o->ol = (uint32_t)(p4 >> 32);
+            o->om = (uint32_t)pm;
+            o->ow = wpre;
+            o->split = split ? 1u : 0u;
             // the last group of its case in this chunk adds the case's part
-            const int c = (int)x.c[7];
+            const int c = (int)x.cs;
             const int64_t first = cs[c].group_base, last = first + cs[c].ngroups - 1;
             if (g == last || t == NT - 1 || g == ngroups - 1) {
                 const int k0 = first > g0 ? (int)(first - g0) : 0;
@@ -572,6 +625,7 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
         ctl->bin_cnt[4] = (uint32_t)k4;
         ctl->bin_cnt[5] = (uint32_t)km;
         ctl->bin_cnt[6] = (uint32_t)(k4 >> 32);
+        ctl->split_level = (uint32_t)L;
     }
 }
 
@@ -580,7 +634,7 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
 __global__ __launch_bounds__(kSampleThreads) void k_sample_write(const CaseDesc* __restrict__ cs,
                                                                 int n,
                                                                 const SampleCounts* __restrict__ cnt,
-                                                                BinLists L)
+                                                                const Ctl* ctl, BinLists L)
 {
     constexpr int NT = kSampleThreads;
     __shared__ uint64_t s_red[NT / kWave + 1];
@@ -589,19 +643,21 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_write(const CaseDesc*
     const GroupRange gr = group_range(cs, n, blockIdx.x);
     if (gr.lo >= gr.hi) return;  // (uniform over the workgroup)
     const SamplerArgs a = sampler_args(cs[gr.c]);
-    const SampleCounts o = cnt[blockIdx.x];
-    const bool split = o.c[6] != 0;
-    uint32_t off1 = o.c[0], off2 = o.c[1], off3 = o.c[2], off4 = o.c[3], offm = o.c[4],
-             offw = o.c[5], offb = o.ne;
+    const SampleCounts& o = cnt[blockIdx.x];
+    const int lvl = (int)ctl->split_level;
+    const bool split = o.split != 0;
+    uint32_t off1 = o.o1, off2 = o.o2, off3 = o.o3, off4 = o.oh, offm = o.om, offw = o.ow,
+             offb = o.ol;
     for (int64_t base = gr.lo; base < gr.hi; base += NT * kCandPerThread) {
         const int nr = gather_sampled<NT>(base, gr.hi, a, s_rows, s_red);
         for (int k0 = 0; k0 < nr; k0 += NT) {  // same trip count in every lane (scans)
             const SampledRow r = classify_row(k0 + t < nr ? s_rows[k0 + t] : -1, a);
-            const bool sp = split && r.elig;
-            const uint32_t n4 = r.bin == 4 ? (sp ? r.want : 1u) : 0u;
-            const uint32_t nf = r.heavy ? n4 : 0u, nb = r.bin == 4 && !r.heavy ? 1u : 0u;
+            const SplitInfo si = split_info(r, a, lvl);
+            const bool sp = split && si.elig;
+            const uint32_t n4 = r.bin == 4 ? (sp ? si.want : 1u) : 0u;
+            const uint32_t nf = si.heavy ? n4 : 0u, nb = r.bin == 4 && !si.heavy ? 1u : 0u;
             const uint32_t nm = sp ? (uint32_t)a.merge_per_row : 0u;
-            const uint32_t nw = sp ? r.want * (uint32_t)a.nwin : 0u;
+            const uint32_t nw = sp ? si.want * (uint32_t)a.nwin : 0u;
             uint64_t t01, t34, tmw;
             // bins 1, 2 and light bin-4 rows in 21-bit fields (at most NT each)
             static_assert(NT < (1 << 21), "21-bit scan fields");
@@ -622,8 +678,8 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_write(const CaseDesc*
                 else if (r.bin == 2) L.b2[off2 + (uint32_t)((p01 >> 21) & 0x1FFFFF)] = it;
                 else L.b3[off3 + (uint32_t)p34] = it;
             } else if (r.bin == 4) {
-                const uint32_t at = r.heavy ? off4 + (uint32_t)(p34 >> 32)
-                                            : L.cap4 - 1u - (offb + (uint32_t)(p01 >> 42));
+                const uint32_t at = si.heavy ? off4 + (uint32_t)(p34 >> 32)
+                                             : L.cap4 - 1u - (offb + (uint32_t)(p01 >> 42));
                 const int32_t slot = sp ? (int32_t)(offw + (uint32_t)(pmw >> 32)) : -1;
                 for (uint32_t p = 0; p < n4; ++p) {
                     BigItem it;

@@ -280,6 +280,7 @@ struct Plan {
     std::vector<int64_t> rf_off;   // workspace row-FLOP offset per case, -1 = caller's
     std::vector<int> st_slot;      // workspace stats slot per case, -1 = caller's
     int64_t cap13 = 1, cap4 = 1, cap5 = 1, ngroups = 0, tiles = 0, rowtmp = 0;
+    int64_t part_windows = kPartWindowsBase;  // scratch windows for the parts of split rows
     int32_t g_tiles = 0, g_flop = 0, g_fixup = 0, g_rows = 0;
     int32_t win_words_max = 4;
     bool win1 = true, vec = true;
@@ -348,12 +349,21 @@ int32_t share_wgs(int n, int64_t budget, W work, Cap cap_c, std::vector<int32_t>
     return (int32_t)g;
 }
 
-Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind)
+// Part windows of a plan: kPartWindowsBase per 32 cases, at most
+// kPartWindowsMax (a call of one case holds 1024 windows, 128 MiB).
+int64_t part_windows_for(int n)
+{
+    return std::min<int64_t>(kPartWindowsMax, (int64_t)kPartWindowsBase * ((n + 31) / 32));
+}
+
+Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind,
+               int64_t part_windows = -1)
 {
     Plan P;
     P.kind = kind;
     P.n = (int)in.size();
     const int n = P.n, cus = h->num_cus;
+    P.part_windows = part_windows > 0 ? part_windows : part_windows_for(std::max(n, 1));
     P.cs.assign(n, CaseDesc{});
     P.rf_off.assign(n, -1);
     P.st_slot.assign(n, -1);
@@ -436,12 +446,12 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind)
     int64_t sumM = 0;
     for (int c = 0; c < n; ++c) sumM += P.cs[c].A.nrows;
     P.cap13 = std::max<int64_t>(1, kind == PLAN_EXACT ? sumM : sumC);
-    P.cap4 = P.cap13 + kMaxPartWindows;
-    P.cap5 = (int64_t)kMaxPartWindows * (kWinWords / kMergeSlice) + 64;
+    P.cap4 = P.cap13 + P.part_windows;
+    P.cap5 = (int64_t)P.part_windows * (kWinWords / kMergeSlice) + 64;
     // workspace layout
     size_t o = 0;
     P.o_ctl = o;     o = align256(o + sizeof(Ctl));
-    P.o_scratch = o; o = align256(o + (size_t)kMaxPartWindows * kWinWords * sizeof(uint32_t));
+    P.o_scratch = o; o = align256(o + (size_t)P.part_windows * kWinWords * sizeof(uint32_t));
     P.o_b1 = o;      o = align256(o + (size_t)P.cap13 * sizeof(BinItem));
     P.o_b2 = o;      o = align256(o + (size_t)P.cap13 * sizeof(BinItem));
     P.o_b3 = o;      o = align256(o + (size_t)P.cap13 * sizeof(BinItem));
@@ -484,6 +494,7 @@ Bound bind_plan(Plan& P, void* ws)
     b.L.merge = reinterpret_cast<MergeItem*>(base + P.o_merge);
     b.L.scratch = reinterpret_cast<uint32_t*>(base + P.o_scratch);
     b.L.cap4 = (uint32_t)P.cap4;
+    b.L.part_windows = (uint32_t)P.part_windows;
     b.tile_row = reinterpret_cast<int32_t*>(base + P.o_tiles);
     b.tile_case = reinterpret_cast<int32_t*>(base + P.o_tcase);
     b.meta = reinterpret_cast<TileMeta*>(base + P.o_meta);
@@ -536,9 +547,9 @@ void launch_sampling(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
     hipLaunchKernelGGL(k_sample_count, dim3((unsigned)P.ngroups), dim3(kSampleThreads), 0, s, b.cs,
                        P.n, b.samp);
     hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(kScanThreads), 0, s, b.samp, P.ngroups, b.cs,
-                       b.ctl);
+                       b.ctl, (uint32_t)P.part_windows);
     hipLaunchKernelGGL(k_sample_write, dim3((unsigned)P.ngroups), dim3(kSampleThreads), 0, s, b.cs,
-                       P.n, (const SampleCounts*)b.samp, b.L);
+                       P.n, (const SampleCounts*)b.samp, (const Ctl*)b.ctl, b.L);
 }
 
 // Symbolic kernels over the four bins, the merge of split rows and the

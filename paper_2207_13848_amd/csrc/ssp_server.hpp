@@ -42,10 +42,11 @@ struct ServerSlot {
 };
 
 // Workspace every plan holds once whatever its cases (control block and the
-// part scratch); a batch needs it once plus each request's own part.
+// part scratch: server plans keep kPartWindowsBase windows whatever their
+// size); a batch needs it once plus each request's own part.
 size_t plan_shared_bytes()
 {
-    return align256(sizeof(Ctl)) + align256((size_t)kMaxPartWindows * kWinWords * sizeof(uint32_t));
+    return align256(sizeof(Ctl)) + align256((size_t)kPartWindowsBase * kWinWords * sizeof(uint32_t));
 }
 
 } // namespace
@@ -77,7 +78,7 @@ ssp_status server_launch(ssp_server_s* S, ServerSlot& slot, std::vector<ServerRe
     std::vector<CaseIn> in;
     in.reserve(reqs.size());
     for (auto& r : reqs) in.push_back(r.in);
-    Plan P = make_plan(&S->ctx, in, PLAN_PREDICT);
+    Plan P = make_plan(&S->ctx, in, PLAN_PREDICT, kPartWindowsBase);
     if (P.total > S->slot_bytes) return SSP_ERR_BUDGET;
     const Bound b = bind_plan(P, slot.ws);
     const bool small = P.n <= kArgCases;
@@ -265,7 +266,7 @@ ssp_status ssp_server_submit(ssp_server S, const ssp_request* r, uint64_t* ticke
         if (st != SSP_OK) return st;
         q.in = case_in(&A, &B, smp, r->sample_rate, r->seed, r->nnz_pred, nullptr, r->stats);
     }
-    const Plan alone = make_plan(&S->ctx, {q.in}, PLAN_PREDICT);
+    const Plan alone = make_plan(&S->ctx, {q.in}, PLAN_PREDICT, kPartWindowsBase);
     if (alone.total > S->slot_bytes) return SSP_ERR_BUDGET;
     q.need = alone.total - plan_shared_bytes();
     {
