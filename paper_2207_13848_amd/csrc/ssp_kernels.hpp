@@ -1,8 +1,8 @@
 // HIP kernels of the prediction path for gfx950 (wave64).
 //
 // A call predicts one product or a batch of them (cases).  Launch order:
-//   k_init             clear counters, per-case results and statistics
-//   k_tiles            merge-path tile starts of the streaming pass
+//   k_setup            clear counters, per-case results and statistics; the
+//                      case table of small calls; merge-path tile starts
 //   k_flop, k_flop_fixup
 //                      products of every row (a pattern SpMV with the row
 //                      lengths of B) into rf, and F
@@ -12,8 +12,10 @@
 //                      table or LDS bitmap); long rows are cut into parts that
 //                      leave their bitmaps in global scratch
 //   k_sym_merge        ORs the parts' bitmaps
-//   k_finalize         z* per case, the empty-sample fallback, the divisor of f*
-//   k_pred_rows        the per-row prediction
+//   k_pred_rows        z* per case, the empty-sample fallback, the divisor of
+//                      f*, and the per-row prediction
+//   (exact structure and reference design: k_finalize, k_finalize_reference,
+//   k_ref_rows)
 // Kernels whose workgroups each serve one case find it by a binary search of
 // the per-case workgroup prefixes; items of the shared bins carry their case.
 #pragma once
@@ -59,11 +61,14 @@ __device__ __forceinline__ int case_of_wg(const CaseDesc* __restrict__ cs, int n
     return lo;
 }
 
-// Workgroups of case c in that grid.
+// Workgroups of case c in that grid (of `total` workgroups, the launch's
+// grid by default).
 template <int32_t CaseDesc::*F>
-__device__ __forceinline__ int32_t wgs_of_case(const CaseDesc* __restrict__ cs, int n, int c)
+__device__ __forceinline__ int32_t wgs_of_case(const CaseDesc* __restrict__ cs, int n, int c,
+                                               int32_t total = -1)
 {
-    return (c + 1 < n ? cs[c + 1].*F : (int32_t)gridDim.x) - cs[c].*F;
+    const int32_t end = total >= 0 ? total : (int32_t)gridDim.x;
+    return (c + 1 < n ? cs[c + 1].*F : end) - cs[c].*F;
 }
 
 typedef unsigned long long ull;
@@ -80,62 +85,14 @@ __device__ __forceinline__ ull* as_ull(uint64_t* p) { return reinterpret_cast<ul
 
 // ---------------------------------------------------------------- init
 
-// One workgroup per case (grid-stride): its results and statistics; the
-// first workgroup also clears the control block.
-__global__ __launch_bounds__(64) void k_init(Ctl* ctl, const CaseDesc* __restrict__ cs,
-                                            CaseRes* __restrict__ cr, int n)
-{
-    const int t = threadIdx.x;
-    if (blockIdx.x == 0 && t < (int)(sizeof(Ctl) / 4)) reinterpret_cast<uint32_t*>(ctl)[t] = 0;
-    for (int c = blockIdx.x; c < n; c += gridDim.x) {
-        uint64_t* r = reinterpret_cast<uint64_t*>(&cr[c]);
-        for (int i = t; i < (int)(sizeof(CaseRes) / 8); i += 64) r[i] = 0;
-        if (t == 0) {
-            ssp_stats* st = cs[c].st;
-            st->total_flop = 0;
-            st->n_sampled = 0;
-            st->sample_flop = 0;
-            st->sample_nnz = 0;
-            st->out_sum = 0;
-            st->nrows = (uint64_t)cs[c].A.nrows;
-            st->flags = 0;
-            st->a_sample_nnz = 0;
-        }
-    }
-}
-
 // Calls of at most kArgCases cases pass the case table in the kernel
-// arguments of k_init_args, which writes it to the workspace (kernel
-// arguments are captured at launch, so the host buffer is free at once and no
-// copy is queued on the stream).  One workgroup per case.
+// arguments of k_setup, which writes it to the workspace (kernel arguments are
+// captured at launch, so the host buffer is free at once and no copy is
+// queued on the stream).
 constexpr int kArgCases = 8;
 struct CaseArgs {
     CaseDesc d[kArgCases];
 };
-
-__global__ __launch_bounds__(64) void k_init_args(Ctl* ctl, CaseDesc* __restrict__ cs,
-                                                 CaseRes* __restrict__ cr, CaseArgs args)
-{
-    const int c = blockIdx.x, t = threadIdx.x;
-    if (c == 0 && t < (int)(sizeof(Ctl) / 4)) reinterpret_cast<uint32_t*>(ctl)[t] = 0;
-    static_assert(sizeof(CaseDesc) % 8 == 0, "copied as 64-bit words");
-    const uint64_t* src = reinterpret_cast<const uint64_t*>(&args.d[c]);
-    uint64_t* dst = reinterpret_cast<uint64_t*>(&cs[c]);
-    for (int i = t; i < (int)(sizeof(CaseDesc) / 8); i += 64) dst[i] = src[i];
-    uint64_t* r = reinterpret_cast<uint64_t*>(&cr[c]);
-    for (int i = t; i < (int)(sizeof(CaseRes) / 8); i += 64) r[i] = 0;
-    if (t == 0) {
-        ssp_stats* st = args.d[c].st;
-        st->total_flop = 0;
-        st->n_sampled = 0;
-        st->sample_flop = 0;
-        st->sample_nnz = 0;
-        st->out_sum = 0;
-        st->nrows = (uint64_t)args.d[c].A.nrows;
-        st->flags = 0;
-        st->a_sample_nnz = 0;
-    }
-}
 
 // ------------------------------------------------------------- binning
 
@@ -267,27 +224,70 @@ __device__ inline void append_row(int32_t row, uint64_t rf, int32_t e0, int32_t 
     (b == 1 ? L.b1 : b == 2 ? L.b2 : L.b3)[i] = it;
 }
 
-// ------------------------------------------------------------ k_tiles
+// ------------------------------------------------------------ tiles
 
 // Merge-path partition of the streaming FLOP pass: tile b of a case starts in
 // row g when its first item b * kFlopTile lies in [rpt[g] + g, rpt[g+1] + g + 1),
 // the span of row g's entries and end marker.  Writes the start row and the
-// case of every global tile (tiles numbered case after case).
-__global__ __launch_bounds__(256) void k_tiles(const CaseDesc* __restrict__ cs, int n,
-                                              int32_t* __restrict__ tile_row,
-                                              int32_t* __restrict__ tile_case)
+// case of every global tile (tiles numbered case after case); `wg` is this
+// workgroup's index in a tile grid of G_all workgroups (256 threads each).
+__device__ __forceinline__ void tile_starts(const CaseDesc* __restrict__ tab, int n, int32_t wg,
+                                            int32_t G_all, int32_t* __restrict__ tile_row,
+                                            int32_t* __restrict__ tile_case)
 {
-    const int c = case_of_wg<&CaseDesc::wg_tiles>(cs, n, blockIdx.x);
-    const int64_t bl = (int64_t)blockIdx.x - cs[c].wg_tiles;
-    const int64_t G = wgs_of_case<&CaseDesc::wg_tiles>(cs, n, c);
-    const Csr A = cs[c].A;
-    const int64_t M = A.nrows, ntiles = cs[c].ntiles, base = cs[c].tile_base;
+    const int c = case_of_wg<&CaseDesc::wg_tiles>(tab, n, wg);
+    const int64_t bl = (int64_t)wg - tab[c].wg_tiles;
+    const int64_t G = wgs_of_case<&CaseDesc::wg_tiles>(tab, n, c, G_all);
+    const Csr A = tab[c].A;
+    const int64_t M = A.nrows, ntiles = tab[c].ntiles, base = tab[c].tile_base;
     const int64_t stride = G * 256;
     for (int64_t g = bl * 256 + threadIdx.x; g < M; g += stride) {
         const int64_t f0 = (int64_t)A.rpt[g] + g, f1 = (int64_t)A.rpt[g + 1] + g + 1;
         for (int64_t b = (f0 + kFlopTile - 1) / kFlopTile; b * kFlopTile < f1 && b < ntiles; ++b) {
             tile_row[base + b] = (int32_t)g;
             tile_case[base + b] = c;
+        }
+    }
+}
+
+// The first kernel of a call: workgroups [0, ninit) clear the cases' results,
+// statistics and the control block (and with ARGS write the case table from
+// the kernel arguments, for calls of at most kArgCases cases); the others
+// write the merge-path tile starts (reading the case table from the kernel
+// arguments with ARGS, else from the workspace, where the host copied it).
+template <bool ARGS>
+__global__ __launch_bounds__(256) void k_setup(Ctl* ctl, CaseDesc* __restrict__ cs,
+                                              CaseRes* __restrict__ cr, int n, int ninit,
+                                              int32_t* __restrict__ tile_row,
+                                              int32_t* __restrict__ tile_case, CaseArgs args)
+{
+    const int t = threadIdx.x;
+    if ((int)blockIdx.x >= ninit) {
+        tile_starts(ARGS ? args.d : cs, n, (int32_t)blockIdx.x - ninit,
+                    (int32_t)gridDim.x - ninit, tile_row, tile_case);
+        return;
+    }
+    if (blockIdx.x == 0 && t < (int)(sizeof(Ctl) / 4)) reinterpret_cast<uint32_t*>(ctl)[t] = 0;
+    for (int c = blockIdx.x; c < n; c += ninit) {
+        const CaseDesc& d = ARGS ? args.d[c] : cs[c];
+        if (ARGS) {
+            static_assert(sizeof(CaseDesc) % 8 == 0, "copied as 64-bit words");
+            const uint64_t* src = reinterpret_cast<const uint64_t*>(&args.d[c]);
+            uint64_t* dst = reinterpret_cast<uint64_t*>(&cs[c]);
+            for (int i = t; i < (int)(sizeof(CaseDesc) / 8); i += 256) dst[i] = src[i];
+        }
+        uint64_t* r = reinterpret_cast<uint64_t*>(&cr[c]);
+        for (int i = t; i < (int)(sizeof(CaseRes) / 8); i += 256) r[i] = 0;
+        if (t == 0) {
+            ssp_stats* st = d.st;
+            st->total_flop = 0;
+            st->n_sampled = 0;
+            st->sample_flop = 0;
+            st->sample_nnz = 0;
+            st->out_sum = 0;
+            st->nrows = (uint64_t)d.A.nrows;
+            st->flags = 0;
+            st->a_sample_nnz = 0;
         }
     }
 }

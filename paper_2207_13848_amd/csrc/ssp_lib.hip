@@ -515,12 +515,6 @@ Bound bind_plan(Plan& P, void* ws)
 template <int MODE>
 void launch_flop(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s, bool timed)
 {
-    {
-        PhaseTimer pt(h, PH_TILES, s, timed);
-        if (P.g_tiles > 0)
-            hipLaunchKernelGGL(k_tiles, dim3(P.g_tiles), dim3(256), 0, s, b.cs, P.n, b.tile_row,
-                               b.tile_case);
-    }
     if (P.g_flop > 0) {
         PhaseTimer pt(h, PH_FLOP, s, timed);
         if (P.vec)
@@ -542,7 +536,7 @@ void launch_flop(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s, boo
 void launch_sampling(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s, bool timed)
 {
     PhaseTimer pt(h, PH_SAMPLE, s, timed);
-    if (P.ngroups == 0) return;  // (the bin counters stay 0 from k_init)
+    if (P.ngroups == 0) return;  // (the bin counters stay 0 from k_setup)
     // count, scan, write: per-group counters instead of device atomics
     hipLaunchKernelGGL(k_sample_count, dim3((unsigned)P.ngroups), dim3(kSampleThreads), 0, s, b.cs,
                        P.n, b.samp);
@@ -571,9 +565,13 @@ void launch_symbolic(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
         hipLaunchKernelGGL((k_sym<kBin2Team, kBin2Words, MODE>),
                            dim3(grid_for(nitems, resident(k_sym<kBin2Team, kBin2Words, MODE>, kBin2Team, cus))),
                            dim3(kBin2Team), 0, s, b.cs, b.L.b2, &b.ctl->bin_cnt[2], b.cr);
-        hipLaunchKernelGGL((k_sym<kBin3Team, kBin3Words, MODE>),
-                           dim3(grid_for(nitems, resident(k_sym<kBin3Team, kBin3Words, MODE>, kBin3Team, cus))),
-                           dim3(kBin3Team), 0, s, b.cs, b.L.b3, &b.ctl->bin_cnt[3], b.cr);
+        // (bin 3 stays empty when every case sends its rows to the long-row kernel)
+        bool bin3 = false;
+        for (int c = 0; c < P.n; ++c) bin3 = bin3 || !P.cs[c].big3;
+        if (bin3)
+            hipLaunchKernelGGL((k_sym<kBin3Team, kBin3Words, MODE>),
+                               dim3(grid_for(nitems, resident(k_sym<kBin3Team, kBin3Words, MODE>, kBin3Team, cus))),
+                               dim3(kBin3Team), 0, s, b.cs, b.L.b3, &b.ctl->bin_cnt[3], b.cr);
     }
     // one window holding all N columns in every case: no window tests
     auto kfun = P.win1 ? k_sym_big<MODE, true> : k_sym_big<MODE, false>;
@@ -615,17 +613,26 @@ void prepare_kernels()
 
 // The whole launch sequence of a call.  `table_on_device`: the case table is
 // already in the workspace (batches, graphs); otherwise (at most kArgCases
-// cases) k_init_args writes it from its kernel arguments.
+// cases) k_setup writes it from its kernel arguments.
 ssp_status launch_plan(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
                        bool table_on_device, bool timed)
 {
-    if (table_on_device) {
-        hipLaunchKernelGGL(k_init, dim3(grid_for(P.n, 1024)), dim3(64), 0, s, b.ctl, b.cs, b.cr, P.n);
-    } else {
+    {
+        // clears, the case table (from the kernel arguments for small calls)
+        // and the merge-path tile starts, in one launch
+        PhaseTimer pt(h, PH_TILES, s, timed);
         CaseArgs args;
         std::memset(&args, 0, sizeof(args));
-        for (int c = 0; c < P.n; ++c) args.d[c] = P.cs[c];
-        hipLaunchKernelGGL(k_init_args, dim3(P.n), dim3(64), 0, s, b.ctl, b.cs, b.cr, args);
+        const int ninit = table_on_device ? (int)grid_for(P.n, 1024) : P.n;
+        const dim3 grid((unsigned)(ninit + P.g_tiles));
+        if (table_on_device) {
+            hipLaunchKernelGGL(k_setup<false>, grid, dim3(256), 0, s, b.ctl, b.cs, b.cr, P.n,
+                               ninit, b.tile_row, b.tile_case, args);
+        } else {
+            for (int c = 0; c < P.n; ++c) args.d[c] = P.cs[c];
+            hipLaunchKernelGGL(k_setup<true>, grid, dim3(256), 0, s, b.ctl, b.cs, b.cr, P.n,
+                               ninit, b.tile_row, b.tile_case, args);
+        }
     }
     SSP_LAUNCHED(h);
     if (P.kind == PLAN_EXACT) {
