@@ -9,7 +9,7 @@ namespace ssp {
 
 // Row bins of the symbolic (distinct-count) kernels, by row FLOP.
 //   bin 1: 1..128 products      -> one wave per row, LDS table <= 256 words
-//   bin 2: 129..1024 products   -> 256 threads per row, LDS table <= 2048 words
+//   bin 2: 129..1024 products   -> 256 threads (or one wave) per row, LDS table <= 2048 words
 //   bin 3: 1025..8192 products  -> 512 threads per row, LDS table <= 16384 words
 //   bin 4: more                 -> 1024 threads, LDS bitmap per column window;
 //                                  rows above kSplitTarget products are cut into
@@ -19,6 +19,10 @@ namespace ssp {
 constexpr uint64_t kBin1Max = 128, kBin2Max = 1024, kBin3Max = 8192;
 constexpr int kBin1Words = 256, kBin2Words = 2048, kBin3Words = 16384;
 constexpr int kBin1Team = 64, kBin2Team = 256, kBin3Team = 512, kBin4Team = 1024;
+// Bin 2 runs one wave per row instead of kBin2Team threads when a call
+// expects at least this many sampled rows: many rows then keep the chip busy,
+// and a wave needs no barriers; few rows want the shorter chain of a team.
+constexpr int64_t kBin2WaveRows = 8192;
 
 // Bin-4 bitmap window: at most 32768 words = 2^20 columns = 128 KiB of LDS.
 constexpr int kWinWords = 32768;

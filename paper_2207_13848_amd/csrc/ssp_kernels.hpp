@@ -1351,13 +1351,10 @@ __device__ __forceinline__ void flop_issue_tile(const CaseDesc* __restrict__ cs,
     R.a0 = R.j0 & ~(int64_t)3;
     const int64_t rlast = i1 < M ? i1 : M - 1;
     const int nb = (int)(rlast - i0 + 2);
-    // only the loads the tile's rows need (nb is uniform: whole instructions
-    // are skipped, which spares the address units most of them on tiles of
-    // long rows)
 #pragma unroll
     for (int u = 0; u < NRP; ++u) {
         const int k = t + u * NT;
-        if (u == 0 || u * NT < nb) R.rp[u] = R.Arpt[i0 + (k < nb ? k : nb - 1)];
+        R.rp[u] = R.Arpt[i0 + (k < nb ? k : nb - 1)];
     }
     // Loads are unconditional from clamped in-range addresses (masked later):
     // a load under a lane condition becomes a branch, and loads in separate
@@ -1401,7 +1398,9 @@ __device__ __forceinline__ int32_t tile_end_row(const CaseDesc* __restrict__ cs,
 }
 
 template <int MODE, bool VEC>
-__global__ __launch_bounds__(kFlopThreads) void k_flop(const CaseDesc* __restrict__ cs,
+// (at least six waves per SIMD: the gathers need the waves in flight)
+__global__ __launch_bounds__(kFlopThreads) __attribute__((amdgpu_waves_per_eu(6)))
+void k_flop(const CaseDesc* __restrict__ cs,
                                                       const int32_t* __restrict__ tile_row,
                                                       const int32_t* __restrict__ tile_case,
                                                       int64_t ntiles_all, TileMeta* meta,

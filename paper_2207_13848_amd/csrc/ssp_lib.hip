@@ -284,6 +284,7 @@ struct Plan {
     int32_t g_tiles = 0, g_flop = 0, g_fixup = 0, g_rows = 0;
     int32_t win_words_max = 4;
     bool win1 = true, vec = true;
+    bool bin2_wave = false;  // bin 2 one wave per row (many sampled rows expected)
     size_t o_ctl = 0, o_scratch = 0, o_b1 = 0, o_b2 = 0, o_b3 = 0, o_b4 = 0, o_merge = 0,
            o_tiles = 0, o_tcase = 0, o_meta = 0, o_samp = 0, o_cases = 0, o_res = 0, o_stats = 0,
            o_rowtmp = 0, total = 0;
@@ -367,7 +368,7 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind,
     P.cs.assign(n, CaseDesc{});
     P.rf_off.assign(n, -1);
     P.st_slot.assign(n, -1);
-    int64_t sumC = 0;
+    int64_t sumC = 0, exp_rows = 0;  // candidates; rows expected in the bins
     for (int c = 0; c < n; ++c) {
         CaseDesc& d = P.cs[c];
         const CaseIn& x = in[c];
@@ -411,7 +412,9 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind,
         P.win_words_max = std::max(P.win_words_max, d.win_words);
         if (d.nwin != 1) P.win1 = false;
         if (M > 0 && !((reinterpret_cast<uintptr_t>(x.A.col) & 15u) == 0 && nnz >= 4)) P.vec = false;
+        exp_rows += kind == PLAN_EXACT ? M : (d.paper ? d.ncand : (int64_t)(x.rate * (double)M));
     }
+    P.bin2_wave = exp_rows >= kBin2WaveRows;
     // sampling groups: about kSampleTarget per call, at least 2048 candidates each
     int64_t gsize = (sumC + kSampleTarget - 1) / kSampleTarget;
     gsize = std::max<int64_t>(2048, (gsize + 255) / 256 * 256);
@@ -440,7 +443,11 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind,
     auto rows_cap = [&](int c) {
         return std::max<int64_t>(1, (Mof(c) + 8 * kRowsThreads - 1) / (8 * kRowsThreads));
     };
-    P.g_rows = share_wgs(n, std::max(1, cus / 2), rows_work, rows_cap, f);
+    // (about four row steps per thread over the call, at least half the CUs)
+    int64_t rows_all = 0;
+    for (int c = 0; c < n; ++c) rows_all += Mof(c);
+    const int64_t rows_budget = std::max<int64_t>(cus / 2, rows_all / (4 * 8 * kRowsThreads));
+    P.g_rows = share_wgs(n, rows_budget, rows_work, rows_cap, f);
     for (int c = 0; c < n; ++c) P.cs[c].wg_rows = f[c];
     // list capacities
     int64_t sumM = 0;
@@ -562,9 +569,14 @@ void launch_symbolic(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
         hipLaunchKernelGGL((k_sym<kBin1Team, kBin1Words, MODE>),
                            dim3(grid_for(nitems, resident(k_sym<kBin1Team, kBin1Words, MODE>, kBin1Team, cus))),
                            dim3(kBin1Team), 0, s, b.cs, b.L.b1, &b.ctl->bin_cnt[1], b.cr);
-        hipLaunchKernelGGL((k_sym<kBin2Team, kBin2Words, MODE>),
-                           dim3(grid_for(nitems, resident(k_sym<kBin2Team, kBin2Words, MODE>, kBin2Team, cus))),
-                           dim3(kBin2Team), 0, s, b.cs, b.L.b2, &b.ctl->bin_cnt[2], b.cr);
+        if (P.bin2_wave)
+            hipLaunchKernelGGL((k_sym<kWave, kBin2Words, MODE>),
+                               dim3(grid_for(nitems, resident(k_sym<kWave, kBin2Words, MODE>, kWave, cus))),
+                               dim3(kWave), 0, s, b.cs, b.L.b2, &b.ctl->bin_cnt[2], b.cr);
+        else
+            hipLaunchKernelGGL((k_sym<kBin2Team, kBin2Words, MODE>),
+                               dim3(grid_for(nitems, resident(k_sym<kBin2Team, kBin2Words, MODE>, kBin2Team, cus))),
+                               dim3(kBin2Team), 0, s, b.cs, b.L.b2, &b.ctl->bin_cnt[2], b.cr);
         // (bin 3 stays empty when every case sends its rows to the long-row kernel)
         bool bin3 = false;
         for (int c = 0; c < P.n; ++c) bin3 = bin3 || !P.cs[c].big3;
