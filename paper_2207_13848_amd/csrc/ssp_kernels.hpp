@@ -1620,6 +1620,7 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __re
 {
     __shared__ uint64_t s_red[kRowsThreads / kWave + 1];
     __shared__ uint64_t s_z;
+    __shared__ Divisor s_div;
     const int c = case_of_wg<&CaseDesc::wg_rows>(cs, n, blockIdx.x);
     const int64_t bl = (int64_t)blockIdx.x - cs[c].wg_rows;
     const int64_t G = wgs_of_case<&CaseDesc::wg_rows>(cs, n, c);
@@ -1644,16 +1645,22 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __re
     };
     const int64_t first = bl * kRowsThreads * U + threadIdx.x;
     load_rows(first);
-    if (threadIdx.x < kWave) {
+    // wave 0 alone sums the slots and derives the divisor (its reciprocal
+    // loop on the scalar unit, which the waves of a CU share)
+    if (__builtin_amdgcn_readfirstlane(threadIdx.x / kWave) == 0) {
         const uint64_t z = wave_sum(z_ld);
-        if (threadIdx.x == 0) s_z = z;
+        const uint64_t f = uniform_u64(fs_ld);
+        Divisor d0{};
+        if (f) d0 = make_divisor(f);
+        if (threadIdx.x == 0) {
+            s_z = z;
+            s_div = d0;
+        }
     }
     __syncthreads();
-    // (uniform values: the divisor's reciprocal loop runs on the scalar unit)
     const uint64_t zs = uniform_u64(s_z), fs = uniform_u64(fs_ld);
     const bool fallback = fs == 0;
-    Divisor D{};
-    if (!fallback) D = make_divisor(fs);
+    const Divisor D = s_div;
     if (bl == 0 && threadIdx.x == 0) {
         st->sample_nnz = zs;
         if (fallback) atomicOr(as_ull(&st->flags), (ull)SSP_FLAG_EMPTY_SAMPLE);
