@@ -881,6 +881,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
     __syncthreads();
     uint32_t it = __builtin_amdgcn_readfirstlane(s_it);
     bool staged = false;  // item `it` is staged in s_nx, s_nb0, s_nb1
+    int clean4 = 0;       // leading 16-byte groups of the bitmap known to be zero
     for (;;) {
         if (it >= n) break;
         BigItem item;
@@ -915,9 +916,14 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
             const int64_t wcols = (N - c_lo) < wcols_full ? (N - c_lo) : wcols_full;
             const int words = (int)((wcols + 31) / 32);
             const int w4 = (words + 3) / 4;  // 16-byte groups (win_words is a multiple of 4)
-            for (int i = t; i < w4; i += TEAM) bm4[i] = make_uint4(0u, 0u, 0u, 0u);
+            // the bitmap is cleared when dirty; the pass that counts a window
+            // zeroes every group it reads
+            if (w4 > clean4) {
+                for (int i = clean4 + t; i < w4; i += TEAM) bm4[i] = make_uint4(0u, 0u, 0u, 0u);
+                clean4 = w4;
+                __syncthreads();
+            }
             const uint32_t clo32 = (uint32_t)c_lo, wc32 = (uint32_t)wcols;
-            __syncthreads();
             for (int64_t i0 = 0; i0 < cnt; i0 += TEAM) {
                 const int64_t i = i0 + t;
                 const bool live = i < cnt;
@@ -1096,6 +1102,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
             // 16-byte LDS reads, eight issued before any is used (a loop of
             // single reads would wait on each)
             constexpr int UR = 8;
+            const uint4 z4 = make_uint4(0u, 0u, 0u, 0u);
             if (item.slot < 0) {
                 uint32_t cnt = 0;
                 for (int i0 = t; i0 < w4; i0 += UR * TEAM) {
@@ -1107,8 +1114,10 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
                     }
 #pragma unroll
                     for (int u = 0; u < UR; ++u)
-                        if (i0 + u * TEAM < w4)
+                        if (i0 + u * TEAM < w4) {
+                            bm4[i0 + u * TEAM] = z4;
                             cnt += __popc(x[u].x) + __popc(x[u].y) + __popc(x[u].z) + __popc(x[u].w);
+                        }
                 }
                 total += block_sum<TEAM, uint64_t>(cnt, s_red);
             } else {
@@ -1126,6 +1135,7 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
                     for (int u = 0; u < UR; ++u)
                         if (i0 + u * TEAM < w4) g[i0 + u * TEAM] = x[u];
                 }
+                clean4 = 0;  // (this pass leaves the bitmap as it is)
             }
             __syncthreads();
         }
