@@ -1149,9 +1149,9 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
     if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
 }
 
-// ORs the part bitmaps of split rows, one slice of a window per item.  With
-// `finalize`, the last workgroup to finish (after every symbolic kernel has
-// added to z*) computes the per-call divisor of f*.
+// ORs the part bitmaps of split rows, one slice of a window per item, and
+// adds the distinct counts (sixteen parts' 16-byte groups in flight per
+// thread: the parts' windows are read once, from L2 or MALL).
 template <int MODE>
 __global__ __launch_bounds__(256) void k_sym_merge(const CaseDesc* __restrict__ cs,
                                                   const MergeItem* __restrict__ items,
@@ -1180,21 +1180,22 @@ __global__ __launch_bounds__(256) void k_sym_merge(const CaseDesc* __restrict__ 
         const int g4 = m.slice * (kMergeSlice / 4) + t;
         uint32_t cnt = 0;
         if (g4 < w4) {
-            // the parts' groups, eight 16-byte loads in flight, then OR
+            // the parts' groups, sixteen 16-byte loads in flight, then OR
+            constexpr int PF = 16;
             const int64_t stride4 = (int64_t)nwin * kWinWords / 4;
             const uint4* src = reinterpret_cast<const uint4*>(
                                    L.scratch + ((int64_t)m.slot + m.window) * (int64_t)kWinWords) +
                                g4;
             uint4 x = make_uint4(0u, 0u, 0u, 0u);
-            for (int p0 = 0; p0 < m.nparts; p0 += 8) {
-                uint4 v[8];
+            for (int p0 = 0; p0 < m.nparts; p0 += PF) {
+                uint4 v[PF];
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < PF; ++u) {
                     const int pp = p0 + u < m.nparts ? p0 + u : m.nparts - 1;
                     v[u] = src[(int64_t)pp * stride4];
                 }
 #pragma unroll
-                for (int u = 0; u < 8; ++u) {
+                for (int u = 0; u < PF; ++u) {
                     x.x |= v[u].x;
                     x.y |= v[u].y;
                     x.z |= v[u].z;

@@ -597,7 +597,7 @@ void launch_symbolic(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
     }
     {
         PhaseTimer pt(h, PH_SYM_MERGE, s, timed);
-        hipLaunchKernelGGL((k_sym_merge<MODE>), dim3((unsigned)(2 * cus)), dim3(256), 0, s, b.cs,
+        hipLaunchKernelGGL((k_sym_merge<MODE>), dim3((unsigned)(4 * cus)), dim3(256), 0, s, b.cs,
                            b.L.merge, &b.ctl->bin_cnt[5], b.L, b.cr);
     }
     if (!finalize) return;  // (the prediction kernel sums z* itself)
