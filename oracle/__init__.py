@@ -17,6 +17,9 @@ Paper anchors (Du et al., arXiv 2207.13848):
   * symmetric F* and eps_f ........ Eq. (3)
   * error identity ................ Eq. (5)
   * precise method (exact) ........ Sec. I (symbolic phase)
+  * numeric product (consumer) .... Sec. I (the output the prediction sizes):
+                                    the definition of C = A.B, and the slot
+                                    layout of a predicted-capacity allocation
 """
 from __future__ import annotations
 
@@ -90,6 +93,8 @@ def _load():
         lib.orc_exact.restype = ctypes.c_int
         lib.orc_rows_nnz.argtypes = [i64, vp, vp, vp, vp, vp, vp, vp]
         lib.orc_rows_nnz.restype = ctypes.c_int
+        lib.orc_spgemm.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
+        lib.orc_spgemm.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -231,6 +236,55 @@ def rows_nnz(A, B, rows):
     if rc:
         raise ValueError(f"oracle rows_nnz failed ({rc})")
     return nnz[: rows.shape[0]], rf[: rows.shape[0]]
+
+
+# ------------------------------------------- the consumer (numeric product)
+
+def spgemm(A, A_val, B, B_val):
+    """C = A.B with values, by the definition (``orc_spgemm``).
+
+    Returns ``(C_rpt int64[M+1], C_col int32, C_val f64, C_abs f64,
+    C_terms int32)``: rows with increasing columns; ``C_abs`` is the sum of
+    |a*b| over an entry's terms and ``C_terms`` their number, which bound the
+    rounding error of any order of summation."""
+    M, K, ar, ac, br, bc = _csr_args(A, B)
+    av = np.ascontiguousarray(A_val, dtype=np.float64)
+    bv = np.ascontiguousarray(B_val, dtype=np.float64)
+    if av.shape[0] != ac.shape[0] or bv.shape[0] != bc.shape[0]:
+        raise ValueError("value arrays must match the column arrays")
+    counts, _ = exact(A, B)
+    rpt = np.zeros(M + 1, dtype=np.int64)
+    np.cumsum(counts, out=rpt[1:])
+    Z = int(rpt[M])
+    col = np.zeros(max(Z, 1), dtype=np.int32)
+    val = np.zeros(max(Z, 1), dtype=np.float64)
+    aab = np.zeros(max(Z, 1), dtype=np.float64)
+    terms = np.zeros(max(Z, 1), dtype=np.int32)
+    N = int(B.ncols)
+    av1 = av if av.size else np.zeros(1)  # (kept alive across the call)
+    bv1 = bv if bv.size else np.zeros(1)
+    rc = _load().orc_spgemm(M, N, _p(ar), _p(ac), _p(av1), _p(br), _p(bc), _p(bv1), _p(rpt),
+                            _p(col), _p(val), _p(aab), _p(terms))
+    if rc:
+        raise ValueError(f"oracle spgemm failed ({rc})")
+    return rpt, col[:Z], val[:Z], aab[:Z], terms[:Z]
+
+
+def spgemm_layout(row_cap, margin_pct: int, counts, ncols: int) -> dict:
+    """Integer outcome of the predicted-capacity consumer.
+
+    Row i gets a slot of ``min(N, c + ceil(c * margin_pct / 100))`` entries,
+    ``c = row_cap[i]`` clamped to [0, N] (a row of C has at most N entries).
+    A row whose nonzero count exceeds its slot overflows and is recomputed by
+    the fallback pass.  Returns nnz, slot_entries, overflow_rows and
+    overflow_nnz as Python ints."""
+    N = int(ncols)
+    cap = np.clip(np.asarray(row_cap, dtype=np.int64), 0, N)
+    slot = np.minimum(N, cap + (cap * int(margin_pct) + 99) // 100)
+    cnt = np.asarray(counts, dtype=np.int64)
+    over = cnt > slot
+    return {"nnz": int(cnt.sum()), "slot_entries": int(slot.sum()),
+            "overflow_rows": int(over.sum()), "overflow_nnz": int(cnt[over].sum())}
 
 
 # ------------------------------------------------------- Sec. VI-A accuracy

@@ -358,3 +358,80 @@ int orc_rows_nnz(int64_t nrows_list, const int32_t* rows, const int32_t* Arpt, c
     free(buf);
     return ORC_OK;
 }
+
+/* ------------------------------------------ the consumer (numeric product) */
+
+/*
+ * Numeric product C = A.B by its definition, for the consumer that sizes C
+ * from the predicted structure (Sec. I: the prediction exists to allocate the
+ * output and balance the numeric phase).  The paper gives no numeric kernel;
+ * this is the plain definition C[i][j] = sum over the stored entries (i,k,a)
+ * of A and (k,j,b) of B of a*b.
+ *
+ * Row i is accumulated in a dense array over the N columns, the terms added
+ * in storage order (A's entries in order, each named B row in order), so the
+ * sum of a column is the left-to-right sum of its terms.  Beside the value
+ * the oracle keeps, for each output entry, the sum of |a*b| and the number of
+ * terms: the rounding error of any summation order is bounded by them.  The
+ * distinct columns of the row are sorted (qsort) and written in increasing
+ * order.  Duplicate entries of A or B simply contribute more terms.
+ *
+ * Crpt (int64[M+1]) must already hold the row offsets of C (the exact counts,
+ * orc_exact, prefix-summed); Ccol/Cval/Cabs/Cterms receive rpt[M] entries.
+ * Returns ORC_ERR_ARG if a row's distinct count disagrees with Crpt.
+ */
+int orc_spgemm(int64_t M, int64_t N, const int32_t* Arpt, const int32_t* Acol, const double* Aval,
+               const int32_t* Brpt, const int32_t* Bcol, const double* Bval, const int64_t* Crpt,
+               int32_t* Ccol, double* Cval, double* Cabs, int32_t* Cterms)
+{
+    if (M < 0 || N < 0) return ORC_ERR_ARG;
+    size_t n = (size_t)(N > 0 ? N : 1);
+    double* acc = (double*)calloc(n, sizeof(double));
+    double* aab = (double*)calloc(n, sizeof(double));
+    int32_t* terms = (int32_t*)calloc(n, sizeof(int32_t));
+    int64_t* seen = (int64_t*)malloc(n * sizeof(int64_t));
+    int32_t* touched = (int32_t*)malloc(n * sizeof(int32_t));
+    int rc = ORC_OK;
+    if (!acc || !aab || !terms || !seen || !touched) rc = ORC_ERR_MEM;
+    for (size_t q = 0; rc == ORC_OK && q < n; ++q) seen[q] = -1;
+    for (int64_t i = 0; rc == ORC_OK && i < M; ++i) {
+        int64_t nt = 0;
+        for (int64_t e = Arpt[i]; e < Arpt[i + 1]; ++e) {
+            const int32_t k = Acol[e];
+            const double a = Aval[e];
+            for (int64_t q = Brpt[k]; q < Brpt[k + 1]; ++q) {
+                const int32_t j = Bcol[q];
+                const double p = a * Bval[q];
+                if (seen[j] != i) {
+                    seen[j] = i;
+                    acc[j] = 0.0;
+                    aab[j] = 0.0;
+                    terms[j] = 0;
+                    touched[nt++] = j;
+                }
+                acc[j] += p;
+                aab[j] += p < 0 ? -p : p;
+                terms[j] += 1;
+            }
+        }
+        if (Crpt[i + 1] - Crpt[i] != nt) {
+            rc = ORC_ERR_ARG;
+            break;
+        }
+        qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);
+        for (int64_t s = 0; s < nt; ++s) {
+            const int32_t j = touched[s];
+            const int64_t o = Crpt[i] + s;
+            Ccol[o] = j;
+            Cval[o] = acc[j];
+            Cabs[o] = aab[j];
+            Cterms[o] = terms[j];
+        }
+    }
+    free(acc);
+    free(aab);
+    free(terms);
+    free(seen);
+    free(touched);
+    return rc;
+}

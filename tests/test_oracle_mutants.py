@@ -40,7 +40,18 @@ MUTANTS = {
     "sample_sums_skip_last": ("for (int64_t s = 0; s < n; ++s) {\n        fs +=",
                               "for (int64_t s = 0; s + 1 < n; ++s) {\n        fs +="),
     "exact_sum_dropped_row": ("Z += z;", "Z += (i ? z : 0);"),
+    "spgemm_assigns_not_adds": ("acc[j] += p;", "acc[j] = p;"),
+    "spgemm_adds_not_multiplies": ("const double p = a * Bval[q];", "const double p = a + Bval[q];"),
+    "spgemm_drops_last_b_entry": (
+        "for (int64_t q = Brpt[k]; q < Brpt[k + 1]; ++q) {\n                const int32_t j",
+        "for (int64_t q = Brpt[k]; q + 1 < Brpt[k + 1]; ++q) {\n                const int32_t j"),
+    "spgemm_wrong_a_value": ("const double a = Aval[e];", "const double a = Aval[Arpt[i]];"),
+    "spgemm_signed_abs": ("aab[j] += p < 0 ? -p : p;", "aab[j] += p;"),
+    "spgemm_terms_not_counted": ("terms[j] += 1;", "terms[j] = 1;"),
+    "spgemm_unsorted_rows": ("qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);", ""),
+    "spgemm_row_offset_shift": ("const int64_t o = Crpt[i] + s;", "const int64_t o = Crpt[i] + s + (s > 0 && i == 0);"),
 }
+PIN_FILES = ("test_oracle_pins.py", "test_oracle_spgemm_pins.py")
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
@@ -54,6 +65,6 @@ def test_pins_catch_mutant(tmp_path, name):
     subprocess.check_call(["gcc", "-O1", "-std=c11", "-fPIC", "-shared", "-o", str(lib), str(mut)])
     env = dict(os.environ, SSP_ORACLE_LIB_OVERRIDE=str(lib))
     r = subprocess.run([sys.executable, "-m", "pytest", "-x", "-q", "-p", "no:cacheprovider",
-                        os.path.join(ROOT, "tests", "test_oracle_pins.py")],
+                        *[os.path.join(ROOT, "tests", f) for f in PIN_FILES]],
                        cwd=ROOT, env=env, capture_output=True, text=True, timeout=600)
     assert r.returncode != 0, f"mutant {name} survived the pins:\n{r.stdout[-2000:]}"

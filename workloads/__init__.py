@@ -1,4 +1,4 @@
-"""Seeded synthetic CSR workloads (structure only, int32 indices).
+"""Seeded synthetic CSR workloads (int32 indices; seeded values for the numeric product).
 
 The paper evaluates on 25 SuiteSparse matrices and their pairwise products
 (Sec. VI, Table II).  Those files are not shipped here; these generators stand
@@ -180,6 +180,25 @@ def make(structure: str, n: int, d: int, seed: int) -> CSR:
     if structure == "zipf":
         return zipf(n, d, seed, 1.5)
     raise ValueError(f"unknown structure {structure!r}")
+
+
+# ------------------------------------------------------------------- values
+
+def values(n: int, seed: int, kind: str = "uniform") -> np.ndarray:
+    """Seeded float64 values for the ``n`` stored entries of a matrix.
+
+    ``uniform``: independent draws from U[-1, 1).  ``int``: small integers in
+    [-4, 4] without 0, so products and their sums are exact in float64 and
+    every summation order gives the same result."""
+    rng = np.random.default_rng(seed)
+    if kind == "uniform":
+        return rng.uniform(-1.0, 1.0, n)
+    if kind == "int":
+        v = rng.integers(1, 5, n).astype(np.float64)
+        return np.where(rng.integers(0, 2, n) == 1, v, -v)
+    if kind == "ones":
+        return np.ones(n, dtype=np.float64)
+    raise ValueError(f"unknown value kind {kind!r}")
 
 
 # ---------------------------------------------------------------- workloads
