@@ -334,6 +334,59 @@ SSP_API ssp_status ssp_server_destroy(ssp_server s);
  */
 SSP_API ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* M, int64_t* n_bad, void* stream);
 
+/* ------------------------------------- the consumer: numeric product */
+
+/*
+ * Numeric C = A.B (float64 values) whose memory is sized by a per-row
+ * capacity, normally the prediction: the output structure is predicted so
+ * that C can be allocated, and the numeric phase balanced, without a symbolic
+ * pass (Sec. I).  The paper stops at the prediction; this consumer is one way
+ * to use it.  Two calls:
+ *
+ * ssp_spgemm_compute.  Row i of C gets a slot of
+ *     s_i = min(N, c + ceil(c * margin_pct / 100)),  c = row_cap[i] clamped to [0, N],
+ * in a slot area of sum(s_i) entries (12 bytes each) that the handle
+ * allocates.  One numeric pass accumulates every row once (rows of at most
+ * 2048 products in an LDS hash table, longer rows in a dense accumulator),
+ * counts its nonzeros and writes the row, columns increasing, into its slot
+ * when it fits.  C_rpt then receives C's row offsets from the exact counts.
+ * Waits for `stream` twice (the slot area's size and the results are read on
+ * the host) and fills *info.
+ *   A_val, B_val : device double[A.nnz], double[B.nnz]; duplicate entries add.
+ *   row_cap      : device int64[A.nrows], any values (clamped as above).
+ *   margin_pct   : 0 .. 10000.
+ *   C_rpt        : device int64[A.nrows + 1], written (C_rpt[0] = 0).
+ *   info         : host, written.
+ *
+ * ssp_spgemm_copy.  Writes C_col / C_val (device, capacity >= info.nnz
+ * entries, else SSP_ERR_INVALID_ARG): rows that fitted are copied from their
+ * slots, rows with more nonzeros than their slot (an under-prediction) are
+ * recomputed straight into their final place.  Asynchronous on `stream`.  A,
+ * B and their values must be unchanged since the compute call; the next
+ * compute call on the handle waits for this copy and replaces its state.
+ *
+ * C keeps every structural entry (terms that cancel leave an explicit 0.0):
+ * C's structure is exactly the structure the prediction estimates
+ * (ssp_exact_structure).  Values are sums of the products in an unspecified
+ * order.  Errors: those of the other calls; SSP_ERR_BUDGET when the slot area
+ * and accumulators exceed the handle's budget.
+ */
+typedef struct {
+    int64_t nnz;           /* NNZ(C)                                                */
+    int64_t total_flop;    /* F                                                     */
+    int64_t slot_entries;  /* sum of the slot sizes s_i                             */
+    int64_t overflow_rows; /* rows with more nonzeros than their slot               */
+    int64_t overflow_nnz;  /* their nonzeros (recomputed by ssp_spgemm_copy)        */
+    int64_t slot_bytes;    /* bytes of the slot area                                */
+} ssp_spgemm_info;
+
+SSP_API ssp_status ssp_spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val,
+                                      const ssp_csr* B, const double* B_val,
+                                      const int64_t* row_cap, int32_t margin_pct,
+                                      int64_t* C_rpt, ssp_spgemm_info* info, void* stream);
+SSP_API ssp_status ssp_spgemm_copy(ssp_handle h, int32_t* C_col, double* C_val,
+                                   int64_t capacity, void* stream);
+
 /* ------------------------------------------------ diagnostics, strings */
 
 /* Per-phase device timing.  While enabled, every phase a call enqueues is
@@ -344,7 +397,9 @@ SSP_API ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* M, int64_t* n_b
  * (the long-row kernel alone), "sym_merge" (OR of split rows' parts),
  * "finalize" (z* or the exact total, the divisor of f*, and the reference
  * design's constants), "pred_rows" and
- * "ref_rows" (the per-row outputs).  ssp_timing_read waits for the recorded
+ * "ref_rows" (the per-row outputs); for the numeric product "num_scan" (slot
+ * and row offsets), "num_hash" and "num_dense" (the numeric pass by bin),
+ * "num_copy" and "num_fallback" (the copy call).  ssp_timing_read waits for the recorded
  * events, writes up to `max` aggregated entries (one per phase seen) and
  * clears them; it returns the number written, -1 on a bad argument.  Timing
  * serialises nothing but adds two event records per phase. */

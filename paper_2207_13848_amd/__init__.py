@@ -25,7 +25,7 @@ from ._native import (FLAG_EMPTY_SAMPLE, FLAG_SATURATED, SAMPLER_BERNOULLI, SAMP
 
 __all__ = ["DeviceCSR", "Handle", "predict_structure", "reference_estimate", "exact_structure",
            "validate_csr", "read_stats", "default_handle", "SspError", "FLAG_EMPTY_SAMPLE",
-           "FLAG_SATURATED", "SAMPLER_BERNOULLI", "SAMPLER_PAPER", "version"]
+           "FLAG_SATURATED", "SAMPLER_BERNOULLI", "SAMPLER_PAPER", "version", "spgemm"]
 
 
 def version() -> str:
@@ -194,6 +194,39 @@ def exact_structure(A: DeviceCSR, B: DeviceCSR, *, handle=None, stream=None, out
                                         _stream_ptr(stream))
     h.check(status, "ssp_exact_structure")
     return ex, st
+
+
+def spgemm(A: DeviceCSR, A_val, B: DeviceCSR, B_val, row_cap, *, margin_pct: int = 0,
+           handle=None, stream=None, capacity=None):
+    """Numeric C = A.B sized by per-row capacities (normally the prediction).
+
+    ``ssp_spgemm_compute`` then ``ssp_spgemm_copy``: returns ``(C_rpt int64[M+1],
+    C_col int32[nnz], C_val float64[nnz], info dict)``.  ``capacity`` (entries
+    of C to allocate) defaults to the exact NNZ(C) the compute call reports."""
+    h = handle or default_handle(A.device)
+    M = A.nrows
+    dev = A.device
+    for name, v, m in (("A_val", A_val, A), ("B_val", B_val, B)):
+        if v.dtype != torch.float64 or v.numel() != m.nnz or v.device != dev:
+            raise ValueError(f"{name} must be float64[{m.nnz}] on {dev}")
+    if row_cap.dtype != torch.int64 or row_cap.numel() != M or row_cap.device != dev:
+        raise ValueError(f"row_cap must be int64[{M}] on {dev}")
+    C_rpt = torch.empty(M + 1, dtype=torch.int64, device=dev)
+    info = _native.SspSpgemmInfo()
+    a, b = A._c(), B._c()
+    status = h._lib.ssp_spgemm_compute(h.ptr, ctypes.byref(a), A_val.data_ptr() if A.nnz else 0,
+                                       ctypes.byref(b), B_val.data_ptr() if B.nnz else 0,
+                                       row_cap.data_ptr() if M else 0, int(margin_pct),
+                                       C_rpt.data_ptr(), ctypes.byref(info), _stream_ptr(stream))
+    h.check(status, "ssp_spgemm_compute")
+    nnz = int(info.nnz)
+    cap = nnz if capacity is None else int(capacity)
+    C_col = torch.empty(max(cap, 1), dtype=torch.int32, device=dev)
+    C_val = torch.empty(max(cap, 1), dtype=torch.float64, device=dev)
+    status = h._lib.ssp_spgemm_copy(h.ptr, C_col.data_ptr(), C_val.data_ptr(), cap,
+                                    _stream_ptr(stream))
+    h.check(status, "ssp_spgemm_copy")
+    return C_rpt, C_col[:nnz], C_val[:nnz], info.as_dict()
 
 
 class Case:

@@ -30,6 +30,7 @@ EXPORTED = (
     "ssp_server_create", "ssp_server_register_matrix", "ssp_server_submit", "ssp_server_poll",
     "ssp_server_wait", "ssp_server_info", "ssp_server_reset_stats", "ssp_server_destroy",
     "ssp_default_tuning", "ssp_get_tuning", "ssp_set_tuning", "ssp_autotune",
+    "ssp_spgemm_compute", "ssp_spgemm_copy",
 )
 
 
@@ -43,6 +44,15 @@ class SspCase(ctypes.Structure):
                 ("reserved", ctypes.c_int32), ("sample_rate", ctypes.c_double),
                 ("seed", ctypes.c_uint64), ("nnz_pred", ctypes.c_void_p),
                 ("row_flop", ctypes.c_void_p), ("stats", ctypes.c_void_p)]
+
+
+class SspSpgemmInfo(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in
+                ("nnz", "total_flop", "slot_entries", "overflow_rows", "overflow_nnz",
+                 "slot_bytes")]
+
+    def as_dict(self) -> dict:
+        return {n: int(getattr(self, n)) for n, _ in self._fields_}
 
 
 class SspTuning(ctypes.Structure):
@@ -154,5 +164,10 @@ def load():
                                  ctypes.POINTER(dbl), vp]
     lib.ssp_version.argtypes = []
     lib.ssp_version.restype = ctypes.c_char_p
+    lib.ssp_spgemm_compute.argtypes = [vp, csr_p, vp, csr_p, vp, vp, ctypes.c_int32, vp,
+                                       ctypes.POINTER(SspSpgemmInfo), vp]
+    lib.ssp_spgemm_compute.restype = cint
+    lib.ssp_spgemm_copy.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
+    lib.ssp_spgemm_copy.restype = cint
     _lib = lib
     return lib

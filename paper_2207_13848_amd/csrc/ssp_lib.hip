@@ -7,13 +7,14 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <memory>
 #include <mutex>
 #include <new>
 #include <string>
 #include <unordered_map>
 #include <vector>
 
-#include "ssp_kernels.hpp"
+#include "ssp_numeric.hpp"
 
 using namespace ssp;
 
@@ -29,11 +30,17 @@ enum Phase {
     PH_FLOP_FIXUP,
     PH_REF_ROWS,
     PH_PRED_ROWS,
+    PH_NUM_SCAN,
+    PH_NUM_HASH,
+    PH_NUM_DENSE,
+    PH_NUM_COPY,
+    PH_NUM_FALLBACK,
     PH_COUNT
 };
-const char* const kPhaseNames[PH_COUNT] = {"sample_bin", "sym_bins",   "sym_long", "sym_merge",
-                                           "finalize",   "tiles",      "flop",     "flop_fixup",
-                                           "ref_rows",   "pred_rows"};
+const char* const kPhaseNames[PH_COUNT] = {"sample_bin", "sym_bins",   "sym_long",  "sym_merge",
+                                           "finalize",   "tiles",      "flop",      "flop_fixup",
+                                           "ref_rows",   "pred_rows",  "num_scan",  "num_hash",
+                                           "num_dense",  "num_copy",   "num_fallback"};
 struct EventPair {
     int phase;
     hipEvent_t a, b;
@@ -90,6 +97,18 @@ struct ssp_context {
     void* pin = nullptr;
     size_t pin_bytes = 0;
     hipEvent_t pin_ev = nullptr;
+    // numeric product: buffers of its own (other calls leave them alone
+    // between ssp_spgemm_compute and ssp_spgemm_copy) and the state the copy
+    // call reads; the dense accumulators are all zero between calls
+    void* num_ws = nullptr;
+    size_t num_ws_bytes = 0;
+    void* num_slots = nullptr;
+    size_t num_slots_bytes = 0;
+    void* num_pool = nullptr;
+    size_t num_pool_bytes = 0;
+    bool num_pool_clean = false;
+    hipEvent_t num_ev = nullptr;  // end of the last copy pass
+    std::shared_ptr<void> num_state;
 };
 
 // A captured batch: its own workspace and case table, and the launch graph.
@@ -626,12 +645,12 @@ void prepare_kernels()
 // The whole launch sequence of a call.  `table_on_device`: the case table is
 // already in the workspace (batches, graphs); otherwise (at most kArgCases
 // cases) k_setup writes it from its kernel arguments.
-ssp_status launch_plan(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
-                       bool table_on_device, bool timed)
+// Clears, the case table (from the kernel arguments for small calls) and the
+// merge-path tile starts, in one launch.
+void launch_setup(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
+                  bool table_on_device, bool timed)
 {
     {
-        // clears, the case table (from the kernel arguments for small calls)
-        // and the merge-path tile starts, in one launch
         PhaseTimer pt(h, PH_TILES, s, timed);
         CaseArgs args;
         std::memset(&args, 0, sizeof(args));
@@ -646,6 +665,12 @@ ssp_status launch_plan(ssp_handle h, const Plan& P, const Bound& b, hipStream_t 
                                ninit, b.tile_row, b.tile_case, args);
         }
     }
+}
+
+ssp_status launch_plan(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
+                       bool table_on_device, bool timed)
+{
+    launch_setup(h, P, b, s, table_on_device, timed);
     SSP_LAUNCHED(h);
     if (P.kind == PLAN_EXACT) {
         launch_flop<FLOP_EXACT_BIN>(h, P, b, s, timed);
@@ -789,9 +814,13 @@ ssp_status ssp_destroy(ssp_handle h)
     if (!h) return SSP_ERR_INVALID_ARG;
     ssp_status st = SSP_OK;
     DeviceGuard g(h->device);
-    if (h->ws) {
-        if (hipDeviceSynchronize() != hipSuccess || hipFree(h->ws) != hipSuccess) st = SSP_ERR_HIP;
+    if (h->ws || h->num_ws || h->num_slots || h->num_pool) {
+        if (hipDeviceSynchronize() != hipSuccess) st = SSP_ERR_HIP;
+        for (void* p : {h->ws, h->num_ws, h->num_slots, h->num_pool})
+            if (p && hipFree(p) != hipSuccess) st = SSP_ERR_HIP;
     }
+    h->num_state.reset();
+    if (h->num_ev) (void)hipEventDestroy(h->num_ev);
     for (auto& p : h->pending) {
         h->event_pool.push_back(p.a);
         h->event_pool.push_back(p.b);
@@ -1127,3 +1156,4 @@ ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* m, int64_t* n_bad, void
 } // extern "C"
 
 #include "ssp_server.hpp"
+#include "ssp_spgemm.hpp"

@@ -1,0 +1,175 @@
+"""Numeric product sized by the prediction: GPU path == CPU oracle, through the C ABI.
+
+Integer parts (C's row offsets and columns, the slot layout's counts) must be
+equal element by element.  Values are sums of float64 products whose order
+differs (the GPU adds with atomics), so they are compared against the error
+bound of any summation order: for an entry of n terms p_k, each side is
+within n u sum|p_k| of the exact sum (u = 2^-53; products rounded once,
+sums n - 1 times), so the two differ by at most 2 (n + 1) u sum|p_k|.  With
+small-integer values every partial sum is exact and the values must be equal.
+"""
+import numpy as np
+import pytest
+
+import oracle
+import workloads
+from tests.csr_util import from_rows, random_csr
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+U = 2.0 ** -53
+
+
+@pytest.fixture(scope="module")
+def ssp():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2207_13848_amd as m
+    return m
+
+
+def _say(msg):
+    print(msg, flush=True)
+
+
+def _run(ssp, A, B, av, bv, cap, margin, Ad=None, Bd=None, capacity=None):
+    Ad = Ad if Ad is not None else ssp.DeviceCSR.from_csr(A, "cuda:0")
+    Bd = Bd if Bd is not None else (Ad if B is A else ssp.DeviceCSR.from_csr(B, "cuda:0"))
+    tav = torch.from_numpy(np.ascontiguousarray(av)).to("cuda:0")
+    tbv = tav if bv is av else torch.from_numpy(np.ascontiguousarray(bv)).to("cuda:0")
+    tcap = cap if isinstance(cap, torch.Tensor) else torch.from_numpy(
+        np.ascontiguousarray(cap, dtype=np.int64)).to("cuda:0")
+    rpt, col, val, info = ssp.spgemm(Ad, tav, Bd, tbv, tcap, margin_pct=margin, capacity=capacity)
+    torch.cuda.synchronize()
+    return rpt.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy(), info, tcap.cpu().numpy()
+
+
+def check(ssp, A, B, av, bv, cap, margin, exact_values, what, **kw):
+    _say(f"spgemm {what}: M={A.nrows} K={A.ncols} N={B.ncols} margin={margin}")
+    rpt, col, val, info, cap_np = _run(ssp, A, B, av, bv, cap, margin, **kw)
+    orpt, ocol, oval, oabs, oterms = oracle.spgemm(A, av, B, bv)
+    assert np.array_equal(rpt, orpt), f"{what}: C_rpt"
+    assert np.array_equal(col, ocol), f"{what}: C_col"
+    if exact_values:
+        assert np.array_equal(val, oval), f"{what}: C_val (integer values)"
+    else:
+        bound = 2.0 * (oterms.astype(np.float64) + 1.0) * U * oabs * (1.0 + 1e-9)
+        bad = np.nonzero(np.abs(val - oval) > bound)[0]
+        assert bad.size == 0, f"{what}: C_val beyond the bound at {bad[:5]}"
+    lay = oracle.spgemm_layout(cap_np, margin, np.diff(orpt), B.ncols)
+    _, F = oracle.row_flop(A, B)
+    for k, v in lay.items():
+        assert info[k] == v, f"{what}: info.{k} gpu={info[k]} oracle={v}"
+    assert info["total_flop"] == F, f"{what}: F"
+    return info
+
+
+def _values(M, seed, kind):
+    return workloads.values(M.nnz, seed, kind)
+
+
+CASES = [
+    ("uniform3000_d8", lambda: workloads.uniform(3000, 3000, 8, 1)),
+    ("zipf4096_d6", lambda: workloads.zipf(4096, 6, 2)),
+    ("banded2500_d12", lambda: workloads.banded(2500, 12, 3)),
+    ("rmat12_d8", lambda: workloads.rmat(1 << 12, 8, 4)),
+    ("blockdiag3000_d16", lambda: workloads.blockdiag(3000, 16, 5)),
+]
+
+
+@pytest.mark.parametrize("name,make", CASES, ids=[c[0] for c in CASES])
+@pytest.mark.parametrize("kind", ["int", "uniform"])
+def test_spgemm_predicted_capacity(ssp, name, make, kind):
+    A = make()
+    av = _values(A, 7, kind)
+    Ad = ssp.DeviceCSR.from_csr(A, "cuda:0")
+    pred, _ = ssp.predict_structure(Ad, Ad, 0.02, 11)[:2]
+    for margin in (0, 10):
+        check(ssp, A, A, av, av, pred, margin, kind == "int", f"{name}/{kind}/pred", Ad=Ad, Bd=Ad)
+
+
+def test_spgemm_capacity_kinds(ssp):
+    A = workloads.zipf(3000, 8, 9)
+    av = _values(A, 3, "int")
+    counts, _ = oracle.exact(A, A)
+    rf, _ = oracle.row_flop(A, A)
+    Ad = ssp.DeviceCSR.from_csr(A, "cuda:0")
+    # the precise structure: nothing overflows
+    info = check(ssp, A, A, av, av, counts, 0, True, "exact caps", Ad=Ad, Bd=Ad)
+    assert info["overflow_rows"] == 0
+    # the upper bound
+    info = check(ssp, A, A, av, av, np.asarray(rf, dtype=np.int64), 0, True, "flop caps", Ad=Ad, Bd=Ad)
+    assert info["overflow_rows"] == 0
+    # no capacity: every row goes through the fallback pass
+    info = check(ssp, A, A, av, av, np.zeros(A.nrows, dtype=np.int64), 0, True, "zero caps",
+                 Ad=Ad, Bd=Ad)
+    assert info["overflow_nnz"] == info["nnz"]
+    # half the exact counts, negative and huge capacities, a margin
+    rng = np.random.default_rng(1)
+    caps = counts // 2
+    caps[rng.random(A.nrows) < 0.1] = -5
+    caps[rng.random(A.nrows) < 0.1] = 1 << 40
+    check(ssp, A, A, av, av, caps, 37, True, "mixed caps", Ad=Ad, Bd=Ad)
+
+
+def test_spgemm_long_rows_dense_path(ssp):
+    # rows of about 4096 products: every row in the dense accumulators;
+    # N above 2^16 and a rectangular B
+    A = workloads.uniform(1500, 2000, 64, 2)
+    B = workloads.uniform(2000, 70000, 64, 3)
+    av, bv = _values(A, 1, "uniform"), _values(B, 2, "uniform")
+    counts, _ = oracle.exact(A, B)
+    check(ssp, A, B, av, bv, counts, 0, False, "dense exact caps")
+    check(ssp, A, B, av, bv, counts - 3, 0, False, "dense overflow")
+    avi, bvi = _values(A, 1, "int"), _values(B, 2, "int")
+    check(ssp, A, B, avi, bvi, counts // 3, 5, True, "dense int")
+
+
+def test_spgemm_mixed_bins_rmat(ssp):
+    # power-law rows: every bin, the dense path included, with under-predicted rows
+    A = workloads.rmat(1 << 13, 12, 6)
+    av = _values(A, 4, "uniform")
+    Ad = ssp.DeviceCSR.from_csr(A, "cuda:0")
+    rf, _ = oracle.row_flop(A, A)
+    assert max(rf) > 2048 and min(r for r in rf if r) <= 128
+    pred, _ = ssp.predict_structure(Ad, Ad, 0.01, 3)[:2]
+    check(ssp, A, A, av, av, pred, 0, False, "rmat13 pred", Ad=Ad, Bd=Ad)
+
+
+def test_spgemm_duplicates_unsorted(ssp):
+    rng = np.random.default_rng(3)
+    A = random_csr(rng, 700, 300, 0.04, dup_prob=0.3)
+    B = random_csr(rng, 300, 900, 0.05, dup_prob=0.3)
+    av, bv = _values(A, 5, "int"), _values(B, 6, "int")
+    counts, _ = oracle.exact(A, B)
+    check(ssp, A, B, av, bv, counts - 1, 0, True, "duplicates")
+
+
+def test_spgemm_edges(ssp):
+    # empty rows, rows naming only empty B rows, an empty A, no entries at all
+    B = from_rows([[0, 3], [], [1], [2, 3, 4]], 5)
+    bv = np.arange(1.0, B.nnz + 1.0)
+    A = from_rows([[], [1], [0, 1, 2], [3], [], [1, 1]], 4)
+    av = np.array([1.0, 2.0, -1.0, 3.0, 4.0, 5.0, 6.0])[: A.nnz]
+    check(ssp, A, B, av, bv, np.array([0, 0, 1, 9, 0, 0]), 0, True, "small")
+    A0 = from_rows([], 4)
+    check(ssp, A0, B, np.zeros(0), bv, np.zeros(0, dtype=np.int64), 0, True, "no rows")
+    Ae = from_rows([[], [], []], 4)
+    check(ssp, Ae, B, np.zeros(0), bv, np.zeros(3, dtype=np.int64), 0, True, "no entries")
+    Bz = from_rows([[], [], [], []], 0)
+    check(ssp, A, Bz, av, np.zeros(0), np.ones(A.nrows, dtype=np.int64), 0, True, "N = 0")
+
+
+def test_spgemm_repeated_calls_and_capacity_error(ssp):
+    # a second call reuses the handle's buffers (accumulators zero again)
+    A = workloads.uniform(800, 800, 48, 8)
+    av = _values(A, 2, "int")
+    counts, _ = oracle.exact(A, A)
+    Ad = ssp.DeviceCSR.from_csr(A, "cuda:0")
+    for r in range(3):
+        check(ssp, A, A, av, av, counts // (r + 1), 0, True, f"repeat {r}", Ad=Ad, Bd=Ad)
+    with pytest.raises(ssp.SspError):
+        _run(ssp, A, A, av, av, counts, 0, Ad=Ad, Bd=Ad, capacity=int(counts.sum()) - 1)
+    # and works again afterwards
+    check(ssp, A, A, av, av, counts, 0, True, "after error", Ad=Ad, Bd=Ad)
