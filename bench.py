@@ -31,7 +31,7 @@ sys.path.insert(0, ROOT)
 
 HBM_PEAK_GBS = 8000.0  # MI355X HBM3E, 8 TB/s
 WORKLOADS = ("rmat20", "uniform4096", "stencil128", "stencil128_x_uniform", "sweep", "serve",
-             "accuracy")
+             "accuracy", "spgemm", "spgemm_rmat18")
 
 
 def parse():
@@ -45,6 +45,8 @@ def parse():
                     help="skip the reference/exact timings and the accuracy figures")
     ap.add_argument("--cpu-budget-s", type=float, default=20.0,
                     help="seconds of oracle work for the CPU baseline")
+    ap.add_argument("--margin", type=int, default=10,
+                    help="spgemm workloads: percent added to each predicted row capacity")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES three times (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
@@ -366,6 +368,175 @@ def main_accuracy(args):
           flush=True)
 
 
+def main_spgemm(args):
+    """The consumer of the prediction: numeric C = A.A (float64 values in
+    U[-1, 1)) whose memory is sized by the predicted structure.  A step is the
+    whole pipeline: ssp_predict_structure, ssp_spgemm_compute with the
+    prediction plus a margin as row capacities, ssp_spgemm_copy.  Beside it,
+    the same numeric product sized by the precise method (ssp_exact_structure
+    first: the symbolic phase the prediction avoids) and by the upper bound
+    (row FLOP: no structure step, the largest slot area).  Sampled rows of C
+    are checked against the CPU oracle."""
+    import numpy as np
+    import torch
+    import paper_2207_13848_amd as ssp
+    import workloads
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    dev = "cuda:0"
+    tg = time.time()
+    if args.workload == "spgemm":
+        A = workloads.stencil27(128)
+        name, rate = "spgemm_stencil27_128", 0.005
+    else:
+        A = workloads.rmat(1 << 18, 16, 1)
+        name, rate = "spgemm_rmat18_d16", 0.005
+    seed = 1001
+    av = workloads.values(A.nnz, 77)
+    Ad = ssp.DeviceCSR.from_csr(A, dev)
+    tav = torch.from_numpy(av).to(dev)
+    t_gen = time.time() - tg
+    M = A.nrows
+    h = ssp.default_handle(dev)
+    pred = torch.empty(M, dtype=torch.int64, device=dev)
+    st = torch.zeros(8, dtype=torch.int64, device=dev)
+    margin = int(args.margin)
+
+    def step():
+        ssp.predict_structure(Ad, Ad, rate, seed, handle=h, out=pred, stats=st)
+        return ssp.spgemm(Ad, tav, Ad, tav, pred, margin_pct=margin, handle=h)
+
+    steps = max(1, min(args.steps, 10))
+    for _ in range(max(1, min(args.warmup, 2))):
+        out = step()
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    ms = (time.perf_counter() - t0) * 1e3 / steps
+    C_rpt, C_col, C_val, info = out
+    F = info["total_flop"]
+    # phase-timed region
+    h._lib.ssp_timing_enable(h.ptr, 1)
+    phase_times(ssp, h)
+    for _ in range(steps):
+        out = step()
+    torch.cuda.synchronize()
+    phases = phase_times(ssp, h)
+    h._lib.ssp_timing_enable(h.ptr, 0)
+    C_rpt, C_col, C_val, info = out
+
+    # algorithmic bytes of the numeric pass: A.rpt pair per row, A.col + A.val
+    # + B.rpt pair per A entry, B.col + B.val per product, the row written
+    # (column + value) and its count
+    rpt64 = A.rpt.astype(np.int64)
+    alen = np.diff(rpt64)
+    _, rf_t, _ = ssp.predict_structure(Ad, Ad, rate, seed, handle=h, return_row_flop=True)
+    rf = rf_t.cpu().numpy()
+    cnt = np.diff(C_rpt.cpu().numpy())
+    dense = rf > 2048
+
+    def pass_bytes(mask):
+        return int(np.sum(8 + 20 * alen[mask] + 12 * rf[mask] + 12 * cnt[mask] + 8))
+
+    phase_bytes = {"num_hash": pass_bytes(~dense & (rf > 0)), "num_dense": pass_bytes(dense),
+                   "num_copy": int(24 * cnt.sum() + 24 * M)}
+    per_phase = {}
+    for pname, (n, tms) in phases.items():
+        r = {"launches": n, "avg_us": round(1e3 * tms / max(n, 1), 2)}
+        if phase_bytes.get(pname):
+            r["algorithmic_bytes"] = phase_bytes[pname] // max(1, n // steps)
+            r["gbps"] = round(phase_bytes[pname] * (n // steps) / max(n, 1) /
+                              (1e-6 * r["avg_us"]) / 1e9, 1) if r["avg_us"] else None
+        per_phase[pname] = r
+    cand = [p for p in ("num_hash", "num_dense", "num_copy") if p in per_phase]
+    dom = max(cand, key=lambda p: per_phase[p]["avg_us"] * per_phase[p]["launches"])
+    dom_us = per_phase[dom]["avg_us"]
+    dom_bytes = per_phase[dom].get("algorithmic_bytes", 0)
+    achieved = dom_bytes / (dom_us * 1e-6) / 1e9 if dom_us else 0.0
+    roofline = {"bound": "hbm", "kernel": {"num_hash": "k_num_hash", "num_dense": "k_num_dense",
+                                           "num_copy": "k_num_copy"}[dom],
+                "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "algorithmic_bytes": dom_bytes, "avg_launch_us": dom_us}
+
+    # the precise method and the upper bound as capacities
+    variants = {"predicted": {"ms": round(ms, 3), "margin_pct": margin,
+                              **{k: info[k] for k in ("slot_entries", "slot_bytes",
+                                                       "overflow_rows", "overflow_nnz")}}}
+    ex = torch.empty(M, dtype=torch.int64, device=dev)
+    for vname in ("precise", "upper_bound"):
+        for i in range(steps + 1):
+            if i == 1:
+                torch.cuda.synchronize()
+                ta = time.perf_counter()
+            if vname == "precise":
+                ssp.exact_structure(Ad, Ad, handle=h, out=ex)
+                r = ssp.spgemm(Ad, tav, Ad, tav, ex, handle=h)
+            else:
+                r = ssp.spgemm(Ad, tav, Ad, tav, rf_t, handle=h)
+        torch.cuda.synchronize()
+        vi = r[3]
+        variants[vname] = {"ms": round((time.perf_counter() - ta) * 1e3 / steps, 3),
+                           **{k: vi[k] for k in ("slot_entries", "slot_bytes", "overflow_rows",
+                                                 "overflow_nnz")}}
+        assert vi["nnz"] == info["nnz"]
+        del r
+    torch.cuda.synchronize()
+
+    # parity spot check: sampled rows against the oracle
+    import oracle
+    rng = np.random.default_rng(5)
+    rows = np.sort(rng.choice(M, size=min(M, 2000), replace=False))
+    idx = np.concatenate([np.arange(rpt64[i], rpt64[i + 1]) for i in rows])
+    srpt = np.zeros(len(rows) + 1, dtype=np.int64)
+    np.cumsum(alen[rows], out=srpt[1:])
+    As = workloads.CSR(len(rows), A.ncols, srpt.astype(np.int32), A.col[idx].copy(), "rows")
+    sub_vals = av[idx]
+    orpt, ocol, oval, oabs, oterms = oracle.spgemm(As, sub_vals, A, av)
+    crpt = C_rpt.cpu().numpy()
+    gidx = np.concatenate([np.arange(crpt[i], crpt[i + 1]) for i in rows])
+    gsel = torch.from_numpy(gidx).to(dev)
+    gc = C_col.index_select(0, gsel).cpu().numpy()
+    gv = C_val.index_select(0, gsel).cpu().numpy()
+    bound = 2.0 * (oterms + 1.0) * 2.0 ** -53 * oabs * (1 + 1e-9)
+    ok = bool(np.array_equal(np.diff(crpt)[rows], np.diff(orpt)) and np.array_equal(gc, ocol)
+              and np.all(np.abs(gv - oval) <= bound))
+
+    result = {
+        "metric": "intermediate products/s of the numeric SpGEMM sized by the prediction",
+        "value": round(F / (ms * 1e-3), 1), "unit": "products/s", "n_gpus": 1, "steps": steps,
+        "warmup": max(1, min(args.warmup, 2)), "ms_per_step": round(ms, 3),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": name, "rows": M, "nnz_A": A.nnz, "sample_rate": rate, "seed": seed,
+                   "margin_pct": margin, "values": "U[-1,1) float64"},
+        "gflops": round(2.0 * F / (ms * 1e-3) / 1e9, 1),
+        "nnz_C": info["nnz"], "F": F, "roofline": roofline, "phases": per_phase,
+        "variants": variants,
+        "parity_spot_check": {"rows": int(len(rows)), "ok": bool(ok)},
+        "kernel_source_hash": kernel_source_hash(), "generate_s": round(t_gen, 2),
+    }
+    if not args.no_cpu_baseline:
+        # the oracle on a bounded sample of rows, scaled to products/s
+        sample_F = int(oterms.sum())
+        tc0 = time.perf_counter()
+        runs = 0
+        while True:
+            oracle.spgemm(As, sub_vals, A, av)
+            runs += 1
+            if time.perf_counter() - tc0 >= min(args.cpu_budget_s, 10.0) or runs >= 20:
+                break
+        t_cpu = (time.perf_counter() - tc0) / runs
+        result["cpu_baseline"] = {"value": round(sample_F / t_cpu, 1), "unit": "products/s",
+                                  "cores": 1, "kind": "oracle",
+                                  "sample": f"{len(rows)} random rows of C ({sample_F} products), "
+                                            f"serial C oracle, {runs} runs"}
+    print(json.dumps(result), flush=True)
+
+
 def get_workload(name: str):
     import workloads
     return getattr(workloads, name)()
@@ -397,6 +568,9 @@ def main():
         return
     if args.workload == "accuracy":
         main_accuracy(args)
+        return
+    if args.workload in ("spgemm", "spgemm_rmat18"):
+        main_spgemm(args)
         return
 
     import numpy as np

@@ -114,7 +114,9 @@ struct Ctl {
     uint32_t pw_ctr;      // part windows handed out (exact path)
     uint32_t big_next;    // work queue of the long-row kernel
     uint32_t split_level; // the call's split level (sampling passes)
-    uint32_t pad[21];
+    uint32_t num_abort;   // numeric product: rows whose first-pass table filled up
+    uint32_t num_next[2]; // numeric product: work queues of the dense passes
+    uint32_t pad[18];
 };
 
 struct BinItem {  // bins 1..3

@@ -181,65 +181,274 @@ __global__ __launch_bounds__(kNumScanThreads) void k_num_scan_rows(NumArgs na)
 
 // ----------------------------------------------------------- LDS hash bins
 
-// Adds v to column c's slot of an LDS table of 2^lg slots (open addressing,
-// linear probing; columns are < 2^31, so the all-ones key marks a free slot).
-__device__ __forceinline__ void num_hash_add(uint32_t* keys, double* vals, uint32_t c, double v,
+// Rows of at most kNumBin3Max products accumulate in an LDS hash table of
+// (column, value) slots: 2^lg slots, at least twice the bound b on the
+// distinct columns the pass must hold.  The first pass only has to keep the
+// rows that fit their slot, so b = min(products, N, slot size); a row whose
+// columns outnumber the table stops (every probe sequence ends after 2^lg
+// steps) and is counted by the symbolic kernel instead.  The fallback pass
+// knows each row's exact count and sizes b by it.
+constexpr int kNumWaveSlots = 512;  // table of a row handled by one wave
+constexpr int kNumWaveWaves = 4;    // such rows per workgroup
+
+__device__ __forceinline__ uint32_t num_table_size(uint64_t b)
+{
+    uint32_t t = 32;
+    while ((uint64_t)t < 2 * b) t <<= 1;
+    return t;
+}
+
+// Bound on the distinct columns of a bin item's row that the pass must hold.
+template <int PASS>
+__device__ __forceinline__ uint64_t num_bound(const NumArgs& na, int64_t row, uint32_t rf)
+{
+    if (PASS == 2) return (uint64_t)na.cnt[row];
+    const int64_t s = na.slot_off[row + 1] - na.slot_off[row];
+    int64_t b = (int64_t)rf < na.N ? (int64_t)rf : na.N;
+    return (uint64_t)(b < s ? b : s);
+}
+
+// Adds v to column c's slot (open addressing, linear probing; columns are
+// < 2^31, so the all-ones key marks a free slot).  False when all 2^lg slots
+// hold other columns.
+__device__ __forceinline__ bool num_hash_add(uint32_t* keys, double* vals, uint32_t c, double v,
                                              int lg)
 {
     const uint32_t mask = (1u << lg) - 1u;
     uint32_t h = (c * 0x9E3779B1u) >> (32 - lg);
-    for (;;) {
+    for (uint32_t n = 0; n <= mask; ++n) {
         const uint32_t cur =
             __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (cur == c) break;
-        if (cur == kEmpty) {
+        bool hit = cur == c;
+        if (!hit && cur == kEmpty) {
             const uint32_t prev = atomicCAS(&keys[h], kEmpty, c);
-            if (prev == kEmpty || prev == c) break;
+            hit = prev == kEmpty || prev == c;
+        }
+        if (hit) {
+            __hip_atomic_fetch_add(&vals[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            return true;
         }
         h = (h + 1u) & mask;
     }
-    __hip_atomic_fetch_add(&vals[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    return false;
 }
 
-// Bins 1..3: one workgroup of TEAM threads per row.  The row's products are
-// enumerated TEAM entries of A at a time (a scan of the B row lengths gives
-// each product's A entry by binary search in LDS, so every thread handles an
-// equal share whatever the B row lengths) and added into the hash table.
-// The occupied slots are then compacted (a scan over the table, each thread
-// holding SLOTS/TEAM slots in registers) and each entry's place in the
-// sorted row is its rank among the keys.
+// Orders the LDS accesses of one wave (the LDS serves a wave's accesses in
+// order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Item k of the hash bins 1..3 taken as one list.
+__device__ __forceinline__ BinItem num_hash_item(const BinLists& L, const uint32_t* cnt, uint32_t k)
+{
+    const uint32_t n1 = cnt[1], n2 = cnt[2];
+    return k < n1 ? L.b1[k] : k < n1 + n2 ? L.b2[k - n1] : L.b3[k - n1 - n2];
+}
+
+// Records a row whose first-pass table filled up (the symbolic kernel counts it).
+__device__ __forceinline__ void num_abort_row(int64_t row, uint32_t rf, Ctl* ctl, BinItem* list)
+{
+    const uint32_t i = atomicAdd(&ctl->num_abort, 1u);
+    BinItem it;
+    it.row = (int32_t)row;
+    it.rf = rf;
+    it.cs = 0;
+    it.pad = 0;
+    list[i] = it;
+}
+
+// Writes the c occupied slots of a table, columns increasing, at dst: each
+// entry's place is its rank among the row's (distinct) keys.  The caller has
+// compacted the entries to keys/vals[0, c) and set keys[c, c4) to kEmpty
+// (c4 = c rounded up to 4).  EPT entries per lane at most (c <= EPT * NT).
+template <int NT, int EPT>
+__device__ __forceinline__ void num_write_ranked(const uint32_t* keys, const double* vals,
+                                                 uint32_t c, int tid, SSP_GLOBAL int32_t* ocol,
+                                                 SSP_GLOBAL double* oval, int64_t dst)
+{
+    const uint32_t c4 = (c + 3u) & ~3u;
+    uint32_t key[EPT], rank[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const uint32_t e = (uint32_t)tid + (uint32_t)u * NT;
+        key[u] = e < c ? keys[e] : kEmpty;
+        rank[u] = 0;
+    }
+    for (uint32_t q = 0; q < c4; q += 4) {
+        const uint4 k4 = *reinterpret_cast<const uint4*>(&keys[q]);
+#pragma unroll
+        for (int u = 0; u < EPT; ++u)
+            rank[u] += (k4.x < key[u]) + (k4.y < key[u]) + (k4.z < key[u]) + (k4.w < key[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+        const uint32_t e = (uint32_t)tid + (uint32_t)u * NT;
+        if (e < c) {
+            ocol[dst + rank[u]] = (int32_t)key[u];
+            oval[dst + rank[u]] = vals[e];
+        }
+    }
+}
+
+// Rows whose table has at most kNumWaveSlots slots: one wave per row,
+// kNumWaveWaves rows per workgroup, each wave with its own table.  The row's
+// products are enumerated 64 entries of A at a time (a wave scan of the B row
+// lengths gives each product's entry by binary search in LDS).
 // PASS 1: count the row, write it to its slot when it fits.
 // PASS 2: rows that did not fit, written to C at their final offset.
+template <int PASS>
+__global__ __launch_bounds__(kNumWaveWaves* kWave) void k_num_wave(const CaseDesc* __restrict__ cs,
+                                                                   BinLists L, Ctl* ctl,
+                                                                   BinItem* abort_list, NumArgs na)
+{
+    constexpr int SPT = kNumWaveSlots / kWave;  // table slots per lane
+    constexpr int EPT = SPT / 2;                 // written entries per lane, at most
+    __shared__ __align__(16) uint32_t s_keys[kNumWaveWaves][kNumWaveSlots];
+    __shared__ double s_vals[kNumWaveWaves][kNumWaveSlots];
+    __shared__ int32_t s_b0[kNumWaveWaves][kWave];
+    __shared__ uint32_t s_off[kNumWaveWaves][kWave];
+    __shared__ double s_a[kNumWaveWaves][kWave];
+    const int lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    uint32_t* keys = s_keys[w];
+    double* vals = s_vals[w];
+    const uint32_t* cnt = ctl->bin_cnt;
+    const uint32_t total = cnt[1] + cnt[2] + cnt[3];
+    const Csr A = cs[0].A, B = cs[0].B;
+    for (uint32_t k = blockIdx.x * kNumWaveWaves + w; k < total;
+         k += gridDim.x * kNumWaveWaves) {
+        const BinItem item = num_hash_item(L, cnt, k);
+        const int64_t row = item.row;
+        if (PASS == 2 && num_fits(na, row, na.cnt[row])) continue;
+        const uint32_t T = num_table_size(num_bound<PASS>(na, row, item.rf));
+        if (T > (uint32_t)kNumWaveSlots) continue;  // (a workgroup kernel's row)
+        const int lg = __builtin_ctz(T);
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const uint32_t s = (uint32_t)lane + (uint32_t)u * kWave;
+            if (s < T) {
+                keys[s] = kEmpty;
+                vals[s] = 0.0;
+            }
+        }
+        wave_sync();
+        bool ok = true;
+        const int32_t a0 = A.rpt[row], a1 = A.rpt[row + 1];
+        for (int32_t a = a0; a < a1; a += kWave) {
+            const int32_t j = a + lane;
+            uint32_t len = 0;
+            int32_t b0 = 0;
+            double av = 0.0;
+            if (j < a1) {
+                const int32_t kk = A.col[j];
+                b0 = B.rpt[kk];
+                len = (uint32_t)(B.rpt[kk + 1] - b0);
+                av = na.Aval[j];
+            }
+            const uint32_t inc = wave_incl_scan(len);
+            const uint32_t tot = lane63(inc);
+            s_b0[w][lane] = b0;
+            s_off[w][lane] = inc - len;
+            s_a[w][lane] = av;
+            wave_sync();
+            const int nent = (a1 - a) < kWave ? (a1 - a) : kWave;
+            for (uint32_t p = lane; p < tot; p += kWave) {
+                int lo = 0, hi = nent;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_off[w][mid] <= p) lo = mid;
+                    else hi = mid;
+                }
+                const int32_t q = s_b0[w][lo] + (int32_t)(p - s_off[w][lo]);
+                ok = num_hash_add(keys, vals, (uint32_t)B.col[q], s_a[w][lo] * na.Bval[q], lg) && ok;
+            }
+            wave_sync();
+        }
+        if (__ballot(!ok)) {  // (the first pass only: the fallback's tables hold every row)
+            if (lane == 0) num_abort_row(row, item.rf, ctl, abort_list);
+            continue;
+        }
+        // compaction of the occupied slots
+        uint32_t kk[SPT];
+        double vv[SPT];
+        uint32_t mine = 0;
+#pragma unroll
+        for (int u = 0; u < SPT; ++u) {
+            const uint32_t s = (uint32_t)lane * SPT + u;
+            kk[u] = s < T ? keys[s] : kEmpty;
+            vv[u] = s < T ? vals[s] : 0.0;
+            mine += kk[u] != kEmpty ? 1u : 0u;
+        }
+        const uint32_t inc = wave_incl_scan(mine);
+        const uint32_t c = lane63(inc);
+        uint32_t pos = inc - mine;
+        wave_sync();
+        int64_t dst;
+        bool write;
+        if (PASS == 1) {
+            if (lane == 0) na.cnt[row] = (int64_t)c;
+            dst = na.slot_off[row];
+            write = (int64_t)c <= na.slot_off[row + 1] - dst;
+        } else {
+            dst = na.C_rpt[row];
+            write = dst + (int64_t)c <= na.capacity;
+        }
+        if (write) {  // (then c <= T / 2)
+#pragma unroll
+            for (int u = 0; u < SPT; ++u)
+                if (kk[u] != kEmpty) {
+                    keys[pos] = kk[u];
+                    vals[pos] = vv[u];
+                    ++pos;
+                }
+            const uint32_t c4 = (c + 3u) & ~3u;
+            if ((uint32_t)lane < c4 - c) keys[c + lane] = kEmpty;
+            wave_sync();
+            num_write_ranked<kWave, EPT>(keys, vals, c, lane, PASS == 1 ? na.slot_col : na.C_col,
+                                         PASS == 1 ? na.slot_val : na.C_val, dst);
+        }
+        wave_sync();  // the table is reset for the next row
+    }
+}
+
+// Rows whose table is larger: one workgroup of TEAM threads per row (bins 2
+// and 3), the same steps with the whole workgroup.
 template <int TEAM, int SLOTS, int PASS>
 __global__ __launch_bounds__(TEAM) void k_num_hash(const CaseDesc* __restrict__ cs,
                                                    const BinItem* __restrict__ items,
-                                                   const uint32_t* count, NumArgs na)
+                                                   const uint32_t* count, Ctl* ctl,
+                                                   BinItem* abort_list, NumArgs na)
 {
     constexpr int SPT = SLOTS / TEAM;
-    static_assert(SPT >= 1 && SLOTS % TEAM == 0, "whole slots per thread");
+    static_assert(SPT >= 2 && SLOTS % TEAM == 0, "whole slots per thread");
     __shared__ __align__(16) uint32_t keys[SLOTS];
     __shared__ double vals[SLOTS];
     __shared__ int32_t s_b0[TEAM];
     __shared__ uint32_t s_off[TEAM];
     __shared__ double s_a[TEAM];
     __shared__ uint32_t s_red[TEAM / kWave + 1];
+    __shared__ uint32_t s_fail;
     const uint32_t n = *count;
     const int t = threadIdx.x;
     const Csr A = cs[0].A, B = cs[0].B;
-    const int64_t N = B.ncols;
     for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
         const BinItem item = items[it];
         const int64_t row = item.row;
         if (PASS == 2 && num_fits(na, row, na.cnt[row])) continue;  // (the same for the whole team)
-        const uint32_t bound = (uint32_t)((int64_t)item.rf < N ? (int64_t)item.rf : N);
-        uint32_t tsize = 32;
-        while (tsize < 2u * bound) tsize <<= 1;
-        const int lg = __builtin_ctz(tsize);
-        for (uint32_t w = t; w < tsize; w += TEAM) {
-            keys[w] = kEmpty;
-            vals[w] = 0.0;
+        const uint32_t T = num_table_size(num_bound<PASS>(na, row, item.rf));
+        if (T <= (uint32_t)kNumWaveSlots) continue;  // (a one-wave row)
+        const int lg = __builtin_ctz(T);
+        for (uint32_t s = t; s < T; s += TEAM) {
+            keys[s] = kEmpty;
+            vals[s] = 0.0;
         }
+        if (t == 0) s_fail = 0;
         __syncthreads();
+        bool ok = true;
         const int32_t a0 = A.rpt[row], a1 = A.rpt[row + 1];
         for (int32_t a = a0; a < a1; a += TEAM) {
             const int32_t j = a + t;
@@ -267,9 +476,16 @@ __global__ __launch_bounds__(TEAM) void k_num_hash(const CaseDesc* __restrict__ 
                     else hi = mid;
                 }
                 const int32_t q = s_b0[lo] + (int32_t)(p - s_off[lo]);
-                num_hash_add(keys, vals, (uint32_t)B.col[q], s_a[lo] * na.Bval[q], lg);
+                ok = num_hash_add(keys, vals, (uint32_t)B.col[q], s_a[lo] * na.Bval[q], lg) && ok;
             }
             __syncthreads();
+        }
+        if (!ok) s_fail = 1;
+        __syncthreads();
+        if (s_fail) {
+            if (t == 0) num_abort_row(row, item.rf, ctl, abort_list);
+            __syncthreads();
+            continue;
         }
         // compaction of the occupied slots
         uint32_t kk[SPT];
@@ -278,13 +494,12 @@ __global__ __launch_bounds__(TEAM) void k_num_hash(const CaseDesc* __restrict__ 
 #pragma unroll
         for (int u = 0; u < SPT; ++u) {
             const uint32_t s = (uint32_t)t * SPT + u;
-            kk[u] = s < tsize ? keys[s] : kEmpty;
-            vv[u] = s < tsize ? vals[s] : 0.0;
+            kk[u] = s < T ? keys[s] : kEmpty;
+            vv[u] = s < T ? vals[s] : 0.0;
             mine += kk[u] != kEmpty ? 1u : 0u;
         }
         uint32_t c;
         uint32_t pos = block_excl_scan<TEAM, uint32_t>(mine, s_red, &c);
-        if (TEAM == kWave) __syncthreads();  // (one wave: no barrier inside the scan)
         int64_t dst;
         bool write;
         if (PASS == 1) {
@@ -295,7 +510,7 @@ __global__ __launch_bounds__(TEAM) void k_num_hash(const CaseDesc* __restrict__ 
             dst = na.C_rpt[row];
             write = dst + (int64_t)c <= na.capacity;
         }
-        if (write) {
+        if (write) {  // (then c <= T / 2)
 #pragma unroll
             for (int u = 0; u < SPT; ++u)
                 if (kk[u] != kEmpty) {
@@ -303,34 +518,11 @@ __global__ __launch_bounds__(TEAM) void k_num_hash(const CaseDesc* __restrict__ 
                     vals[pos] = vv[u];
                     ++pos;
                 }
-            const uint32_t c4 = (c + 3u) & ~3u;  // (c4 <= tsize / 2: c <= bound)
+            const uint32_t c4 = (c + 3u) & ~3u;
             if ((uint32_t)t < c4 - c) keys[c + t] = kEmpty;
             __syncthreads();
-            SSP_GLOBAL int32_t* ocol = PASS == 1 ? na.slot_col : na.C_col;
-            SSP_GLOBAL double* oval = PASS == 1 ? na.slot_val : na.C_val;
-            // rank of each entry among the row's keys (all keys distinct)
-            constexpr int EPT = SPT;  // entries per thread (c <= tsize / 2 <= SLOTS / 2)
-            uint32_t key[EPT], rank[EPT];
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) {
-                const uint32_t e = (uint32_t)t + (uint32_t)u * TEAM;
-                key[u] = e < c ? keys[e] : kEmpty;
-                rank[u] = 0;
-            }
-            for (uint32_t q = 0; q < c4; q += 4) {
-                const uint4 k4 = *reinterpret_cast<const uint4*>(&keys[q]);
-#pragma unroll
-                for (int u = 0; u < EPT; ++u)
-                    rank[u] += (k4.x < key[u]) + (k4.y < key[u]) + (k4.z < key[u]) + (k4.w < key[u]);
-            }
-#pragma unroll
-            for (int u = 0; u < EPT; ++u) {
-                const uint32_t e = (uint32_t)t + (uint32_t)u * TEAM;
-                if (e < c) {
-                    ocol[dst + rank[u]] = (int32_t)key[u];
-                    oval[dst + rank[u]] = vals[e];
-                }
-            }
+            num_write_ranked<TEAM, SPT / 2>(keys, vals, c, t, PASS == 1 ? na.slot_col : na.C_col,
+                                            PASS == 1 ? na.slot_val : na.C_val, dst);
         }
         __syncthreads();  // the table is reset for the next row
     }
@@ -338,42 +530,90 @@ __global__ __launch_bounds__(TEAM) void k_num_hash(const CaseDesc* __restrict__ 
 
 // ------------------------------------------------------ dense accumulators
 
+// Global-memory OR of `bits` into word `word` for every lane of the wave (all
+// 64 lanes call it; a lane with nothing passes kNoWord): neighbouring lanes
+// naming one word (sorted B rows put consecutive products in one word) are
+// combined first, one atomic per run.
+__device__ __forceinline__ void wave_or_global(SSP_GLOBAL uint32_t* bm, uint32_t word,
+                                               uint32_t bits)
+{
+    const int lane = lane_id();
+    const uint64_t valid = __ballot(word != kNoWord);
+    if (valid == 0) return;
+    const uint32_t prev = __shfl_up(word, 1, kWave);
+    const bool head = lane == 0 || prev != word;
+    uint32_t acc = bits;
+#pragma unroll
+    for (int off = 1; off < kWave; off <<= 1) {
+        const uint32_t ow = __shfl_down(word, off, kWave);
+        const uint32_t ob = __shfl_down(acc, off, kWave);
+        if (lane + off < kWave && ow == word) acc |= ob;
+    }
+    if (head && word != kNoWord)
+        __hip_atomic_fetch_or(&bm[word], acc, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+}
+
 // Bin 4: rows of more than kNumBin3Max products.  A persistent grid of
-// pool_slots workgroups; workgroup w owns accumulator w (N values and an
-// N-bit column bitmap in global memory, all zero between rows) and takes the
-// bin's items w, w + G, ...  Products are shared out as in the hash bins and
-// added with global atomics; the touched columns are marked in the bitmap.
-// The row is then read back in column order over the bitmap words between
-// its smallest and largest column: a scan of the words' popcounts ranks each
-// set bit, the entry is written at its rank, and the value and the word are
+// pool_slots workgroups takes the rows from a work queue; workgroup w owns
+// accumulator w (N values in global memory, zero between rows).  Products
+// are shared out as in the hash bins.  A product whose column is in the
+// workgroup's LDS cache (an open-addressing table of kNumCacheSlots columns,
+// filled up to half by the first columns met: the frequent ones) is added
+// there; the others go to the accumulator with a global atomic, and the
+// cache is added to the accumulator once at the end of the row (power-law
+// rows meet a few columns very often: their atomics would otherwise
+// serialise on one address).  The touched columns are marked in a bitmap, in
+// LDS when N <= 2^19 (LDSMASK), else in the accumulator's global bitmap.  The
+// row is then read back in column order over the bitmap words between its
+// smallest and largest column: a scan of the words' popcounts ranks each set
+// bit, the entry is written at its rank, and the value and the word are
 // cleared again.
-template <int PASS>
+constexpr int kNumCacheLg = 11, kNumCacheSlots = 1 << kNumCacheLg;
+constexpr int kNumCacheProbes = 8;
+constexpr int64_t kNumLdsMaskWords = 16384;
+
+template <int PASS, bool LDSMASK>
 __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense(const CaseDesc* __restrict__ cs,
                                                              const BigItem* __restrict__ items,
-                                                             const uint32_t* cnt_heavy,
-                                                             const uint32_t* cnt_light,
-                                                             uint32_t cap4, NumArgs na)
+                                                             Ctl* ctl, uint32_t cap4, NumArgs na)
 {
     constexpr int TEAM = kNumDenseTeam;
+    extern __shared__ __align__(16) uint32_t s_mask[];  // LDSMASK: mask_words words
     __shared__ int32_t s_b0[TEAM];
     __shared__ uint32_t s_off[TEAM];
     __shared__ double s_a[TEAM];
     __shared__ uint64_t s_red[TEAM / kWave + 1];
-    __shared__ uint32_t s_mm[2];
+    __shared__ uint32_t s_mm[2], s_k, s_fill;
+    __shared__ uint32_t c_keys[kNumCacheSlots];
+    __shared__ double c_vals[kNumCacheSlots];
     const int t = threadIdx.x;
-    const uint32_t nheavy = *cnt_heavy, total = nheavy + *cnt_light;
+    const uint32_t nheavy = ctl->bin_cnt[4], total = nheavy + ctl->bin_cnt[6];
+    uint32_t* next = &ctl->num_next[PASS - 1];
     const Csr A = cs[0].A, B = cs[0].B;
     SSP_GLOBAL double* acc = na.pool + (int64_t)blockIdx.x * na.N;
-    SSP_GLOBAL uint32_t* mask = na.pool_mask + (int64_t)blockIdx.x * na.mask_words;
-    for (uint32_t k = blockIdx.x; k < total; k += gridDim.x) {
-        const BigItem item = items[big_index(k, nheavy, cap4)];
-        const int64_t row = item.row;
-        if (PASS == 2 && num_fits(na, row, na.cnt[row])) continue;
+    SSP_GLOBAL uint32_t* gmask = na.pool_mask + (int64_t)blockIdx.x * na.mask_words;
+    if (LDSMASK)
+        for (int64_t w = t; w < na.mask_words; w += TEAM) s_mask[w] = 0u;
+    for (int s = t; s < kNumCacheSlots; s += TEAM) {
+        c_keys[s] = kEmpty;
+        c_vals[s] = 0.0;
+    }
+    for (;;) {
         if (t == 0) {
+            s_k = atomicAdd(next, 1u);
             s_mm[0] = 0xFFFFFFFFu;
             s_mm[1] = 0u;
+            s_fill = 0;
         }
         __syncthreads();
+        const uint32_t k = s_k;
+        if (k >= total) break;
+        const BigItem item = items[big_index(k, nheavy, cap4)];
+        const int64_t row = item.row;
+        if (PASS == 2 && num_fits(na, row, na.cnt[row])) {
+            __syncthreads();  // (s_k is rewritten)
+            continue;
+        }
         uint32_t wmin = 0xFFFFFFFFu, wmax = 0u;
         const int32_t a0 = item.e_lo, a1 = item.e_hi;
         for (int32_t a = a0; a < a1; a += TEAM) {
@@ -394,36 +634,84 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense(const CaseDesc* __r
             s_a[t] = av;
             __syncthreads();
             const int nent = (a1 - a) < TEAM ? (a1 - a) : TEAM;
-            for (uint32_t p = t; p < tot; p += TEAM) {
-                int lo = 0, hi = nent;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_off[mid] <= p) lo = mid;
-                    else hi = mid;
+            for (uint32_t p0 = 0; p0 < tot; p0 += TEAM) {  // same trip count in every lane
+                const uint32_t p = p0 + t;
+                uint32_t word = kNoWord, bit = 0;
+                if (p < tot) {
+                    int lo = 0, hi = nent;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_off[mid] <= p) lo = mid;
+                        else hi = mid;
+                    }
+                    const int32_t q = s_b0[lo] + (int32_t)(p - s_off[lo]);
+                    const uint32_t col = (uint32_t)B.col[q];
+                    const double v = s_a[lo] * na.Bval[q];
+                    // the LDS cache, else the accumulator
+                    uint32_t h = (col * 0x9E3779B1u) >> (32 - kNumCacheLg);
+                    bool done = false;
+                    for (int n = 0; n < kNumCacheProbes; ++n) {
+                        uint32_t cur = __hip_atomic_load(&c_keys[h], __ATOMIC_RELAXED,
+                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
+                        if (cur == kEmpty &&
+                            __hip_atomic_load(&s_fill, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <
+                                (uint32_t)(kNumCacheSlots / 2)) {
+                            cur = atomicCAS(&c_keys[h], kEmpty, col);
+                            if (cur == kEmpty) {
+                                atomicAdd(&s_fill, 1u);
+                                cur = col;
+                            }
+                        }
+                        if (cur == col) {
+                            __hip_atomic_fetch_add(&c_vals[h], v, __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
+                            done = true;
+                            break;
+                        }
+                        if (cur == kEmpty) break;  // (the cache is full enough)
+                        h = (h + 1u) & (uint32_t)(kNumCacheSlots - 1);
+                    }
+                    if (!done)
+                        __hip_atomic_fetch_add(&acc[col], v, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                    word = col >> 5;
+                    bit = 1u << (col & 31u);
+                    wmin = word < wmin ? word : wmin;
+                    wmax = word > wmax ? word : wmax;
                 }
-                const int32_t q = s_b0[lo] + (int32_t)(p - s_off[lo]);
-                const uint32_t col = (uint32_t)B.col[q];
-                __hip_atomic_fetch_add(&acc[col], s_a[lo] * na.Bval[q], __ATOMIC_RELAXED,
-                                       __HIP_MEMORY_SCOPE_AGENT);
-                __hip_atomic_fetch_or(&mask[col >> 5], 1u << (col & 31u), __ATOMIC_RELAXED,
-                                      __HIP_MEMORY_SCOPE_AGENT);
-                const uint32_t w = col >> 5;
-                wmin = w < wmin ? w : wmin;
-                wmax = w > wmax ? w : wmax;
+                if (LDSMASK)
+                    wave_bitmap_or(s_mask, word, bit);
+                else
+                    wave_or_global(gmask, word, bit);
             }
             __syncthreads();
         }
         atomicMin(&s_mm[0], wmin);
         atomicMax(&s_mm[1], wmax);
-        __threadfence();  // the global atomics have completed
+        // the cache into the accumulator (and cleared)
+        for (int s = t; s < kNumCacheSlots; s += TEAM) {
+            const uint32_t key = c_keys[s];
+            if (key != kEmpty) {
+                __hip_atomic_fetch_add(&acc[key], c_vals[s], __ATOMIC_RELAXED,
+                                       __HIP_MEMORY_SCOPE_WORKGROUP);
+                c_keys[s] = kEmpty;
+                c_vals[s] = 0.0;
+            }
+        }
+        // (workgroup scope: the accumulator is this workgroup's alone, and an
+        //  agent-scope fence would write back and invalidate the whole L2)
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
         const uint32_t w0 = s_mm[0], w1 = s_mm[1];
+        auto mask_word = [&](uint32_t w) -> uint32_t {
+            return LDSMASK ? s_mask[w]
+                           : __hip_atomic_load(&gmask[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+        };
         // count
         uint64_t mine = 0;
         if (w0 <= w1)
-            for (uint32_t w = w0 + t; w <= w1; w += TEAM)
-                mine += (uint64_t)__popc(
-                    __hip_atomic_load(&mask[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT));
+            for (uint32_t w = w0 + t; w <= w1; w += TEAM) mine += (uint64_t)__popc(mask_word(w));
         const uint64_t c = block_sum<TEAM, uint64_t>(mine, s_red);
         int64_t dst;
         bool write;
@@ -442,9 +730,7 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense(const CaseDesc* __r
         if (w0 <= w1)
             for (uint32_t wb = w0; wb <= w1; wb += TEAM) {
                 const uint32_t w = wb + t;
-                uint32_t bits = 0;
-                if (w <= w1)
-                    bits = __hip_atomic_load(&mask[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+                uint32_t bits = w <= w1 ? mask_word(w) : 0u;
                 uint64_t ctot;
                 const uint64_t ex =
                     block_excl_scan<TEAM, uint64_t>((uint64_t)__popc(bits), s_red, &ctot);
@@ -456,59 +742,94 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense(const CaseDesc* __r
                     if (write) {
                         ocol[o] = (int32_t)col;
                         oval[o] = __hip_atomic_load(&acc[col], __ATOMIC_RELAXED,
-                                                    __HIP_MEMORY_SCOPE_AGENT);
+                                                    __HIP_MEMORY_SCOPE_WORKGROUP);
                         ++o;
                     }
                     acc[col] = 0.0;
                 }
-                if (w <= w1) mask[w] = 0u;
+                if (w <= w1) {
+                    if (LDSMASK) s_mask[w] = 0u;
+                    else gmask[w] = 0u;
+                }
                 base += (int64_t)ctot;
             }
-        __threadfence();  // the clears are visible before the next row's atomics
+        // the clears are seen by the next row's atomics
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
         __syncthreads();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
     }
 }
 
 // ------------------------------------------------------------- copy pass
 
-// Rows that fitted their slot are copied to C at their final offsets:
-// kNumCopyRows rows per workgroup, their entries shared out over the threads
-// (each finds its row by binary search over the rows' starts in LDS).
+// Rows that fitted their slot are copied to C at their final offsets.  Each
+// workgroup copies a chunk of kNumCopyChunk entries of C (so a long row is
+// shared by many workgroups): it finds the rows that overlap its chunk by
+// binary search over C's row offsets and takes them kNumCopyRows at a time,
+// their entries shared out over the threads (each finds its row by binary
+// search in LDS).
+constexpr int64_t kNumCopyChunk = 8192;
+
 __global__ __launch_bounds__(kNumCopyRows) void k_num_copy(NumArgs na)
 {
     __shared__ int64_t s_start[kNumCopyRows + 1];
     __shared__ int64_t s_src[kNumCopyRows], s_dst[kNumCopyRows];
     __shared__ int64_t s_red[kNumCopyRows / kWave + 1];
+    __shared__ int64_t s_rows[2];
     const int t = threadIdx.x;
-    for (int64_t r0 = (int64_t)blockIdx.x * kNumCopyRows; r0 < na.M;
-         r0 += (int64_t)gridDim.x * kNumCopyRows) {
-        const int64_t i = r0 + t;
-        int64_t n = 0, src = 0, dst = 0;
-        if (i < na.M) {
-            const int64_t c = na.cnt[i];
-            src = na.slot_off[i];
-            dst = na.C_rpt[i];
-            if (num_fits(na, i, c) && dst + c <= na.capacity) n = c;
+    const int64_t nnz = na.C_rpt[na.M];
+    // last row whose offset is <= e (rows are [C_rpt[i], C_rpt[i+1]))
+    auto row_of = [&](int64_t e) {
+        int64_t lo = 0, hi = na.M;
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if (na.C_rpt[mid] <= e) lo = mid;
+            else hi = mid;
         }
-        int64_t tot;
-        const int64_t ex = block_excl_scan<kNumCopyRows, int64_t>(n, s_red, &tot);
-        s_start[t] = ex;
-        s_src[t] = src;
-        s_dst[t] = dst;
-        if (t == 0) s_start[kNumCopyRows] = tot;
+        return lo;
+    };
+    for (int64_t e0 = (int64_t)blockIdx.x * kNumCopyChunk; e0 < nnz;
+         e0 += (int64_t)gridDim.x * kNumCopyChunk) {
+        const int64_t e1 = (e0 + kNumCopyChunk) < nnz ? (e0 + kNumCopyChunk) : nnz;
+        if (t == 0) {
+            s_rows[0] = row_of(e0);
+            s_rows[1] = row_of(e1 - 1);
+        }
         __syncthreads();
-        for (int64_t q = t; q < tot; q += kNumCopyRows) {
-            int lo = 0, hi = kNumCopyRows;
-            while (hi - lo > 1) {
-                const int mid = (lo + hi) >> 1;
-                if (s_start[mid] <= q) lo = mid;
-                else hi = mid;
+        const int64_t r_first = s_rows[0], r_last = s_rows[1];
+        for (int64_t r0 = r_first; r0 <= r_last; r0 += kNumCopyRows) {
+            const int64_t i = r0 + t;
+            int64_t n = 0, src = 0, dst = 0;
+            if (i <= r_last) {
+                const int64_t c = na.cnt[i], beg = na.C_rpt[i];
+                const int64_t lo = beg > e0 ? beg : e0;
+                const int64_t hi = (beg + c) < e1 ? (beg + c) : e1;
+                if (num_fits(na, i, c) && beg + c <= na.capacity && hi > lo) {
+                    n = hi - lo;
+                    src = na.slot_off[i] + (lo - beg);
+                    dst = lo;
+                }
             }
-            const int64_t d = q - s_start[lo];
-            na.C_col[s_dst[lo] + d] = na.slot_col[s_src[lo] + d];
-            na.C_val[s_dst[lo] + d] = na.slot_val[s_src[lo] + d];
+            int64_t tot;
+            const int64_t ex = block_excl_scan<kNumCopyRows, int64_t>(n, s_red, &tot);
+            s_start[t] = ex;
+            s_src[t] = src;
+            s_dst[t] = dst;
+            if (t == 0) s_start[kNumCopyRows] = tot;
+            __syncthreads();
+            for (int64_t q = t; q < tot; q += kNumCopyRows) {
+                int lo = 0, hi = kNumCopyRows;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_start[mid] <= q) lo = mid;
+                    else hi = mid;
+                }
+                const int64_t d = q - s_start[lo];
+                na.C_col[s_dst[lo] + d] = na.slot_col[s_src[lo] + d];
+                na.C_val[s_dst[lo] + d] = na.slot_val[s_src[lo] + d];
+            }
+            __syncthreads();
         }
-        __syncthreads();
     }
 }
 

@@ -14,6 +14,7 @@ struct NumState {
     NumArgs na;
     uint32_t bins[4] = {0, 0, 0, 0};  // items in bins 1..3 and bin 4
     int32_t dense_grid = 0;
+    BinItem* abort_list = nullptr;    // rows whose first-pass table filled up
     ssp_spgemm_info info{};
 };
 
@@ -64,39 +65,65 @@ void launch_num_scan(const NumArgs& na, int kind, int cus, hipStream_t s)
     }
 }
 
+// The dense kernel's LDS bitmap (up to 2^19 columns) needs more than the
+// default dynamic LDS limit; set once.
+void prepare_num_kernels()
+{
+    static std::once_flag once;
+    std::call_once(once, [] {
+        const int bytes = (int)(kNumLdsMaskWords * sizeof(uint32_t));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_num_dense<1, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_num_dense<2, true>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
+    });
+}
+
 // The numeric kernels over the bins (pass 1 into the slots, pass 2 the rows
-// that overflowed, into C).
+// that overflowed, into C); after pass 1 the symbolic kernel counts the rows
+// whose first-pass table filled up.
 template <int PASS>
 void launch_num_rows(ssp_handle h, const NumState& S, hipStream_t s)
 {
     const int cus = h->num_cus;
     const CaseDesc* cs = S.b.cs;
+    Ctl* ctl = S.b.ctl;
+    const uint32_t nhash = S.bins[0] + S.bins[1] + S.bins[2];
     {
         PhaseTimer pt(h, PASS == 1 ? PH_NUM_HASH : PH_NUM_FALLBACK, s);
-        auto grid = [&](uint32_t items, int64_t res) {
-            return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(items, res)));
+        auto grid = [&](int64_t units, int64_t res) {
+            return dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(units, res)));
         };
-        if (S.bins[0])
-            hipLaunchKernelGGL((k_num_hash<kNumTeam1, kNumSlots1, PASS>),
-                               grid(S.bins[0], resident(k_num_hash<kNumTeam1, kNumSlots1, PASS>, kNumTeam1, cus)),
-                               dim3(kNumTeam1), 0, s, cs, (const BinItem*)S.b.L.b1,
-                               (const uint32_t*)&S.b.ctl->bin_cnt[1], S.na);
+        if (nhash)
+            hipLaunchKernelGGL((k_num_wave<PASS>),
+                               grid((nhash + kNumWaveWaves - 1) / kNumWaveWaves,
+                                    resident(k_num_wave<PASS>, kNumWaveWaves * kWave, cus)),
+                               dim3(kNumWaveWaves * kWave), 0, s, cs, S.b.L, ctl, S.abort_list, S.na);
         if (S.bins[1])
             hipLaunchKernelGGL((k_num_hash<kNumTeam2, kNumSlots2, PASS>),
                                grid(S.bins[1], resident(k_num_hash<kNumTeam2, kNumSlots2, PASS>, kNumTeam2, cus)),
                                dim3(kNumTeam2), 0, s, cs, (const BinItem*)S.b.L.b2,
-                               (const uint32_t*)&S.b.ctl->bin_cnt[2], S.na);
+                               (const uint32_t*)&ctl->bin_cnt[2], ctl, S.abort_list, S.na);
         if (S.bins[2])
             hipLaunchKernelGGL((k_num_hash<kNumTeam3, kNumSlots3, PASS>),
                                grid(S.bins[2], resident(k_num_hash<kNumTeam3, kNumSlots3, PASS>, kNumTeam3, cus)),
                                dim3(kNumTeam3), 0, s, cs, (const BinItem*)S.b.L.b3,
-                               (const uint32_t*)&S.b.ctl->bin_cnt[3], S.na);
+                               (const uint32_t*)&ctl->bin_cnt[3], ctl, S.abort_list, S.na);
+        if (PASS == 1 && nhash)  // (the list is usually empty: the kernel then ends at once)
+            hipLaunchKernelGGL((k_sym<kBin3Team, kBin3Words, 1>), dim3((unsigned)cus), dim3(kBin3Team),
+                               0, s, cs, (const BinItem*)S.abort_list, (const uint32_t*)&ctl->num_abort,
+                               S.b.cr);
     }
     if (S.bins[3] && S.dense_grid > 0) {
         PhaseTimer pt(h, PASS == 1 ? PH_NUM_DENSE : PH_NUM_FALLBACK, s);
-        hipLaunchKernelGGL((k_num_dense<PASS>), dim3((unsigned)S.dense_grid), dim3(kNumDenseTeam), 0,
-                           s, cs, (const BigItem*)S.b.L.b4, (const uint32_t*)&S.b.ctl->bin_cnt[4],
-                           (const uint32_t*)&S.b.ctl->bin_cnt[6], S.b.L.cap4, S.na);
+        if (S.na.mask_words <= kNumLdsMaskWords)
+            hipLaunchKernelGGL((k_num_dense<PASS, true>), dim3((unsigned)S.dense_grid),
+                               dim3(kNumDenseTeam), (size_t)S.na.mask_words * sizeof(uint32_t), s, cs,
+                               (const BigItem*)S.b.L.b4, ctl, S.b.L.cap4, S.na);
+        else
+            hipLaunchKernelGGL((k_num_dense<PASS, false>), dim3((unsigned)S.dense_grid),
+                               dim3(kNumDenseTeam), 0, s, cs, (const BigItem*)S.b.L.b4, ctl,
+                               S.b.L.cap4, S.na);
     }
 }
 
@@ -109,6 +136,7 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     // the previous call's copy pass may still read the slots and use the accumulators
     if (h->num_ev) SSP_HIP(h, hipEventSynchronize(h->num_ev));
     h->num_state.reset();
+    prepare_num_kernels();
     const int cus = h->num_cus;
     const int64_t M = A->nrows, N = B->ncols;
     // the precise method's plan routes the rows; the numeric bins replace its limits
@@ -122,6 +150,7 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     const size_t o_slot = o; o = align256(o + (size_t)(M + 1) * sizeof(int64_t));
     const size_t o_part = o; o = align256(o + (size_t)std::max<int64_t>(3 * nblk, 1) * sizeof(int64_t));
     const size_t o_agg = o;  o = align256(o + 8 * sizeof(uint64_t));
+    const size_t o_abort = o; o = align256(o + (size_t)std::max<int64_t>(M, 1) * sizeof(BinItem));
     ssp_status st = grow_buffer(h, &h->num_ws, &h->num_ws_bytes, o, true);
     if (st != SSP_OK) return st;
     char* base = static_cast<char*>(h->num_ws);
@@ -143,6 +172,7 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     na.slot_off = (decltype(na.slot_off))(base + o_slot);
     na.part = (decltype(na.part))(base + o_part);
     na.agg = (decltype(na.agg))(base + o_agg);
+    S->abort_list = reinterpret_cast<BinItem*>(base + o_abort);
     na.C_rpt = (decltype(na.C_rpt))C_rpt;
     na.M = M;
     na.N = N;
@@ -176,7 +206,10 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     if (S->bins[3] > 0) {
         na.mask_words = ((N + 31) / 32 + 1) / 2 * 2;  // (even: whole 8-byte words)
         const int64_t per_slot = N * (int64_t)sizeof(double) + na.mask_words * (int64_t)sizeof(uint32_t);
-        const int64_t want = std::min<int64_t>({(int64_t)S->bins[3], 2LL * cus,
+        const int64_t res = na.mask_words <= kNumLdsMaskWords
+                                ? resident(k_num_dense<1, true>, kNumDenseTeam, cus, kNumLdsMaskWords * sizeof(uint32_t))
+                                : resident(k_num_dense<1, false>, kNumDenseTeam, cus);
+        const int64_t want = std::min<int64_t>({(int64_t)S->bins[3], res,
                                                 std::max<int64_t>(1, kNumPoolBytesMax / per_slot)});
         const size_t bytes = (size_t)(want * per_slot);
         if (bytes > h->num_pool_bytes) h->num_pool_clean = false;
@@ -238,13 +271,15 @@ ssp_status spgemm_copy(ssp_handle h, int32_t* C_col, double* C_val, int64_t capa
     const int cus = h->num_cus;
     if (S->info.nnz > S->info.overflow_nnz) {
         PhaseTimer pt(h, PH_NUM_COPY, s);
-        const int64_t blocks = (na.M + kNumCopyRows - 1) / kNumCopyRows;
+        const int64_t blocks = (S->info.nnz + kNumCopyChunk - 1) / kNumCopyChunk;
         hipLaunchKernelGGL(k_num_copy, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, 16LL * cus))),
                            dim3(kNumCopyRows), 0, s, na);
     }
     SSP_LAUNCHED(h);
     if (S->info.overflow_rows > 0) {
         h->num_pool_clean = false;
+        // (the dense fallback's work queue starts at 0 on every copy call)
+        SSP_HIP(h, hipMemsetAsync(&S->b.ctl->num_next[1], 0, sizeof(uint32_t), s));
         launch_num_rows<2>(h, *S, s);
         SSP_LAUNCHED(h);
         h->num_pool_clean = true;
