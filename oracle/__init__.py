@@ -20,6 +20,8 @@ Paper anchors (Du et al., arXiv 2207.13848):
   * numeric product (consumer) .... Sec. I (the output the prediction sizes):
                                     the definition of C = A.B, and the slot
                                     layout of a predicted-capacity allocation
+  * the sketch estimator (KMV) .... Sec. III (Amossen et al.; BHash's p = 1/10
+                                    row and column sampling, NNZ(C')/p^2)
 """
 from __future__ import annotations
 
@@ -95,6 +97,8 @@ def _load():
         lib.orc_rows_nnz.restype = ctypes.c_int
         lib.orc_spgemm.argtypes = [i64, i64, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp, vp]
         lib.orc_spgemm.restype = ctypes.c_int
+        lib.orc_kmv.argtypes = [i64, i64, vp, vp, vp, vp, u64, u64, u64] + [ctypes.POINTER(u64)] * 5
+        lib.orc_kmv.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -285,6 +289,39 @@ def spgemm_layout(row_cap, margin_pct: int, counts, ncols: int) -> dict:
     over = cnt > slot
     return {"nnz": int(cnt.sum()), "slot_entries": int(slot.sum()),
             "overflow_rows": int(over.sum()), "overflow_nnz": int(cnt[over].sum())}
+
+
+# ------------------------------------------ Sec. III: the sketch estimator
+
+def kmv(A, B, rate: float, k: int, seed: int) -> dict:
+    """Amossen's k-minimum-values estimate with BHash's row and column
+    sampling (``orc_kmv``; definitions in its comment).  Returns the integer
+    results and the estimates: ``nnz_sample`` = k / v (v = the k-th smallest
+    distinct hash / 2^53) or the distinct count when there are fewer than k,
+    ``nnz_estimate`` = nnz_sample / (p_r p_c) with the realised proportions
+    p_r = rows kept / M and p_c = columns kept / N (None when nothing is kept)."""
+    M, K, ar, ac, br, bc = _csr_args(A, B)
+    T = rate_threshold(rate)
+    out = [ctypes.c_uint64(0) for _ in range(5)]
+    rc = _load().orc_kmv(M, int(B.ncols), _p(ar), _p(ac), _p(br), _p(bc), T, seed % (1 << 64),
+                         int(k), *[ctypes.byref(o) for o in out])
+    if rc:
+        raise ValueError(f"oracle kmv failed ({rc})")
+    nr, nc, npr, d, kv = (int(o.value) for o in out)
+    return dict(rows_kept=nr, cols_kept=nc, products=npr, distinct=d, kth_hash=kv, k=int(k),
+                **kmv_estimates(M, int(B.ncols), nr, nc, d, kv, int(k)))
+
+
+def kmv_estimates(M: int, N: int, nr: int, nc: int, distinct: int, kth: int, k: int) -> dict:
+    """The estimates of the sketch from its integer results (float64, the
+    order of operations both sides use)."""
+    if distinct >= k and kth > 0:
+        zs = float(k) / (float(kth) / 9007199254740992.0)
+    else:
+        zs = float(distinct)
+    if nr == 0 or nc == 0:
+        return {"nnz_sample": zs, "nnz_estimate": None}
+    return {"nnz_sample": zs, "nnz_estimate": zs / ((nr / M) * (nc / N))}
 
 
 # ------------------------------------------------------- Sec. VI-A accuracy

@@ -435,3 +435,87 @@ int orc_spgemm(int64_t M, int64_t N, const int32_t* Arpt, const int32_t* Acol, c
     free(touched);
     return rc;
 }
+
+/* ------------------------------- the sketch estimator of related work (KMV) */
+
+static int cmp_u64(const void* a, const void* b)
+{
+    uint64_t x = *(const uint64_t*)a, y = *(const uint64_t*)b;
+    return (x > y) - (x < y);
+}
+
+/*
+ * The existing sampling estimator of Amossen et al. as BHash uses it (Sec. III):
+ * rows of A and columns of B are each kept with probability p, every
+ * intermediate product (i, j) of C' = A'B' is hashed to [0, 1), the k-th
+ * smallest distinct hashed value v estimates NNZ(C') = k / v, and
+ * NNZ(C) = NNZ(C') / p^2 (p taken as the realised proportions of kept rows and
+ * columns).
+ *
+ * Definitions of this build (all from the splitmix64 stream above):
+ *   row i of A kept     iff (splitmix64(seed,     i) >> 11) < T
+ *   column j of B kept  iff (splitmix64(seed + 1, j) >> 11) < T
+ *   hash of (i, j)      =   splitmix64(seed + 2, i * N + j) >> 11   (53 bits; value / 2^53)
+ * T = floor(rate * 2^53) as for the row sampler.  Distinctness is of the
+ * 53-bit hash values.  When fewer than k distinct values exist, the sample's
+ * NNZ is their number (the sketch is exact).
+ * Outputs: rows and columns kept, products of C', distinct hash values of C',
+ * and the k-th smallest distinct value (0 when fewer than k).
+ */
+int orc_kmv(int64_t M, int64_t N, const int32_t* Arpt, const int32_t* Acol, const int32_t* Brpt,
+            const int32_t* Bcol, uint64_t T, uint64_t seed, uint64_t k, uint64_t* rows_kept,
+            uint64_t* cols_kept, uint64_t* products, uint64_t* distinct, uint64_t* kth)
+{
+    if (M < 0 || N < 0 || k == 0) return ORC_ERR_ARG;
+    uint64_t nr = 0, nc = 0, np = 0;
+    unsigned char* colk = (unsigned char*)malloc((size_t)(N > 0 ? N : 1));
+    if (!colk) return ORC_ERR_MEM;
+    for (int64_t j = 0; j < N; ++j) {
+        colk[j] = (orc_splitmix64(seed + 1u, (uint64_t)j) >> 11) < T;
+        nc += colk[j];
+    }
+    size_t cap = 1024, n = 0;
+    uint64_t* h = (uint64_t*)malloc(cap * sizeof(uint64_t));
+    if (!h) {
+        free(colk);
+        return ORC_ERR_MEM;
+    }
+    for (int64_t i = 0; i < M; ++i) {
+        if (!((orc_splitmix64(seed, (uint64_t)i) >> 11) < T)) continue;
+        ++nr;
+        for (int64_t e = Arpt[i]; e < Arpt[i + 1]; ++e) {
+            const int32_t kk = Acol[e];
+            for (int64_t q = Brpt[kk]; q < Brpt[kk + 1]; ++q) {
+                const int32_t j = Bcol[q];
+                if (!colk[j]) continue;
+                ++np;
+                if (n == cap) {
+                    cap *= 2;
+                    uint64_t* g = (uint64_t*)realloc(h, cap * sizeof(uint64_t));
+                    if (!g) {
+                        free(h);
+                        free(colk);
+                        return ORC_ERR_MEM;
+                    }
+                    h = g;
+                }
+                h[n++] = orc_splitmix64(seed + 2u, (uint64_t)i * (uint64_t)N + (uint64_t)j) >> 11;
+            }
+        }
+    }
+    qsort(h, n, sizeof(uint64_t), cmp_u64);
+    uint64_t d = 0, kv = 0;
+    for (size_t s = 0; s < n; ++s) {
+        if (s > 0 && h[s] == h[s - 1]) continue;
+        ++d;
+        if (d == k) kv = h[s];
+    }
+    free(h);
+    free(colk);
+    *rows_kept = nr;
+    *cols_kept = nc;
+    *products = np;
+    *distinct = d;
+    *kth = kv;
+    return ORC_OK;
+}

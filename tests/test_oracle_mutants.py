@@ -50,8 +50,15 @@ MUTANTS = {
     "spgemm_terms_not_counted": ("terms[j] += 1;", "terms[j] = 1;"),
     "spgemm_unsorted_rows": ("qsort(touched, (size_t)nt, sizeof(int32_t), cmp_i32);", ""),
     "spgemm_row_offset_shift": ("const int64_t o = Crpt[i] + s;", "const int64_t o = Crpt[i] + s + (s > 0 && i == 0);"),
+    "kmv_counts_duplicates": ("        if (s > 0 && h[s] == h[s - 1]) continue;\n", ""),
+    "kmv_column_seed": ("colk[j] = (orc_splitmix64(seed + 1u, (uint64_t)j) >> 11) < T;",
+                        "colk[j] = (orc_splitmix64(seed, (uint64_t)j) >> 11) < T;"),
+    "kmv_pair_transposed": ("(uint64_t)i * (uint64_t)N + (uint64_t)j) >> 11;",
+                            "(uint64_t)j * (uint64_t)M + (uint64_t)i) >> 11;"),
+    "kmv_kth_off_by_one": ("if (d == k) kv = h[s];", "if (d == k + 1) kv = h[s];"),
+    "kmv_unsampled_columns": ("                if (!colk[j]) continue;\n", ""),
 }
-PIN_FILES = ("test_oracle_pins.py", "test_oracle_spgemm_pins.py")
+PIN_FILES = ("test_oracle_pins.py", "test_oracle_spgemm_pins.py", "test_oracle_kmv_pins.py")
 
 
 @pytest.mark.parametrize("name", sorted(MUTANTS))
