@@ -387,6 +387,39 @@ SSP_API ssp_status ssp_spgemm_compute(ssp_handle h, const ssp_csr* A, const doub
 SSP_API ssp_status ssp_spgemm_copy(ssp_handle h, int32_t* C_col, double* C_val,
                                    int64_t capacity, void* stream);
 
+/* ----------------------- the existing sampling estimator (related work) */
+
+/*
+ * Amossen et al.'s k-minimum-values estimate of NNZ(C) with BHash's sampling
+ * (Sec. III), the comparison the paper's reference design stands for: rows of
+ * A and columns of B are each kept with probability `sample_rate`, every
+ * intermediate product (i, j) of C' = A'B' is hashed to [0, 1), the k-th
+ * smallest distinct hashed value v gives NNZ(C') = k / v, and
+ * NNZ(C) = NNZ(C') / (p_r p_c) with the realised proportions p_r = rows kept / M,
+ * p_c = columns kept / N (the paper's p^2).  Definitions (splitmix64 as for the
+ * row sampler, T = floor(sample_rate * 2^53)):
+ *   row i kept     iff (splitmix64(seed,     i) >> 11) < T
+ *   column j kept  iff (splitmix64(seed + 1, j) >> 11) < T
+ *   hash of (i, j) = (splitmix64(seed + 2, i * N + j) >> 11) / 2^53.
+ * With fewer than k distinct values the sample's NNZ is their number (exact).
+ * Synchronous: waits for `stream`, fills *out (host).  k in 1 .. 4096.
+ */
+typedef struct {
+    uint64_t rows_kept;     /* rows of A'                                        */
+    uint64_t cols_kept;     /* columns of B'                                     */
+    uint64_t products;      /* intermediate products of C' = A'B'                */
+    uint64_t distinct_kept; /* distinct hashes below the final threshold         */
+    uint64_t kth_hash;      /* k-th smallest distinct 53-bit hash, 0 if < k      */
+    uint64_t k;
+    uint64_t threshold;     /* the final threshold on the 53-bit hashes          */
+    double nnz_sample;      /* NNZ(C') estimate: k / v, or the distinct count    */
+    double nnz_estimate;    /* NNZ(C) estimate; -1 when no row or column is kept */
+} ssp_kmv_result;
+
+SSP_API ssp_status ssp_kmv_estimate(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
+                                    double sample_rate, uint32_t k, uint64_t seed,
+                                    ssp_kmv_result* out, void* stream);
+
 /* ------------------------------------------------ diagnostics, strings */
 
 /* Per-phase device timing.  While enabled, every phase a call enqueues is

@@ -25,7 +25,8 @@ from ._native import (FLAG_EMPTY_SAMPLE, FLAG_SATURATED, SAMPLER_BERNOULLI, SAMP
 
 __all__ = ["DeviceCSR", "Handle", "predict_structure", "reference_estimate", "exact_structure",
            "validate_csr", "read_stats", "default_handle", "SspError", "FLAG_EMPTY_SAMPLE",
-           "FLAG_SATURATED", "SAMPLER_BERNOULLI", "SAMPLER_PAPER", "version", "spgemm"]
+           "FLAG_SATURATED", "SAMPLER_BERNOULLI", "SAMPLER_PAPER", "version", "spgemm",
+           "kmv_estimate"]
 
 
 def version() -> str:
@@ -227,6 +228,21 @@ def spgemm(A: DeviceCSR, A_val, B: DeviceCSR, B_val, row_cap, *, margin_pct: int
                                     _stream_ptr(stream))
     h.check(status, "ssp_spgemm_copy")
     return C_rpt, C_col[:nnz], C_val[:nnz], info.as_dict()
+
+
+def kmv_estimate(A: DeviceCSR, B: DeviceCSR, sample_rate: float, k: int, seed: int, *,
+                 handle=None, stream=None) -> dict:
+    """The existing sampling estimator of related work (Amossen's k minimum
+    values with BHash's row and column sampling): ``ssp_kmv_estimate``, a dict
+    of its results."""
+    h = handle or default_handle(A.device)
+    out = _native.SspKmvResult()
+    a, b = A._c(), B._c()
+    status = h._lib.ssp_kmv_estimate(h.ptr, ctypes.byref(a), ctypes.byref(b), float(sample_rate),
+                                     int(k), int(seed) % (1 << 64), ctypes.byref(out),
+                                     _stream_ptr(stream))
+    h.check(status, "ssp_kmv_estimate")
+    return out.as_dict()
 
 
 class Case:

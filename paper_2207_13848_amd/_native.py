@@ -30,7 +30,7 @@ EXPORTED = (
     "ssp_server_create", "ssp_server_register_matrix", "ssp_server_submit", "ssp_server_poll",
     "ssp_server_wait", "ssp_server_info", "ssp_server_reset_stats", "ssp_server_destroy",
     "ssp_default_tuning", "ssp_get_tuning", "ssp_set_tuning", "ssp_autotune",
-    "ssp_spgemm_compute", "ssp_spgemm_copy",
+    "ssp_spgemm_compute", "ssp_spgemm_copy", "ssp_kmv_estimate",
 )
 
 
@@ -53,6 +53,19 @@ class SspSpgemmInfo(ctypes.Structure):
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
+
+
+class SspKmvResult(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in
+                ("rows_kept", "cols_kept", "products", "distinct_kept", "kth_hash", "k",
+                 "threshold")] + [("nnz_sample", ctypes.c_double), ("nnz_estimate", ctypes.c_double)]
+
+    def as_dict(self) -> dict:
+        d = {n: getattr(self, n) for n, _ in self._fields_}
+        d = {n: (int(v) if isinstance(v, int) else float(v)) for n, v in d.items()}
+        if d["nnz_estimate"] < 0:
+            d["nnz_estimate"] = None
+        return d
 
 
 class SspTuning(ctypes.Structure):
@@ -169,5 +182,8 @@ def load():
     lib.ssp_spgemm_compute.restype = cint
     lib.ssp_spgemm_copy.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     lib.ssp_spgemm_copy.restype = cint
+    lib.ssp_kmv_estimate.argtypes = [vp, csr_p, csr_p, dbl, ctypes.c_uint32, u64,
+                                     ctypes.POINTER(SspKmvResult), vp]
+    lib.ssp_kmv_estimate.restype = cint
     _lib = lib
     return lib

@@ -1157,3 +1157,4 @@ ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* m, int64_t* n_bad, void
 
 #include "ssp_server.hpp"
 #include "ssp_spgemm.hpp"
+#include "ssp_kmv.hpp"

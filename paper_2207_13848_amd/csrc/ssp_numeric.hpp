@@ -189,6 +189,7 @@ __global__ __launch_bounds__(kNumScanThreads) void k_num_scan_rows(NumArgs na)
 // steps) and is counted by the symbolic kernel instead.  The fallback pass
 // knows each row's exact count and sizes b by it.
 constexpr int kNumWaveSlots = 512;  // table of a row handled by one wave
+constexpr int kNumUnroll = 4;       // products per lane whose loads are in flight together
 constexpr int kNumWaveWaves = 4;    // such rows per workgroup
 
 __device__ __forceinline__ uint32_t num_table_size(uint64_t b)
@@ -356,15 +357,28 @@ __global__ __launch_bounds__(kNumWaveWaves* kWave) void k_num_wave(const CaseDes
             s_a[w][lane] = av;
             wave_sync();
             const int nent = (a1 - a) < kWave ? (a1 - a) : kWave;
-            for (uint32_t p = lane; p < tot; p += kWave) {
-                int lo = 0, hi = nent;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_off[w][mid] <= p) lo = mid;
-                    else hi = mid;
+            // kNumUnroll products per lane at a time: their loads in flight together
+            for (uint32_t p0 = 0; p0 < tot; p0 += kWave * kNumUnroll) {
+                uint32_t col[kNumUnroll];
+                double v[kNumUnroll];
+#pragma unroll
+                for (int u = 0; u < kNumUnroll; ++u) {
+                    const uint32_t pr = p0 + (uint32_t)(u * kWave + lane);
+                    const uint32_t p = pr < tot ? pr : tot - 1;  // (clamped: loads unconditional)
+                    int lo = 0, hi = nent;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_off[w][mid] <= p) lo = mid;
+                        else hi = mid;
+                    }
+                    const int32_t q = s_b0[w][lo] + (int32_t)(p - s_off[w][lo]);
+                    col[u] = (uint32_t)B.col[q];
+                    v[u] = s_a[w][lo] * na.Bval[q];
                 }
-                const int32_t q = s_b0[w][lo] + (int32_t)(p - s_off[w][lo]);
-                ok = num_hash_add(keys, vals, (uint32_t)B.col[q], s_a[w][lo] * na.Bval[q], lg) && ok;
+#pragma unroll
+                for (int u = 0; u < kNumUnroll; ++u)
+                    if (p0 + (uint32_t)(u * kWave + lane) < tot)
+                        ok = num_hash_add(keys, vals, col[u], v[u], lg) && ok;
             }
             wave_sync();
         }
@@ -468,15 +482,27 @@ __global__ __launch_bounds__(TEAM) void k_num_hash(const CaseDesc* __restrict__ 
             s_a[t] = av;
             __syncthreads();
             const int nent = (a1 - a) < TEAM ? (a1 - a) : TEAM;
-            for (uint32_t p = t; p < tot; p += TEAM) {
-                int lo = 0, hi = nent;
-                while (hi - lo > 1) {
-                    const int mid = (lo + hi) >> 1;
-                    if (s_off[mid] <= p) lo = mid;
-                    else hi = mid;
+            for (uint32_t p0 = 0; p0 < tot; p0 += TEAM * kNumUnroll) {
+                uint32_t col[kNumUnroll];
+                double v[kNumUnroll];
+#pragma unroll
+                for (int u = 0; u < kNumUnroll; ++u) {
+                    const uint32_t pr = p0 + (uint32_t)(u * TEAM + t);
+                    const uint32_t p = pr < tot ? pr : tot - 1;
+                    int lo = 0, hi = nent;
+                    while (hi - lo > 1) {
+                        const int mid = (lo + hi) >> 1;
+                        if (s_off[mid] <= p) lo = mid;
+                        else hi = mid;
+                    }
+                    const int32_t q = s_b0[lo] + (int32_t)(p - s_off[lo]);
+                    col[u] = (uint32_t)B.col[q];
+                    v[u] = s_a[lo] * na.Bval[q];
                 }
-                const int32_t q = s_b0[lo] + (int32_t)(p - s_off[lo]);
-                ok = num_hash_add(keys, vals, (uint32_t)B.col[q], s_a[lo] * na.Bval[q], lg) && ok;
+#pragma unroll
+                for (int u = 0; u < kNumUnroll; ++u)
+                    if (p0 + (uint32_t)(u * TEAM + t) < tot)
+                        ok = num_hash_add(keys, vals, col[u], v[u], lg) && ok;
             }
             __syncthreads();
         }
@@ -634,10 +660,40 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense(const CaseDesc* __r
             s_a[t] = av;
             __syncthreads();
             const int nent = (a1 - a) < TEAM ? (a1 - a) : TEAM;
-            for (uint32_t p0 = 0; p0 < tot; p0 += TEAM) {  // same trip count in every lane
-                const uint32_t p = p0 + t;
-                uint32_t word = kNoWord, bit = 0;
-                if (p < tot) {
+            // the LDS cache, else the accumulator
+            auto add = [&](uint32_t col, double v) {
+                uint32_t h = (col * 0x9E3779B1u) >> (32 - kNumCacheLg);
+                for (int n = 0; n < kNumCacheProbes; ++n) {
+                    uint32_t cur =
+                        __hip_atomic_load(&c_keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+                    if (cur == kEmpty &&
+                        __hip_atomic_load(&s_fill, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <
+                            (uint32_t)(kNumCacheSlots / 2)) {
+                        cur = atomicCAS(&c_keys[h], kEmpty, col);
+                        if (cur == kEmpty) {
+                            atomicAdd(&s_fill, 1u);
+                            cur = col;
+                        }
+                    }
+                    if (cur == col) {
+                        __hip_atomic_fetch_add(&c_vals[h], v, __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        return;
+                    }
+                    if (cur == kEmpty) break;  // (the cache is full enough)
+                    h = (h + 1u) & (uint32_t)(kNumCacheSlots - 1);
+                }
+                __hip_atomic_fetch_add(&acc[col], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+            };
+            // same trip count in every lane; kNumUnroll products per lane whose
+            // loads are in flight together
+            for (uint32_t p0 = 0; p0 < tot; p0 += TEAM * kNumUnroll) {
+                uint32_t colv[kNumUnroll];
+                double vv[kNumUnroll];
+#pragma unroll
+                for (int u = 0; u < kNumUnroll; ++u) {
+                    const uint32_t pr = p0 + (uint32_t)(u * TEAM + t);
+                    const uint32_t p = pr < tot ? pr : tot - 1;
                     int lo = 0, hi = nent;
                     while (hi - lo > 1) {
                         const int mid = (lo + hi) >> 1;
@@ -645,44 +701,25 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense(const CaseDesc* __r
                         else hi = mid;
                     }
                     const int32_t q = s_b0[lo] + (int32_t)(p - s_off[lo]);
-                    const uint32_t col = (uint32_t)B.col[q];
-                    const double v = s_a[lo] * na.Bval[q];
-                    // the LDS cache, else the accumulator
-                    uint32_t h = (col * 0x9E3779B1u) >> (32 - kNumCacheLg);
-                    bool done = false;
-                    for (int n = 0; n < kNumCacheProbes; ++n) {
-                        uint32_t cur = __hip_atomic_load(&c_keys[h], __ATOMIC_RELAXED,
-                                                         __HIP_MEMORY_SCOPE_WORKGROUP);
-                        if (cur == kEmpty &&
-                            __hip_atomic_load(&s_fill, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) <
-                                (uint32_t)(kNumCacheSlots / 2)) {
-                            cur = atomicCAS(&c_keys[h], kEmpty, col);
-                            if (cur == kEmpty) {
-                                atomicAdd(&s_fill, 1u);
-                                cur = col;
-                            }
-                        }
-                        if (cur == col) {
-                            __hip_atomic_fetch_add(&c_vals[h], v, __ATOMIC_RELAXED,
-                                                   __HIP_MEMORY_SCOPE_WORKGROUP);
-                            done = true;
-                            break;
-                        }
-                        if (cur == kEmpty) break;  // (the cache is full enough)
-                        h = (h + 1u) & (uint32_t)(kNumCacheSlots - 1);
-                    }
-                    if (!done)
-                        __hip_atomic_fetch_add(&acc[col], v, __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-                    word = col >> 5;
-                    bit = 1u << (col & 31u);
-                    wmin = word < wmin ? word : wmin;
-                    wmax = word > wmax ? word : wmax;
+                    colv[u] = (uint32_t)B.col[q];
+                    vv[u] = s_a[lo] * na.Bval[q];
                 }
-                if (LDSMASK)
-                    wave_bitmap_or(s_mask, word, bit);
-                else
-                    wave_or_global(gmask, word, bit);
+#pragma unroll
+                for (int u = 0; u < kNumUnroll; ++u) {
+                    uint32_t word = kNoWord, bit = 0;
+                    if (p0 + (uint32_t)(u * TEAM + t) < tot) {
+                        const uint32_t col = colv[u];
+                        add(col, vv[u]);
+                        word = col >> 5;
+                        bit = 1u << (col & 31u);
+                        wmin = word < wmin ? word : wmin;
+                        wmax = word > wmax ? word : wmax;
+                    }
+                    if (LDSMASK)
+                        wave_bitmap_or(s_mask, word, bit);
+                    else
+                        wave_or_global(gmask, word, bit);
+                }
             }
             __syncthreads();
         }
