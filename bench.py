@@ -301,7 +301,10 @@ def main_accuracy(args):
     proposed prediction (Z2* = F z*/f*), the reference design (Z1* = z* M/n_s)
     and the exact total Z, all on the GPU, with the Bernoulli sampler at 1% and
     the paper's fixed-count sampler; errors eps = estimate / Z - 1, with
-    eps_f = F*/F - 1 for F* = f* M / n_s (Eq. (5): (1+eps2)(1+epsf) = 1+eps1)."""
+    eps_f = F*/F - 1 for F* = f* M / n_s (Eq. (5): (1+eps2)(1+epsf) = 1+eps1).
+    Beside them the existing estimator of related work (Sec. III): Amossen's
+    k minimum values (k = 1024) with BHash's row and column sampling at
+    p = 1/10 (1% of the products, as the 1% row sample)."""
     import numpy as np
     import torch
     import paper_2207_13848_amd as ssp
@@ -322,6 +325,7 @@ def main_accuracy(args):
             _, rst = ssp.reference_estimate(A, A, w.rate, w.seed, sampler=smp)
             s_, r_ = ssp.read_stats(st), ssp.read_stats(rst)
             out[smp] = (s_, r_)
+        out["kmv"] = ssp.kmv_estimate(A, A, 0.1, 1024, w.seed)["nnz_estimate"]
         e = ssp.read_stats(exs)
         out["Z"], out["F"] = e["out_sum"], e["total_flop"]
         rows.append(out)
@@ -360,9 +364,24 @@ def main_accuracy(args):
                     "worst_abs_eps2": float(np.max(np.abs(e2[m])))}
         return out
 
+    def summarise_kmv():
+        recs = [(r["structure"], r["kmv"] / r["Z"] - 1) for r in rows
+                if r["Z"] and r["kmv"] is not None]
+        st = np.array([x[0] for x in recs])
+        e = np.array([x[1] for x in recs])
+        out = {"cases": int(len(recs)), "mean_abs_eps": float(np.mean(np.abs(e))),
+               "worst_abs_eps": float(np.max(np.abs(e))), "by_structure": {}}
+        for sname in workloads.STRUCTURES:
+            m = st == sname
+            if m.any():
+                out["by_structure"][sname] = {"mean_abs_eps": float(np.mean(np.abs(e[m]))),
+                                              "worst_abs_eps": float(np.max(np.abs(e[m])))}
+        return out
+
     print(json.dumps({"study": "accuracy over the 625-case sweep", "run_s": round(t_run, 1),
                       "bernoulli_1pct": summarise("bernoulli"),
                       "paper_sampler": summarise("paper"),
+                      "kmv_p10_k1024": summarise_kmv(),
                       "paper_reports": {"mean_abs_eps1": 0.0812, "mean_abs_eps2": 0.0156,
                                         "worst_abs_eps1": 1.58, "worst_abs_eps2": 0.25}}),
           flush=True)
@@ -737,6 +756,15 @@ def main():
                                                   exact_np[nz])) if nz.any() else None,
         }
         result["predict_vs_exact_time"] = round(ms_per_step / result["exact_ms"], 4)
+        # the existing estimator of related work (Sec. III): k minimum values, p = 1/10
+        ssp.kmv_estimate(Ad, Bd, 0.1, 1024, w.seed, handle=h)
+        torch.cuda.synchronize()
+        tk = time.perf_counter()
+        for _ in range(3):
+            kmv = ssp.kmv_estimate(Ad, Bd, 0.1, 1024, w.seed, handle=h)
+        result["kmv_ms"] = round((time.perf_counter() - tk) * 1e3 / 3, 4)
+        result["accuracy"]["eps_kmv_p10_k1024"] = (kmv["nnz_estimate"] / Z - 1) if Z and \
+            kmv["nnz_estimate"] is not None else None
 
     if not args.no_extras:
         # batched vs plain on the small end of the sweep (sizes 2^12, 2^14: 250 cases)

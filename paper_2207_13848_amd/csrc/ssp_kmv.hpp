@@ -24,12 +24,14 @@ constexpr uint32_t kKmvMaxKept = 16384;               // values the selection so
 constexpr uint32_t kKmvStop = 2 * kKmvMaxKept;        // inserts stop here (tau is then halved)
 constexpr uint32_t kKmvKMax = 4096;
 constexpr int kKmvThreads = 256;
+constexpr int kKmvUnroll = 8;  // products per thread whose loads are in flight together
 
 struct KmvCounters {
     uint64_t rows, cols, products;
     uint32_t distinct, overflow;
     uint64_t kth;
-    uint64_t pad[3];
+    uint32_t nlight, nheavy;  // work items: kept rows of <= kKmvThreads entries; chunks of longer rows
+    uint64_t pad[2];
 };
 
 __device__ __forceinline__ bool kmv_kept(uint64_t seed, uint64_t i, uint64_t T)
@@ -76,77 +78,126 @@ __global__ __launch_bounds__(kKmvThreads) void k_kmv_cols(int64_t N, uint64_t T,
     if (threadIdx.x == 0 && n) atomicAdd((unsigned long long*)&c->cols, (unsigned long long)n);
 }
 
-// MODE 0: kept rows and the products of C'.  MODE 1: every product's hash
-// below tau into the set.  A workgroup takes 256 rows at a time, compacts the
-// kept ones and enumerates each kept row's products over the whole workgroup
-// (scan of the B row lengths, owner by binary search in LDS).
+// The kept rows of A as work items: a row of at most kKmvThreads entries is
+// one item (light list); a longer row is cut into chunks of kKmvThreads
+// entries, one item each (heavy list), so hub rows are shared out over many
+// workgroups.  Light rows are appended with one atomic per wave.
+__global__ __launch_bounds__(kKmvThreads) void k_kmv_rows(Csr A, uint64_t T, uint64_t seed,
+                                                         int32_t* light, int2* heavy,
+                                                         KmvCounters* c)
+{
+    const int lane = lane_id();
+    for (int64_t r0 = (int64_t)blockIdx.x * kKmvThreads; r0 < A.nrows;
+         r0 += (int64_t)gridDim.x * kKmvThreads) {
+        const int64_t r = r0 + threadIdx.x;
+        const bool kept = r < A.nrows && kmv_kept(seed, (uint64_t)r, T);
+        const int32_t len = kept ? A.rpt[r + 1] - A.rpt[r] : 0;
+        const bool lt = kept && len <= kKmvThreads;
+        const uint64_t m = __ballot(lt);
+        if (m) {
+            const int leader = __ffsll((long long)m) - 1;
+            uint32_t pos = 0;
+            if (lane == leader) pos = atomicAdd(&c->nlight, (uint32_t)__popcll(m));
+            pos = __shfl(pos, leader, kWave);
+            if (lt) light[pos + rank_in(m)] = (int32_t)r;
+        }
+        if (kept && !lt) {
+            const int32_t nch = (len + kKmvThreads - 1) / kKmvThreads;
+            const uint32_t base = atomicAdd(&c->nheavy, (uint32_t)nch);
+            for (int32_t q = 0; q < nch; ++q) heavy[base + q] = make_int2((int32_t)r, q);
+        }
+        const uint64_t km = __ballot(kept);
+        if (lane == 0 && km)
+            atomicAdd((unsigned long long*)&c->rows, (unsigned long long)__popcll(km));
+    }
+}
+
+// MODE 0: the products of C'.  MODE 1: every product's hash below tau into
+// the set.  One work item (a light row or a chunk of a heavy one, at most
+// kKmvThreads entries of A) per workgroup at a time; its products are
+// enumerated over the workgroup (scan of the B row lengths, owner by binary
+// search in LDS), kKmvUnroll per thread with their loads in flight together.
 template <int MODE>
 __global__ __launch_bounds__(kKmvThreads) void k_kmv_pass(Csr A, Csr B, uint64_t T, uint64_t seed,
                                                          uint64_t tau, uint64_t* set,
+                                                         const int32_t* light, const int2* heavy,
                                                          KmvCounters* c)
 {
     constexpr int NT = kKmvThreads;
-    __shared__ int32_t s_rows[NT];
     __shared__ int32_t s_b0[NT];
     __shared__ uint32_t s_off[NT];
     __shared__ uint32_t s_red[NT / kWave + 1];
     __shared__ uint64_t s_red64[NT / kWave + 1];
     const int t = threadIdx.x;
     const int64_t N = B.ncols;
-    uint64_t rows = 0, prods = 0;
-    for (int64_t r0 = (int64_t)blockIdx.x * NT; r0 < A.nrows; r0 += (int64_t)gridDim.x * NT) {
-        const int64_t r = r0 + t;
-        const uint32_t kept = (r < A.nrows && kmv_kept(seed, (uint64_t)r, T)) ? 1u : 0u;
-        uint32_t nk;
-        const uint32_t pos = block_excl_scan<NT, uint32_t>(kept, s_red, &nk);
-        if (kept) s_rows[pos] = (int32_t)r;
+    const uint32_t nl = c->nlight, nitems = nl + c->nheavy;
+    uint64_t prods = 0;
+    for (uint32_t it = blockIdx.x; it < nitems; it += gridDim.x) {
+        int32_t i, a, a1;
+        if (it < nl) {
+            i = light[it];
+            a = A.rpt[i];
+            a1 = A.rpt[i + 1];
+        } else {
+            const int2 h = heavy[it - nl];
+            i = h.x;
+            a = A.rpt[i] + h.y * NT;
+            const int32_t e = A.rpt[i + 1];
+            a1 = (a + NT) < e ? (a + NT) : e;
+        }
+        const int32_t j = a + t;
+        uint32_t len = 0;
+        int32_t b0 = 0;
+        if (j < a1) {
+            const int32_t k = A.col[j];
+            b0 = B.rpt[k];
+            len = (uint32_t)(B.rpt[k + 1] - b0);
+        }
+        uint32_t tot;
+        const uint32_t off = block_excl_scan<NT, uint32_t>(len, s_red, &tot);
+        s_b0[t] = b0;
+        s_off[t] = off;
         __syncthreads();
-        rows += nk;
-        for (uint32_t s = 0; s < nk; ++s) {
-            const int32_t i = s_rows[s];
-            const int32_t a0 = A.rpt[i], a1 = A.rpt[i + 1];
-            for (int32_t a = a0; a < a1; a += NT) {
-                const int32_t j = a + t;
-                uint32_t len = 0;
-                int32_t b0 = 0;
-                if (j < a1) {
-                    const int32_t k = A.col[j];
-                    b0 = B.rpt[k];
-                    len = (uint32_t)(B.rpt[k + 1] - b0);
+        const int nent = a1 - a;
+        for (uint32_t p0 = 0; p0 < tot; p0 += NT * kKmvUnroll) {
+            int32_t colv[kKmvUnroll];
+#pragma unroll
+            for (int u = 0; u < kKmvUnroll; ++u) {
+                const uint32_t pr = p0 + (uint32_t)(u * NT + t);
+                const uint32_t p = pr < tot ? pr : tot - 1;  // (clamped: loads unconditional)
+                int lo = 0, hi = nent;
+                while (hi - lo > 1) {
+                    const int mid = (lo + hi) >> 1;
+                    if (s_off[mid] <= p) lo = mid;
+                    else hi = mid;
                 }
-                uint32_t tot;
-                const uint32_t off = block_excl_scan<NT, uint32_t>(len, s_red, &tot);
-                s_b0[t] = b0;
-                s_off[t] = off;
-                __syncthreads();
-                const int nent = (a1 - a) < NT ? (a1 - a) : NT;
-                for (uint32_t p = t; p < tot; p += NT) {
-                    int lo = 0, hi = nent;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_off[mid] <= p) lo = mid;
-                        else hi = mid;
-                    }
-                    const int32_t q = s_b0[lo] + (int32_t)(p - s_off[lo]);
-                    const uint64_t col = (uint64_t)B.col[q];
-                    if (!kmv_kept(seed + 1u, col, T)) continue;
-                    if (MODE == 0) {
-                        ++prods;
-                    } else {
-                        const uint64_t hv = splitmix64_at(seed + 2u, (uint64_t)i * (uint64_t)N + col) >> 11;
-                        if (hv < tau) kmv_insert(set, hv, c);
-                    }
+                colv[u] = B.col[s_b0[lo] + (int32_t)(p - s_off[lo])];
+            }
+#pragma unroll
+            for (int u = 0; u < kKmvUnroll; ++u) {
+                const uint64_t col = (uint64_t)colv[u];
+                if (p0 + (uint32_t)(u * NT + t) >= tot || !kmv_kept(seed + 1u, col, T)) continue;
+                if (MODE == 0) {
+                    ++prods;
+                } else {
+                    const uint64_t hv = splitmix64_at(seed + 2u, (uint64_t)i * (uint64_t)N + col) >> 11;
+                    if (hv < tau) kmv_insert(set, hv, c);
                 }
-                __syncthreads();
             }
         }
+        __syncthreads();
     }
     if (MODE == 0) {
         prods = block_sum<NT, uint64_t>(prods, s_red64);
-        if (t == 0) {
-            if (rows) atomicAdd((unsigned long long*)&c->rows, (unsigned long long)rows);
-            if (prods) atomicAdd((unsigned long long*)&c->products, (unsigned long long)prods);
-        }
+        if (t == 0 && prods) atomicAdd((unsigned long long*)&c->products, (unsigned long long)prods);
+    }
+}
+
+__global__ void k_kmv_reset(KmvCounters* c)
+{
+    if (threadIdx.x == 0) {
+        c->distinct = 0;
+        c->overflow = 0;
     }
 }
 
@@ -203,24 +254,33 @@ ssp_status kmv_estimate(ssp_handle h, const ssp_csr* A, const ssp_csr* B, double
                                   hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)(kKmvMaxKept * sizeof(uint64_t)));
     });
+    const int64_t M = A->nrows, N = B->ncols;
     const size_t set_bytes = ((size_t)1 << kKmvSetLg) * sizeof(uint64_t);
-    ssp_status st = ensure_workspace(h, set_bytes + align256(sizeof(KmvCounters)));
+    const size_t o_light = set_bytes + align256(sizeof(KmvCounters));
+    const size_t o_heavy = o_light + align256((size_t)std::max<int64_t>(M, 1) * sizeof(int32_t));
+    // (chunks of the long rows: at most nnz(A) / kKmvThreads + rows)
+    const size_t heavy_cap = (size_t)(A->nnz / kKmvThreads + M + 1);
+    ssp_status st = ensure_workspace(h, o_heavy + heavy_cap * sizeof(int2));
     if (st != SSP_OK) return st;
     uint64_t* set = static_cast<uint64_t*>(h->ws);
     KmvCounters* cnt = reinterpret_cast<KmvCounters*>(static_cast<char*>(h->ws) + set_bytes);
+    int32_t* light = reinterpret_cast<int32_t*>(static_cast<char*>(h->ws) + o_light);
+    int2* heavy = reinterpret_cast<int2*>(static_cast<char*>(h->ws) + o_heavy);
     const Csr a = to_csr(A), b = to_csr(B);
-    const int64_t M = A->nrows, N = B->ncols;
     const uint64_t T = rate_threshold(rate);
     const int cus = h->num_cus;
     const unsigned grid_rows = (unsigned)std::max<int64_t>(1, std::min<int64_t>((M + kKmvThreads - 1) / kKmvThreads, 8LL * cus));
     const unsigned grid_cols = (unsigned)std::max<int64_t>(1, std::min<int64_t>((N + kKmvThreads - 1) / kKmvThreads, 4LL * cus));
     const unsigned grid_set = (unsigned)(((1u << kKmvSetLg) + 255) / 256);
+    const unsigned grid_items = (unsigned)(8 * cus);  // (the items are counted on the device)
     const int64_t words = (int64_t)((set_bytes + sizeof(KmvCounters)) / sizeof(uint64_t));
     // kept rows and columns, products of C'
     hipLaunchKernelGGL(k_num_zero, dim3(grid_set), dim3(256), 0, s, (uint64_t*)h->ws, words);
     hipLaunchKernelGGL(k_kmv_cols, dim3(grid_cols), dim3(kKmvThreads), 0, s, N, T, seed, cnt);
-    hipLaunchKernelGGL(k_kmv_pass<0>, dim3(grid_rows), dim3(kKmvThreads), 0, s, a, b, T, seed,
-                       (uint64_t)0, set, cnt);
+    hipLaunchKernelGGL(k_kmv_rows, dim3(grid_rows), dim3(kKmvThreads), 0, s, a, T, seed, light,
+                       heavy, cnt);
+    hipLaunchKernelGGL(k_kmv_pass<0>, dim3(grid_items), dim3(kKmvThreads), 0, s, a, b, T, seed,
+                       (uint64_t)0, set, (const int32_t*)light, (const int2*)heavy, cnt);
     SSP_LAUNCHED(h);
     KmvCounters hc;
     SSP_HIP(h, hipMemcpyAsync(&hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
@@ -245,9 +305,12 @@ ssp_status kmv_estimate(ssp_handle h, const ssp_csr* A, const ssp_csr* B, double
                 h->last_error = "sketch threshold did not settle";
                 return SSP_ERR_HIP;
             }
-            hipLaunchKernelGGL(k_num_zero, dim3(grid_set), dim3(256), 0, s, (uint64_t*)h->ws, words);
-            hipLaunchKernelGGL(k_kmv_pass<1>, dim3(grid_rows), dim3(kKmvThreads), 0, s, a, b, T, seed,
-                               tau, set, cnt);
+            // (the set and the insert counters; the item lists and their sizes stay)
+            hipLaunchKernelGGL(k_num_zero, dim3(grid_set), dim3(256), 0, s, (uint64_t*)h->ws,
+                               (int64_t)(set_bytes / sizeof(uint64_t)));
+            hipLaunchKernelGGL(k_kmv_reset, dim3(1), dim3(64), 0, s, cnt);
+            hipLaunchKernelGGL(k_kmv_pass<1>, dim3(grid_items), dim3(kKmvThreads), 0, s, a, b, T, seed,
+                               tau, set, (const int32_t*)light, (const int2*)heavy, cnt);
             SSP_LAUNCHED(h);
             SSP_HIP(h, hipMemcpyAsync(&hc, cnt, sizeof(hc), hipMemcpyDeviceToHost, s));
             SSP_HIP(h, hipStreamSynchronize(s));
