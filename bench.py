@@ -65,10 +65,15 @@ def copy_calibration(nbytes: int):
     print(json.dumps({"copy_calibration_bytes": 4 * n, "launches": 3}), flush=True)
 
 
+# Sources of the prediction path's kernels and their launches (the numeric
+# product's and the sketch's files add kernels and entry points of their own).
+PREDICT_SOURCES = ("ssp_device.hpp", "ssp_internal.hpp", "ssp_kernels.hpp", "ssp_lib.hip")
+
+
 def kernel_source_hash() -> str:
     h = hashlib.sha256()
     csrc = os.path.join(ROOT, "paper_2207_13848_amd", "csrc")
-    for f in sorted(os.listdir(csrc)):
+    for f in PREDICT_SOURCES:
         with open(os.path.join(csrc, f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()[:16]
