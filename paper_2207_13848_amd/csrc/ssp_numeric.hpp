@@ -265,11 +265,12 @@ __device__ __forceinline__ void num_abort_row(int64_t row, uint32_t rf, Ctl* ctl
 // Writes the c occupied slots of a table, columns increasing, at dst: each
 // entry's place is its rank among the row's (distinct) keys.  The caller has
 // compacted the entries to keys/vals[0, c) and set keys[c, c4) to kEmpty
-// (c4 = c rounded up to 4).  EPT entries per lane at most (c <= EPT * NT).
+// (c4 = c rounded up to 4).  EPT entries per lane (c <= EPT * NT); the rank
+// loop costs c * EPT compares per lane, so the caller picks the smallest EPT.
 template <int NT, int EPT>
-__device__ __forceinline__ void num_write_ranked(const uint32_t* keys, const double* vals,
-                                                 uint32_t c, int tid, SSP_GLOBAL int32_t* ocol,
-                                                 SSP_GLOBAL double* oval, int64_t dst)
+__device__ __forceinline__ void num_write_ranked_n(const uint32_t* keys, const double* vals,
+                                                   uint32_t c, int tid, SSP_GLOBAL int32_t* ocol,
+                                                   SSP_GLOBAL double* oval, int64_t dst)
 {
     const uint32_t c4 = (c + 3u) & ~3u;
     uint32_t key[EPT], rank[EPT];
@@ -293,6 +294,21 @@ __device__ __forceinline__ void num_write_ranked(const uint32_t* keys, const dou
             oval[dst + rank[u]] = vals[e];
         }
     }
+}
+
+// The same with the entries per lane chosen from c (uniform over the team):
+// 1, 2, then EPT_MAX.
+template <int NT, int EPT_MAX>
+__device__ __forceinline__ void num_write_ranked(const uint32_t* keys, const double* vals,
+                                                 uint32_t c, int tid, SSP_GLOBAL int32_t* ocol,
+                                                 SSP_GLOBAL double* oval, int64_t dst)
+{
+    if (c <= (uint32_t)NT)
+        num_write_ranked_n<NT, 1>(keys, vals, c, tid, ocol, oval, dst);
+    else if (EPT_MAX > 2 && c <= 2u * NT)
+        num_write_ranked_n<NT, (EPT_MAX > 2 ? 2 : EPT_MAX)>(keys, vals, c, tid, ocol, oval, dst);
+    else
+        num_write_ranked_n<NT, EPT_MAX>(keys, vals, c, tid, ocol, oval, dst);
 }
 
 // Rows whose table has at most kNumWaveSlots slots: one wave per row,
