@@ -205,6 +205,36 @@ __device__ __forceinline__ void append_small_bins(int b, int32_t row, uint64_t r
     }
 }
 
+// The same over a whole workgroup of NT threads (every thread calls it): the
+// three bins' counts are scanned in one pass (21-bit fields of one 64-bit
+// value) and each bin's counter takes one atomic for the workgroup, from
+// lanes 1..3 in parallel.  `sm` needs NT/64 entries, `s_base` 4.
+template <int NT>
+__device__ __forceinline__ void block_append_small_bins(int b, int32_t row, uint64_t rf, int32_t ci,
+                                                        Ctl* ctl, const BinLists& L, uint64_t* sm,
+                                                        uint32_t* s_base)
+{
+    const uint64_t flag = b == 1 ? 1ull : b == 2 ? (1ull << 21) : b == 3 ? (1ull << 42) : 0ull;
+    uint64_t tot;
+    const uint64_t pre = block_excl_scan<NT, uint64_t>(flag, sm, &tot);
+    const int t = threadIdx.x;
+    if (t >= 1 && t <= 3) {
+        const uint32_t n = (uint32_t)((tot >> (21 * (t - 1))) & 0x1FFFFFu);
+        s_base[t] = n ? atomicAdd(&ctl->bin_cnt[t], n) : 0u;
+    }
+    __syncthreads();
+    if (b >= 1 && b <= 3) {
+        BinItem it;
+        it.row = row;
+        it.rf = (uint32_t)rf;
+        it.cs = ci;
+        it.pad = 0;
+        const uint32_t pos = s_base[b] + (uint32_t)((pre >> (21 * (b - 1))) & 0x1FFFFFu);
+        (b == 1 ? L.b1 : b == 2 ? L.b2 : L.b3)[pos] = it;
+    }
+    __syncthreads();  // (s_base is rewritten by the next call)
+}
+
 // One row, appended by a single lane.
 __device__ inline void append_row(int32_t row, uint64_t rf, int32_t e0, int32_t e1, int32_t ci,
                                   const CaseDesc& cd, Ctl* ctl, const BinLists& L)
@@ -1423,6 +1453,7 @@ void k_flop(const CaseDesc* __restrict__ cs,
     __shared__ uint32_t s_x[CH];
     __shared__ uint64_t s_pre0[NT], s_pre1[NT];
     __shared__ uint64_t s_w[2 * (NT / kWave)];
+    __shared__ uint32_t s_base[4];  // (binning: the bins' offsets of a round of rows)
 
     const int t = threadIdx.x, lane = lane_id(), wid = t / kWave;
     const int64_t G = gridDim.x;
@@ -1551,7 +1582,8 @@ void k_flop(const CaseDesc* __restrict__ cs,
             if (MODE == FLOP_EXACT_BIN) {
                 const CaseDesc& cd = cs[cur.c];
                 const int bn_ = emit ? bin_route(sum, cd) : 0;
-                append_small_bins(bn_, (int32_t)r, sum, cur.c, ctl, L);
+                // (s_w is free here: the tile's scans are done)
+                block_append_small_bins<NT>(bn_, (int32_t)r, sum, cur.c, ctl, L, s_w, s_base);
                 if (emit && (bn_ == 0 || bn_ == 4)) cur.out[r] = 0;
                 if (emit && bn_ == 4)
                     append_big((int32_t)r, sum, s_bnd[k], s_bnd[k + 1], cur.c, cd, ctl, L);
@@ -1589,6 +1621,9 @@ __global__ __launch_bounds__(256) void k_flop_fixup(const CaseDesc* __restrict__
     const int64_t g_first = (int64_t)blockIdx.x * 256;
     const int c0 = tile_case[g_first];  // (the grid covers ntiles_all, so g_first is a tile)
     uint64_t F = 0;
+    int bin = 0;  // (binning: a small-bin row that ends here, appended by the whole wave)
+    int32_t brow = 0, bcase = 0;
+    uint64_t brf = 0;
     if (g < ntiles_all) {
         const int c = tile_case[g];
         const CaseDesc& cd = cs[c];
@@ -1606,12 +1641,24 @@ __global__ __launch_bounds__(256) void k_flop_fixup(const CaseDesc* __restrict__
                     total += meta[bb].head;
                     if (tile_end_row(cs, tile_row, tile_case, ntiles_all, bb) > i1) break;
                 }
-                emit_row<MODE>(cs, c, i1, total, ctl, L);
+                if (MODE == FLOP_ONLY) {
+                    emit_row<MODE>(cs, c, i1, total, ctl, L);
+                } else {
+                    const int b = bin_route(total, cd);
+                    if (b == 0 || b == 4) cd.out[i1] = 0;
+                    if (b == 4)
+                        append_big((int32_t)i1, total, cd.A.rpt[i1], cd.A.rpt[i1 + 1], c, cd, ctl, L);
+                    bin = b == 4 ? 0 : b;
+                    brow = (int32_t)i1;
+                    bcase = c;
+                    brf = total;
+                }
             }
         }
         if (c == c0) F = meta[g].fsum;
         else if (meta[g].fsum) atomicAdd(as_ull(&cd.st->total_flop), (ull)meta[g].fsum);
     }
+    if (MODE != FLOP_ONLY) append_small_bins(bin, brow, brf, bcase, ctl, L);  // (every lane)
     const uint64_t Fs = block_sum<256, uint64_t>(F, s_red);
     if (threadIdx.x == 0 && Fs) atomicAdd(as_ull(&cs[c0].st->total_flop), (ull)Fs);
 }
