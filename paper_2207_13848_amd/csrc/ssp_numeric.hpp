@@ -886,6 +886,203 @@ __global__ __launch_bounds__(kNumCopyRows) void k_num_copy(NumArgs na)
     }
 }
 
+// ------------------------------------------- dense rows by column windows
+
+// Rows of more than kNumBin3Max products when every row of B lists its
+// columns in non-decreasing order (checked on the device per call): each row
+// is accumulated one window of kNumWinCols columns at a time, entirely in LDS
+// (a dense float64 window and its bitmap), with no global atomics.  A cursor
+// per A entry of the row (its next position in the named B row, and that
+// position's column) lives in global scratch between windows, so every
+// product is read once: in a window an entry whose cursor column lies beyond
+// the window is skipped, the others find their end in the window by
+// exponential search.  Window by window the set bits are ranked (popcount
+// scan) and the row's entries written in column order; the first pass writes
+// only what fits the row's slot (a row that turns out not to fit is redone by
+// the fallback pass anyway) and records the exact count.
+constexpr int kNumWinCols = 16384;
+
+// agg[5] != 0 when some row of B has a column smaller than its predecessor.
+__global__ __launch_bounds__(256) void k_num_check_sorted(Csr B, NumArgs na)
+{
+    const int lane = lane_id();
+    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kWave;
+    const int64_t nwaves = (int64_t)gridDim.x * 256 / kWave;
+    bool bad = false;
+    for (int64_t r = wave; r < B.nrows; r += nwaves) {
+        const int32_t b0 = B.rpt[r], b1 = B.rpt[r + 1];
+        for (int32_t q = b0 + lane; q + 1 < b1; q += kWave) bad = bad || (B.col[q] > B.col[q + 1]);
+    }
+    if (__ballot(bad) && lane == 0) atomicOr((unsigned long long*)&na.agg[5], 1ull);
+}
+
+// agg[4] = the largest number of A entries of a bin-4 row.
+__global__ __launch_bounds__(256) void k_num_maxlen(const BigItem* __restrict__ items, Ctl* ctl,
+                                                    uint32_t cap4, NumArgs na)
+{
+    const uint32_t nheavy = ctl->bin_cnt[4], total = nheavy + ctl->bin_cnt[6];
+    uint64_t m = 0;
+    for (uint32_t k = blockIdx.x * 256 + threadIdx.x; k < total; k += gridDim.x * 256) {
+        const BigItem it = items[big_index(k, nheavy, cap4)];
+        const uint64_t len = (uint64_t)(it.e_hi - it.e_lo);
+        m = len > m ? len : m;
+    }
+    // (a wave maximum, then one atomic per wave)
+    for (int off = 32; off > 0; off >>= 1) {
+        const uint64_t o = __shfl_down(m, off, kWave);
+        m = o > m ? o : m;
+    }
+    if (lane_id() == 0 && m) atomicMax((unsigned long long*)&na.agg[4], (unsigned long long)m);
+}
+
+template <int PASS>
+__global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc* __restrict__ cs,
+                                                                 const BigItem* __restrict__ items,
+                                                                 Ctl* ctl, uint32_t cap4, NumArgs na,
+                                                                 int2* __restrict__ cursors,
+                                                                 int64_t cur_stride)
+{
+    constexpr int TEAM = kNumDenseTeam, WW = kNumWinCols / 32;
+    extern __shared__ __align__(16) double s_acc[];  // kNumWinCols values
+    __shared__ uint32_t s_flag[WW];
+    __shared__ int32_t s_b0[TEAM];
+    __shared__ uint32_t s_off[TEAM];
+    __shared__ double s_a[TEAM];
+    __shared__ uint64_t s_red[TEAM / kWave + 1];
+    __shared__ uint32_t s_k;
+    const int t = threadIdx.x;
+    const uint32_t nheavy = ctl->bin_cnt[4], total = nheavy + ctl->bin_cnt[6];
+    uint32_t* next = &ctl->num_next[PASS - 1];
+    const Csr A = cs[0].A, B = cs[0].B;
+    const int64_t N = B.ncols;
+    int2* cur = cursors + (int64_t)blockIdx.x * cur_stride;  // (position, its column) per A entry
+    for (int i = t; i < kNumWinCols; i += TEAM) s_acc[i] = 0.0;
+    for (int i = t; i < WW; i += TEAM) s_flag[i] = 0u;
+    for (;;) {
+        if (t == 0) s_k = atomicAdd(next, 1u);
+        __syncthreads();
+        const uint32_t k = s_k;
+        if (k >= total) break;
+        const BigItem item = items[big_index(k, nheavy, cap4)];
+        const int64_t row = item.row;
+        if (PASS == 2 && num_fits(na, row, na.cnt[row])) {
+            __syncthreads();  // (s_k is rewritten)
+            continue;
+        }
+        const int32_t a0 = item.e_lo, a1 = item.e_hi;
+        // cursors at the start of every named B row
+        for (int32_t e = a0 + t; e < a1; e += TEAM) {
+            const int32_t kk = A.col[e];
+            const int32_t p = B.rpt[kk], pe = B.rpt[kk + 1];
+            cur[e - a0] = make_int2(p, p < pe ? B.col[p] : INT32_MAX);
+        }
+        __threadfence_block();
+        __syncthreads();
+        int64_t dst, cap;
+        if (PASS == 1) {
+            dst = na.slot_off[row];
+            cap = na.slot_off[row + 1] - dst;
+        } else {
+            dst = na.C_rpt[row];
+            cap = na.cnt[row];
+        }
+        SSP_GLOBAL int32_t* ocol = PASS == 1 ? na.slot_col : na.C_col;
+        SSP_GLOBAL double* oval = PASS == 1 ? na.slot_val : na.C_val;
+        int64_t c_total = 0;
+        for (int64_t lo = 0; lo < N; lo += kNumWinCols) {
+            const int64_t hi = (lo + kNumWinCols) < N ? (lo + kNumWinCols) : N;
+            uint32_t any = 0;
+            for (int32_t a = a0; a < a1; a += TEAM) {
+                const int32_t e = a + t;
+                uint32_t len = 0;
+                int32_t p = 0;
+                double av = 0.0;
+                if (e < a1) {
+                    const int2 c = cur[e - a0];
+                    p = c.x;
+                    if ((int64_t)c.y < hi) {  // (INT32_MAX: the B row is used up)
+                        const int32_t pe = B.rpt[A.col[e] + 1];
+                        // first position in (p, pe) whose column is >= hi, by
+                        // exponential then binary search (columns non-decreasing)
+                        int32_t good = p, step = 1;
+                        while (good + step < pe && (int64_t)B.col[good + step] < hi) {
+                            good += step;
+                            step <<= 1;
+                        }
+                        int32_t bad = (good + step) < pe ? (good + step) : pe;
+                        while (bad - good > 1) {
+                            const int32_t mid = (good + bad) >> 1;
+                            if ((int64_t)B.col[mid] < hi) good = mid;
+                            else bad = mid;
+                        }
+                        len = (uint32_t)(bad - p);
+                        cur[e - a0] = make_int2(bad, bad < pe ? B.col[bad] : INT32_MAX);
+                        av = na.Aval[e];
+                    }
+                }
+                uint32_t tot;
+                const uint32_t off = block_excl_scan<TEAM, uint32_t>(len, (uint32_t*)s_red, &tot);
+                s_b0[t] = p;
+                s_off[t] = off;
+                s_a[t] = av;
+                __syncthreads();
+                any |= tot;
+                const int nent = (a1 - a) < TEAM ? (a1 - a) : TEAM;
+                for (uint32_t p0 = 0; p0 < tot; p0 += TEAM * kNumUnroll) {
+                    uint32_t colv[kNumUnroll];
+                    double vv[kNumUnroll];
+#pragma unroll
+                    for (int u = 0; u < kNumUnroll; ++u) {
+                        const uint32_t pr = p0 + (uint32_t)(u * TEAM + t);
+                        const uint32_t pp = pr < tot ? pr : tot - 1;
+                        int lo2 = 0, hi2 = nent;
+                        while (hi2 - lo2 > 1) {
+                            const int mid = (lo2 + hi2) >> 1;
+                            if (s_off[mid] <= pp) lo2 = mid;
+                            else hi2 = mid;
+                        }
+                        const int32_t q = s_b0[lo2] + (int32_t)(pp - s_off[lo2]);
+                        colv[u] = (uint32_t)B.col[q];
+                        vv[u] = s_a[lo2] * na.Bval[q];
+                    }
+#pragma unroll
+                    for (int u = 0; u < kNumUnroll; ++u) {
+                        if (p0 + (uint32_t)(u * TEAM + t) >= tot) continue;
+                        const uint32_t x = colv[u] - (uint32_t)lo;  // (in [0, kNumWinCols))
+                        __hip_atomic_fetch_add(&s_acc[x], vv[u], __ATOMIC_RELAXED,
+                                               __HIP_MEMORY_SCOPE_WORKGROUP);
+                        atomicOr(&s_flag[x >> 5], 1u << (x & 31u));
+                    }
+                }
+                __syncthreads();
+            }
+            if (!any) continue;  // (uniform: no product of the row in this window)
+            // the window's entries in column order, then cleared
+            const uint32_t bits = t < WW ? s_flag[t] : 0u;
+            uint64_t wtot;
+            const uint64_t ex = block_excl_scan<TEAM, uint64_t>((uint64_t)__popc(bits), s_red, &wtot);
+            int64_t o = c_total + (int64_t)ex;
+            uint32_t bb = bits;
+            while (bb) {
+                const uint32_t b = (uint32_t)__builtin_ctz(bb);
+                bb &= bb - 1u;
+                const uint32_t x = (uint32_t)t * 32u + b;
+                if (o < cap) {
+                    ocol[dst + o] = (int32_t)(lo + x);
+                    oval[dst + o] = s_acc[x];
+                }
+                s_acc[x] = 0.0;
+                ++o;
+            }
+            if (t < WW) s_flag[t] = 0u;
+            c_total += (int64_t)wtot;
+            __syncthreads();
+        }
+        if (PASS == 1 && t == 0) na.cnt[row] = c_total;
+        __syncthreads();
+    }
+}
+
 // Sets n doubles (and the words after them) to zero: the dense accumulators
 // when they are first allocated.
 __global__ void k_num_zero(uint64_t* p, int64_t n)

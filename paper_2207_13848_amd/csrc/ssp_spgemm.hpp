@@ -15,6 +15,9 @@ struct NumState {
     uint32_t bins[4] = {0, 0, 0, 0};  // items in bins 1..3 and bin 4
     int32_t dense_grid = 0;
     BinItem* abort_list = nullptr;    // rows whose first-pass table filled up
+    bool win = false;                 // long rows by LDS column windows (B's rows sorted)
+    int2* cursors = nullptr;          // their per-entry cursors (pool memory)
+    int64_t cur_stride = 0;
     ssp_spgemm_info info{};
 };
 
@@ -71,6 +74,11 @@ void prepare_num_kernels()
 {
     static std::once_flag once;
     std::call_once(once, [] {
+        const int wbytes = (int)(kNumWinCols * sizeof(double));
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_num_dense_win<1>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, wbytes);
+        (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_num_dense_win<2>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, wbytes);
         const int bytes = (int)(kNumLdsMaskWords * sizeof(uint32_t));
         (void)hipFuncSetAttribute(reinterpret_cast<const void*>(&k_num_dense<1, true>),
                                   hipFuncAttributeMaxDynamicSharedMemorySize, bytes);
@@ -116,7 +124,11 @@ void launch_num_rows(ssp_handle h, const NumState& S, hipStream_t s)
     }
     if (S.bins[3] && S.dense_grid > 0) {
         PhaseTimer pt(h, PASS == 1 ? PH_NUM_DENSE : PH_NUM_FALLBACK, s);
-        if (S.na.mask_words <= kNumLdsMaskWords)
+        if (S.win)
+            hipLaunchKernelGGL((k_num_dense_win<PASS>), dim3((unsigned)S.dense_grid), dim3(kNumDenseTeam),
+                               (size_t)kNumWinCols * sizeof(double), s, cs, (const BigItem*)S.b.L.b4,
+                               ctl, S.b.L.cap4, S.na, S.cursors, S.cur_stride);
+        else if (S.na.mask_words <= kNumLdsMaskWords)
             hipLaunchKernelGGL((k_num_dense<PASS, true>), dim3((unsigned)S.dense_grid),
                                dim3(kNumDenseTeam), (size_t)S.na.mask_words * sizeof(uint32_t), s, cs,
                                (const BigItem*)S.b.L.b4, ctl, S.b.L.cap4, S.na);
@@ -181,10 +193,17 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     // 1. row FLOP and bins (Alg. 1), slot sizes and their offsets
     launch_setup(h, P, S->b, s, false, true);
     SSP_LAUNCHED(h);
+    hipLaunchKernelGGL(k_num_zero, dim3(1), dim3(64), 0, s, (uint64_t*)na.agg, (int64_t)8);
     launch_flop<FLOP_EXACT_BIN>(h, P, S->b, s, true);
     {
         PhaseTimer pt(h, PH_NUM_SCAN, s);
         launch_num_scan(na, 0, cus, s);
+        // (for the long rows: whether B's rows are sorted, their longest A row)
+        if (B->nrows > 0 && B->nnz > 0)
+            hipLaunchKernelGGL(k_num_check_sorted, dim3((unsigned)std::min<int64_t>((B->nrows + 3) / 4, 8LL * cus)),
+                               dim3(256), 0, s, P.cs[0].B, na);
+        hipLaunchKernelGGL(k_num_maxlen, dim3((unsigned)(2 * cus)), dim3(256), 0, s,
+                           (const BigItem*)S->b.L.b4, S->b.ctl, S->b.L.cap4, na);
     }
     SSP_LAUNCHED(h);
     SSP_HIP(h, hipStreamSynchronize(s));
@@ -203,7 +222,18 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     if ((st = grow_buffer(h, &h->num_slots, &h->num_slots_bytes, slot_bytes, true)) != SSP_OK) return st;
     na.slot_val = (decltype(na.slot_val))h->num_slots;
     na.slot_col = (decltype(na.slot_col))((char*)h->num_slots + (size_t)std::max<int64_t>(slots, 1) * sizeof(double));
-    if (S->bins[3] > 0) {
+    S->win = S->bins[3] > 0 && agg[5] == 0;
+    if (S->win) {
+        // LDS windows: no accumulators in global memory, a cursor per A entry
+        S->cur_stride = std::max<int64_t>(1, (int64_t)agg[4]);
+        const int64_t res = resident(k_num_dense_win<1>, kNumDenseTeam, cus, kNumWinCols * sizeof(double));
+        const int64_t want = std::min<int64_t>((int64_t)S->bins[3], res);
+        const size_t bytes = (size_t)(want * S->cur_stride) * sizeof(int2);
+        if ((st = grow_buffer(h, &h->num_pool, &h->num_pool_bytes, bytes, false)) != SSP_OK) return st;
+        h->num_pool_clean = false;  // (the cursors overwrite the accumulators' zeros)
+        S->cursors = reinterpret_cast<int2*>(h->num_pool);
+        S->dense_grid = (int32_t)want;
+    } else if (S->bins[3] > 0) {
         na.mask_words = ((N + 31) / 32 + 1) / 2 * 2;  // (even: whole 8-byte words)
         const int64_t per_slot = N * (int64_t)sizeof(double) + na.mask_words * (int64_t)sizeof(uint32_t);
         const int64_t res = na.mask_words <= kNumLdsMaskWords
@@ -228,10 +258,11 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
 
     // 3. the numeric pass into the slots, then C's row offsets (a launched
     //    pass leaves the accumulators zero; one that failed to launch may not)
+    const bool was_clean = h->num_pool_clean;
     h->num_pool_clean = false;
     launch_num_rows<1>(h, *S, s);
     SSP_LAUNCHED(h);
-    h->num_pool_clean = true;
+    h->num_pool_clean = S->win ? false : (S->bins[3] > 0 || was_clean);
     {
         PhaseTimer pt(h, PH_NUM_SCAN, s);
         launch_num_scan(na, 1, cus, s);
@@ -277,12 +308,14 @@ ssp_status spgemm_copy(ssp_handle h, int32_t* C_col, double* C_val, int64_t capa
     }
     SSP_LAUNCHED(h);
     if (S->info.overflow_rows > 0) {
+        const bool was_clean = h->num_pool_clean;
         h->num_pool_clean = false;
         // (the dense fallback's work queue starts at 0 on every copy call)
         SSP_HIP(h, hipMemsetAsync(&S->b.ctl->num_next[1], 0, sizeof(uint32_t), s));
         launch_num_rows<2>(h, *S, s);
         SSP_LAUNCHED(h);
-        h->num_pool_clean = true;
+        // (the accumulators kernel leaves them zero; the windows kernel keeps cursors there)
+        h->num_pool_clean = S->bins[3] > 0 ? !S->win : was_clean;
     }
     if (!h->num_ev) SSP_HIP(h, hipEventCreateWithFlags(&h->num_ev, hipEventDisableTiming));
     SSP_HIP(h, hipEventRecord(h->num_ev, s));

@@ -173,3 +173,43 @@ def test_spgemm_repeated_calls_and_capacity_error(ssp):
         _run(ssp, A, A, av, av, counts, 0, Ad=Ad, Bd=Ad, capacity=int(counts.sum()) - 1)
     # and works again afterwards
     check(ssp, A, A, av, av, counts, 0, True, "after error", Ad=Ad, Bd=Ad)
+
+
+def _shuffled_rows(M, vals, seed):
+    """The same matrix with every row's entries (and values) in random order."""
+    rng = np.random.default_rng(seed)
+    col, v = M.col.copy(), vals.copy()
+    for i in range(M.nrows):
+        a, b = int(M.rpt[i]), int(M.rpt[i + 1])
+        p = rng.permutation(b - a)
+        col[a:b], v[a:b] = col[a:b][p], v[a:b][p]
+    return workloads.CSR(M.nrows, M.ncols, M.rpt, col, M.name + "_shuffled"), v
+
+
+def _doubled_entries(M, vals):
+    """Every entry stored twice, next to itself (rows stay non-decreasing)."""
+    col = np.repeat(M.col, 2)
+    v = np.repeat(vals, 2) * 0.5
+    return workloads.CSR(M.nrows, M.ncols, (M.rpt * 2).astype(np.int32), col, M.name + "_x2"), v
+
+
+def test_spgemm_long_rows_unsorted_b(ssp):
+    # rows of B not sorted: the long rows take the global-accumulator kernel
+    A = workloads.uniform(600, 2000, 64, 5)
+    B, bv = _shuffled_rows(workloads.uniform(2000, 30000, 64, 6), _values(
+        workloads.uniform(2000, 30000, 64, 6), 2, "int"), 3)
+    av = _values(A, 1, "int")
+    counts, _ = oracle.exact(A, B)
+    check(ssp, A, B, av, bv, counts, 0, True, "dense, unsorted B")
+    check(ssp, A, B, av, bv, counts - 5, 0, True, "dense, unsorted B, overflow")
+
+
+def test_spgemm_long_rows_repeated_columns(ssp):
+    # sorted rows of B with every column twice: the column-window kernel
+    A = workloads.uniform(500, 1500, 48, 7)
+    B0 = workloads.uniform(1500, 50000, 40, 8)
+    B, bv = _doubled_entries(B0, _values(B0, 3, "int"))
+    av = _values(A, 4, "int")
+    counts, _ = oracle.exact(A, B)
+    check(ssp, A, B, av, bv, counts, 0, True, "dense, repeated columns")
+    check(ssp, A, B, av, bv, counts // 2, 0, True, "dense, repeated columns, overflow")
