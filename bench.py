@@ -491,7 +491,10 @@ def main_spgemm(args):
                               **{k: info[k] for k in ("slot_entries", "slot_bytes",
                                                        "overflow_rows", "overflow_nnz")}}}
     ex = torch.empty(M, dtype=torch.int64, device=dev)
-    for vname in ("precise", "upper_bound"):
+    # other margins on the prediction (memory against recomputed rows), the
+    # precise method and the upper bound
+    other = [m for m in (0, 30, 100) if m != margin]
+    for vname in [f"predicted_m{m}" for m in other] + ["precise", "upper_bound"]:
         for i in range(steps + 1):
             if i == 1:
                 torch.cuda.synchronize()
@@ -499,11 +502,16 @@ def main_spgemm(args):
             if vname == "precise":
                 ssp.exact_structure(Ad, Ad, handle=h, out=ex)
                 r = ssp.spgemm(Ad, tav, Ad, tav, ex, handle=h)
-            else:
+            elif vname == "upper_bound":
                 r = ssp.spgemm(Ad, tav, Ad, tav, rf_t, handle=h)
+            else:
+                ssp.predict_structure(Ad, Ad, rate, seed, handle=h, out=pred, stats=st)
+                r = ssp.spgemm(Ad, tav, Ad, tav, pred, margin_pct=int(vname.split("_m")[1]),
+                               handle=h)
         torch.cuda.synchronize()
         vi = r[3]
         variants[vname] = {"ms": round((time.perf_counter() - ta) * 1e3 / steps, 3),
+                           **({"margin_pct": int(vname.split("_m")[1])} if "_m" in vname else {}),
                            **{k: vi[k] for k in ("slot_entries", "slot_bytes", "overflow_rows",
                                                  "overflow_nnz")}}
         assert vi["nnz"] == info["nnz"]
