@@ -213,3 +213,29 @@ def test_spgemm_long_rows_repeated_columns(ssp):
     counts, _ = oracle.exact(A, B)
     check(ssp, A, B, av, bv, counts, 0, True, "dense, repeated columns")
     check(ssp, A, B, av, bv, counts // 2, 0, True, "dense, repeated columns, overflow")
+
+
+def test_spgemm_large_tables_team_kernels(ssp):
+    # rows of 1024..2048 products with over a thousand distinct columns: tables of
+    # 4096 slots (the 512-thread kernel) and of 2048 (the 256-thread kernel)
+    A = workloads.uniform(3000, 3000, 40, 11)
+    av = _values(A, 6, "int")
+    counts, _ = oracle.exact(A, A)
+    assert counts.min() > 700
+    check(ssp, A, A, av, av, counts, 0, True, "bin 3, 4096-slot tables")
+    B = workloads.uniform(3000, 3000, 20, 12)
+    bv = _values(B, 7, "int")
+    counts2, _ = oracle.exact(A, B)
+    check(ssp, A, B, av, bv, counts2, 0, True, "bin 2, 2048-slot tables")
+    check(ssp, A, B, av, bv, counts2 // 2, 0, True, "bin 2, overflow")
+
+
+def test_spgemm_long_rows_unsorted_wide_b(ssp):
+    # unsorted B wider than 2^19 columns: the accumulators' bitmap in global memory
+    A = workloads.uniform(300, 2000, 64, 13)
+    B0 = workloads.uniform(2000, 600000, 64, 14)
+    B, bv = _shuffled_rows(B0, _values(B0, 8, "int"), 5)
+    av = _values(A, 9, "int")
+    counts, _ = oracle.exact(A, B)
+    check(ssp, A, B, av, bv, counts, 0, True, "dense, unsorted B, N = 600000")
+    check(ssp, A, B, av, bv, counts - 7, 0, True, "dense, unsorted B, N = 600000, overflow")
