@@ -761,31 +761,46 @@ __device__ __forceinline__ uint32_t hash_insert(uint32_t* tab, uint32_t c, int l
     }
 }
 
-// Bins 1..3: one workgroup of TEAM threads per row.  The row's products are
-// enumerated chunk by chunk of TEAM entries of A: a scan of the B row lengths
-// gives each product's owner, found by binary search in LDS, so every thread
-// handles an equal share of products whatever the B row lengths.  Counting
-// uses an LDS bitmap of all N columns when that is no larger than the hash
-// table, else the hash table (size >= 2 x the row's distinct bound).
+// Orders the LDS accesses of one wave (the LDS serves a wave's accesses in
+// order; this keeps the compiler from moving them across).
+__device__ __forceinline__ void wave_sync()
+{
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+// Synchronisation of a team: the workgroup, or its own wave for TEAM = 64.
+template <int TEAM>
+__device__ __forceinline__ void team_sync()
+{
+    if (TEAM == kWave) wave_sync();
+    else __syncthreads();
+}
+
+// Bins 1..3: one team of TEAM threads per row (a workgroup, or one wave of
+// one).  The row's products are enumerated chunk by chunk of TEAM entries of
+// A: a scan of the B row lengths gives each product's owner, found by binary
+// search in LDS, so every thread handles an equal share of products whatever
+// the B row lengths.  Counting uses an LDS bitmap of all N columns when that
+// is no larger than the hash table, else the hash table (size >= 2 x the
+// row's distinct bound).  The team takes items first, first + stride, ...;
+// `t` is its thread's index in the team, `slot` its distinct-count slot.
 // MODE 0: add the count to the case's z*.  MODE 1: write it to out[row]
 // (and to the case's total).
 template <int TEAM, int WORDS, int MODE>
-__global__ __launch_bounds__(TEAM) void k_sym(const CaseDesc* __restrict__ cs,
-                                             const BinItem* __restrict__ items,
-                                             const uint32_t* count, CaseRes* __restrict__ cr)
+__device__ __forceinline__ void sym_rows(const CaseDesc* __restrict__ cs,
+                                         const BinItem* __restrict__ items, uint32_t n,
+                                         uint32_t first, uint32_t stride, int t, uint32_t* tab,
+                                         int32_t* s_b0, uint32_t* s_off, uint32_t* s_red,
+                                         CaseRes* __restrict__ cr, uint32_t slot)
 {
-    __shared__ uint32_t tab[WORDS];
-    __shared__ int32_t s_b0[TEAM];
-    __shared__ uint32_t s_off[TEAM];
-    __shared__ uint32_t s_red[TEAM / kWave + 1];
-    const uint32_t n = *count;
-    const int t = threadIdx.x;
     int zc = -1;  // case of zsum (items of a case are consecutive in the list)
     uint64_t zsum = 0;
-    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
+    for (uint32_t it = first; it < n; it += stride) {
         const BinItem item = items[it];
         if (item.cs != zc) {
-            if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
+            if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[slot]), (ull)zsum);
             zsum = 0;
             zc = item.cs;
         }
@@ -800,7 +815,7 @@ __global__ __launch_bounds__(TEAM) void k_sym(const CaseDesc* __restrict__ cs,
         const int lg = __builtin_ctz(tsize);
         const uint32_t fill = bitmap ? 0u : kEmpty;
         for (uint32_t w = t; w < words; w += TEAM) tab[w] = fill;
-        __syncthreads();
+        team_sync<TEAM>();
         uint32_t cnt = 0;
         const int32_t a0 = A.rpt[item.row], a1 = A.rpt[item.row + 1];
         for (int32_t a = a0; a < a1; a += TEAM) {
@@ -816,7 +831,7 @@ __global__ __launch_bounds__(TEAM) void k_sym(const CaseDesc* __restrict__ cs,
             const uint32_t off = block_excl_scan<TEAM, uint32_t>(len, s_red, &tot);
             s_b0[t] = b0;
             s_off[t] = off;
-            __syncthreads();
+            team_sync<TEAM>();
             const int na = (a1 - a) < TEAM ? (a1 - a) : TEAM;
             constexpr int U = 4;
             // same trip count in every lane; U independent loads in flight per lane
@@ -844,7 +859,7 @@ __global__ __launch_bounds__(TEAM) void k_sym(const CaseDesc* __restrict__ cs,
                         cnt += hash_insert(tab, c[u], lg);
                 }
             }
-            __syncthreads();
+            team_sync<TEAM>();
         }
         if (bitmap)
             for (uint32_t w = t; w < words; w += TEAM) cnt += (uint32_t)__popc(tab[w]);
@@ -853,9 +868,56 @@ __global__ __launch_bounds__(TEAM) void k_sym(const CaseDesc* __restrict__ cs,
             zsum += total;
             if (MODE == 1) cs[zc].out[item.row] = (int64_t)total;
         }
-        __syncthreads();
+        team_sync<TEAM>();
     }
-    if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[blockIdx.x % kAccSlots]), (ull)zsum);
+    if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[slot]), (ull)zsum);
+}
+
+template <int TEAM, int WORDS, int MODE>
+__global__ __launch_bounds__(TEAM) void k_sym(const CaseDesc* __restrict__ cs,
+                                             const BinItem* __restrict__ items,
+                                             const uint32_t* count, CaseRes* __restrict__ cr)
+{
+    __shared__ uint32_t tab[WORDS];
+    __shared__ int32_t s_b0[TEAM];
+    __shared__ uint32_t s_off[TEAM];
+    __shared__ uint32_t s_red[TEAM / kWave + 1];
+    sym_rows<TEAM, WORDS, MODE>(cs, items, *count, blockIdx.x, gridDim.x, threadIdx.x, tab, s_b0,
+                                s_off, s_red, cr, blockIdx.x % kAccSlots);
+}
+
+// Bins 1 and 2 in one launch of 256-thread workgroups: the first g1 take
+// bin-1 rows four at a time (one per wave), the others bin-2 rows (a
+// workgroup per row), so the two bins' latency chains overlap.
+constexpr int kBins12Threads = 256;
+
+template <int MODE>
+__global__ __launch_bounds__(kBins12Threads) void k_sym_bins12(const CaseDesc* __restrict__ cs,
+                                                              const BinItem* __restrict__ b1,
+                                                              const uint32_t* n1,
+                                                              const BinItem* __restrict__ b2,
+                                                              const uint32_t* n2, uint32_t g1,
+                                                              CaseRes* __restrict__ cr)
+{
+    constexpr int NW = kBins12Threads / kWave;
+    constexpr int W1 = kBin1Words + 2 * kWave + 2;  // per wave: table, owners, offsets, scan
+    constexpr int W2 = kBin2Words + 2 * kBins12Threads + NW + 1;
+    constexpr int WORDS = NW * W1 > W2 ? NW * W1 : W2;
+    __shared__ uint32_t sm[WORDS];
+    const int t = threadIdx.x, lane = lane_id();
+    const int w = __builtin_amdgcn_readfirstlane(t / kWave);
+    const uint32_t slot = blockIdx.x % kAccSlots;
+    if (blockIdx.x < g1) {
+        uint32_t* base = sm + w * W1;
+        sym_rows<kWave, kBin1Words, MODE>(cs, b1, *n1, blockIdx.x * NW + w, g1 * NW, lane, base,
+                                          (int32_t*)(base + kBin1Words), base + kBin1Words + kWave,
+                                          base + kBin1Words + 2 * kWave, cr, slot);
+    } else {
+        sym_rows<kBins12Threads, kBin2Words, MODE>(cs, b2, *n2, blockIdx.x - g1, gridDim.x - g1, t, sm,
+                                                   (int32_t*)(sm + kBin2Words),
+                                                   sm + kBin2Words + kBins12Threads,
+                                                   sm + kBin2Words + 2 * kBins12Threads, cr, slot);
+    }
 }
 
 // Bin 4: long rows, 1024 threads per item, an LDS bitmap per window of

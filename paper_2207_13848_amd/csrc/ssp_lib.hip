@@ -585,17 +585,26 @@ void launch_symbolic(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
         // bins 1..3: a grid of the resident capacity (more rows in flight hide
         // the latency of each row's chain of loads)
         PhaseTimer pt(h, PH_SYM_BINS, s, timed);
-        hipLaunchKernelGGL((k_sym<kBin1Team, kBin1Words, MODE>),
-                           dim3(grid_for(nitems, resident(k_sym<kBin1Team, kBin1Words, MODE>, kBin1Team, cus))),
-                           dim3(kBin1Team), 0, s, b.cs, b.L.b1, &b.ctl->bin_cnt[1], b.cr);
-        if (P.bin2_wave)
+        if (P.bin2_wave) {
+            hipLaunchKernelGGL((k_sym<kBin1Team, kBin1Words, MODE>),
+                               dim3(grid_for(nitems, resident(k_sym<kBin1Team, kBin1Words, MODE>, kBin1Team, cus))),
+                               dim3(kBin1Team), 0, s, b.cs, b.L.b1, &b.ctl->bin_cnt[1], b.cr);
             hipLaunchKernelGGL((k_sym<kWave, kBin2Words, MODE>),
                                dim3(grid_for(nitems, resident(k_sym<kWave, kBin2Words, MODE>, kWave, cus))),
                                dim3(kWave), 0, s, b.cs, b.L.b2, &b.ctl->bin_cnt[2], b.cr);
-        else
-            hipLaunchKernelGGL((k_sym<kBin2Team, kBin2Words, MODE>),
-                               dim3(grid_for(nitems, resident(k_sym<kBin2Team, kBin2Words, MODE>, kBin2Team, cus))),
-                               dim3(kBin2Team), 0, s, b.cs, b.L.b2, &b.ctl->bin_cnt[2], b.cr);
+        } else {
+            // bins 1 and 2 in one launch (few rows: the two latency chains
+            // overlap), half the resident workgroups each
+            const int64_t half =
+                std::max<int64_t>(1, resident(k_sym_bins12<MODE>, kBins12Threads, cus) / 2);
+            const int64_t nw = kBins12Threads / kWave;
+            const int64_t g1 = std::max<int64_t>(1, std::min<int64_t>((nitems + nw - 1) / nw, half));
+            const int64_t g2 = std::max<int64_t>(1, std::min<int64_t>(nitems, half));
+            hipLaunchKernelGGL((k_sym_bins12<MODE>), dim3((unsigned)(g1 + g2)), dim3(kBins12Threads), 0,
+                               s, b.cs, (const BinItem*)b.L.b1, (const uint32_t*)&b.ctl->bin_cnt[1],
+                               (const BinItem*)b.L.b2, (const uint32_t*)&b.ctl->bin_cnt[2],
+                               (uint32_t)g1, b.cr);
+        }
         // (bin 3 stays empty when every case sends its rows to the long-row kernel)
         bool bin3 = false;
         for (int c = 0; c < P.n; ++c) bin3 = bin3 || !P.cs[c].big3;

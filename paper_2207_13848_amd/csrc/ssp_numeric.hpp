@@ -234,15 +234,6 @@ __device__ __forceinline__ bool num_hash_add(uint32_t* keys, double* vals, uint3
     return false;
 }
 
-// Orders the LDS accesses of one wave (the LDS serves a wave's accesses in
-// order; this keeps the compiler from moving them across).
-__device__ __forceinline__ void wave_sync()
-{
-    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-    __builtin_amdgcn_wave_barrier();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-}
-
 // Item k of the hash bins 1..3 taken as one list.
 __device__ __forceinline__ BinItem num_hash_item(const BinLists& L, const uint32_t* cnt, uint32_t k)
 {
