@@ -114,6 +114,25 @@ __device__ __forceinline__ uint64_t ceil_mul_div(uint64_t a, uint64_t b, const D
     return q + (r != 0);
 }
 
+// The same ceiling from a double-precision estimate corrected in integers, for
+// a < 2^48 and b <= d < 2^62, with r = (double)b / (double)d.  a is exact as a
+// double, and the rounding of b, d, r and a r (each within 2^-53 relative)
+// leaves the estimate within 2^48 * 2^-51 = 1/8 of a b / d, so q0 = floor of
+// the estimate has a b - q0 d in [-d/8, 9d/8): that remainder, taken modulo
+// 2^64, is exact as a signed 64-bit value and places a b / d in (q0 - 1, q0),
+// [q0, q0 + 1) or [q0 + 1, q0 + 2).  Six 32-bit multiplies against fifteen.
+constexpr uint64_t kEstMaxA = 1ull << 48;
+constexpr uint64_t kEstMaxD = 1ull << 62;
+
+__device__ __forceinline__ uint64_t ceil_mul_div_est(uint64_t a, uint64_t b, uint64_t d, double r)
+{
+    const uint64_t q0 = (uint64_t)((double)a * r);  // truncation = floor (non-negative)
+    const int64_t R = (int64_t)(a * b - q0 * d);
+    if (R < 0) return q0;
+    if ((uint64_t)R < d) return q0 + (R != 0);
+    return q0 + 1 + ((uint64_t)R != d);
+}
+
 __device__ __forceinline__ bool u128_lt(u128 a, u128 b)
 {
     return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
@@ -300,6 +319,31 @@ __device__ __forceinline__ void block_excl_scan2(T a, T b, T* sm, T* ea, T* eb, 
     *eb = (wid > 0 ? lane_value(xb, wid - 1) : T(0)) + ib - b;
     *ta = lane_value(xa, NW - 1);
     *tb = lane_value(xb, NW - 1);
+    __syncthreads();
+}
+
+// K exclusive scans over the workgroup at once, with one pair of barriers for
+// all of them.  `sm` needs K * NT/64 entries.  Ends with a barrier.
+template <int NT, int K, typename T>
+__device__ __forceinline__ void block_excl_scan_n(const T (&v)[K], T* sm, T (&ex)[K], T (&total)[K])
+{
+    constexpr int NW = NT / kWave;
+    const int wid = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    T inc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) inc[k] = wave_incl_scan(v[k]);
+    if (lane_id() == kWave - 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) sm[k * NW + wid] = inc[k];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int k = 0; k < K; ++k) {
+        const T x = scan_wave_totals<NW>(sm + k * NW);
+        const T pre = wid > 0 ? lane_value(x, wid - 1) : T(0);
+        total[k] = lane_value(x, NW - 1);
+        ex[k] = pre + inc[k] - v[k];
+    }
     __syncthreads();
 }
 

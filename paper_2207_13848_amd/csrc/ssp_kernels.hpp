@@ -549,57 +549,85 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc*
 // offsets of every group in every list at that level, the split decision (a
 // group's eligible rows are split when all part windows requested up to and
 // including the group fit the scratch), the list sizes, and per case n_s, f*
-// and the sample's A entries (one atomic per case and chunk of groups).
-constexpr int kScanThreads = 512;
+// and the sample's A entries (one atomic per case and chunk of groups).  The
+// first chunk's records are read with the first pass, and the scans of a
+// chunk go in two rounds (the second depends on the split decision) of one
+// barrier pair each.
+constexpr int kScanThreads = 1024;
+
+struct GroupRec {  // the counts of SampleCounts (k_sample_count's output)
+    uint32_t n1, n2, n3, n4, cs;
+    uint32_t lv[kSplitLevels][4];
+    uint64_t ns, fs, as;
+};
+
+__device__ __forceinline__ GroupRec load_group(const SampleCounts* __restrict__ cnt, int64_t g,
+                                               int64_t ngroups)
+{
+    GroupRec x{};
+    if (g < ngroups) {
+        const SampleCounts& y = cnt[g];
+        x.n1 = y.n1;
+        x.n2 = y.n2;
+        x.n3 = y.n3;
+        x.n4 = y.n4;
+        x.cs = y.cs;
+#pragma unroll
+        for (int lv = 0; lv < kSplitLevels; ++lv)
+#pragma unroll
+            for (int j = 0; j < 4; ++j) x.lv[lv][j] = y.lv[lv][j];
+        x.ns = y.ns;
+        x.fs = y.fs;
+        x.as = y.as;
+    }
+    return x;
+}
 
 __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __restrict__ cnt,
                                                              int64_t ngroups,
                                                              const CaseDesc* __restrict__ cs,
                                                              Ctl* ctl, uint32_t budget)
 {
-    constexpr int NT = kScanThreads;
-    __shared__ uint64_t s_red[NT / kWave + 1];
+    constexpr int NT = kScanThreads, NW = NT / kWave;
+    __shared__ uint64_t s_red[5 * NW];
     __shared__ uint64_t s_e[3][NT];  // exclusive prefixes of ns, fs, as in the chunk
     const int t = threadIdx.x;
-    uint64_t wsum[kSplitLevels] = {};
-    for (int64_t g = t; g < ngroups; g += NT) {
+    const GroupRec r0 = load_group(cnt, t, ngroups);
+    uint64_t wsum[kSplitLevels];
+#pragma unroll
+    for (int lv = 0; lv < kSplitLevels; ++lv) wsum[lv] = r0.lv[lv][1];
+    for (int64_t g = t + NT; g < ngroups; g += NT) {
 #pragma unroll
         for (int lv = 0; lv < kSplitLevels; ++lv) wsum[lv] += cnt[g].lv[lv][1];
     }
+    uint64_t wex[kSplitLevels], wtot[kSplitLevels];
+    block_excl_scan_n<NT, kSplitLevels>(wsum, s_red, wex, wtot);
     int L = kSplitLevels - 1;
 #pragma unroll
     for (int lv = kSplitLevels - 1; lv >= 0; --lv)
-        if (block_sum<NT, uint64_t>(wsum[lv], s_red) <= (uint64_t)budget) L = lv;
+        if (uniform_u64(wtot[lv]) <= (uint64_t)budget) L = lv;
     uint64_t k01 = 0, k2w = 0, k4 = 0, km = 0;  // carries (k01, k2w, k4: two u32 fields)
     for (int64_t g0 = 0; g0 < ngroups; g0 += NT) {
         const int64_t g = g0 + t;
-        // (fields read one by one: the level index is dynamic, a struct copy
-        // indexed by it would live in scratch)
-        struct {
-            uint32_t n1, n2, n3, n4, cs;
-            uint64_t ns, fs, as;
-        } x{};
+        const GroupRec x = g0 == 0 ? r0 : load_group(cnt, g, ngroups);
+        // level L's counts (selected: the level is dynamic, an indexed
+        // register array would live in scratch)
         uint32_t items = 0, wins = 0, ne = 0, nh = 0;
-        if (g < ngroups) {
-            const SampleCounts& y = cnt[g];
-            x.n1 = y.n1;
-            x.n2 = y.n2;
-            x.n3 = y.n3;
-            x.n4 = y.n4;
-            x.cs = y.cs;
-            x.ns = y.ns;
-            x.fs = y.fs;
-            x.as = y.as;
-            items = y.lv[L][0];
-            wins = y.lv[L][1];
-            ne = y.lv[L][2];
-            nh = y.lv[L][3];
+#pragma unroll
+        for (int lv = 0; lv < kSplitLevels; ++lv) {
+            if (lv == L) {
+                items = x.lv[lv][0];
+                wins = x.lv[lv][1];
+                ne = x.lv[lv][2];
+                nh = x.lv[lv][3];
+            }
         }
-        uint64_t t01, t2w, tns, tfs, tas;
-        const uint64_t p01 = k01 + block_excl_scan<NT, uint64_t>(
-                                       (uint64_t)x.n1 | ((uint64_t)x.n2 << 32), s_red, &t01);
-        const uint64_t p2w = k2w + block_excl_scan<NT, uint64_t>(
-                                       (uint64_t)x.n3 | ((uint64_t)wins << 32), s_red, &t2w);
+        const uint64_t va[5] = {(uint64_t)x.n1 | ((uint64_t)x.n2 << 32),
+                                (uint64_t)x.n3 | ((uint64_t)wins << 32), x.ns, x.fs, x.as};
+        uint64_t ea[5], ta[5];
+        block_excl_scan_n<NT, 5>(va, s_red, ea, ta);
+        const uint64_t p01 = k01 + ea[0], p2w = k2w + ea[1];
+        const uint64_t ens = ea[2], efs = ea[3], eas = ea[4];
         const uint32_t wpre = (uint32_t)(p2w >> 32);
         const bool split = wins != 0 && (uint64_t)wpre + wins <= (uint64_t)budget;
         // bin 4: heavy items (front: parts of split rows, heavy unsplit rows)
@@ -607,13 +635,10 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
         const uint32_t nf = split ? items - x.n4 + nh : nh;
         const uint32_t nb = x.n4 - nh;
         const uint32_t nm = split ? ne * (uint32_t)cs[x.cs].merge_per_row : 0u;
-        uint64_t t4, tm;
-        const uint64_t p4 =
-            k4 + block_excl_scan<NT, uint64_t>((uint64_t)nf | ((uint64_t)nb << 32), s_red, &t4);
-        const uint64_t pm = km + block_excl_scan<NT, uint64_t>((uint64_t)nm, s_red, &tm);
-        const uint64_t ens = block_excl_scan<NT, uint64_t>(x.ns, s_red, &tns);
-        const uint64_t efs = block_excl_scan<NT, uint64_t>(x.fs, s_red, &tfs);
-        const uint64_t eas = block_excl_scan<NT, uint64_t>(x.as, s_red, &tas);
+        const uint64_t vb[2] = {(uint64_t)nf | ((uint64_t)nb << 32), (uint64_t)nm};
+        uint64_t eb[2], tb[2];
+        block_excl_scan_n<NT, 2>(vb, s_red, eb, tb);
+        const uint64_t p4 = k4 + eb[0], pm = km + eb[1];
         s_e[0][t] = ens;
         s_e[1][t] = efs;
         s_e[2][t] = eas;
@@ -643,10 +668,10 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
             }
         }
         __syncthreads();  // s_e is rewritten by the next chunk
-        k01 += t01;
-        k2w += t2w;
-        k4 += t4;
-        km += tm;
+        k01 += ta[0];
+        k2w += ta[1];
+        k4 += tb[0];
+        km += tb[1];
     }
     if (t == 0) {
         ctl->bin_cnt[1] = (uint32_t)k01;
@@ -1668,7 +1693,7 @@ void k_flop(const CaseDesc* __restrict__ cs,
 }
 
 // One thread per global tile: a row that begins in tile g and goes on (its
-// partial is g's carry) collects the heads of the case's following tiles until
+// partial is g's carry) collects the heads of the case's following tiles up to
 // the tile holding its end marker, then gets its output.  Adds each case's F:
 // one atomic for the workgroup's first case, one per tile of any other case.
 template <int MODE>
@@ -1698,10 +1723,18 @@ __global__ __launch_bounds__(256) void k_flop_fixup(const CaseDesc* __restrict__
         if (i1 < M) {
             const int64_t rs = cd.A.rpt[i1];
             if (rs >= j0 && rs < j1) {
+                // the tile holding the row's end marker, item i1 + rpt[i1 + 1]
+                // of the merged sequence; the heads up to it are independent
+                // loads, eight in flight
+                const int64_t e = cd.tile_base + (i1 + (int64_t)cd.A.rpt[i1 + 1]) / kFlopTile;
+                const int64_t bend = e < last - 1 ? e : last - 1;
                 uint64_t total = meta[g].carry;
-                for (int64_t bb = g + 1; bb < last; ++bb) {
-                    total += meta[bb].head;
-                    if (tile_end_row(cs, tile_row, tile_case, ntiles_all, bb) > i1) break;
+                for (int64_t bb = g + 1; bb <= bend; bb += 8) {
+                    uint64_t hd[8];
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) hd[u] = bb + u <= bend ? meta[bb + u].head : 0;
+#pragma unroll
+                    for (int u = 0; u < 8; ++u) total += hd[u];
                 }
                 if (MODE == FLOP_ONLY) {
                     emit_row<MODE>(cs, c, i1, total, ctl, L);
@@ -1730,17 +1763,19 @@ __global__ __launch_bounds__(256) void k_flop_fixup(const CaseDesc* __restrict__
 constexpr int kRowsThreads = 1024;
 
 // nnz_pred[i] = ceil(rf_i z* / f*) (Eq. 3 per row), rf_i when the sample has
-// no products.  Grid-stride with few workgroups (at least one per case, rows
-// or not): each adds its part of the output total with one atomic.  Every
-// workgroup first sums its case's distinct-count slots into z* and derives
-// the divisor of f*; the case's first workgroup records z* and the
-// empty-sample flag in the statistics.
-__global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __restrict__ cs, int n,
-                                                            const CaseRes* __restrict__ cr)
+// no products.  Grid-stride (at least one workgroup per case, rows or not):
+// a step covers U G blocks of kRowsThreads rows and workgroup bl takes the
+// blocks bl, bl + G, ..., so even a case of few rows spreads over every
+// workgroup it is given; each adds its part of the output total with one
+// atomic.  Every wave sums its case's distinct-count slots into z* itself (no
+// barrier before the rows); the case's first workgroup records z* and the
+// empty-sample flag in the statistics.  Rows of fewer than 2^48 products take
+// the double-precision estimate with an integer correction (exact, see
+// ceil_mul_div_est), the others the 128-bit division, with the divisor
+// derived where it is needed.
+__global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __restrict__ cs, int n, const CaseRes* __restrict__ cr)
 {
     __shared__ uint64_t s_red[kRowsThreads / kWave + 1];
-    __shared__ uint64_t s_z;
-    __shared__ Divisor s_div;
     const int c = case_of_wg<&CaseDesc::wg_rows>(cs, n, blockIdx.x);
     const int64_t bl = (int64_t)blockIdx.x - cs[c].wg_rows;
     const int64_t G = wgs_of_case<&CaseDesc::wg_rows>(cs, n, c);
@@ -1748,39 +1783,27 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __re
     SSP_GLOBAL int64_t* __restrict__ out = cs[c].out;
     const int64_t M = cs[c].A.nrows;
     ssp_stats* st = cs[c].st;
-    static_assert(kAccSlots == kWave, "one slot per lane of wave 0");
+    static_assert(kAccSlots == kWave, "one slot per lane");
     // Loads issued at once: the case's f*, its distinct-count slots, and the
     // first step's row products (none of them waits on another).
-    const uint64_t fs_ld = st->sample_flop;
-    const uint64_t z_ld = threadIdx.x < kWave ? cr[c].zacc[threadIdx.x] : 0;
-    constexpr int U = 8;  // rows per thread and step, loaded together
-    const int64_t stride = G * kRowsThreads * U;
+    const uint64_t fs = uniform_u64(st->sample_flop);
+    const uint64_t z_ld = cr[c].zacc[lane_id()];
+    constexpr int U = 4;  // rows per thread and step, loaded together
+    const int64_t bstride = G * kRowsThreads, stride = bstride * U;
     uint64_t rf[U];
     auto load_rows = [&](int64_t i0) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t i = i0 + u * kRowsThreads;
+            const int64_t i = i0 + u * bstride;
             rf[u] = i < M ? (uint64_t)__builtin_nontemporal_load(rf_in + i) : 0;
         }
     };
-    const int64_t first = bl * kRowsThreads * U + threadIdx.x;
+    const int64_t first = bl * kRowsThreads + threadIdx.x;
     load_rows(first);
-    // wave 0 alone sums the slots and derives the divisor (its reciprocal
-    // loop on the scalar unit, which the waves of a CU share)
-    if (__builtin_amdgcn_readfirstlane(threadIdx.x / kWave) == 0) {
-        const uint64_t z = wave_sum(z_ld);
-        const uint64_t f = uniform_u64(fs_ld);
-        Divisor d0{};
-        if (f) d0 = make_divisor(f);
-        if (threadIdx.x == 0) {
-            s_z = z;
-            s_div = d0;
-        }
-    }
-    __syncthreads();
-    const uint64_t zs = uniform_u64(s_z), fs = uniform_u64(fs_ld);
+    const uint64_t zs = wave_sum(z_ld);
     const bool fallback = fs == 0;
-    const Divisor D = s_div;
+    const bool est = fs < kEstMaxD;  // (z* <= f*: a row has no more columns than products)
+    const double ratio = fallback ? 0.0 : (double)zs / (double)fs;
     if (bl == 0 && threadIdx.x == 0) {
         st->sample_nnz = zs;
         if (fallback) atomicOr(as_ull(&st->flags), (ull)SSP_FLAG_EMPTY_SAMPLE);
@@ -1790,9 +1813,13 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __re
         if (i0 != first) load_rows(i0);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const int64_t i = i0 + u * kRowsThreads;
+            const int64_t i = i0 + u * bstride;
             if (i < M) {
-                const uint64_t pred = fallback ? rf[u] : (rf[u] ? ceil_mul_div(rf[u], zs, D) : 0);
+                const uint64_t a = rf[u];
+                const uint64_t pred = fallback ? a
+                                      : a == 0 ? 0
+                                      : (est && a < kEstMaxA) ? ceil_mul_div_est(a, zs, fs, ratio)
+                                                              : ceil_mul_div(a, zs, make_divisor(fs));
                 __builtin_nontemporal_store((int64_t)pred, out + i);
                 osum += pred;
             }

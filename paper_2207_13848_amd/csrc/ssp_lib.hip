@@ -459,13 +459,15 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind,
     // (every case gets a workgroup of the row kernels, rows or not: the
     // prediction kernel also finishes the case's statistics)
     auto rows_work = [&](int c) { return std::max<int64_t>(Mof(c), 1); };
-    auto rows_cap = [&](int c) {
-        return std::max<int64_t>(1, (Mof(c) + 8 * kRowsThreads - 1) / (8 * kRowsThreads));
+    auto rows_cap = [&](int c) {  // (at least four rows per thread)
+        return std::max<int64_t>(1, (Mof(c) + 4 * kRowsThreads - 1) / (4 * kRowsThreads));
     };
-    // (about four row steps per thread over the call, at least half the CUs)
+    // (about 32 rows per thread over the call, at least one workgroup per CU;
+    // on 2^20 and 2^21 rows, 512 or 1024 workgroups took longer than 256:
+    // each adds a same-address atomic and its own chain of dependent loads)
     int64_t rows_all = 0;
     for (int c = 0; c < n; ++c) rows_all += Mof(c);
-    const int64_t rows_budget = std::max<int64_t>(cus / 2, rows_all / (4 * 8 * kRowsThreads));
+    const int64_t rows_budget = std::max<int64_t>(cus, rows_all / (4 * 8 * kRowsThreads));
     P.g_rows = share_wgs(n, rows_budget, rows_work, rows_cap, f);
     for (int c = 0; c < n; ++c) P.cs[c].wg_rows = f[c];
     // list capacities

@@ -204,6 +204,37 @@ def test_bin_boundaries(ssp):
     check_all(ssp, A, B, 0.4, 12)
 
 
+def _copies_case(n, kinds):
+    # for every length L in 1..n, B holds c identical rows {0..L-1} for the
+    # largest c in `kinds`, and A a row naming k of them for every k in
+    # `kinds`: k L products, L distinct columns
+    c = max(kinds)
+    brows, arows = [], []
+    for L in range(1, n + 1):
+        base = len(brows)
+        brows += [list(range(L))] * c
+        arows += [list(range(base, base + k)) for k in kinds]
+    return from_rows(arows, len(brows)), from_rows(brows, n)
+
+
+@pytest.mark.parametrize("kinds,num,den", [((4, 2), 1, 3), ((10,), 1, 10), ((7, 3, 3), 3, 13)])
+def test_prediction_ceiling_at_whole_quotients(ssp, kinds, num, den):
+    # At rate 1 the sampled ratio z*/f* is num/den exactly (kinds (4, 2):
+    # 2S columns over 6S products), so a row of rf products is predicted
+    # ceil(rf num / den), a whole quotient whenever den divides rf num, where
+    # the double nearest num/den lies a little below (1/3) or above (1/10).
+    A, B = _copies_case(300, kinds)
+    _say(f"whole quotients {kinds}")
+    Ad, Bd = _dev(ssp, A), _dev(ssp, B)
+    st = check_predict(ssp, A, B, 1.0, 3, Ad=Ad, Bd=Bd)
+    assert st.sample_nnz * den == st.sample_flop * num
+    pred, rf, _ = ssp.predict_structure(Ad, Bd, 1.0, 3, return_row_flop=True)
+    rf = rf.cpu().numpy()
+    assert np.array_equal(pred.cpu().numpy(), -((-rf * num) // den))
+    assert np.any(rf * num % den == 0)
+    check_predict(ssp, A, B, 0.5, 4, Ad=Ad, Bd=Bd)
+
+
 def _long_rows(ncols, nbig, seed):
     # long rows whose entries name B rows of all three length classes the
     # long-row kernel treats differently: huge (>= 2048 entries), medium
