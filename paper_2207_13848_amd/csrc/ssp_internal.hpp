@@ -160,10 +160,13 @@ struct SampleCounts {
     uint32_t n1, n2, n3, n4;   // sampled rows in bins 1..3 and bin 4
     uint32_t cs;               // case
     uint32_t split;            // (scan) 1 if the group's eligible rows are split
-    uint32_t lv[kSplitLevels][4];  // per level: bin-4 items, part windows, eligible rows, heavy rows
+    // per level: bin-4 items, part windows, merge items of the eligible rows
+    // (when split), heavy rows
+    uint32_t lv[kSplitLevels][4];
     uint32_t o1, o2, o3;       // (scan) offsets in bins 1..3
     uint32_t oh, ol;           // (scan) offsets among the heavy and the light bin-4 items
     uint32_t om, ow;           // (scan) offset in the merge list, first part window
+    uint32_t gfirst, glast;    // first and last group of the case
     uint32_t pad;
     uint64_t ns, fs, as;       // sampled rows, their products, their A entries
 };

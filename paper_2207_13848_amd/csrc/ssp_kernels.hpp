@@ -508,7 +508,7 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc*
                 const SplitInfo si = split_info(r, a, lv);
                 c[4 + 4 * lv + 0] += r.bin == 4 ? si.want : 0u;
                 c[4 + 4 * lv + 1] += si.elig ? si.want * (uint32_t)a.nwin : 0u;
-                c[4 + 4 * lv + 2] += si.elig ? 1u : 0u;
+                c[4 + 4 * lv + 2] += si.elig ? (uint32_t)a.merge_per_row : 0u;
                 c[4 + 4 * lv + 3] += si.heavy ? 1u : 0u;
             }
         }
@@ -537,6 +537,8 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc*
     }
     if (threadIdx.x == 0) {
         o->cs = (uint32_t)gr.c;
+        o->gfirst = (uint32_t)cs[gr.c].group_base;
+        o->glast = (uint32_t)(cs[gr.c].group_base + cs[gr.c].ngroups - 1);
         o->ns = Ns;
         o->fs = Fs;
         o->as = As;
@@ -550,13 +552,14 @@ __global__ __launch_bounds__(kSampleThreads) void k_sample_count(const CaseDesc*
 // group's eligible rows are split when all part windows requested up to and
 // including the group fit the scratch), the list sizes, and per case n_s, f*
 // and the sample's A entries (one atomic per case and chunk of groups).  The
-// first chunk's records are read with the first pass, and the scans of a
-// chunk go in two rounds (the second depends on the split decision) of one
-// barrier pair each.
+// first chunk's records are read with the first pass, the scans of a chunk go
+// in two rounds (the second depends on the split decision) of one barrier
+// pair each, and the records carry what the scan would otherwise look up in
+// the case table (merge items, the case's groups).
 constexpr int kScanThreads = 1024;
 
 struct GroupRec {  // the counts of SampleCounts (k_sample_count's output)
-    uint32_t n1, n2, n3, n4, cs;
+    uint32_t n1, n2, n3, n4, cs, gfirst, glast;
     uint32_t lv[kSplitLevels][4];
     uint64_t ns, fs, as;
 };
@@ -572,6 +575,8 @@ __device__ __forceinline__ GroupRec load_group(const SampleCounts* __restrict__ 
         x.n3 = y.n3;
         x.n4 = y.n4;
         x.cs = y.cs;
+        x.gfirst = y.gfirst;
+        x.glast = y.glast;
 #pragma unroll
         for (int lv = 0; lv < kSplitLevels; ++lv)
 #pragma unroll
@@ -610,15 +615,16 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
     for (int64_t g0 = 0; g0 < ngroups; g0 += NT) {
         const int64_t g = g0 + t;
         const GroupRec x = g0 == 0 ? r0 : load_group(cnt, g, ngroups);
+        ssp_stats* const st = cs[x.cs].st;  // (issued now, used after the scans)
         // level L's counts (selected: the level is dynamic, an indexed
         // register array would live in scratch)
-        uint32_t items = 0, wins = 0, ne = 0, nh = 0;
+        uint32_t items = 0, wins = 0, me = 0, nh = 0;
 #pragma unroll
         for (int lv = 0; lv < kSplitLevels; ++lv) {
             if (lv == L) {
                 items = x.lv[lv][0];
                 wins = x.lv[lv][1];
-                ne = x.lv[lv][2];
+                me = x.lv[lv][2];
                 nh = x.lv[lv][3];
             }
         }
@@ -634,7 +640,7 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
         // and light rows (back); eligible rows are heavy
         const uint32_t nf = split ? items - x.n4 + nh : nh;
         const uint32_t nb = x.n4 - nh;
-        const uint32_t nm = split ? ne * (uint32_t)cs[x.cs].merge_per_row : 0u;
+        const uint32_t nm = split ? me : 0u;
         const uint64_t vb[2] = {(uint64_t)nf | ((uint64_t)nb << 32), (uint64_t)nm};
         uint64_t eb[2], tb[2];
         block_excl_scan_n<NT, 2>(vb, s_red, eb, tb);
@@ -654,14 +660,12 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
             o->ow = wpre;
             o->split = split ? 1u : 0u;
             // the last group of its case in this chunk adds the case's part
-            const int c = (int)x.cs;
-            const int64_t first = cs[c].group_base, last = first + cs[c].ngroups - 1;
+            const int64_t first = x.gfirst, last = x.glast;
             if (g == last || t == NT - 1 || g == ngroups - 1) {
                 const int k0 = first > g0 ? (int)(first - g0) : 0;
                 const uint64_t dns = ens + x.ns - s_e[0][k0];
                 const uint64_t dfs = efs + x.fs - s_e[1][k0];
                 const uint64_t das = eas + x.as - s_e[2][k0];
-                ssp_stats* st = cs[c].st;
                 if (dns) atomicAdd(as_ull(&st->n_sampled), (ull)dns);
                 if (dfs) atomicAdd(as_ull(&st->sample_flop), (ull)dfs);
                 if (das) atomicAdd(as_ull(&st->a_sample_nnz), (ull)das);
