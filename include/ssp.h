@@ -239,6 +239,11 @@ SSP_API ssp_status ssp_batch_graph_destroy(ssp_batch_graph graph);
  *                 kernel; 0: never.
  *   split_target: long rows above this many products are split into parts
  *                 (2^12..2^40; default 2^17).
+ *   est_max_rf  : the prediction's per-row ceiling ceil(rf z* / f*) takes a
+ *                 double-precision estimate corrected in integers for rows
+ *                 of fewer than est_max_rf products, a 128-bit division for
+ *                 the others (0..2^48; default 2^48, the largest value for
+ *                 which the estimate is exact).
  */
 typedef struct {
     uint32_t bin_max[3];
@@ -246,6 +251,7 @@ typedef struct {
     uint32_t long_len;
     int32_t big3;
     uint64_t split_target;
+    uint64_t est_max_rf;
 } ssp_tuning;
 
 /* Defaults, current value, and change (SSP_ERR_INVALID_ARG outside the limits). */

@@ -341,7 +341,7 @@ def _tuning_struct(d: dict) -> "_native.SspTuning":
     t = _native.SspTuning()
     t.bin_max[:] = [int(x) for x in d["bin_max"]]
     t.hash_mult, t.long_len, t.big3 = int(d["hash_mult"]), int(d["long_len"]), int(d["big3"])
-    t.split_target = int(d["split_target"])
+    t.split_target, t.est_max_rf = int(d["split_target"]), int(d["est_max_rf"])
     return t
 
 

@@ -71,11 +71,12 @@ class SspKmvResult(ctypes.Structure):
 class SspTuning(ctypes.Structure):
     _fields_ = [("bin_max", ctypes.c_uint32 * 3), ("hash_mult", ctypes.c_uint32),
                 ("long_len", ctypes.c_uint32), ("big3", ctypes.c_int32),
-                ("split_target", ctypes.c_uint64)]
+                ("split_target", ctypes.c_uint64), ("est_max_rf", ctypes.c_uint64)]
 
     def as_dict(self) -> dict:
         return {"bin_max": list(self.bin_max), "hash_mult": self.hash_mult,
-                "long_len": self.long_len, "big3": self.big3, "split_target": self.split_target}
+                "long_len": self.long_len, "big3": self.big3, "split_target": self.split_target,
+                "est_max_rf": self.est_max_rf}
 
 
 class SspRequest(ctypes.Structure):

@@ -43,7 +43,8 @@ __device__ __forceinline__ u128 mul_64x64(uint64_t a, uint64_t b)
 // Reciprocal of a normalised divisor d (top bit set):
 //   v = floor((2^128 - 1) / d) - 2^64,
 // i.e. the 64-bit quotient of the 128-bit number (~d, ~0) by d.  Plain
-// restoring division; run once per call, not per row.
+// restoring division; run only for rows of 2^48 or more products (the others
+// take ceil_mul_div_est).
 __device__ inline uint64_t reciprocal_of_normalised(uint64_t d)
 {
     uint64_t rem = ~d, low = ~0ull, q = 0;

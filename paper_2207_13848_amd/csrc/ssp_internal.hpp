@@ -94,6 +94,7 @@ struct CaseDesc {
     uint32_t long_len;      // long-row kernel: B rows of at least this many columns go in units
     uint32_t pad;
     uint64_t split_target;  // products per part of a split long row
+    uint64_t est_max_rf;    // prediction: rows of fewer products take the estimated ceiling
 };
 
 // Per-case results written by the kernels.

@@ -1773,11 +1773,12 @@ constexpr int kRowsThreads = 1024;
 // workgroup it is given; each adds its part of the output total with one
 // atomic.  Every wave sums its case's distinct-count slots into z* itself (no
 // barrier before the rows); the case's first workgroup records z* and the
-// empty-sample flag in the statistics.  Rows of fewer than 2^48 products take
-// the double-precision estimate with an integer correction (exact, see
-// ceil_mul_div_est), the others the 128-bit division, with the divisor
-// derived where it is needed.
-__global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __restrict__ cs, int n, const CaseRes* __restrict__ cr)
+// empty-sample flag in the statistics.  Rows of fewer than est_max_rf (at
+// most 2^48) products take the double-precision estimate with an integer
+// correction (exact, see ceil_mul_div_est), the others the 128-bit division,
+// with the divisor derived where it is needed.
+__global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __restrict__ cs, int n,
+                                                            const CaseRes* __restrict__ cr)
 {
     __shared__ uint64_t s_red[kRowsThreads / kWave + 1];
     const int c = case_of_wg<&CaseDesc::wg_rows>(cs, n, blockIdx.x);
@@ -1807,6 +1808,7 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __re
     const uint64_t zs = wave_sum(z_ld);
     const bool fallback = fs == 0;
     const bool est = fs < kEstMaxD;  // (z* <= f*: a row has no more columns than products)
+    const uint64_t est_max = cs[c].est_max_rf;  // (at most kEstMaxA)
     const double ratio = fallback ? 0.0 : (double)zs / (double)fs;
     if (bl == 0 && threadIdx.x == 0) {
         st->sample_nnz = zs;
@@ -1822,7 +1824,7 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __re
                 const uint64_t a = rf[u];
                 const uint64_t pred = fallback ? a
                                       : a == 0 ? 0
-                                      : (est && a < kEstMaxA) ? ceil_mul_div_est(a, zs, fs, ratio)
+                                      : (est && a < est_max) ? ceil_mul_div_est(a, zs, fs, ratio)
                                                               : ceil_mul_div(a, zs, make_divisor(fs));
                 __builtin_nontemporal_store((int64_t)pred, out + i);
                 osum += pred;

@@ -59,6 +59,7 @@ ssp_tuning default_tuning()
     t.long_len = ssp::kLongLenDefault;
     t.big3 = 1;
     t.split_target = ssp::kSplitTarget;
+    t.est_max_rf = ssp::kEstMaxA;
     return t;
 }
 
@@ -77,6 +78,7 @@ bool tuning_valid(const ssp_tuning& t)
     if (t.long_len < 8 || t.long_len > 1024) return false;
     if (t.big3 != 0 && t.big3 != 1) return false;
     if (t.split_target < (1ull << 12) || t.split_target > (1ull << 40)) return false;
+    if (t.est_max_rf > ssp::kEstMaxA) return false;
     return true;
 }
 } // namespace
@@ -412,6 +414,7 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind,
         d.hash_mult = tu.hash_mult;
         d.long_len = tu.long_len;
         d.split_target = tu.split_target;
+        d.est_max_rf = tu.est_max_rf;
         int32_t mpr = 0;  // merge items of a split row: slices of every window
         for (int32_t w = 0; w < d.nwin; ++w) {
             const int64_t cols = std::min<int64_t>(N - (int64_t)w * d.win_words * 32,

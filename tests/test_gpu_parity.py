@@ -233,6 +233,14 @@ def test_prediction_ceiling_at_whole_quotients(ssp, kinds, num, den):
     assert np.array_equal(pred.cpu().numpy(), -((-rf * num) // den))
     assert np.any(rf * num % den == 0)
     check_predict(ssp, A, B, 0.5, 4, Ad=Ad, Bd=Bd)
+    # the same ceilings by the 128-bit division (rows of 2^48 or more
+    # products take it by default; a tuning sends every row there)
+    h = ssp.Handle(0)
+    ssp.set_tuning(dict(ssp.default_tuning(), est_max_rf=0), handle=h)
+    pred2, _, _ = ssp.predict_structure(Ad, Bd, 1.0, 3, handle=h)
+    torch.cuda.synchronize()
+    assert np.array_equal(pred2.cpu().numpy(), -((-rf * num) // den))
+    h.close()
 
 
 def _long_rows(ncols, nbig, seed):

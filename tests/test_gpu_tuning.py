@@ -18,11 +18,17 @@ def ssp():
     return m
 
 
+# (est_max_rf 0: every row's ceiling by the 128-bit division; 1000: the long
+# rows by it, the others by the estimate)
 VARIANTS = [
-    dict(bin_max=[64, 512, 4096], hash_mult=4, long_len=16, big3=0, split_target=1 << 15),
-    dict(bin_max=[32, 256, 2048], hash_mult=8, long_len=128, big3=1, split_target=1 << 19),
-    dict(bin_max=[1, 1, 1], hash_mult=2, long_len=8, big3=1, split_target=1 << 12),
-    dict(bin_max=[128, 1024, 8192], hash_mult=2, long_len=1024, big3=0, split_target=1 << 40),
+    dict(bin_max=[64, 512, 4096], hash_mult=4, long_len=16, big3=0, split_target=1 << 15,
+         est_max_rf=0),
+    dict(bin_max=[32, 256, 2048], hash_mult=8, long_len=128, big3=1, split_target=1 << 19,
+         est_max_rf=1000),
+    dict(bin_max=[1, 1, 1], hash_mult=2, long_len=8, big3=1, split_target=1 << 12,
+         est_max_rf=1 << 48),
+    dict(bin_max=[128, 1024, 8192], hash_mult=2, long_len=1024, big3=0, split_target=1 << 40,
+         est_max_rf=1),
 ]
 
 
@@ -66,7 +72,8 @@ def test_set_tuning_rejects_values_outside_the_limits(ssp):
     bad = [dict(good, hash_mult=3), dict(good, bin_max=[256, 1024, 8192]),
            dict(good, bin_max=[128, 2048, 8192]), dict(good, bin_max=[128, 1024, 16384]),
            dict(good, bin_max=[512, 256, 8192], hash_mult=2), dict(good, long_len=4),
-           dict(good, long_len=2048), dict(good, big3=2), dict(good, split_target=100)]
+           dict(good, long_len=2048), dict(good, big3=2), dict(good, split_target=100),
+           dict(good, est_max_rf=(1 << 48) + 1)]
     for b in bad:
         with pytest.raises(ssp.SspError) as ei:
             ssp.set_tuning(b, handle=h)
