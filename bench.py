@@ -9,7 +9,8 @@ predicted nnz of every row.  The default workload is C = A.A with A the
 duplicates merged, sampled at 0.5%.
 
 Prints one JSON line.  `value` is predicted rows per second.  Beside it:
-algorithmic HBM GB/s of the step, the roofline of the dominant phase (its
+algorithmic HBM GB/s of the step, the device time of 100 single calls (p50,
+p99, mean), the roofline of the dominant phase (its
 duration from HIP events recorded on the launch stream over a second timed
 region of the same steps: the events hold the queue at each phase boundary,
 so the headline region runs without them), the reference design and exact
@@ -637,6 +638,19 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     ms_per_step = (t1 - t0) * 1e3 / args.steps
+    # Per-call device time over 100 calls: HIP events on the call's stream
+    # before and after each call, all calls queued back to back.
+    nlat = 100
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for _ in range(nlat)]
+    for a, b in ev:
+        a.record(stream)
+        ssp.predict_structure(Ad, Bd, w.rate, w.seed, handle=h, out=out, stats=st)
+        b.record(stream)
+    torch.cuda.synchronize()
+    lat = np.sort(np.array([a.elapsed_time(b) for a, b in ev]))
+    call_ms = {"runs": nlat, "p50": round(float(np.percentile(lat, 50)), 4),
+               "p99": round(float(np.percentile(lat, 99)), 4), "mean": round(float(lat.mean()), 4)}
     # The phase-timed region: the same steps, HIP events around every phase
     # on the call's stream; the kernel durations of the roofline come from it.
     h._lib.ssp_timing_enable(h.ptr, 1)
@@ -726,6 +740,7 @@ def main():
         "phases": phase_report,
         "phase_timing": {"steps": args.steps, "ms_per_step_with_phase_events":
                          round(ms_per_step_timed, 4)},
+        "call_ms": call_ms,
         "stats": stats,
         "kernel_source_hash": src_hash,
         "generate_s": round(t_gen, 2),
