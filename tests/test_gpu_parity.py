@@ -289,6 +289,32 @@ def test_long_rows_over_several_bitmap_windows(ssp):
     check_all(ssp, A, B, 1.0, 3)
 
 
+def test_widest_b(ssp):
+    # B with 2^31 - 1 columns, the largest 32-bit column count: columns at
+    # both ends of the range, short rows hashed over the whole range, and a
+    # few long rows whose bitmap walks 2048 windows of 2^20 columns
+    N = 2 ** 31 - 1
+    rng = np.random.default_rng(9)
+    K = 400
+    brows = []
+    for k in range(K):
+        L = 3000 if k < 8 else int(rng.integers(0, 40))
+        cols = set(int(c) for c in rng.integers(0, N, L))
+        if k % 5 == 0:
+            cols |= {0, N - 1, N - 2, (1 << 20) - 1, 1 << 20}
+        brows.append(sorted(cols))
+    B = from_rows(brows, N)
+    arows = [list(range(8)) + rng.choice(K, 20, replace=False).tolist() for _ in range(3)]
+    arows += [rng.choice(np.arange(8, K), int(rng.integers(0, 30)), replace=False).tolist()
+              for _ in range(297)]
+    A = from_rows(arows, K)
+    rf, _ = oracle.row_flop(A, B)
+    assert rf.max() > 8192 and B.col.max() == N - 1
+    _say("widest B")
+    check_all(ssp, A, B, 1.0, 1)
+    check_all(ssp, A, B, 0.3, 2)
+
+
 def test_misaligned_column_array(ssp):
     # a column array that is not 16-byte aligned takes the scalar-load path
     A = workloads.zipf(20000, 8, 4)
