@@ -588,14 +588,22 @@ __device__ __forceinline__ GroupRec load_group(const SampleCounts* __restrict__ 
     return x;
 }
 
-__global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __restrict__ cnt,
-                                                             int64_t ngroups,
-                                                             const CaseDesc* __restrict__ cs,
-                                                             Ctl* ctl, uint32_t budget)
+// Offsets of one group in the lists (k_sample_scan's per-group output).
+struct GroupOff {
+    uint32_t o1, o2, o3, oh, ol, om, ow, split;
+};
+
+// The scan of pass 2 by one workgroup of NT threads.  all: every chunk of
+// groups, with the statistics atomics and the list sizes; else only the chunks
+// up to group gt's.  WRITE: every group's offsets stored in its record.  Group
+// gt's offsets (gt >= 0) land in *s_go before the routine's last barrier.
+// Returns the split level (every thread).  s_red: 5 NT/64 entries.
+template <int NT, bool WRITE>
+__device__ __forceinline__ int scan_groups(SampleCounts* __restrict__ cnt, int64_t ngroups,
+                                           const CaseDesc* __restrict__ cs, Ctl* ctl,
+                                           uint32_t budget, bool all, int64_t gt,
+                                           uint64_t* s_red, uint64_t (*s_e)[NT], GroupOff* s_go)
 {
-    constexpr int NT = kScanThreads, NW = NT / kWave;
-    __shared__ uint64_t s_red[5 * NW];
-    __shared__ uint64_t s_e[3][NT];  // exclusive prefixes of ns, fs, as in the chunk
     const int t = threadIdx.x;
     const GroupRec r0 = load_group(cnt, t, ngroups);
     uint64_t wsum[kSplitLevels];
@@ -612,7 +620,7 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
     for (int lv = kSplitLevels - 1; lv >= 0; --lv)
         if (uniform_u64(wtot[lv]) <= (uint64_t)budget) L = lv;
     uint64_t k01 = 0, k2w = 0, k4 = 0, km = 0;  // carries (k01, k2w, k4: two u32 fields)
-    for (int64_t g0 = 0; g0 < ngroups; g0 += NT) {
+    for (int64_t g0 = 0; g0 < ngroups && (all || g0 <= gt); g0 += NT) {
         const int64_t g = g0 + t;
         const GroupRec x = g0 == 0 ? r0 : load_group(cnt, g, ngroups);
         ssp_stats* const st = cs[x.cs].st;  // (issued now, used after the scans)
@@ -650,18 +658,30 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
         s_e[2][t] = eas;
         __syncthreads();
         if (g < ngroups) {
-            SampleCounts* o = &cnt[g];
-            o->o1 = (uint32_t)p01;
-            o->o2 = (uint32_t)(p01 >> 32);
-            o->o3 = (uint32_t)p2w;
-            o->oh = (uint32_t)p4;
-            o->ol = (uint32_t)(p4 >> 32);
-            o->om = (uint32_t)pm;
-            o->ow = wpre;
-            o->split = split ? 1u : 0u;
+            GroupOff go;
+            go.o1 = (uint32_t)p01;
+            go.o2 = (uint32_t)(p01 >> 32);
+            go.o3 = (uint32_t)p2w;
+            go.oh = (uint32_t)p4;
+            go.ol = (uint32_t)(p4 >> 32);
+            go.om = (uint32_t)pm;
+            go.ow = wpre;
+            go.split = split ? 1u : 0u;
+            if (WRITE) {
+                SampleCounts* o = &cnt[g];
+                o->o1 = go.o1;
+                o->o2 = go.o2;
+                o->o3 = go.o3;
+                o->oh = go.oh;
+                o->ol = go.ol;
+                o->om = go.om;
+                o->ow = go.ow;
+                o->split = go.split;
+            }
+            if (g == gt) *s_go = go;
             // the last group of its case in this chunk adds the case's part
             const int64_t first = x.gfirst, last = x.glast;
-            if (g == last || t == NT - 1 || g == ngroups - 1) {
+            if (all && (g == last || t == NT - 1 || g == ngroups - 1)) {
                 const int k0 = first > g0 ? (int)(first - g0) : 0;
                 const uint64_t dns = ens + x.ns - s_e[0][k0];
                 const uint64_t dfs = efs + x.fs - s_e[1][k0];
@@ -677,7 +697,7 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
         k4 += tb[0];
         km += tb[1];
     }
-    if (t == 0) {
+    if (all && t == 0) {
         ctl->bin_cnt[1] = (uint32_t)k01;
         ctl->bin_cnt[2] = (uint32_t)(k01 >> 32);
         ctl->bin_cnt[3] = (uint32_t)k2w;
@@ -686,24 +706,64 @@ __global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __re
         ctl->bin_cnt[6] = (uint32_t)(k4 >> 32);
         ctl->split_level = (uint32_t)L;
     }
+    return L;
+}
+
+__global__ __launch_bounds__(kScanThreads) void k_sample_scan(SampleCounts* __restrict__ cnt,
+                                                             int64_t ngroups,
+                                                             const CaseDesc* __restrict__ cs,
+                                                             Ctl* ctl, uint32_t budget)
+{
+    constexpr int NT = kScanThreads;
+    __shared__ uint64_t s_red[5 * (NT / kWave)];
+    __shared__ uint64_t s_e[3][NT];  // exclusive prefixes of ns, fs, as in the chunk
+    (void)scan_groups<NT, true>(cnt, ngroups, cs, ctl, budget, true, -1, s_red, s_e, nullptr);
 }
 
 // Pass 3: every group regenerates its candidates and writes its rows at its
 // offsets (positions inside the group by workgroup scans, in candidate order).
+// FUSED (calls of at most kFusedScanGroups groups, one chunk of the scan):
+// pass 2 is not launched; every workgroup runs the scan itself, and
+// workgroup 0 also adds the statistics and sets the list sizes.  Timed: a
+// call of one group 0.047 -> 0.044 ms; with 512 groups (two chunks) no faster
+// than the separate pass, with 1024 twice as slow (every workgroup scans).
+constexpr int64_t kFusedScanGroups = kSampleThreads;
+
+template <bool FUSED>
 __global__ __launch_bounds__(kSampleThreads) void k_sample_write(const CaseDesc* __restrict__ cs,
                                                                 int n,
-                                                                const SampleCounts* __restrict__ cnt,
-                                                                const Ctl* ctl, BinLists L)
+                                                                SampleCounts* __restrict__ cnt,
+                                                                Ctl* ctl, BinLists L,
+                                                                int64_t ngroups, uint32_t budget)
 {
     constexpr int NT = kSampleThreads;
-    __shared__ uint64_t s_red[NT / kWave + 1];
+    __shared__ uint64_t s_red[5 * (NT / kWave)];
     __shared__ int64_t s_rows[NT * kCandPerThread];
+    __shared__ uint64_t s_e[FUSED ? 3 : 1][FUSED ? NT : 1];
+    __shared__ GroupOff s_go;
     const int t = threadIdx.x;
+    GroupOff o;
+    int lvl;
+    if constexpr (FUSED) {
+        lvl = scan_groups<NT, false>(cnt, ngroups, cs, ctl, budget, blockIdx.x == 0,
+                                     (int64_t)blockIdx.x, s_red,
+                                     reinterpret_cast<uint64_t (*)[NT]>(&s_e[0][0]), &s_go);
+        o = s_go;  // (written before the routine's last barrier)
+    } else {
+        const SampleCounts& y = cnt[blockIdx.x];
+        o.o1 = y.o1;
+        o.o2 = y.o2;
+        o.o3 = y.o3;
+        o.oh = y.oh;
+        o.ol = y.ol;
+        o.om = y.om;
+        o.ow = y.ow;
+        o.split = y.split;
+        lvl = (int)ctl->split_level;
+    }
     const GroupRange gr = group_range(cs, n, blockIdx.x);
     if (gr.lo >= gr.hi) return;  // (uniform over the workgroup)
     const SamplerArgs a = sampler_args(cs[gr.c]);
-    const SampleCounts& o = cnt[blockIdx.x];
-    const int lvl = (int)ctl->split_level;
     const bool split = o.split != 0;
     uint32_t off1 = o.o1, off2 = o.o2, off3 = o.o3, off4 = o.oh, offm = o.om, offw = o.ow,
              offb = o.ol;

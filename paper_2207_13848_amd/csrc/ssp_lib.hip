@@ -571,10 +571,15 @@ void launch_sampling(ssp_handle h, const Plan& P, const Bound& b, hipStream_t s,
     // count, scan, write: per-group counters instead of device atomics
     hipLaunchKernelGGL(k_sample_count, dim3((unsigned)P.ngroups), dim3(kSampleThreads), 0, s, b.cs,
                        P.n, b.samp);
-    hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(kScanThreads), 0, s, b.samp, P.ngroups, b.cs,
-                       b.ctl, (uint32_t)P.part_windows);
-    hipLaunchKernelGGL(k_sample_write, dim3((unsigned)P.ngroups), dim3(kSampleThreads), 0, s, b.cs,
-                       P.n, (const SampleCounts*)b.samp, (const Ctl*)b.ctl, b.L);
+    if (P.ngroups <= kFusedScanGroups) {
+        hipLaunchKernelGGL(k_sample_write<true>, dim3((unsigned)P.ngroups), dim3(kSampleThreads), 0,
+                           s, b.cs, P.n, b.samp, b.ctl, b.L, P.ngroups, (uint32_t)P.part_windows);
+    } else {
+        hipLaunchKernelGGL(k_sample_scan, dim3(1), dim3(kScanThreads), 0, s, b.samp, P.ngroups,
+                           b.cs, b.ctl, (uint32_t)P.part_windows);
+        hipLaunchKernelGGL(k_sample_write<false>, dim3((unsigned)P.ngroups), dim3(kSampleThreads), 0,
+                           s, b.cs, P.n, b.samp, b.ctl, b.L, P.ngroups, (uint32_t)P.part_windows);
+    }
 }
 
 // Symbolic kernels over the four bins, the merge of split rows and the
