@@ -100,8 +100,7 @@ struct CaseDesc {
 // Per-case results written by the kernels.
 struct CaseRes {
     uint64_t zacc[kAccSlots];
-    uint64_t div_dn, div_v;        // Divisor of f*
-    uint32_t div_shift, fallback;  // fallback 1: f* = 0, predict row FLOP
+    uint32_t fallback, pad0;       // reference design: 1 when f* = 0 (predict row FLOP)
     uint64_t ref_q_lo, ref_q_hi;   // reference design: z* M
     uint64_t ref_d_lo, ref_d_hi;   // reference design: n_s F
     uint64_t pad[8];

@@ -8,12 +8,13 @@
 //                      lengths of B) into rf, and F
 //   k_sample_count / _scan / _write
 //                      the sampled rows (splitmix64), f*, n_s, and their bins
+//                      (no scan launch for calls of few sampling groups)
 //   k_sym, k_sym_big   exact distinct-column count of every binned row (LDS hash
 //                      table or LDS bitmap); long rows are cut into parts that
 //                      leave their bitmaps in global scratch
 //   k_sym_merge        ORs the parts' bitmaps
-//   k_pred_rows        z* per case, the empty-sample fallback, the divisor of
-//                      f*, and the per-row prediction
+//   k_pred_rows        z* per case, the empty-sample fallback and the per-row
+//                      prediction
 //   (exact structure and reference design: k_finalize, k_finalize_reference,
 //   k_ref_rows)
 // Kernels whose workgroups each serve one case find it by a binary search of
@@ -1396,11 +1397,10 @@ __global__ __launch_bounds__(256) void k_sym_merge(const CaseDesc* __restrict__ 
 
 // ---------------------------------------------------------- finalize
 
-// One workgroup of kAccSlots threads per case after the symbolic kernels:
-// sums the case's distinct-count slots into z* (MODE 0) or the exact total
-// (MODE 1).  For MODE 0 it also takes the case's decisions: the empty-sample
-// fallback (f* = 0: every row predicts its own product count) and the divisor
-// of f* for the per-row ceilings.
+// One workgroup of kAccSlots threads per case after the symbolic kernels of
+// the reference design (MODE 0) or the exact structure (MODE 1): sums the
+// case's distinct-count slots into z* or the exact total.  (The prediction
+// kernel sums z* itself.)
 template <int MODE>
 __global__ __launch_bounds__(kAccSlots) void k_finalize(const CaseDesc* __restrict__ cs,
                                                        CaseRes* __restrict__ cr, int n)
@@ -1415,17 +1415,6 @@ __global__ __launch_bounds__(kAccSlots) void k_finalize(const CaseDesc* __restri
             continue;
         }
         st->sample_nnz = z;
-        const uint64_t fs = st->sample_flop;
-        if (fs == 0) {
-            cr[c].fallback = 1;
-            st->flags |= SSP_FLAG_EMPTY_SAMPLE;
-            continue;
-        }
-        cr[c].fallback = 0;
-        const Divisor D = make_divisor(fs);
-        cr[c].div_dn = D.dn;
-        cr[c].div_v = D.v;
-        cr[c].div_shift = D.shift;
     }
 }
 
