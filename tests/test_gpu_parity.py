@@ -328,6 +328,19 @@ def test_misaligned_column_array(ssp):
     check_exact(ssp, A, A, Ad=Ad, Bd=Bd)
 
 
+@pytest.mark.parametrize("M", [256 * 2048, 256 * 2048 + 1])
+def test_sampling_scan_with_and_without_its_own_launch(ssp, M):
+    # 2048 candidates per sampling group: 256 groups (the write pass scans the
+    # group counts itself) and 257 (a scan launch of its own)
+    A = workloads.uniform(M, 4096, 2, 6)
+    B = workloads.uniform(4096, 4096, 4, 7)
+    _say(f"sampling groups M={M}")
+    Ad, Bd = _dev(ssp, A), _dev(ssp, B)
+    check_predict(ssp, A, B, 0.01, 21, Ad=Ad, Bd=Bd)
+    check_predict(ssp, A, B, 0.7, 22, Ad=Ad, Bd=Bd)
+    check_reference(ssp, A, B, 0.01, 23, Ad=Ad, Bd=Bd)
+
+
 def test_repeat_calls_are_identical(ssp):
     A = workloads.rmat(1 << 16, 16, 9)
     Ad = _dev(ssp, A)
