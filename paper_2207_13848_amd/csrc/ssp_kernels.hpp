@@ -1155,8 +1155,21 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
                     j = __builtin_amdgcn_readfirstlane(j);
                     if (lane == 0) s_nt = j;
                     if (j < n) {
-                        const BigItem nx = items[big_index(j, nheavy, L.cap4)];
-                        if (lane < 8) s_nx[lane] = reinterpret_cast<const int32_t*>(&nx)[lane];
+                        // the descriptor's eight words, one per lane (a copy of
+                        // the struct indexed by lane would go through scratch)
+                        const int32_t* src =
+                            reinterpret_cast<const int32_t*>(items + big_index(j, nheavy, L.cap4));
+                        const int32_t wv = src[lane < 8 ? lane : 0];
+                        if (lane < 8) s_nx[lane] = wv;
+                        BigItem nx;
+                        nx.row = __builtin_amdgcn_readlane(wv, 0);
+                        nx.slot = __builtin_amdgcn_readlane(wv, 1);
+                        nx.part = __builtin_amdgcn_readlane(wv, 2);
+                        nx.nparts = __builtin_amdgcn_readlane(wv, 3);
+                        nx.e_lo = __builtin_amdgcn_readlane(wv, 4);
+                        nx.e_hi = __builtin_amdgcn_readlane(wv, 5);
+                        nx.cs = __builtin_amdgcn_readlane(wv, 6);
+                        nx.pad = 0;
                         const Csr A2 = cs[nx.cs].A, B2 = cs[nx.cs].B;
                         const int32_t ne0 = nx.e_lo + nx.part, nP = nx.nparts;
                         const int64_t ncnt =
