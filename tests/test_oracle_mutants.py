@@ -27,6 +27,8 @@ MUTANTS = {
                              "z = (z ^ (z >> 29)) * 0x94D049BB133111EBULL;"),
     "sample_le_threshold": ("if ((orc_splitmix64(seed, (uint64_t)i) >> 11) < T)",
                             "if ((orc_splitmix64(seed, (uint64_t)i) >> 12) < T)"),
+    "wide_division_drops_low_bits": ("rem = (rem << 1) | ((bits_lo >> b) & 1u);", "rem = (rem << 1);"),
+    "wide_division_drops_carry": ("u128 rem = (low >> 64) + high;", "u128 rem = high;"),
     "reference_drops_M": ("u128 q = (u128)st->sample_nnz * (uint64_t)M;",
                           "u128 q = (u128)st->sample_nnz;"),
     "reference_uses_sample_flop": ("u128 d = (u128)st->n_sampled * st->total_flop;",
@@ -37,6 +39,13 @@ MUTANTS = {
     "paper_sample_num_round": ("int64_t s = (int64_t)(0.003 * (double)M);",
                                "int64_t s = (int64_t)(0.003 * (double)M + 0.5);"),
     "paper_sample_cap": ("return s < 300 ? s : 300;", "return s;"),
+    "paper_draw_mod_not_scale": ("rows[r] = (int32_t)(((u128)(uint64_t)M * u53) >> 53);",
+                                 "rows[r] = (int32_t)(u53 % (uint64_t)M);"),
+    "paper_draw_stream_seed_plus_one": (
+        "uint64_t u53 = orc_splitmix64(seed, (uint64_t)r) >> 11;",
+        "uint64_t u53 = orc_splitmix64(seed + 1u, (uint64_t)r) >> 11;"),
+    "paper_draw_rounds": ("rows[r] = (int32_t)(((u128)(uint64_t)M * u53) >> 53);",
+                          "rows[r] = (int32_t)(((u128)(uint64_t)M * u53 + ((u128)1 << 52)) >> 53);"),
     "sample_sums_skip_last": ("for (int64_t s = 0; s < n; ++s) {\n        fs +=",
                               "for (int64_t s = 0; s + 1 < n; ++s) {\n        fs +="),
     "exact_sum_dropped_row": ("Z += z;", "Z += (i ? z : 0);"),

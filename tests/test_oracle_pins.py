@@ -342,6 +342,48 @@ def test_paper_sampler_mode(oracle_mod):
     assert st.n_sampled == 0 and st.flags & oracle_mod.FLAG_EMPTY_SAMPLE
 
 
+def test_paper_sampler_known_rows(oracle_mod):
+    # Alg. 2 and Sec. V-B: draw r picks row floor(M u_r).  Known answers worked
+    # by hand from the published first outputs of splitmix64 from state 0
+    # (golden/worked_example.json): they fix the draw -> row mapping (floor of
+    # M u, not u mod M, not a rounding) and the stream (seed, counter from 0).
+    ex = json.load(open(os.path.join(GOLDEN, "worked_example.json")))["paper_sampler_seed0"]
+    S = oracle_mod.sample_rows(1000, 0.0, 0, oracle_mod.PAPER)
+    assert S.tolist() == ex["M1000"]["rows"]
+    S = oracle_mod.sample_rows(46835, 0.0, 0, oracle_mod.PAPER)
+    assert S.size == ex["M46835"]["sample_num"]
+    assert S[:3].tolist() == ex["M46835"]["first_rows"]
+    # every draw, by exact rational arithmetic on the pinned generator outputs:
+    # row = floor(M * (x >> 11) / 2^53), which lies in [0, M) for any x
+    for M, seed in ((46835, 0), (100_000, 1001), (2**31 - 1, 7), (334, 2**64 - 1)):
+        S = oracle_mod.sample_rows(M, 0.0, seed, oracle_mod.PAPER)
+        assert S.size == oracle_mod.paper_sample_num(M)
+        for r, row in enumerate(S.tolist()):
+            u = Fraction(oracle_mod.splitmix64(seed, r) >> 11, 2**53)
+            assert row == math.floor(M * u) and 0 <= row < M
+
+
+def test_reference_wide_division(oracle_mod):
+    # Eq. (2) per row: ceil(rf z* M / (n_s F)).  Its quotient is at most M N <
+    # 2^62 but the numerator reaches 2^155 under the int32 CSR format (rf <
+    # 2^62, z* M < 2^93), so the oracle divides a 192-bit product; checked
+    # against Python's exact integers, at the format's extremes too.
+    rng = np.random.default_rng(11)
+    cases = [(1, 1, 1), (5, 12, 17), (2**62 - 1, (2**62 - 1) * (2**31 - 1), 2**31 * (2**62 - 1)),
+             (2**62 - 1, 2**93 - 1, 2**93 - 1), (3, 2**64 + 5, 7)]
+    for _ in range(2000):
+        a = int(rng.integers(1, 2**62))
+        d = int(rng.integers(1, 2**62)) * int(rng.integers(1, 2**31))
+        qmax = (d << 64) // a  # keep the quotient below 2^64
+        q = int(rng.integers(0, 2**62)) * int(rng.integers(1, 2**31)) % max(qmax, 1)
+        cases.append((a, q, d))
+    wide = 0
+    for a, q, d in cases:
+        assert oracle_mod.ceil_mul_div_wide(a, q, d) == -(-(a * q) // d), (a, q, d)
+        wide += a * q >= 2**128
+    assert wide > 100  # the 192-bit branch is exercised
+
+
 def test_check_csr(oracle_mod):
     A = workloads.uniform(100, 50, 5, 1)
     assert oracle_mod.check_csr(A) == 0
