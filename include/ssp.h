@@ -21,8 +21,13 @@
  *    are DEVICE pointers on the handle's device.  The caller owns them and
  *    keeps them alive until the work queued on `stream` has finished.
  *  - `stream` is a hipStream_t passed as void* (NULL = the null stream).
- *    Every compute entry point only enqueues work: it returns once the
- *    kernels are queued and never waits for the device.
+ *    The prediction, reference, exact and batch entry points enqueue their
+ *    work and return once it is queued.  They block the host in two cases
+ *    only: when the handle's workspace has to grow (hipDeviceSynchronize
+ *    before the old workspace is freed), and, for calls of more than 8
+ *    cases, when the pinned buffer that stages the case table is still being
+ *    copied from by the previous such call (hipEventSynchronize on that
+ *    copy).  Calls documented below as synchronous say so.
  *  - The library owns one device workspace per handle.  It grows on demand
  *    (hipMalloc) up to the handle's HBM budget; once a call of a given size
  *    has run, repeated calls of that size or smaller allocate nothing.  A
@@ -102,7 +107,8 @@ typedef struct {
 /* f* = 0 (no sampled row has a product): the ratio is undefined and every
  * row falls back to its product count, the upper bound. */
 #define SSP_FLAG_EMPTY_SAMPLE 1u
-/* some row of the reference design exceeded INT64_MAX and was saturated */
+/* reserved (never set): every value of the reference design fits int64,
+ * being at most M N < 2^62 */
 #define SSP_FLAG_SATURATED 2u
 
 /* Row sampler.  BERNOULLI: row i is sampled iff
@@ -152,7 +158,8 @@ SSP_API ssp_status ssp_predict_structure_ex(ssp_handle h, const ssp_csr* A, cons
  * The reference design of the existing sampling estimator on the same sample
  * (Sec. IV-C, Eq. (2)): Z1* = z* / p with p = n_s / M, and every row gets
  *     nnz_ref[i] = ceil(row_flop[i] * z* * M / (n_s * F)),
- * not clamped; INT64_MAX with SSP_FLAG_SATURATED if a value does not fit.
+ * not clamped (a value is at most M N; its numerator, up to 2^155, is
+ * divided exactly).
  * Same fallback as above when f* = 0.
  *   nnz_ref : device int64[A.nrows], written.
  */

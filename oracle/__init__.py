@@ -40,7 +40,6 @@ _LIB = os.path.join(_HERE, "liboracle.so")
 _LIB = os.environ.get("SSP_ORACLE_LIB_OVERRIDE", _LIB)
 
 FLAG_EMPTY_SAMPLE = 1
-FLAG_SATURATED = 2
 BERNOULLI, PAPER = 0, 1
 
 
@@ -84,6 +83,8 @@ def _load():
         lib.orc_sample_paper.restype = i64
         lib.orc_paper_sample_num.argtypes = [i64]
         lib.orc_paper_sample_num.restype = i64
+        lib.orc_ceil_mul_div_wide.argtypes = [u64, u64, u64, u64, u64]
+        lib.orc_ceil_mul_div_wide.restype = u64
         for name in ("orc_predict", "orc_reference"):
             f = getattr(lib, name)
             f.restype = ctypes.c_int
@@ -187,6 +188,13 @@ def sample_rows(M: int, rate: float, seed: int, mode: int = BERNOULLI) -> np.nda
         out = np.empty(max(M, 1), dtype=np.int32)
         n = lib.orc_sample_bernoulli(M, seed, lib.orc_rate_threshold(rate), _p(out))
     return out[:n].copy()
+
+
+def ceil_mul_div_wide(a: int, q: int, d: int) -> int:
+    """ceil(a q / d) as the reference design computes it (64-bit a, 128-bit
+    q and d, a quotient below 2^64)."""
+    m = (1 << 64) - 1
+    return int(_load().orc_ceil_mul_div_wide(a, q >> 64, q & m, d >> 64, d & m))
 
 
 def paper_sample_num(M: int) -> int:

@@ -34,12 +34,11 @@ typedef struct {
     uint64_t sample_nnz;  /* z*: distinct output columns of the sampled rows         */
     uint64_t out_sum;     /* sum of the per-row output                               */
     uint64_t nrows;       /* M                                                       */
-    uint64_t flags;       /* bit 0 empty sample (fallback), bit 1 saturated output   */
+    uint64_t flags;       /* bit 0: empty sample (fallback)                          */
     uint64_t a_sample_nnz; /* stored entries of A in the sampled rows (per draw)     */
 } orc_stats;
 
 #define ORC_FLAG_EMPTY_SAMPLE 1u
-#define ORC_FLAG_SATURATED 2u
 
 enum { ORC_OK = 0, ORC_ERR_ARG = -1, ORC_ERR_DIM = -2, ORC_ERR_CSR = -8, ORC_ERR_MEM = -5 };
 
@@ -183,7 +182,34 @@ int64_t orc_sample_paper(int64_t M, uint64_t seed, int32_t* rows)
 
 static uint64_t ceil_div_u128(u128 num, u128 den) { return (uint64_t)((num + den - 1) / den); }
 
-#define INT64_MAX_U ((uint64_t)0x7fffffffffffffffULL)
+/*
+ * ceil(a * q / d) for a 64-bit a and 128-bit q and d (0 < d < 2^127) whose
+ * quotient is below 2^64: binary long division of the 192-bit product.  Its
+ * top 128 bits (bits 64..191) are then below d, so they are the first partial
+ * remainder, and the 64 low bits are brought down one at a time, each giving
+ * one quotient bit.  Returns UINT64_MAX when the quotient does not fit (which
+ * the reference design never asks for).
+ */
+uint64_t orc_ceil_mul_div_wide(uint64_t a, uint64_t q_hi, uint64_t q_lo, uint64_t d_hi,
+                               uint64_t d_lo)
+{
+    u128 d = ((u128)d_hi << 64) | d_lo;
+    u128 low = (u128)a * q_lo;                    /* a times the low half of q  */
+    u128 high = (u128)a * q_hi;                   /* a times the high half of q */
+    uint64_t bits_lo = (uint64_t)low;             /* bits 0..63 of a q          */
+    u128 rem = (low >> 64) + high;                /* bits 64..191 of a q        */
+    if (d == 0 || (d >> 127) != 0 || rem >= d) return UINT64_MAX;
+    uint64_t quo = 0;
+    for (int b = 63; b >= 0; --b) {
+        rem = (rem << 1) | ((bits_lo >> b) & 1u);
+        quo <<= 1;
+        if (rem >= d) {
+            rem -= d;
+            quo |= 1u;
+        }
+    }
+    return quo + (rem != 0);
+}
 
 /*
  * The sampled part of Alg. 2: f* (sample_flop) and z* (sample_nnz) summed
@@ -266,9 +292,10 @@ int orc_predict(int64_t M, int64_t K, const int32_t* Arpt, const int32_t* Acol,
  * sampled proportion n_s / M, so Z1* = z* M / n_s.  The compression ratio is
  * F / Z1* and each row is predicted as ceil(row_flop[i] * Z1* / F)
  * = ceil(row_flop[i] * z* * M / (n_s * F)).  Not clamped.  Fallback as in
- * orc_predict when f* = 0.  If the exact quotient exceeds INT64_MAX, or the
- * numerator exceeds 128 bits, the row saturates at INT64_MAX and the
- * saturated flag is set.
+ * orc_predict when f* = 0.  Every value fits: z* <= n_s N (no sampled row has
+ * more than N columns) and row_flop[i] <= F, so the quotient is at most
+ * M N < 2^62; the numerator, though, can reach 2^155 (row_flop < 2^62,
+ * z* M < 2^93), so it is divided as a 192-bit number.
  */
 int orc_reference(int64_t M, int64_t K, const int32_t* Arpt, const int32_t* Acol,
                   const int32_t* Brpt, const int32_t* Bcol, double rate, uint64_t seed,
@@ -288,20 +315,11 @@ int orc_reference(int64_t M, int64_t K, const int32_t* Arpt, const int32_t* Acol
         st->flags |= ORC_FLAG_EMPTY_SAMPLE;
         for (int64_t i = 0; i < M; ++i) { nnz_ref[i] = (int64_t)rf[i]; sum += rf[i]; }
     } else {
-        u128 q = (u128)st->sample_nnz * (uint64_t)M;  /* z* M   (< 2^96) */
-        u128 d = (u128)st->n_sampled * st->total_flop; /* n_s F (< 2^128) */
+        u128 q = (u128)st->sample_nnz * (uint64_t)M;  /* z* M  (< 2^93) */
+        u128 d = (u128)st->n_sampled * st->total_flop; /* n_s F (< 2^93) */
         for (int64_t i = 0; i < M; ++i) {
-            uint64_t v;
-            /* rf * q overflows 128 bits iff rf > (2^128 - 1) / q */
-            if (rf[i] != 0 && (u128)rf[i] > (~(u128)0) / q) {
-                v = INT64_MAX_U;
-                st->flags |= ORC_FLAG_SATURATED;
-            } else {
-                u128 num = (u128)rf[i] * q;
-                u128 c = num / d + (num % d != 0);
-                if (c > INT64_MAX_U) { v = INT64_MAX_U; st->flags |= ORC_FLAG_SATURATED; }
-                else v = (uint64_t)c;
-            }
+            uint64_t v = orc_ceil_mul_div_wide(rf[i], (uint64_t)(q >> 64), (uint64_t)q,
+                                               (uint64_t)(d >> 64), (uint64_t)d);
             nnz_ref[i] = (int64_t)v;
             sum += v;
         }

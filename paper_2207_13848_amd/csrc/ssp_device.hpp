@@ -134,12 +134,12 @@ __device__ __forceinline__ uint64_t ceil_mul_div_est(uint64_t a, uint64_t b, uin
     return q0 + 1 + ((uint64_t)R != d);
 }
 
-__device__ __forceinline__ bool u128_lt(u128 a, u128 b)
+__host__ __device__ __forceinline__ bool u128_lt(u128 a, u128 b)
 {
     return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);
 }
 
-__device__ __forceinline__ u128 u128_sub(u128 a, u128 b)
+__host__ __device__ __forceinline__ u128 u128_sub(u128 a, u128 b)
 {
     u128 r;
     r.lo = a.lo - b.lo;
@@ -183,6 +183,28 @@ __device__ inline u128 u128_ceil_div(u128 n, u128 d)
         q.hi += (q.lo == 0);
     }
     return q;
+}
+
+// ceil(n / d) for the 192-bit n = (n2, n1, n0) (n2 the top 64 bits) and
+// 0 < d < 2^127 with (n2, n1) < d, i.e. a quotient below 2^64: the top 128
+// bits are the first partial remainder and the 64 low bits are brought down
+// one per step (restoring division; the partial remainder stays below d, so
+// doubling it cannot overflow).  The reference design's rows whose numerator
+// exceeds 128 bits.
+__host__ __device__ inline uint64_t ceil_div_192_by_128(uint64_t n2, uint64_t n1, uint64_t n0,
+                                                        u128 d)
+{
+    u128 r{n1, n2};
+    uint64_t q = 0;
+    for (int b = 63; b >= 0; --b) {
+        r = u128{(r.lo << 1) | ((n0 >> b) & 1u), (r.hi << 1) | (r.lo >> 63)};
+        q <<= 1;
+        if (!u128_lt(r, d)) {
+            r = u128_sub(r, d);
+            q |= 1u;
+        }
+    }
+    return q + ((r.lo | r.hi) != 0);
 }
 
 // ---------------------------------------------------- wave / block ops

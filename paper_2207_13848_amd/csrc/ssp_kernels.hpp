@@ -1828,7 +1828,7 @@ __global__ __launch_bounds__(256) void k_flop_fixup(const CaseDesc* __restrict__
 
 constexpr int kRowsThreads = 1024;
 
-// nnz_pred[i] = ceil(rf_i z* / f*) (Eq. 3 per row), rf_i when the sample has
+// nnz_pred[i] = ceil(rf_i z* / f*) (Eq. (4) per row), rf_i when the sample has
 // no products.  Grid-stride (at least one workgroup per case, rows or not):
 // a step covers U G blocks of kRowsThreads rows and workgroup bl takes the
 // blocks bl, bl + G, ..., so even a case of few rows spreads over every
@@ -1899,8 +1899,10 @@ __global__ __launch_bounds__(kRowsThreads) void k_pred_rows(const CaseDesc* __re
 
 // --------------------------------------------------- reference rows
 
-// nnz_ref[i] = ceil(rf_i * (z* M) / (n_s F)), saturating at INT64_MAX.
-// Grid-stride like k_pred_rows.
+// nnz_ref[i] = ceil(rf_i * (z* M) / (n_s F)).  The value is at most M N <
+// 2^62 (z* <= n_s N, rf_i <= F) but the numerator can exceed 128 bits (rf_i <
+// 2^62, z* M < 2^93): such rows divide the 192-bit product.  Grid-stride like
+// k_pred_rows.
 __global__ __launch_bounds__(kRowsThreads) void k_ref_rows(const CaseDesc* __restrict__ cs, int n,
                                                            const CaseRes* __restrict__ cr)
 {
@@ -1916,36 +1918,21 @@ __global__ __launch_bounds__(kRowsThreads) void k_ref_rows(const CaseDesc* __res
     const u128 Q = {cr[c].ref_q_lo, cr[c].ref_q_hi};
     const u128 Dd = {cr[c].ref_d_lo, cr[c].ref_d_hi};
     uint64_t osum = 0;
-    bool any_sat = false;
     const int64_t stride = G * kRowsThreads;
-    const int64_t iters = (M + stride - 1) / stride;
-    for (int64_t k = 0; k < iters; ++k) {  // same trip count in every lane (ballot below)
-        const int64_t i = k * stride + bl * kRowsThreads + threadIdx.x;
-        uint64_t v = 0;
-        bool sat = false;
-        if (i < M) {
-            const uint64_t rf = (uint64_t)rf_in[i];
-            if (fallback || rf == 0) {
-                v = rf;
-            } else {
-                const u128 p0 = mul_64x64(rf, Q.lo), p1 = mul_64x64(rf, Q.hi);
-                const uint64_t l1 = p0.hi + p1.lo;
-                const uint64_t l2 = p1.hi + (l1 < p0.hi);
-                if (l2 != 0) {
-                    sat = true;
-                } else {
-                    const u128 c = u128_ceil_div(u128{p0.lo, l1}, Dd);
-                    if (c.hi != 0 || c.lo > 0x7fffffffffffffffull) sat = true;
-                    else v = c.lo;
-                }
-                if (sat) v = 0x7fffffffffffffffull;
-            }
-            out[i] = (int64_t)v;
+    for (int64_t i = bl * kRowsThreads + threadIdx.x; i < M; i += stride) {
+        const uint64_t rf = (uint64_t)rf_in[i];
+        uint64_t v = rf;
+        if (!fallback && rf != 0) {
+            // rf Q = (l2, l1, p0.lo)
+            const u128 p0 = mul_64x64(rf, Q.lo), p1 = mul_64x64(rf, Q.hi);
+            const uint64_t l1 = p0.hi + p1.lo;
+            const uint64_t l2 = p1.hi + (l1 < p0.hi);
+            v = l2 == 0 ? u128_ceil_div(u128{p0.lo, l1}, Dd).lo
+                        : ceil_div_192_by_128(l2, l1, p0.lo, Dd);
         }
+        out[i] = (int64_t)v;
         osum += v;
-        any_sat = any_sat || sat;
     }
-    if (__ballot(any_sat) && lane_id() == 0) atomicOr(as_ull(&st->flags), (ull)SSP_FLAG_SATURATED);
     const uint64_t O = block_sum<kRowsThreads, uint64_t>(osum, s_red);
     if (threadIdx.x == 0 && O) atomicAdd(as_ull(&st->out_sum), (ull)O);
 }
