@@ -134,6 +134,24 @@ __device__ __forceinline__ uint64_t ceil_mul_div_est(uint64_t a, uint64_t b, uin
     return q0 + 1 + ((uint64_t)R != d);
 }
 
+// Part windows in the sampling scan's running sums, which carry them in the
+// upper 32 bits of a packed 64-bit value: a group's count is clamped to
+// budget + 1, and so is the carry between chunks of groups.  A prefix above
+// the budget only has to stay above it (no later group is split then), and
+// with these bounds the field cannot wrap, whatever the counts (a chunk adds
+// at most 1024 (budget + 1) to a carry of at most budget + 1, budget <= 2^13).
+__host__ __device__ __forceinline__ uint32_t clamp_windows(uint32_t wins, uint32_t budget)
+{
+    return wins <= budget ? wins : budget + 1u;
+}
+
+__host__ __device__ __forceinline__ uint64_t saturate_windows_hi(uint64_t packed, uint32_t budget)
+{
+    return (packed >> 32) <= (uint64_t)budget
+               ? packed
+               : (packed & 0xffffffffull) | ((uint64_t)(budget + 1u) << 32);
+}
+
 __host__ __device__ __forceinline__ bool u128_lt(u128 a, u128 b)
 {
     return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo);

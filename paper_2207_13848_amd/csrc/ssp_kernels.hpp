@@ -638,7 +638,8 @@ __device__ __forceinline__ int scan_groups(SampleCounts* __restrict__ cnt, int64
             }
         }
         const uint64_t va[5] = {(uint64_t)x.n1 | ((uint64_t)x.n2 << 32),
-                                (uint64_t)x.n3 | ((uint64_t)wins << 32), x.ns, x.fs, x.as};
+                                (uint64_t)x.n3 | ((uint64_t)clamp_windows(wins, budget) << 32),
+                                x.ns, x.fs, x.as};
         uint64_t ea[5], ta[5];
         block_excl_scan_n<NT, 5>(va, s_red, ea, ta);
         const uint64_t p01 = k01 + ea[0], p2w = k2w + ea[1];
@@ -694,7 +695,7 @@ __device__ __forceinline__ int scan_groups(SampleCounts* __restrict__ cnt, int64
         }
         __syncthreads();  // s_e is rewritten by the next chunk
         k01 += ta[0];
-        k2w += ta[1];
+        k2w = saturate_windows_hi(k2w + ta[1], budget);
         k4 += tb[0];
         km += tb[1];
     }

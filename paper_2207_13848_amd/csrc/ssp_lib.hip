@@ -500,6 +500,17 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind,
     return P;
 }
 
+// The lists index their items with 32-bit offsets: a call whose rows (the
+// sampled candidates, or every row for the exact structure) and part windows
+// reach 2^31 is refused.
+ssp_status plan_fits_lists(ssp_handle h, const Plan& P)
+{
+    if (P.cap4 < (int64_t)INT32_MAX) return SSP_OK;
+    h->last_error = "the call's lists would hold " + std::to_string(P.cap4) +
+                    " items, beyond 32-bit offsets";
+    return SSP_ERR_OVERFLOW;
+}
+
 // Device pointers of a plan in a workspace at `base`; resolves the case
 // table's workspace-backed row-FLOP arrays and statistics.
 struct Bound {
@@ -745,7 +756,9 @@ ssp_status run_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind, 
 {
     prepare_kernels();
     Plan P = make_plan(h, in, kind);
-    ssp_status st = ensure_workspace(h, P.total);
+    ssp_status st = plan_fits_lists(h, P);
+    if (st != SSP_OK) return st;
+    st = ensure_workspace(h, P.total);
     if (st != SSP_OK) return st;
     const Bound b = bind_plan(P, h->ws);
     const bool small = P.n <= kArgCases;
@@ -975,6 +988,7 @@ ssp_status ssp_batch_graph_create(ssp_handle h, int n, const ssp_case* cases,
     if (!g.ok()) return SSP_ERR_NO_DEVICE;
     prepare_kernels();
     Plan P = make_plan(h, in, PLAN_PREDICT);
+    if ((s = plan_fits_lists(h, P)) != SSP_OK) return s;
     if (h->budget && P.total > h->budget) {
         h->last_error = "graph workspace of " + std::to_string(P.total) +
                         " bytes exceeds the budget of " + std::to_string(h->budget);

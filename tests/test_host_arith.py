@@ -48,3 +48,56 @@ def test_ceil_div_192_by_128(wide_div_exe):
         assert int(got) == -(-(a * q) // d), (a, q, d)
         wide += a * q >= 2**128
     assert wide > 100  # most cases need the 192-bit product
+
+
+@pytest.fixture(scope="module")
+def window_scan_exe(tmp_path_factory):
+    if not (os.path.exists(HIPCC) or shutil.which("hipcc")):
+        pytest.skip("hipcc not available")
+    exe = tmp_path_factory.mktemp("hostscan") / "window_scan_check"
+    subprocess.check_call([HIPCC, "--offload-host-only", "-O2", "-std=c++17", "-o", str(exe),
+                           os.path.join(HERE, "host", "window_scan_check.cpp")])
+    return str(exe)
+
+
+def _window_scan(exe, budget, n3, wins):
+    text = f"{budget} {len(n3)}\n" + "".join(f"{a} {w}\n" for a, w in zip(n3, wins))
+    out = subprocess.run([exe], input=text, capture_output=True, text=True,
+                         check=True).stdout.split()
+    return np.array(out, dtype=np.int64).reshape(-1, 3)
+
+
+def test_window_prefix_never_wraps(window_scan_exe):
+    """The sampling scan splits a group's long rows when every part window
+    requested up to and including the group fits the budget.  With the
+    counts clamped, that decision equals the one taken on exact (unbounded)
+    prefixes, and the bin-3 offsets below stay exact, even where the raw
+    window counts would wrap a 32-bit field many times over."""
+    rng = np.random.default_rng(11)
+    cases = []
+    for budget in (1024, 8192):
+        # huge counts from the start: the unclamped field wraps after two groups
+        cases.append((budget, [5] * 3000, [2**31 + 7] * 3000))
+        # small counts that fill the budget, then counts that would wrap
+        w = [int(x) for x in rng.integers(0, 40, 2500)] + [2**32 - 1] * 2000
+        cases.append((budget, [int(x) for x in rng.integers(0, 9, len(w))], w))
+        # a sum of 2^32 exactly early on, then zeros and small counts
+        w = [2**30] * 4 + [0] * 1500 + [int(x) for x in rng.integers(0, 3, 1500)]
+        cases.append((budget, [1] * len(w), w))
+        # wraps inside one chunk, no split after the first overflowing group
+        w = [int(x) for x in rng.integers(0, 2**32, 5000)]
+        cases.append((budget, [int(x) for x in rng.integers(0, 1000, 5000)], w))
+    nsplit = 0
+    for budget, n3, wins in cases:
+        got = _window_scan(window_scan_exe, budget, n3, wins)
+        wp = np.concatenate([[0], np.cumsum(np.array(wins, dtype=object))[:-1]])
+        o3 = np.concatenate([[0], np.cumsum(np.array(n3, dtype=np.int64))[:-1]])
+        split = [int(w != 0 and p + w <= budget) for p, w in zip(wp, wins)]
+        assert np.array_equal(got[:, 2], split), budget
+        assert np.array_equal(got[:, 0], o3 % 2**32), budget
+        # where a group is split, its window offset is the exact prefix
+        for g, s in enumerate(split):
+            if s:
+                assert got[g, 1] == wp[g]
+        nsplit += sum(split)
+    assert nsplit > 200  # the cases do exercise the split decision
