@@ -155,6 +155,33 @@ SSP_API ssp_status ssp_predict_structure_ex(ssp_handle h, const ssp_csr* A, cons
                                     void* stream);
 
 /*
+ * For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * prediction as ssp_predict_structure_ex, same arguments, outputs and
+ * statistics, bit-identical to it, but its workspace is a fixed array of
+ * 256 MiB in the library's device code (one copy per device, taken when the
+ * library loads and held until the process ends) instead of the handle's
+ * workspace.  It calls no hipMalloc, hipFree or other allocating routine and
+ * never blocks the host; it writes none of the handle's workspace and records
+ * no timing events.  A product whose workspace plan does not fit the array
+ * (about 88 bytes per row of A, 80 when row_flop is given, plus the bitmap
+ * windows of split long rows, 1024 of 128 KiB as in the allocating call or,
+ * when the rows leave less room, down to 16: about 3 million rows at most)
+ * returns SSP_ERR_BUDGET, with the sizes in ssp_last_error(), and queues
+ * nothing.  Every call on one device shares that
+ * device's array, whatever the handle: calls whose work overlaps on the
+ * device (different streams, handles or threads) race and give wrong
+ * results; calls queued on one stream are ordered and safe.  Each call
+ * clears what it needs cleared itself; the array keeps the last call's
+ * contents.
+ */
+SSP_API ssp_status ssp_predict_structure_noalloc(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
+                                                 ssp_sampler sampler, double sample_rate,
+                                                 uint64_t seed, int64_t* nnz_pred,
+                                                 int64_t* row_flop, ssp_stats* stats,
+                                                 void* stream);
+
+/*
  * The reference design of the existing sampling estimator on the same sample
  * (Sec. IV-C, Eq. (2)): Z1* = z* / p with p = n_s / M, and every row gets
  *     nnz_ref[i] = ceil(row_flop[i] * z* * M / (n_s * F)),

@@ -23,7 +23,8 @@ from . import _native
 from ._native import (FLAG_EMPTY_SAMPLE, FLAG_SATURATED, SAMPLER_BERNOULLI, SAMPLER_PAPER,
                       SspError)
 
-__all__ = ["DeviceCSR", "Handle", "predict_structure", "reference_estimate", "exact_structure",
+__all__ = ["DeviceCSR", "Handle", "predict_structure", "predict_structure_noalloc",
+           "reference_estimate", "exact_structure",
            "validate_csr", "read_stats", "default_handle", "SspError", "FLAG_EMPTY_SAMPLE",
            "FLAG_SATURATED", "SAMPLER_BERNOULLI", "SAMPLER_PAPER", "version", "spgemm",
            "kmv_estimate"]
@@ -165,6 +166,25 @@ def predict_structure(A: DeviceCSR, B: DeviceCSR, sample_rate: float, seed: int,
         else 0, st.data_ptr(), _stream_ptr(stream))
     h.check(status, "ssp_predict_structure")
     return pred, rf, st
+
+
+def predict_structure_noalloc(A: DeviceCSR, B: DeviceCSR, sample_rate: float, seed: int, *,
+                              sampler="bernoulli", handle=None, stream=None, out, row_flop=None,
+                              stats):
+    """predict_structure into caller-given tensors, with the library's fixed
+    device scratch as its workspace (ssp_predict_structure_noalloc): nothing
+    is allocated, so the call may run under graph capture.  `out` (int64[M]),
+    `stats` (int64[8]) and the optional `row_flop` (int64[M]) are written."""
+    h = handle or default_handle(A.device)
+    M = A.nrows
+    a, b = A._c(), B._c()
+    status = h._lib.ssp_predict_structure_noalloc(
+        h.ptr, ctypes.byref(a), ctypes.byref(b), _sampler_id(sampler), float(sample_rate),
+        int(seed) % (1 << 64), out.data_ptr() if M else 0,
+        row_flop.data_ptr() if row_flop is not None and M else 0, stats.data_ptr(),
+        _stream_ptr(stream))
+    h.check(status, "ssp_predict_structure_noalloc")
+    return out, row_flop, stats
 
 
 def reference_estimate(A: DeviceCSR, B: DeviceCSR, sample_rate: float, seed: int, *,

@@ -31,6 +31,7 @@ EXPORTED = (
     "ssp_server_wait", "ssp_server_info", "ssp_server_reset_stats", "ssp_server_destroy",
     "ssp_default_tuning", "ssp_get_tuning", "ssp_set_tuning", "ssp_autotune",
     "ssp_spgemm_compute", "ssp_spgemm_copy", "ssp_kmv_estimate",
+    "ssp_predict_structure_noalloc",
 )
 
 
@@ -139,10 +140,13 @@ def load():
     lib.ssp_workspace_bytes.restype = ctypes.c_size_t
     lib.ssp_predict_structure.argtypes = [vp, csr_p, csr_p, dbl, u64, vp, vp, vp, vp]
     lib.ssp_predict_structure_ex.argtypes = [vp, csr_p, csr_p, cint, dbl, u64, vp, vp, vp, vp]
+    lib.ssp_predict_structure_noalloc.argtypes = [vp, csr_p, csr_p, cint, dbl, u64, vp, vp, vp,
+                                                  vp]
     lib.ssp_reference_estimate.argtypes = [vp, csr_p, csr_p, cint, dbl, u64, vp, vp, vp]
     lib.ssp_exact_structure.argtypes = [vp, csr_p, csr_p, vp, vp, vp]
     lib.ssp_validate_csr.argtypes = [vp, csr_p, vp, vp]
     for f in ("ssp_create", "ssp_destroy", "ssp_predict_structure", "ssp_predict_structure_ex",
+              "ssp_predict_structure_noalloc",
               "ssp_reference_estimate", "ssp_exact_structure", "ssp_validate_csr"):
         getattr(lib, f).restype = cint
     lib.ssp_status_string.argtypes = [cint]

@@ -124,7 +124,42 @@ struct ssp_batch_graph_s {
     int n = 0;
 };
 
+// Scratch of ssp_predict_structure_noalloc: its whole workspace, one copy per
+// device, held from the library's load until the process ends.  Host code
+// reaches it only through the address hipGetSymbolAddress gives for each
+// device (noalloc_base); the array's name is not a device address on the
+// host.
+constexpr size_t kNoAllocBytes = 256ull << 20;
+constexpr int64_t kNoAllocMinWindows = 16;  // part windows it may shrink to
+static __device__ __align__(256) unsigned char scratch[kNoAllocBytes];
+
 namespace {
+
+// The scratch array's device address per device, taken once per device with
+// that device current (at ssp_create).
+constexpr int kNoAllocDevices = 64;
+struct NoAllocSlot {
+    std::once_flag once;
+    void* ptr = nullptr;
+    hipError_t err = hipSuccess;
+};
+NoAllocSlot g_noalloc[kNoAllocDevices];
+
+void noalloc_init(int device)
+{
+    if (device < 0 || device >= kNoAllocDevices) return;
+    NoAllocSlot& s = g_noalloc[device];
+    std::call_once(s.once, [&s] {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e == hipSuccess && p) {
+            s.ptr = p;
+        } else {
+            (void)hipGetLastError();
+            s.err = e == hipSuccess ? hipErrorInvalidSymbol : e;
+        }
+    });
+}
 
 class DeviceGuard {
   public:
@@ -837,6 +872,10 @@ ssp_status ssp_create(ssp_handle* out, int device, size_t hbm_budget_bytes)
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess && prop.multiProcessorCount > 0)
         h->num_cus = prop.multiProcessorCount;
+    {
+        DeviceGuard g(device);
+        if (g.ok()) noalloc_init(device);
+    }
     *out = h;
     return SSP_OK;
 }
@@ -921,6 +960,42 @@ ssp_status ssp_predict_structure(ssp_handle h, const ssp_csr* A, const ssp_csr* 
 {
     return ssp_predict_structure_ex(h, A, B, SSP_SAMPLER_BERNOULLI, sample_rate, seed, nnz_pred,
                                     row_flop, stats, stream);
+}
+
+ssp_status ssp_predict_structure_noalloc(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
+                                         ssp_sampler sampler, double rate, uint64_t seed,
+                                         int64_t* nnz_pred, int64_t* row_flop, ssp_stats* stats,
+                                         void* stream)
+{
+    const ssp_status s = common_checks(h, A, B, sampler, rate, nnz_pred);
+    if (s != SSP_OK) return s;
+    DeviceGuard g(h->device);
+    if (!g.ok()) return SSP_ERR_NO_DEVICE;
+    if (h->device >= kNoAllocDevices) {
+        h->last_error = "no scratch array on device " + std::to_string(h->device);
+        return SSP_ERR_NO_DEVICE;
+    }
+    const NoAllocSlot& slot = g_noalloc[h->device];
+    if (!slot.ptr) return hip_fail(h, slot.err, "hipGetSymbolAddress(scratch)");
+    prepare_kernels();
+    // the plan of the allocating call; when it does not fit the array, fewer
+    // part windows (rows split less, the counts are the same)
+    const std::vector<CaseIn> in{case_in(A, B, sampler, rate, seed, nnz_pred, row_flop, stats)};
+    Plan P;
+    for (int64_t pw = kPartWindowsBase; pw >= kNoAllocMinWindows; pw /= 2) {
+        P = make_plan(h, in, PLAN_PREDICT, pw);
+        if (P.total <= kNoAllocBytes) break;
+    }
+    const ssp_status fit = plan_fits_lists(h, P);
+    if (fit != SSP_OK) return fit;
+    if (P.total > kNoAllocBytes) {
+        h->last_error = "ssp_predict_structure_noalloc: needs " + std::to_string(P.total) +
+                        " bytes of scratch, the fixed array holds " +
+                        std::to_string(kNoAllocBytes);
+        return SSP_ERR_BUDGET;
+    }
+    const Bound b = bind_plan(P, slot.ptr);
+    return launch_plan(h, P, b, static_cast<hipStream_t>(stream), false, false);
 }
 
 ssp_status ssp_reference_estimate(ssp_handle h, const ssp_csr* A, const ssp_csr* B,
