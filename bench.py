@@ -54,6 +54,11 @@ def parse():
     return ap.parse_args()
 
 
+def progress(msg: str):
+    """A progress line on stderr (the JSON result goes to stdout)."""
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
 def copy_calibration(nbytes: int):
     import torch
     n = nbytes // 4
@@ -121,15 +126,66 @@ def long_row_mask(rf_s, ncols: int):
     return rf_s > lim
 
 
-def sweep_compare(ssp, params, reps: int = 3):
+def eps_from_stats(s: dict, Z: int) -> dict:
+    """The errors of Sec. VI-A from one prediction's integer statistics and
+    the exact total Z: eps1 = Z1*/Z - 1 with Z1* = z* M / n_s (Eq. (2)),
+    epsf = F*/F - 1 with F* = f* M / n_s (Eq. (3)), eps2 = Z2*/Z - 1 with
+    Z2* = F z* / f* (Eq. (4)), eps2_alloc = (sum of the per-row ceilings)/Z - 1.
+    Each is the exact rational's nearest double (Python's int / int rounds
+    correctly); None where an estimate or the truth is zero."""
+    M, F = s["nrows"], s["total_flop"]
+    ns, fs, zs = s["n_sampled"], s["sample_flop"], s["sample_nnz"]
+    out = {"eps1": None, "epsf": None, "eps2": None, "eps2_alloc": None}
+    if Z > 0 and ns > 0:
+        out["eps1"] = (zs * M - ns * Z) / (ns * Z)
+    if F > 0 and ns > 0:
+        out["epsf"] = (fs * M - ns * F) / (ns * F)
+    if Z > 0 and fs > 0:
+        out["eps2"] = (F * zs - fs * Z) / (fs * Z)
+    if Z > 0:
+        out["eps2_alloc"] = (s["out_sum"] - Z) / Z
+    return out
+
+
+def summarise_eps(recs) -> dict:
+    """Mean and worst |eps| over cases (Sec. VI-A's statistics) from
+    (structure, eps dict) records; cases with an undefined eps are counted
+    as excluded."""
+    import numpy as np
+    keep = [(st, e) for st, e in recs if None not in (e["eps1"], e["epsf"], e["eps2"])]
+    out = {"cases": len(keep), "excluded": len(recs) - len(keep)}
+    if not keep:
+        return out
+    arr = {k: np.array([e[k] for _, e in keep]) for k in ("eps1", "epsf", "eps2", "eps2_alloc")}
+    for k, v in arr.items():
+        out[f"mean_abs_{k}"] = float(np.mean(np.abs(v)))
+        out[f"worst_abs_{k}"] = float(np.max(np.abs(v)))
+    out["frac_abs_eps2_lt_abs_eps1"] = float(np.mean(np.abs(arr["eps2"]) < np.abs(arr["eps1"])))
+    out["by_structure"] = {}
+    sts = np.array([st for st, _ in keep])
+    for name in sorted(set(sts.tolist())):
+        m = sts == name
+        out["by_structure"][name] = {"mean_abs_eps1": float(np.mean(np.abs(arr["eps1"][m]))),
+                                     "mean_abs_eps2": float(np.mean(np.abs(arr["eps2"][m]))),
+                                     "worst_abs_eps2": float(np.max(np.abs(arr["eps2"][m])))}
+    return out
+
+
+def sweep_compare(ssp, params, reps: int = 3, accuracy: bool = False):
     """Plain (one call per matrix, back to back on one stream) vs batched (one
     ssp_predict_batch) vs graph (one launch of a captured batch) over the given
     sweep cases; the three outputs are checked equal.  Times in ms: minimum
-    over `reps` timed runs after one warm-up."""
+    over `reps` timed runs after one warm-up.  With `accuracy`, every case's
+    exact structure (ssp_exact_structure) judges the batch's prediction:
+    mean and worst |eps1|, |eps2|, |epsf| over the cases."""
     import torch
     import workloads
     t0 = time.time()
-    hosts = [workloads.sweep_workload(p) for p in params]
+    hosts = []
+    for k, p in enumerate(params):
+        hosts.append(workloads.sweep_workload(p))
+        if k % 125 == 124:
+            progress(f"generated {k + 1}/{len(params)} cases")
     t_gen = time.time() - t0
     dev = "cuda:0"
     h = ssp.default_handle(dev)
@@ -147,6 +203,7 @@ def sweep_compare(ssp, params, reps: int = 3):
             "graph": g.launch}
     ms = {}
     for name, fn in runs.items():
+        progress(f"timing {name}")
         fn()
         torch.cuda.synchronize()
         best = None
@@ -177,6 +234,19 @@ def sweep_compare(ssp, params, reps: int = 3):
     out["speedup_graph_vs_plain"] = round(ms["plain"] / ms["graph"], 2)
     out["graph_gbps_algorithmic"] = round(out["algorithmic_bytes"] / (ms["graph"] * 1e-3) / 1e9, 1)
     g.close()
+    if accuracy:
+        ta = time.time()
+        maxM = max(w.A.nrows for w in hosts)
+        ex = torch.empty(maxM, dtype=torch.int64, device=dev)
+        est = torch.zeros(8, dtype=torch.int64, device=dev)
+        recs = []
+        for p, A, c in zip(params, devA, batch):
+            ssp.exact_structure(A, A, handle=h, out=ex[:A.nrows], stats=est)
+            Z = ssp.read_stats(est)["out_sum"]
+            recs.append((p[0], eps_from_stats(ssp.read_stats(c.stats), Z)))
+        out["accuracy"] = summarise_eps(recs)
+        out["accuracy"]["sampler"] = "bernoulli-splitmix64, rate 1%"
+        out["accuracy"]["exact_s"] = round(time.time() - ta, 1)
     return out
 
 
@@ -201,7 +271,7 @@ def main_sweep(args):
         "sweep": r}), flush=True)
 
 
-def main_serve(args):
+def serve_run(ssp) -> dict:
     """Serving: Poisson arrivals (2000/s) of A.A predictions over a
     device-resident pool of 64 matrices (rows 2^U, U ~ Uniform[10, 21],
     structure uniform over the five generators, d uniform over 2..32, rate 1%),
@@ -210,11 +280,7 @@ def main_serve(args):
     prediction made alone."""
     import numpy as np
     import torch
-    import paper_2207_13848_amd as ssp
     import workloads
-    if not torch.cuda.is_available():
-        print(json.dumps({"error": "no GPU visible"}))
-        sys.exit(1)
     rng = np.random.default_rng(8)
     t0 = time.time()
     pool = []
@@ -273,13 +339,9 @@ def main_serve(args):
     sat_reqs, sat_wall, sat_info = run(4000, None)
     sat_rows = sum(pool[r[1]].nrows for r in sat_reqs)
     srv.close()
-    print(json.dumps({
-        "metric": "served requests/s with p50/p99 latency (Poisson 2000/s, continuous batching)",
-        "value": round(len(reqs) / wall, 1), "unit": "requests/s", "n_gpus": 1,
-        "steps": len(reqs), "warmup": len(warm), "ms_per_step": round(1e3 * wall / len(reqs), 4),
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
-        "data": "synthetic",
-        "config": {"workload": "serve_poisson2000", "pool": len(pool),
+    return {
+        "requests_per_s": round(len(reqs) / wall, 1), "requests": len(reqs),
+        "warmup": len(warm), "config": {"workload": "serve_poisson2000", "pool": len(pool),
                    "pool_rows_mean": float(np.mean([m.nrows for m in pool])),
                    "pool_nnz_total": int(sum(m.nnz for m in pool)), "sample_rate": 0.01,
                    "slots": 4, "slot_bytes": 2 << 30, "max_batch": 64, "duration_s": duration},
@@ -299,7 +361,24 @@ def main_serve(args):
                        "batches": sat_info["batches"],
                        "max_batch_seen": sat_info["max_batch_seen"],
                        "max_slots_busy": sat_info["max_slots_busy"]},
-        "results_equal_alone": f"{ok}/{nchk}", "generate_s": round(t_gen, 1)}), flush=True)
+        "results_equal_alone": f"{ok}/{nchk}", "generate_s": round(t_gen, 1)}
+
+
+def main_serve(args):
+    import torch
+    import paper_2207_13848_amd as ssp
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    r = serve_run(ssp)
+    print(json.dumps({
+        "metric": "served requests/s with p50/p99 latency (Poisson 2000/s, continuous batching)",
+        "value": r["requests_per_s"], "unit": "requests/s", "n_gpus": 1,
+        "steps": r["requests"], "warmup": r["warmup"],
+        "ms_per_step": round(1e3 / r["requests_per_s"], 4),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "int64",
+        "data": "synthetic", **{k: v for k, v in r.items() if k not in ("requests_per_s",)}}),
+        flush=True)
 
 
 def main_accuracy(args):
@@ -582,40 +661,16 @@ def phase_times(ssp, handle):
     return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(n)}
 
 
-def main():
-    args = parse()
-    if args.copy_calibration:
-        copy_calibration(args.copy_calibration)
-        return
-    world = int(os.environ.get("WORLD_SIZE", "1"))
-    if args.gpus != 1 or world != 1:
-        print(json.dumps({"error": "this build runs on one GPU only: bench.py --gpus 1 "
-                                   "(the multi-GPU sharding is a design note, not built)"}))
-        sys.exit(2)
-
-    if args.workload == "sweep":
-        main_sweep(args)
-        return
-    if args.workload == "serve":
-        main_serve(args)
-        return
-    if args.workload == "accuracy":
-        main_accuracy(args)
-        return
-    if args.workload in ("spgemm", "spgemm_rmat18"):
-        main_spgemm(args)
-        return
-
+def measure(ssp, w, args, *, extras: bool, cpu: bool) -> dict:
+    """One workload's line: K timed predictions on device-resident inputs,
+    100 single-call device times, the phase-timed region and the roofline of
+    its dominant kernel; with `extras` the reference design, the exact
+    structure, the accuracy and the sketch on the same input; with `cpu` the
+    oracle timed on the host."""
     import numpy as np
     import torch
-    import paper_2207_13848_amd as ssp
-
-    if not torch.cuda.is_available():
-        print(json.dumps({"error": "no GPU visible"}))
-        sys.exit(1)
     dev = "cuda:0"
     t_gen = time.time()
-    w = get_workload(args.workload)
     A, B = w.A, w.B
     aliased = B is A
     Ad = ssp.DeviceCSR.from_csr(A, dev)
@@ -746,7 +801,7 @@ def main():
         "generate_s": round(t_gen, 2),
     }
 
-    if not args.no_extras:
+    if extras:
         # reference design and exact structure on the same input
         ref_out = torch.empty(M, dtype=torch.int64, device=dev)
         ref_st = torch.zeros(8, dtype=torch.int64, device=dev)
@@ -794,12 +849,7 @@ def main():
         result["accuracy"]["eps_kmv_p10_k1024"] = (kmv["nnz_estimate"] / Z - 1) if Z and \
             kmv["nnz_estimate"] is not None else None
 
-    if not args.no_extras:
-        # batched vs plain on the small end of the sweep (sizes 2^12, 2^14: 250 cases)
-        import workloads
-        result["batch"] = sweep_compare(ssp, workloads.sweep_cases(sizes=(1 << 12, 1 << 14)))
-
-    if not args.no_cpu_baseline:
+    if cpu:
         import oracle
         cores = 1
         oracle.predict(A, B, w.rate, w.seed)  # warm-up (page-in)
@@ -823,7 +873,68 @@ def main():
             "sample": f"the whole {w.name} prediction (all {M} rows), serial C oracle, "
                       f"1 warm-up + {runs} timed runs, {t_cpu:.2f} s each",
             "host_cpu": cpu_model, "host_nproc": os.cpu_count()}
+    return result
 
+
+# The other configurations measured beside the headline R-MAT line: the
+# uniform 4096^2 product (1%), the 27-point stencil 128^3 squared and the
+# stencil times a 2,097,152 x 65,536 uniform B (0.5%).
+OTHER_CONFIGS = ("uniform4096", "stencil128", "stencil128_x_uniform")
+CONFIG_KEYS = ("value", "unit", "ms_per_step", "config", "hbm_gbps_algorithmic", "nnz_A_per_s",
+               "step_algorithmic_bytes", "roofline", "phases", "call_ms", "stats")
+
+
+def main():
+    args = parse()
+    if args.copy_calibration:
+        copy_calibration(args.copy_calibration)
+        return
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print(json.dumps({"error": "this build runs on one GPU only: bench.py --gpus 1 "
+                                   "(the multi-GPU sharding is a design note, not built)"}))
+        sys.exit(2)
+
+    if args.workload == "sweep":
+        main_sweep(args)
+        return
+    if args.workload == "serve":
+        main_serve(args)
+        return
+    if args.workload == "accuracy":
+        main_accuracy(args)
+        return
+    if args.workload in ("spgemm", "spgemm_rmat18"):
+        main_spgemm(args)
+        return
+
+    import torch
+    import paper_2207_13848_amd as ssp
+
+    if not torch.cuda.is_available():
+        print(json.dumps({"error": "no GPU visible"}))
+        sys.exit(1)
+    progress(f"workload {args.workload}")
+    result = measure(ssp, get_workload(args.workload), args, extras=not args.no_extras,
+                     cpu=not args.no_cpu_baseline)
+    if not args.no_extras and args.workload == "rmat20":
+        # every other configuration of the benchmark, each with its roofline
+        result["configs"] = {}
+        for name in OTHER_CONFIGS:
+            progress(f"workload {name}")
+            r = measure(ssp, get_workload(name), args, extras=False, cpu=False)
+            result["configs"][r["config"]["workload"]] = {k: r[k] for k in CONFIG_KEYS}
+            torch.cuda.empty_cache()
+        # the 625-case sweep: plain vs batched vs graph, accuracy against the
+        # exact structure
+        import workloads
+        progress("625-case sweep")
+        result["sweep"] = sweep_compare(ssp, workloads.sweep_cases(), accuracy=True)
+        torch.cuda.empty_cache()
+        # serving: Poisson arrivals at 2000/s with continuous batching
+        progress("serving")
+        result["serve"] = serve_run(ssp)
+    progress("done")
     print(json.dumps(result), flush=True)
 
 

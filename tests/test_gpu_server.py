@@ -1,12 +1,17 @@
 """Serving with continuous batching: every request's result equals the
-per-matrix call bit for bit, alone or in a mix of concurrent requests; batches
-run on several slots at once; errors come back at submission."""
+per-matrix call and the CPU oracle bit for bit, alone or in a mix of
+concurrent requests; batches run on several slots at once; errors come back
+at submission."""
+import os
 import time
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
 
+import oracle
 import workloads
+from tests.test_gpu_parity import STAT_KEYS
 
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
@@ -45,8 +50,17 @@ def _alone(ssp, devs, j, rate, seed):
     return p, st
 
 
+def _oracle_many(jobs):
+    """oracle.predict of every (matrix, rate, seed) job, on a thread pool (the
+    oracle's C calls release the interpreter lock)."""
+    workers = max(1, min(16, os.cpu_count() or 1))
+    with ThreadPoolExecutor(workers) as ex:
+        res = list(ex.map(lambda j: oracle.predict(j[0], j[0], j[1], j[2]), jobs))
+    return res
+
+
 def test_server_results_equal_single_calls(ssp, pool):
-    _, devs = pool
+    mats, devs = pool
     srv = ssp.Server(slots=3, slot_bytes=1 << 30, max_batch=16)
     ids = [srv.register(d) for d in devs]
     rng = np.random.default_rng(7)
@@ -71,6 +85,15 @@ def test_server_results_equal_single_calls(ssp, pool):
         assert torch.equal(out, p), f"ticket {t}: nnz_pred differs from the single call"
         assert torch.equal(st, s), f"ticket {t}: stats differ from the single call"
     srv.close()
+    # every served result against the CPU oracle
+    t0 = time.time()
+    orc = _oracle_many([(mats[j], rate, seed) for _, j, rate, seed, _, _ in reqs])
+    _say(f"oracle for {len(reqs)} requests in {time.time() - t0:.1f}s")
+    for (t, j, rate, seed, out, st), (o_pred, _, o_st) in zip(reqs, orc):
+        assert np.array_equal(out.cpu().numpy(), o_pred), f"ticket {t}: nnz_pred != oracle"
+        got = ssp.read_stats(st)
+        for k in STAT_KEYS:
+            assert got[k] == getattr(o_st, k), f"ticket {t}: stats.{k} != oracle"
 
 
 def test_server_request_alone_equals_request_in_mix(ssp, pool):
