@@ -542,6 +542,17 @@ __device__ __forceinline__ void lane_bitmap_insert_all(uint32_t* bm, const uint3
 typedef int32_t i32x2u __attribute__((ext_vector_type(2), aligned(4)));
 typedef int32_t i32x4u __attribute__((ext_vector_type(4), aligned(4)));
 
+// A raw buffer resource over the `bytes` bytes at p (clamped to 2^32 - 1).
+// Loads through it at a byte offset (register plus instruction offset) at or
+// past the end return 0 and touch no memory.
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_rsrc(const SSP_GLOBAL void* p,
+                                                              uint64_t bytes)
+{
+    const uint32_t n = bytes < 0xFFFFFFFFull ? (uint32_t)bytes : 0xFFFFFFFFu;
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>((const void*)p), (short)0, (int)n,
+                                             0x00020000);
+}
+
 // Length of row k of a CSR matrix from its row pointers: one 8-byte read
 // of rpt[k], rpt[k+1].
 __device__ __forceinline__ uint32_t csr_row_len(const SSP_GLOBAL int32_t* __restrict__ rpt,

@@ -1475,11 +1475,12 @@ __device__ __forceinline__ void emit_row(const CaseDesc* __restrict__ cs, int c,
 // Merge-path tile b of a case covers the items [b T, (b+1) T) of the sequence
 // that interleaves A's entries with one end marker per row (Merrill &
 // Garland, SC16), so every tile has at most T = kFlopTile rows + entries
-// whatever the row lengths.  A tile's entries are loaded with two 16-byte
-// loads per thread (each load instruction fully coalesced, non-temporal so the
-// stream does not evict B's row pointers from L2) and each contributes the
-// length of the B row it names (one 8-byte gather).  An exclusive scan of
-// these lengths gives the running product count at every row boundary, and a
+// whatever the row lengths.  A tile's entries are loaded in runs of 64
+// consecutive entries per load instruction (fully coalesced, non-temporal so
+// the stream does not evict B's row pointers from L2) and each contributes
+// the length of the B row it names (one 8-byte gather, consecutive entries in
+// consecutive lanes).  An exclusive scan of these lengths (in 32 bits when the
+// lengths allow) gives the running product count at every row boundary, and a
 // row's count is the difference of its two boundaries.  Rows that begin in an
 // earlier tile or end in a later one leave their partial counts in the tile's
 // metadata for k_flop_fixup.
@@ -1498,23 +1499,11 @@ struct FlopTileRegs {
     const SSP_GLOBAL int32_t* Arpt;
     const SSP_GLOBAL int32_t* Brpt;
     SSP_GLOBAL int64_t* out;
-    int64_t M, nnzA;
+    int64_t M, nnzA, K;
     int64_t i0, i1, j0, j1, a0;
-    int4 col[2];   // as loaded; shifted by sh[q] positions when the load was clamped
-    int32_t sh[2];
+    int32_t col[8];  // entry q HALF + 256 wave + 64 l + lane in col[4 q + l]
     int32_t rp[kFlopTile / kFlopThreads + 1];
 };
-
-// Column index of position l of the loaded quad (see flop_issue_tile).
-// (written with masks, not an index, so the quad stays in registers)
-__device__ __forceinline__ int32_t quad_at(int32_t w0, int32_t w1, int32_t w2, int32_t w3, int sh,
-                                           int l)
-{
-    const int i = l + sh;  // 0..6; only 0..3 are used unmasked
-    const int32_t m0 = -(int32_t)(i == 0), m1 = -(int32_t)(i == 1), m2 = -(int32_t)(i == 2);
-    const int32_t m3 = ~(m0 | m1 | m2);
-    return (w0 & m0) | (w1 & m1) | (w2 & m2) | (w3 & m3);
-}
 
 // Issues the loads of global tile g of case c, whose rows are [i0, i1].
 template <int MODE, bool VEC>
@@ -1535,6 +1524,7 @@ __device__ __forceinline__ void flop_issue_tile(const CaseDesc* __restrict__ cs,
     const int64_t M = cd.A.nrows, nnzA = cd.A.nnz;
     R.M = M;
     R.nnzA = nnzA;
+    R.K = cd.B.nrows;
     const int64_t d0 = (g - cd.tile_base) * kFlopTile;
     const int64_t d1 = (d0 + kFlopTile) < (M + nnzA) ? (d0 + kFlopTile) : (M + nnzA);
     i0 = (int64_t)__builtin_amdgcn_readfirstlane((int)i0);
@@ -1546,38 +1536,52 @@ __device__ __forceinline__ void flop_issue_tile(const CaseDesc* __restrict__ cs,
     R.a0 = R.j0 & ~(int64_t)3;
     const int64_t rlast = i1 < M ? i1 : M - 1;
     const int nb = (int)(rlast - i0 + 2);
+    if (VEC) {
+        // buffer loads: the row bounds past the tile's read 0 (no clamps)
+        const __amdgpu_buffer_rsrc_t rr = buffer_rsrc(R.Arpt + i0, 4 * (uint64_t)nb);
 #pragma unroll
-    for (int u = 0; u < NRP; ++u) {
-        const int k = t + u * NT;
-        R.rp[u] = R.Arpt[i0 + (k < nb ? k : nb - 1)];
+        for (int u = 0; u < NRP; ++u)
+            R.rp[u] = __builtin_amdgcn_raw_buffer_load_b32(rr, 4u * (uint32_t)(t + u * NT), 0, 0);
+    } else {
+#pragma unroll
+        for (int u = 0; u < NRP; ++u) {
+            const int k = t + u * NT;
+            R.rp[u] = R.Arpt[i0 + (k < nb ? k : nb - 1)];
+        }
     }
-    // Loads are unconditional from clamped in-range addresses (masked later):
-    // a load under a lane condition becomes a branch, and loads in separate
-    // branches are not kept in flight together.  VEC needs nnz(A) >= 4.
+    // Loads are unconditional (masked later): a load under a lane condition
+    // becomes a branch, and loads in separate branches are not kept in flight
+    // together.  The fast form (VEC) reads through buffer resources, whose
+    // lanes past the end read 0, the other form from clamped addresses.  Each
+    // wave loads its 256 entries of a half as four runs of 64 consecutive
+    // entries, one per load instruction, so that the gathers see consecutive
+    // entries in consecutive lanes: in banded and stencil-like rows those name
+    // nearby B rows, whose row pointers then share few cache lines per
+    // instruction (the first-level cache looks up one line per clock).
+    const int lane = t & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(t / kWave);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
-        const int64_t p = R.a0 + q * HALF + 4 * t;
-        int4 v;
+        const int64_t sb = R.a0 + q * HALF + 4 * kWave * wv;  // uniform
         if (VEC) {
-            typedef int v4i __attribute__((ext_vector_type(4)));
-            const int64_t pl = (p + 3 < nnzA) ? p : nnzA - 4; // 4-byte aligned when clamped
-            const v4i w = __builtin_nontemporal_load(reinterpret_cast<const v4i*>(Acol + pl));
-            v = make_int4(w.x, w.y, w.z, w.w);
-            // positions >= nnz(A) are masked anyway; cap the shift so quad_at stays in range
-            const int64_t sh = p - pl;
-            R.sh[q] = (int32_t)(sh < 3 ? sh : 3);
+            // a buffer over the wave's segment: entries past the last read 0;
+            // one offset register, the runs at instruction offsets
+            // (non-temporal: the stream should not evict B's row pointers)
+            const __amdgpu_buffer_rsrc_t rc =
+                buffer_rsrc(Acol + (sb < nnzA ? sb : 0), sb < nnzA ? 4 * (uint64_t)(nnzA - sb) : 0);
+#pragma unroll
+            for (int l = 0; l < 4; ++l)
+                R.col[4 * q + l] = __builtin_amdgcn_raw_buffer_load_b32(
+                    rc, 4u * (uint32_t)lane + 4u * kWave * l, 0, 2);
         } else {
-            R.sh[q] = 0;
-            v = make_int4(0, 0, 0, 0);
-            if (nnzA > 0) {  // A may have no entries (and no column array) at all
-                const int64_t last = nnzA - 1;
-                v.x = Acol[(p + 0) < last ? (p + 0) : last];
-                v.y = Acol[(p + 1) < last ? (p + 1) : last];
-                v.z = Acol[(p + 2) < last ? (p + 2) : last];
-                v.w = Acol[(p + 3) < last ? (p + 3) : last];
+#pragma unroll
+            for (int l = 0; l < 4; ++l) {
+                const int64_t p = sb + kWave * l + lane;
+                int32_t v = 0;
+                if (nnzA > 0)  // A may have no entries (and no column array) at all
+                    v = Acol[p < nnzA ? p : nnzA - 1];
+                R.col[4 * q + l] = v;
             }
         }
-        R.col[q] = v;
     }
 }
 
@@ -1604,7 +1608,7 @@ void k_flop(const CaseDesc* __restrict__ cs,
     constexpr int NT = kFlopThreads, CH = kFlopChunk, HALF = CH / 2;
     constexpr int T = (int)kFlopTile, NRP = kFlopTile / kFlopThreads + 1;
     __shared__ int32_t s_bnd[T + 2];
-    __shared__ uint32_t s_x[CH];
+    __shared__ __align__(16) uint32_t s_x[CH];
     __shared__ uint64_t s_pre0[NT], s_pre1[NT];
     __shared__ uint64_t s_w[2 * (NT / kWave)];
     __shared__ uint32_t s_base[4];  // (binning: the bins' offsets of a round of rows)
@@ -1646,20 +1650,35 @@ void k_flop(const CaseDesc* __restrict__ cs,
         const int64_t i0 = cur.i0, i1 = cur.i1, j0 = cur.j0, j1 = cur.j1, a0 = cur.a0;
         const int64_t M = cur.M;
         const SSP_GLOBAL int32_t* __restrict__ Brpt = cur.Brpt;
-        uint32_t x[8];
+        uint32_t x[8];  // (entry q HALF + 256 wave + 64 l + lane in x[4 q + l])
+        // VEC: B has fewer than 2^30 rows (the host checks), so its row
+        // pointers are read through a buffer resource at 32-bit byte offsets
+        // (one address register per lane).  Entry j is live when
+        // j0 <= j < j1; relative to a0 both bounds are small (j0 - a0 < 4,
+        // j1 - a0 <= kFlopChunk).
+        const int rlo = (int)(j0 - a0), rhi = (int)(j1 - a0);
+        const __amdgpu_buffer_rsrc_t brs = buffer_rsrc(Brpt, VEC ? 4 * (uint64_t)(cur.K + 1) : 0);
 #pragma unroll
         for (int q = 0; q < 2; ++q) {
-            const int64_t p = a0 + q * HALF + 4 * t;
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
-                const int64_t j = p + l;
-                const bool in = j >= j0 && j < j1;
-                const int32_t cc = quad_at(cur.col[q].x, cur.col[q].y, cur.col[q].z,
-                                           cur.col[q].w, cur.sh[q], l);
+                const int rel = q * HALF + kWave * (4 * wid + l) + lane;
+                const bool in = rel >= rlo && rel < rhi;
+                const int32_t cc = in ? cur.col[4 * q + l] : 0;
                 uint32_t len = 0;
                 // row 0 of B when masked; with no entries at all (then K may be
                 // 0 and B's row pointers hold one value) nothing is read
-                if (VEC || cur.nnzA > 0) len = csr_row_len(Brpt, in ? cc : 0);
+                if (VEC || cur.nnzA > 0) {
+                    if (VEC) {
+                        // masked lanes read past the end: 0
+                        typedef int32_t v2i __attribute__((ext_vector_type(2)));
+                        const uint32_t off = in ? 4u * (uint32_t)cc : 0xFFFFFFF8u;
+                        const v2i v = __builtin_amdgcn_raw_buffer_load_b64(brs, off, 0, 0);
+                        len = (uint32_t)(v.y - v.x);
+                    } else {
+                        len = csr_row_len(Brpt, cc);
+                    }
+                }
                 x[4 * q + l] = in ? len : 0u;
             }
         }
@@ -1674,16 +1693,30 @@ void k_flop(const CaseDesc* __restrict__ cs,
             const int k = t + u * NT;
             if (u * NT < nb && k < nb) s_bnd[k] = cur.rp[u];
         }
-        uint64_t s0 = 0, s1 = 0;
+        // the lengths in entry order; each thread then takes its four
+        // consecutive entries of each half (the wave's own segment of s_x:
+        // LDS operations of a wave complete in order, no barrier needed)
 #pragma unroll
-        for (int l = 0; l < 4; ++l) {
-            s_x[4 * t + l] = x[l];
-            s_x[HALF + 4 * t + l] = x[4 + l];
-            s0 += x[l];
-            s1 += x[4 + l];
+        for (int q = 0; q < 2; ++q)
+#pragma unroll
+            for (int l = 0; l < 4; ++l) s_x[q * HALF + kWave * (4 * wid + l) + lane] = x[4 * q + l];
+        __builtin_amdgcn_wave_barrier();
+        const uint4 xq0 = *reinterpret_cast<const uint4*>(&s_x[4 * t]);
+        const uint4 xq1 = *reinterpret_cast<const uint4*>(&s_x[HALF + 4 * t]);
+        const uint64_t s0 = (uint64_t)xq0.x + xq0.y + xq0.z + xq0.w;
+        const uint64_t s1 = (uint64_t)xq1.x + xq1.y + xq1.z + xq1.w;
+        // exclusive scans of the two halves, in lockstep; in 32 bits when
+        // every length the wave holds is below 2^21 (its sums then stay below
+        // 2^29), the usual case
+        const uint32_t orx = xq0.x | xq0.y | xq0.z | xq0.w | xq1.x | xq1.y | xq1.z | xq1.w;
+        uint64_t i0s, i1s;
+        if (!__any(orx >= (1u << 21))) {
+            i0s = wave_incl_scan<uint32_t>((uint32_t)s0);
+            i1s = wave_incl_scan<uint32_t>((uint32_t)s1);
+        } else {
+            i0s = wave_incl_scan(s0);
+            i1s = wave_incl_scan(s1);
         }
-        // exclusive scans of the two halves, in lockstep
-        const uint64_t i0s = wave_incl_scan(s0), i1s = wave_incl_scan(s1);
         if (lane == kWave - 1) {
             s_w[wid] = i0s;
             s_w[NT / kWave + wid] = i1s;

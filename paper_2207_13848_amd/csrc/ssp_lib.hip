@@ -468,7 +468,9 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind,
         sumC += d.ncand;
         P.win_words_max = std::max(P.win_words_max, d.win_words);
         if (d.nwin != 1) P.win1 = false;
-        if (M > 0 && !((reinterpret_cast<uintptr_t>(x.A.col) & 15u) == 0 && nnz >= 4)) P.vec = false;
+        // (the streaming kernel's fast form reads through buffer resources:
+        // B's row pointers at 32-bit byte offsets)
+        if (M > 0 && (nnz < 1 || x.B.nrows >= ((int64_t)1 << 30))) P.vec = false;
         exp_rows += kind == PLAN_EXACT ? M : (d.paper ? d.ncand : (int64_t)(x.rate * (double)M));
     }
     P.bin2_wave = exp_rows >= kBin2WaveRows;

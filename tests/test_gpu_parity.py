@@ -7,6 +7,7 @@ boundaries, split long rows and multi-window bitmaps, with ragged tails; the
 full-size workloads run in the launch configuration the benchmark times.
 """
 import ctypes
+import hashlib
 import json
 import os
 
@@ -72,14 +73,31 @@ def check_reference(ssp, A, B, rate, seed, sampler="bernoulli", Ad=None, Bd=None
     _check_stats(ssp.read_stats(st), o_st, "reference")
 
 
-def check_exact(ssp, A, B, Ad=None, Bd=None, full_limit=10 ** 8):
-    """Every row when the serial oracle can afford it (F <= full_limit), else
-    the 40 longest rows and 2000 random rows one by one plus F and the sum."""
+def _exact_golden(name):
+    """The oracle's every-row exact structure of a full-size product, as
+    written by tests/golden/make_exact_oracle.py (Z, F, SHA-256 of nnz_exact
+    as little-endian int64)."""
+    with open(os.path.join(GOLDEN, "exact_oracle.json")) as f:
+        return json.load(f)[name]
+
+
+def check_exact(ssp, A, B, Ad=None, Bd=None, full_limit=10 ** 8, golden=None):
+    """Every row when the serial oracle can afford it (F <= full_limit), or
+    against the stored digest of the oracle's every-row result (`golden`);
+    else (and besides) the 40 longest rows and 2000 random rows one by one
+    plus F and the sum."""
     Ad = Ad if Ad is not None else _dev(ssp, A)
     Bd = Bd if Bd is not None else (Ad if B is A else _dev(ssp, B))
     ex, st = ssp.exact_structure(Ad, Bd)
     torch.cuda.synchronize()
     ex = ex.cpu().numpy()
+    if golden is not None:
+        g = _exact_golden(golden)
+        assert g["nrows"] == A.nrows and g["nnz_A"] == A.nnz and g["nnz_B"] == B.nnz
+        s = ssp.read_stats(st)
+        assert s["out_sum"] == g["Z"] and s["total_flop"] == g["F"], "Z or F != oracle"
+        digest = hashlib.sha256(np.ascontiguousarray(ex, dtype="<i8").tobytes()).hexdigest()
+        assert digest == g["nnz_exact_sha256"], "nnz_exact differs from the oracle's rows"
     rf, F = oracle.row_flop(A, B)
     if F <= full_limit:
         o_ex, o_st = oracle.exact(A, B)
@@ -315,8 +333,39 @@ def test_widest_b(ssp):
     check_all(ssp, A, B, 0.3, 2)
 
 
+def test_b_with_more_than_2_30_rows(ssp):
+    # K = 2^30 + 5 rows of B (a 4 GiB row-pointer array): beyond the 32-bit
+    # byte offsets of the streaming kernel's buffer loads, so it takes its
+    # other form; A's entries name rows at both ends of the range
+    K = (1 << 30) + 5
+    N = 5000
+    rng = np.random.default_rng(12)
+    ks = np.unique(np.concatenate([rng.integers(0, K, 3000), [0, 1, K - 1, K - 2, 1 << 30,
+                                                              (1 << 30) - 1]])).astype(np.int64)
+    lens = rng.integers(0, 60, ks.shape[0])
+    lens[ks == K - 1] = 3000  # one long B row: the long-row kernel too
+    rpt = np.zeros(K + 1, dtype=np.int32)
+    ends = np.cumsum(lens)
+    for j in range(ks.shape[0]):  # rpt[i] = products of rows below i
+        rpt[ks[j] + 1: (ks[j + 1] + 1 if j + 1 < ks.shape[0] else K + 1)] = ends[j]
+    col = np.concatenate([np.sort(rng.choice(N, int(L), replace=False)) for L in lens]
+                         ).astype(np.int32)
+    B = workloads.CSR(K, N, rpt, col, "b_2_30_rows")
+    arows = [rng.choice(ks, int(rng.integers(0, 40)), replace=False).tolist() for _ in range(1500)]
+    arows[7] = ks.tolist()[:300] + [K - 1]
+    A = from_rows(arows, K)
+    _say(f"B with {K} rows")
+    Ad, Bd = _dev(ssp, A), _dev(ssp, B)
+    check_predict(ssp, A, B, 0.3, 5, Ad=Ad, Bd=Bd)
+    check_reference(ssp, A, B, 0.3, 5, Ad=Ad, Bd=Bd)
+    check_exact(ssp, A, B, Ad=Ad, Bd=Bd)
+    del Bd
+    torch.cuda.empty_cache()
+
+
 def test_misaligned_column_array(ssp):
-    # a column array that is not 16-byte aligned takes the scalar-load path
+    # a column array that is not 16-byte aligned (the streaming kernel's
+    # buffer loads take it as it is)
     A = workloads.zipf(20000, 8, 4)
     big = torch.zeros(A.nnz + 1, dtype=torch.int32, device="cuda:0")
     big[1:] = torch.as_tensor(A.col, device="cuda:0")
@@ -423,8 +472,9 @@ def test_full_rmat20(ssp):
     Ad = _dev(ssp, w.A)
     check_predict(ssp, w.A, w.A, w.rate, w.seed, Ad=Ad, Bd=Ad)
     check_reference(ssp, w.A, w.A, w.rate, w.seed, Ad=Ad, Bd=Ad)
-    # exact structure: every row would take the serial oracle many minutes
-    check_exact(ssp, w.A, w.A, Ad=Ad, Bd=Ad)
+    # exact structure: every row against the oracle's stored result (the
+    # serial oracle takes many minutes), and sampled rows recomputed here
+    check_exact(ssp, w.A, w.A, Ad=Ad, Bd=Ad, golden="rmat20")
 
 
 def _stencil_closed_form(n):
@@ -450,9 +500,4 @@ def test_full_stencil128_times_uniform(ssp):
     _say("full stencil128 x uniform")
     Ad, Bd = _dev(ssp, w.A), _dev(ssp, w.B)
     check_predict(ssp, w.A, w.B, w.rate, w.seed, Ad=Ad, Bd=Bd)
-    ex, st = ssp.exact_structure(Ad, Bd)
-    torch.cuda.synchronize()
-    ex = ex.cpu().numpy()
-    rows = np.random.default_rng(1).integers(0, w.A.nrows, 5000).astype(np.int32)
-    o_nnz, _ = oracle.rows_nnz(w.A, w.B, rows)
-    assert np.array_equal(ex[rows], o_nnz)
+    check_exact(ssp, w.A, w.B, Ad=Ad, Bd=Bd, golden="stencil128_x_uniform")
