@@ -164,11 +164,11 @@ SSP_API ssp_status ssp_predict_structure_ex(ssp_handle h, const ssp_csr* A, cons
  * workspace.  It calls no hipMalloc, hipFree or other allocating routine and
  * never blocks the host; it writes none of the handle's workspace and records
  * no timing events.  A product whose workspace plan does not fit the array
- * (about 88 bytes per row of A, 80 when row_flop is given, plus the bitmap
- * windows of split long rows, 1024 of 128 KiB as in the allocating call or,
- * when the rows leave less room, down to 16: about 3 million rows at most)
- * returns SSP_ERR_BUDGET, with the sizes in ssp_last_error(), and queues
- * nothing.  Every call on one device shares that
+ * (about 88 bytes per row of A, 80 when row_flop is given, 2 per row of B,
+ * and the bitmap windows of split long rows, 1024 of 128 KiB as in the
+ * allocating call or, when the rows leave less room, down to 16: about 3
+ * million rows at most) returns SSP_ERR_BUDGET, with the sizes in
+ * ssp_last_error(), and queues nothing.  Every call on one device shares that
  * device's array, whatever the handle: calls whose work overlaps on the
  * device (different streams, handles or threads) race and give wrong
  * results; calls queued on one stream are ordered and safe.  Each call

@@ -41,6 +41,9 @@ constexpr int kMergeSlice = 1024;             // words per merge item
 constexpr int kFlopThreads = 256;
 constexpr int kFlopChunk = 2048;
 constexpr int64_t kFlopTile = 2040;
+// A.A tiles whose columns lie within kNearRows of their rows gather B's row
+// pointers (A's, just streamed) instead of the separate row lengths.
+constexpr int64_t kNearRows = 1 << 15;
 
 // Distinct counts (z*, or the exact total) are added by the symbolic kernels
 // into kAccSlots slots per case, chosen by workgroup: atomics on one address
@@ -75,6 +78,8 @@ struct CaseDesc {
     SSP_GLOBAL int64_t* out;  // per-row output (prediction, reference or exact counts)
     SSP_GLOBAL int64_t* rf;   // per-row FLOP (the caller's array or workspace)
     ssp_stats* st;       // statistics (the caller's, or the case's workspace slot)
+    SSP_GLOBAL uint16_t* blen;  // B's row lengths saturated at 0xFFFF (workspace; null:
+                                // the streaming kernel reads B's row pointers)
     uint64_t seed, thresh;
     int64_t ncand;       // sampling candidates: rows (Bernoulli) or draws (paper)
     int64_t tile_base;   // first global tile of this case (tiles numbered case after case)
@@ -92,7 +97,7 @@ struct CaseDesc {
     uint32_t bin_max[3];    // product limits of bins 1..3
     uint32_t hash_mult;     // hash tables hold at least hash_mult x the distinct bound
     uint32_t long_len;      // long-row kernel: B rows of at least this many columns go in units
-    uint32_t pad;
+    uint32_t blen_own;      // this case writes blen (cases of one B share the array)
     uint64_t split_target;  // products per part of a split long row
     uint64_t est_max_rf;    // prediction: rows of fewer products take the estimated ceiling
 };

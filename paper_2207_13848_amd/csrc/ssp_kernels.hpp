@@ -279,6 +279,17 @@ __device__ __forceinline__ void tile_starts(const CaseDesc* __restrict__ tab, in
             tile_case[base + b] = c;
         }
     }
+    // B's row lengths in two bytes each (saturated): the streaming pass
+    // gathers them instead of pairs of row pointers, a quarter of the bytes,
+    // so they stay in L2 (a million rows: 2 MiB against 8)
+    SSP_GLOBAL uint16_t* const blen = tab[c].blen;
+    if (blen && tab[c].blen_own) {
+        const Csr B = tab[c].B;
+        for (int64_t k = bl * 256 + threadIdx.x; k < B.nrows; k += stride) {
+            const int32_t l = B.rpt[k + 1] - B.rpt[k];
+            blen[k] = (uint16_t)(l < 0xFFFF ? l : 0xFFFF);
+        }
+    }
 }
 
 // The first kernel of a call: workgroups [0, ninit) clear the cases' results,
@@ -1498,6 +1509,7 @@ struct FlopTileRegs {
     int32_t c;        // its case
     const SSP_GLOBAL int32_t* Arpt;
     const SSP_GLOBAL int32_t* Brpt;
+    const SSP_GLOBAL uint16_t* blen;
     SSP_GLOBAL int64_t* out;
     int64_t M, nnzA, K;
     int64_t i0, i1, j0, j1, a0;
@@ -1519,6 +1531,7 @@ __device__ __forceinline__ void flop_issue_tile(const CaseDesc* __restrict__ cs,
     R.c = c;
     R.Arpt = cd.A.rpt;
     R.Brpt = cd.B.rpt;
+    R.blen = cd.blen;
     R.out = MODE == FLOP_ONLY ? cd.rf : cd.out;
     const SSP_GLOBAL int32_t* Acol = cd.A.col;
     const int64_t M = cd.A.nrows, nnzA = cd.A.nnz;
@@ -1651,41 +1664,95 @@ void k_flop(const CaseDesc* __restrict__ cs,
         const int64_t M = cur.M;
         const SSP_GLOBAL int32_t* __restrict__ Brpt = cur.Brpt;
         uint32_t x[8];  // (entry q HALF + 256 wave + 64 l + lane in x[4 q + l])
-        // VEC: B has fewer than 2^30 rows (the host checks), so its row
-        // pointers are read through a buffer resource at 32-bit byte offsets
-        // (one address register per lane).  Entry j is live when
+        // VEC: B has fewer than 2^30 rows (the host checks) and its row
+        // lengths are in blen, two bytes each, read through a buffer resource
+        // at 32-bit byte offsets (one address register per lane; masked lanes
+        // read past the end: 0); a saturated length (a row of 65535 entries
+        // or more) is read again from the row pointers.  Entry j is live when
         // j0 <= j < j1; relative to a0 both bounds are small (j0 - a0 < 4,
         // j1 - a0 <= kFlopChunk).
         const int rlo = (int)(j0 - a0), rhi = (int)(j1 - a0);
-        const __amdgpu_buffer_rsrc_t brs = buffer_rsrc(Brpt, VEC ? 4 * (uint64_t)(cur.K + 1) : 0);
+        // (VEC: 0 or 1, the half of the loaded word that is the length; 2:
+        // the length itself)
+        uint32_t xodd[8];
+        if (VEC) {
+            // A.A whose columns stay near the tile's rows (banded,
+            // stencil-like): B's row pointers are A's, which the stream has
+            // just brought in, so the gathers read them; otherwise the
+            // two-byte lengths, whose smaller footprint stays in L2
+            // (judged per wave from two of its columns, lane 0's first and
+            // lane 63's last: near when both lie within kNearRows of the
+            // tile's rows; the choice changes no result)
+            bool near = false;
+            if (cur.Brpt == cur.Arpt) {
+                const int64_t c0 = __builtin_amdgcn_readlane(cur.col[0], 0);
+                const int64_t c7 = __builtin_amdgcn_readlane(cur.col[7], kWave - 1);
+                near = c0 >= i0 - kNearRows && c0 <= i1 + kNearRows && c7 >= i0 - kNearRows &&
+                       c7 <= i1 + kNearRows;
+            }
+            if (near) {
+                const __amdgpu_buffer_rsrc_t brs = buffer_rsrc(Brpt, 4 * (uint64_t)(cur.K + 1));
 #pragma unroll
-        for (int q = 0; q < 2; ++q) {
+                for (int q = 0; q < 2; ++q) {
 #pragma unroll
-            for (int l = 0; l < 4; ++l) {
-                const int rel = q * HALF + kWave * (4 * wid + l) + lane;
-                const bool in = rel >= rlo && rel < rhi;
-                const int32_t cc = in ? cur.col[4 * q + l] : 0;
-                uint32_t len = 0;
-                // row 0 of B when masked; with no entries at all (then K may be
-                // 0 and B's row pointers hold one value) nothing is read
-                if (VEC || cur.nnzA > 0) {
-                    if (VEC) {
-                        // masked lanes read past the end: 0
+                    for (int l = 0; l < 4; ++l) {
+                        const int rel = q * HALF + kWave * (4 * wid + l) + lane;
+                        const bool in = rel >= rlo && rel < rhi;
                         typedef int32_t v2i __attribute__((ext_vector_type(2)));
-                        const uint32_t off = in ? 4u * (uint32_t)cc : 0xFFFFFFF8u;
-                        const v2i v = __builtin_amdgcn_raw_buffer_load_b64(brs, off, 0, 0);
-                        len = (uint32_t)(v.y - v.x);
-                    } else {
-                        len = csr_row_len(Brpt, cc);
+                        const v2i v = __builtin_amdgcn_raw_buffer_load_b64(
+                            brs, in ? 4u * (uint32_t)cur.col[4 * q + l] : 0xFFFFFFF8u, 0, 0);
+                        x[4 * q + l] = (uint32_t)(v.y - v.x);
+                        xodd[4 * q + l] = 2u;
                     }
                 }
-                x[4 * q + l] = in ? len : 0u;
+            } else {
+                const __amdgpu_buffer_rsrc_t bls =
+                    buffer_rsrc(cur.blen, (2 * (uint64_t)cur.K + 3) & ~3ull);
+#pragma unroll
+                for (int q = 0; q < 2; ++q) {
+#pragma unroll
+                    for (int l = 0; l < 4; ++l) {
+                        const int rel = q * HALF + kWave * (4 * wid + l) + lane;
+                        const bool in = rel >= rlo && rel < rhi;
+                        const uint32_t cc = (uint32_t)cur.col[4 * q + l];
+                        // (the aligned 4-byte word holding the length: dword
+                        // loads run at the full rate of the address unit)
+                        x[4 * q + l] = __builtin_amdgcn_raw_buffer_load_b32(
+                            bls, in ? 4u * (cc >> 1) : 0xFFFFFFF0u, 0, 0);
+                        xodd[4 * q + l] = cc & 1u;
+                    }
+                }
+            }
+        } else {
+#pragma unroll
+            for (int q = 0; q < 2; ++q) {
+#pragma unroll
+                for (int l = 0; l < 4; ++l) {
+                    const int rel = q * HALF + kWave * (4 * wid + l) + lane;
+                    const bool in = rel >= rlo && rel < rhi;
+                    const int32_t cc = in ? cur.col[4 * q + l] : 0;
+                    uint32_t len = 0;
+                    // row 0 of B when masked; with no entries at all (then K
+                    // may be 0 and B's row pointers hold one value) nothing is read
+                    if (cur.nnzA > 0) len = csr_row_len(Brpt, cc);
+                    x[4 * q + l] = in ? len : 0u;
+                }
             }
         }
         // 2. loads of the next tile, unconditionally (a branch here would make
         //    the compiler drain every load in flight at its join)
         flop_issue_tile<MODE, VEC>(cs, bn, s_tcase[kk + 1], s_trow[kk + 1], s_next[kk + 1], nxt);
-        // 3. the current tile
+        // 3. the current tile (VEC: the halves of the loaded words; a
+        //    saturated length is read from the row pointers, after the next
+        //    tile's loads were issued: a lane branch waits for the loads)
+        if (VEC) {
+#pragma unroll
+            for (int u = 0; u < 8; ++u) {
+                if (xodd[u] == 2u) continue;
+                x[u] = xodd[u] ? (x[u] >> 16) : (x[u] & 0xFFFFu);
+                if (x[u] == 0xFFFFu) x[u] = csr_row_len(Brpt, cur.col[u]);
+            }
+        }
         const int64_t rlast = i1 < M ? i1 : M - 1;
         const int nb = (int)(rlast - i0 + 2);
 #pragma unroll

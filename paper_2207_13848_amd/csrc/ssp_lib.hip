@@ -334,6 +334,7 @@ struct Plan {
     int n = 0;
     std::vector<CaseDesc> cs;
     std::vector<int64_t> rf_off;   // workspace row-FLOP offset per case, -1 = caller's
+    std::vector<int64_t> blen_off; // workspace byte offset of B's row lengths per case (vec)
     std::vector<int> st_slot;      // workspace stats slot per case, -1 = caller's
     int64_t cap13 = 1, cap4 = 1, cap5 = 1, ngroups = 0, tiles = 0, rowtmp = 0;
     int64_t part_windows = kPartWindowsBase;  // scratch windows for the parts of split rows
@@ -343,7 +344,7 @@ struct Plan {
     bool bin2_wave = false;  // bin 2 one wave per row (many sampled rows expected)
     size_t o_ctl = 0, o_scratch = 0, o_b1 = 0, o_b2 = 0, o_b3 = 0, o_b4 = 0, o_merge = 0,
            o_tiles = 0, o_tcase = 0, o_meta = 0, o_samp = 0, o_cases = 0, o_res = 0, o_stats = 0,
-           o_rowtmp = 0, total = 0;
+           o_rowtmp = 0, o_blen = 0, total = 0;
 };
 
 // Columns per bitmap window of the long-row kernel: all N columns when they
@@ -533,6 +534,27 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind,
     P.o_res = o;     o = align256(o + (size_t)n * sizeof(CaseRes));
     P.o_stats = o;   o = align256(o + (size_t)n * sizeof(ssp_stats));
     P.o_rowtmp = o;  o = align256(o + (size_t)std::max<int64_t>(P.rowtmp, 1) * sizeof(int64_t));
+    // B's row lengths, two bytes each, for the streaming kernel's fast form
+    P.o_blen = o;
+    P.blen_off.assign(n, -1);
+    if (P.vec) {
+        // (one array per distinct B: cases of one B gather from one copy)
+        size_t b = 0;
+        std::unordered_map<const void*, int> first;
+        for (int c = 0; c < n; ++c) {
+            const void* key = (const void*)P.cs[c].B.rpt;
+            auto it = first.find(key);
+            if (it != first.end() && P.cs[it->second].B.nrows == P.cs[c].B.nrows) {
+                P.blen_off[c] = P.blen_off[it->second];
+                continue;
+            }
+            first[key] = c;
+            P.cs[c].blen_own = 1;
+            P.blen_off[c] = (int64_t)b;
+            b = align256(b + (size_t)P.cs[c].B.nrows * sizeof(uint16_t));
+        }
+        o += b;
+    }
     P.total = o;
     return P;
 }
@@ -585,6 +607,9 @@ Bound bind_plan(Plan& P, void* ws)
     for (int c = 0; c < P.n; ++c) {
         if (P.rf_off[c] >= 0) P.cs[c].rf = (decltype(P.cs[c].rf))(rowtmp + P.rf_off[c]);
         if (P.st_slot[c] >= 0) P.cs[c].st = stats + P.st_slot[c];
+        P.cs[c].blen = P.blen_off[c] >= 0
+                           ? (decltype(P.cs[c].blen))(base + P.o_blen + P.blen_off[c])
+                           : nullptr;
     }
     return b;
 }
