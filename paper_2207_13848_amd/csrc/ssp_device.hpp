@@ -454,6 +454,14 @@ __device__ __forceinline__ void wave_bitmap_or(uint32_t* bm, uint32_t word, uint
     wave_bitmap_or_needed(bm, need ? word : kNoWord, need);
 }
 
+// Word w of a bitmap lives at w ^ ((w >> 6) & 63): its 64-word row keeps its
+// place and the low six bits (the LDS bank) are scrambled by the row index,
+// so lanes striding a sorted B row (word index advancing a few words per lane)
+// spread over the banks instead of meeting every 64 words.  A bijection on
+// every aligned run of 64 words; popcounts and ORs of whole bitmaps do not
+// see it.
+__device__ __forceinline__ uint32_t swz(uint32_t w) { return w ^ ((w >> 6) & 63u); }
+
 // V columns per lane (kNoWord = none), normally neighbours in one B row:
 // runs of them that fall in one bitmap word (sorted rows make such runs
 // contiguous) are first combined inside the lane; then every remaining word
@@ -481,11 +489,11 @@ __device__ __forceinline__ void lane_bitmap_insert(uint32_t* bm, const uint32_t 
         word[v - 1] = same ? kNoWord : word[v - 1];
     }
 #pragma unroll
-    for (int v = 0; v < V; ++v) old[v] = bm[word[v] != kNoWord ? word[v] : 0u];
+    for (int v = 0; v < V; ++v) old[v] = bm[word[v] != kNoWord ? swz(word[v]) : 0u];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const uint32_t need = word[v] != kNoWord ? (bits[v] & ~old[v]) : 0u;
-        if (need) atomicOr(&bm[word[v]], need);
+        if (need) atomicOr(&bm[swz(word[v])], need);
     }
 }
 
@@ -501,16 +509,17 @@ __device__ __forceinline__ void lane_bitmap_insert4(uint32_t* bm, const int32_t 
     b1 |= s1 ? b0 : 0u;
     b2 |= s2 ? b1 : 0u;
     b3 |= s3 ? b2 : 0u;
-    const uint32_t o0 = bm[w0], o1 = bm[w1], o2 = bm[w2], o3 = bm[w3];
+    const uint32_t p0 = swz(w0), p1 = swz(w1), p2 = swz(w2), p3 = swz(w3);
+    const uint32_t o0 = bm[p0], o1 = bm[p1], o2 = bm[p2], o3 = bm[p3];
     // a word is written at the end of its run only
     const uint32_t n0 = s1 ? 0u : (b0 & ~o0);
     const uint32_t n1 = s2 ? 0u : (b1 & ~o1);
     const uint32_t n2 = s3 ? 0u : (b2 & ~o2);
     const uint32_t n3 = b3 & ~o3;
-    if (n0) atomicOr(&bm[w0], n0);
-    if (n1) atomicOr(&bm[w1], n1);
-    if (n2) atomicOr(&bm[w2], n2);
-    if (n3) atomicOr(&bm[w3], n3);
+    if (n0) atomicOr(&bm[p0], n0);
+    if (n1) atomicOr(&bm[p1], n1);
+    if (n2) atomicOr(&bm[p2], n2);
+    if (n3) atomicOr(&bm[p3], n3);
 }
 
 // V independent columns per lane (kNoWord = none), one window holding all
@@ -520,11 +529,11 @@ __device__ __forceinline__ void lane_bitmap_insert_all(uint32_t* bm, const uint3
 {
     uint32_t old[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) old[v] = bm[col[v] != kNoWord ? (col[v] >> 5) : 0u];
+    for (int v = 0; v < V; ++v) old[v] = bm[col[v] != kNoWord ? swz(col[v] >> 5) : 0u];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const uint32_t need = col[v] != kNoWord ? ((1u << (col[v] & 31)) & ~old[v]) : 0u;
-        if (need) atomicOr(&bm[col[v] >> 5], need);
+        if (need) atomicOr(&bm[swz(col[v] >> 5)], need);
     }
 }
 

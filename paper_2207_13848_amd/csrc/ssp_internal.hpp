@@ -36,6 +36,13 @@ constexpr int kPartWindowsMax = 8192;
 constexpr int kMaxSplitWindows = 4;           // rows needing more windows are not split
 constexpr int kMergeSlice = 1024;             // words per merge item
 
+// Words of the long-row bitmap for `cols` columns: whole 64-word rows (the
+// bitmap's words are swizzled inside their row).
+__host__ __device__ inline int64_t bitmap_words(int64_t cols)
+{
+    return (cols + 2047) / 2048 * 64;
+}
+
 // Streaming FLOP kernels: 256 threads, tiles of kFlopTile merge-path items
 // (rows + entries of A), at most kFlopTile + 3 < 2048 entries per tile.
 constexpr int kFlopThreads = 256;

@@ -119,7 +119,7 @@ __device__ inline void write_merge_items(MergeItem* dst, int32_t row, int32_t sl
     int k = 0;
     for (int w = 0; w < cd.nwin; ++w) {
         const int64_t cols = (N - w * wcols_full) < wcols_full ? (N - w * wcols_full) : wcols_full;
-        const int slices = (int)(((cols + 31) / 32 + kMergeSlice - 1) / kMergeSlice);
+        const int slices = (int)((bitmap_words(cols) + kMergeSlice - 1) / kMergeSlice);
         for (int sl = 0; sl < slices; ++sl) {
             MergeItem m;
             m.row = row;
@@ -1031,7 +1031,9 @@ __global__ __launch_bounds__(kBins12Threads) void k_sym_bins12(const CaseDesc* _
 // 16-byte load, kUnitsInFlight - 1 units ahead of the inserts.  The short B rows are
 // flattened (owner by binary search in LDS) and shared out over the whole
 // workgroup.  An unsplit item counts its bits; a part of a split row stores
-// its window bitmap to global scratch for k_sym_merge.
+// its window bitmap to global scratch for k_sym_merge.  Bitmap words are
+// swizzled inside their 64-word rows (swz): neighbouring lanes striding a
+// sorted B row would otherwise meet on one LDS bank every 64 words.
 constexpr uint32_t kUnitCols = 4 * kWave;
 constexpr int kUnitsInFlight = 4;  // 16-byte loads in flight per lane in the unit loop
 
@@ -1108,8 +1110,8 @@ __global__ __launch_bounds__(kBin4Team) void k_sym_big(const CaseDesc* __restric
         for (int w = 0; w < nwin; ++w) {
             const int64_t c_lo = w * wcols_full;
             const int64_t wcols = (N - c_lo) < wcols_full ? (N - c_lo) : wcols_full;
-            const int words = (int)((wcols + 31) / 32);
-            const int w4 = (words + 3) / 4;  // 16-byte groups (win_words is a multiple of 4)
+            const int words = (int)bitmap_words(wcols);
+            const int w4 = words / 4;  // 16-byte groups (words: whole 64-word rows)
             // the bitmap is cleared when dirty; the pass that counts a window
             // zeroes every group it reads
             if (w4 > clean4) {
@@ -1383,7 +1385,7 @@ __global__ __launch_bounds__(256) void k_sym_merge(const CaseDesc* __restrict__ 
         const int64_t wcols_full = (int64_t)cs[zc].win_words * 32;
         const int64_t c_lo = (int64_t)m.window * wcols_full;
         const int64_t wcols = (N - c_lo) < wcols_full ? (N - c_lo) : wcols_full;
-        const int w4 = (int)((wcols + 127) / 128);  // 16-byte groups of this window
+        const int w4 = (int)(bitmap_words(wcols) / 4);  // 16-byte groups of this window
         const int g4 = m.slice * (kMergeSlice / 4) + t;
         uint32_t cnt = 0;
         if (g4 < w4) {

@@ -351,9 +351,9 @@ struct Plan {
 // fit the LDS window, else 2^20-column windows.
 void window_shape(int64_t N, int32_t* words, int32_t* nwin)
 {
-    const int64_t need = (N + 31) / 32;
+    const int64_t need = bitmap_words(N);
     if (need <= kWinWords) {
-        *words = (int32_t)std::max<int64_t>((need + 3) / 4 * 4, 4);  // whole 16-byte groups
+        *words = (int32_t)std::max<int64_t>(need, 64);  // whole 64-word rows
         *nwin = 1;
     } else {
         *words = kWinWords;
@@ -455,7 +455,7 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind,
         for (int32_t w = 0; w < d.nwin; ++w) {
             const int64_t cols = std::min<int64_t>(N - (int64_t)w * d.win_words * 32,
                                                    (int64_t)d.win_words * 32);
-            mpr += (int32_t)(((cols + 31) / 32 + kMergeSlice - 1) / kMergeSlice);
+            mpr += (int32_t)((bitmap_words(cols) + kMergeSlice - 1) / kMergeSlice);
         }
         d.merge_per_row = mpr;
         d.ntiles = M > 0 ? flop_tiles(M, nnz) : 0;
