@@ -899,8 +899,29 @@ __device__ __forceinline__ void sym_rows(const CaseDesc* __restrict__ cs,
 {
     int zc = -1;  // case of zsum (items of a case are consecutive in the list)
     uint64_t zsum = 0;
-    for (uint32_t it = first; it < n; it += stride) {
-        const BinItem item = items[it];
+    // The team's next row is prefetched in stages while the current one is
+    // counted, so a row does not begin on its chain of dependent loads (item,
+    // A row bounds, A columns, B row bounds): the item when a row begins, its
+    // A row bounds after the table is cleared, the A columns of its first
+    // chunk after the last products are issued, their B row bounds after the
+    // count.
+    uint32_t it = first;
+    BinItem item{};
+    int32_t ra0 = 0, ra1 = 0;  // the current row's A entries
+    int32_t pb0 = 0;           // its first chunk's B row start and length,
+    uint32_t plen = 0;         // for entry ra0 + t, when `staged`
+    bool staged = false;
+    if (it < n) {
+        item = items[it];
+        const Csr A = cs[item.cs].A;
+        ra0 = A.rpt[item.row];
+        ra1 = A.rpt[item.row + 1];
+    }
+    for (; it < n; it += stride) {
+        const uint32_t itn = it + stride;
+        const bool more = itn < n;
+        BinItem nx{};
+        if (more) nx = items[itn];
         if (item.cs != zc) {
             if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[slot]), (ull)zsum);
             zsum = 0;
@@ -918,13 +939,23 @@ __device__ __forceinline__ void sym_rows(const CaseDesc* __restrict__ cs,
         const uint32_t fill = bitmap ? 0u : kEmpty;
         for (uint32_t w = t; w < words; w += TEAM) tab[w] = fill;
         team_sync<TEAM>();
+        // (the next row's A row bounds)
+        int32_t na0 = 0, na1 = 0;
+        if (more) {
+            const Csr An = cs[nx.cs].A;
+            na0 = An.rpt[nx.row];
+            na1 = An.rpt[nx.row + 1];
+        }
         uint32_t cnt = 0;
-        const int32_t a0 = A.rpt[item.row], a1 = A.rpt[item.row + 1];
-        for (int32_t a = a0; a < a1; a += TEAM) {
+        int32_t nk = -1;  // (the next row's first-chunk column of this thread)
+        for (int32_t a = ra0; a < ra1; a += TEAM) {
             const int32_t j = a + t;
             uint32_t len = 0;
             int32_t b0 = 0;
-            if (j < a1) {
+            if (staged && a == ra0) {
+                b0 = pb0;
+                len = plen;
+            } else if (j < ra1) {
                 const int32_t k = A.col[j];
                 b0 = B.rpt[k];
                 len = (uint32_t)(B.rpt[k + 1] - b0);
@@ -934,9 +965,11 @@ __device__ __forceinline__ void sym_rows(const CaseDesc* __restrict__ cs,
             s_b0[t] = b0;
             s_off[t] = off;
             team_sync<TEAM>();
-            const int na = (a1 - a) < TEAM ? (a1 - a) : TEAM;
+            const int na = (ra1 - a) < TEAM ? (ra1 - a) : TEAM;
             constexpr int U = 4;
             // same trip count in every lane; U independent loads in flight per lane
+            // (software-pipelining the rounds, the next round's loads issued
+            // before this round's inserts, was slower: registers)
             for (uint32_t p0 = 0; p0 < tot; p0 += TEAM * U) {
                 uint32_t c[U];
 #pragma unroll
@@ -953,6 +986,9 @@ __device__ __forceinline__ void sym_rows(const CaseDesc* __restrict__ cs,
                     const uint32_t cv = (uint32_t)B.col[s_b0[lo] + (int32_t)(p - s_off[lo])];
                     c[u] = pr < tot ? cv : kNoWord;
                 }
+                // (the last chunk's last round: the next row's first-chunk columns)
+                if (more && a + TEAM >= ra1 && p0 + TEAM * U >= tot && na0 + t < na1)
+                    nk = cs[nx.cs].A.col[na0 + t];
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (bitmap)
@@ -963,6 +999,8 @@ __device__ __forceinline__ void sym_rows(const CaseDesc* __restrict__ cs,
             }
             team_sync<TEAM>();
         }
+        // (a row whose chunks issued no round: its columns now)
+        if (more && nk < 0 && na0 + t < na1) nk = cs[nx.cs].A.col[na0 + t];
         if (bitmap)
             for (uint32_t w = t; w < words; w += TEAM) cnt += (uint32_t)__popc(tab[w]);
         const uint32_t total = block_sum<TEAM, uint32_t>(cnt, s_red);
@@ -970,7 +1008,19 @@ __device__ __forceinline__ void sym_rows(const CaseDesc* __restrict__ cs,
             zsum += total;
             if (MODE == 1) cs[zc].out[item.row] = (int64_t)total;
         }
+        // (the next row's first-chunk B row bounds)
+        pb0 = 0;
+        plen = 0;
+        if (nk >= 0) {
+            const Csr Bn = cs[nx.cs].B;
+            pb0 = Bn.rpt[nk];
+            plen = (uint32_t)(Bn.rpt[nk + 1] - pb0);
+        }
         team_sync<TEAM>();
+        item = nx;
+        ra0 = na0;
+        ra1 = na1;
+        staged = more;
     }
     if (t == 0 && zsum) atomicAdd(as_ull(&cr[zc].zacc[slot]), (ull)zsum);
 }
