@@ -48,6 +48,8 @@ def parse():
                     help="seconds of oracle work for the CPU baseline")
     ap.add_argument("--margin", type=int, default=10,
                     help="spgemm workloads: percent added to each predicted row capacity")
+    ap.add_argument("--spill", type=int, default=25,
+                    help="spgemm workloads: overflow area shared by the rows, percent of the slots")
     ap.add_argument("--copy-calibration", type=int, default=0, metavar="BYTES",
                     help="only run a plain device copy of BYTES three times (the reference "
                          "kernel for scaling rocprofv3 FETCH_SIZE / WRITE_SIZE) and exit")
@@ -476,7 +478,8 @@ def main_spgemm(args):
     """The consumer of the prediction: numeric C = A.A (float64 values in
     U[-1, 1)) whose memory is sized by the predicted structure.  A step is the
     whole pipeline: ssp_predict_structure, ssp_spgemm_compute with the
-    prediction plus a margin as row capacities, ssp_spgemm_copy.  Beside it,
+    prediction plus a margin as row capacities and an overflow area shared by
+    the rows, ssp_spgemm_copy.  Beside it, other margins and areas,
     the same numeric product sized by the precise method (ssp_exact_structure
     first: the symbolic phase the prediction avoids) and by the upper bound
     (row FLOP: no structure step, the largest slot area).  Sampled rows of C
@@ -505,11 +508,11 @@ def main_spgemm(args):
     h = ssp.default_handle(dev)
     pred = torch.empty(M, dtype=torch.int64, device=dev)
     st = torch.zeros(8, dtype=torch.int64, device=dev)
-    margin = int(args.margin)
+    margin, spill = int(args.margin), int(args.spill)
 
     def step():
         ssp.predict_structure(Ad, Ad, rate, seed, handle=h, out=pred, stats=st)
-        return ssp.spgemm(Ad, tav, Ad, tav, pred, margin_pct=margin, handle=h)
+        return ssp.spgemm(Ad, tav, Ad, tav, pred, margin_pct=margin, spill_pct=spill, handle=h)
 
     steps = max(1, min(args.steps, 10))
     for _ in range(max(1, min(args.warmup, 2))):
@@ -567,14 +570,17 @@ def main_spgemm(args):
                 "algorithmic_bytes": dom_bytes, "avg_launch_us": dom_us}
 
     # the precise method and the upper bound as capacities
-    variants = {"predicted": {"ms": round(ms, 3), "margin_pct": margin,
-                              **{k: info[k] for k in ("slot_entries", "slot_bytes",
-                                                       "overflow_rows", "overflow_nnz")}}}
+    info_keys = ("slot_entries", "slot_bytes", "overflow_rows", "overflow_nnz", "spill_rows",
+                 "spill_nnz", "spill_bytes")
+    variants = {f"predicted_m{margin}_s{spill}": {
+        "ms": round(ms, 3), "margin_pct": margin, "spill_pct": spill, "headline": True,
+        **{k: info[k] for k in info_keys}}}
     ex = torch.empty(M, dtype=torch.int64, device=dev)
-    # other margins on the prediction (memory against recomputed rows), the
-    # precise method and the upper bound
-    other = [m for m in (0, 30, 100) if m != margin]
-    for vname in [f"predicted_m{m}" for m in other] + ["precise", "upper_bound"]:
+    # other margins and overflow areas on the prediction (memory against
+    # recomputed rows), the precise method and the upper bound
+    other = [(m, sp) for m, sp in ((0, 0), (10, 0), (30, 0), (100, 0), (0, 25), (0, 50), (10, 50))
+             if (m, sp) != (margin, spill)]
+    for vname in [f"predicted_m{m}_s{sp}" for m, sp in other] + ["precise", "upper_bound"]:
         for i in range(steps + 1):
             if i == 1:
                 torch.cuda.synchronize()
@@ -585,15 +591,15 @@ def main_spgemm(args):
             elif vname == "upper_bound":
                 r = ssp.spgemm(Ad, tav, Ad, tav, rf_t, handle=h)
             else:
+                m, sp = (int(x) for x in vname[len("predicted_m"):].split("_s"))
                 ssp.predict_structure(Ad, Ad, rate, seed, handle=h, out=pred, stats=st)
-                r = ssp.spgemm(Ad, tav, Ad, tav, pred, margin_pct=int(vname.split("_m")[1]),
-                               handle=h)
+                r = ssp.spgemm(Ad, tav, Ad, tav, pred, margin_pct=m, spill_pct=sp, handle=h)
         torch.cuda.synchronize()
         vi = r[3]
-        variants[vname] = {"ms": round((time.perf_counter() - ta) * 1e3 / steps, 3),
-                           **({"margin_pct": int(vname.split("_m")[1])} if "_m" in vname else {}),
-                           **{k: vi[k] for k in ("slot_entries", "slot_bytes", "overflow_rows",
-                                                 "overflow_nnz")}}
+        vr = {"ms": round((time.perf_counter() - ta) * 1e3 / steps, 3)}
+        if vname.startswith("predicted"):
+            vr["margin_pct"], vr["spill_pct"] = m, sp
+        variants[vname] = {**vr, **{k: vi[k] for k in info_keys}}
         assert vi["nnz"] == info["nnz"]
         del r
     torch.cuda.synchronize()
@@ -624,7 +630,7 @@ def main_spgemm(args):
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": name, "rows": M, "nnz_A": A.nnz, "sample_rate": rate, "seed": seed,
-                   "margin_pct": margin, "values": "U[-1,1) float64"},
+                   "margin_pct": margin, "spill_pct": spill, "values": "U[-1,1) float64"},
         "gflops": round(2.0 * F / (ms * 1e-3) / 1e9, 1),
         "nnz_C": info["nnz"], "F": F, "roofline": roofline, "phases": per_phase,
         "variants": variants,

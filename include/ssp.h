@@ -385,22 +385,33 @@ SSP_API ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* M, int64_t* n_b
  *
  * ssp_spgemm_compute.  Row i of C gets a slot of
  *     s_i = min(N, c + ceil(c * margin_pct / 100)),  c = row_cap[i] clamped to [0, N],
- * in a slot area of sum(s_i) entries (12 bytes each) that the handle
- * allocates.  One numeric pass accumulates every row once (rows of at most
- * 2048 products in an LDS hash table, longer rows in a dense accumulator),
- * counts its nonzeros and writes the row, columns increasing, into its slot
- * when it fits.  C_rpt then receives C's row offsets from the exact counts.
- * Waits for `stream` twice (the slot area's size and the results are read on
- * the host) and fills *info.
+ * in a slot area of S = sum(s_i) entries (12 bytes each) that the handle
+ * allocates, and the rows share an overflow area of ceil(S * spill_pct / 100)
+ * entries (12 bytes each, plus 24 bytes per record of where its runs go).
+ * One numeric pass accumulates every row once (rows of at most 2048 products
+ * in an LDS hash table, longer rows in a dense accumulator), counts its
+ * nonzeros and writes the row, columns increasing, into its slot when it
+ * fits.  A row with more nonzeros than its slot keeps them in the overflow
+ * area while the area lasts: a row of more than 2048 products the entries
+ * past its first s_i (B's rows sorted), a shorter row all of them when it
+ * completes within half its hash table (rows of at most 256 products always
+ * do: with spill_pct > 0 their tables are sized for all their products).
+ * The other overflowing rows are recomputed.  C_rpt then receives
+ * C's row offsets from the exact counts.  Waits for `stream` twice (the slot
+ * area's size and the results are read on the host) and fills *info.
  *   A_val, B_val : device double[A.nnz], double[B.nnz]; duplicate entries add.
  *   row_cap      : device int64[A.nrows], any values (clamped as above).
  *   margin_pct   : 0 .. 10000.
+ *   spill_pct    : 0 .. 10000 (0: no overflow area).
  *   C_rpt        : device int64[A.nrows + 1], written (C_rpt[0] = 0).
  *   info         : host, written.
+ * Which overflowing rows the area holds depends on the order in which rows
+ * finish when it runs short (spill_rows, spill_nnz); C does not.
  *
  * ssp_spgemm_copy.  Writes C_col / C_val (device, capacity >= info.nnz
  * entries, else SSP_ERR_INVALID_ARG): rows that fitted are copied from their
- * slots, rows with more nonzeros than their slot (an under-prediction) are
+ * slots, rows held in the overflow area from their slot and the area, the
+ * other rows with more nonzeros than their slot (an under-prediction) are
  * recomputed straight into their final place.  Asynchronous on `stream`.  A,
  * B and their values must be unchanged since the compute call; the next
  * compute call on the handle waits for this copy and replaces its state.
@@ -408,22 +419,27 @@ SSP_API ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* M, int64_t* n_b
  * C keeps every structural entry (terms that cancel leave an explicit 0.0):
  * C's structure is exactly the structure the prediction estimates
  * (ssp_exact_structure).  Values are sums of the products in an unspecified
- * order.  Errors: those of the other calls; SSP_ERR_BUDGET when the slot area
- * and accumulators exceed the handle's budget.
+ * order.  Errors: those of the other calls; SSP_ERR_BUDGET when the slot area,
+ * the overflow area and the accumulators exceed the handle's budget.
  */
 typedef struct {
     int64_t nnz;           /* NNZ(C)                                                */
     int64_t total_flop;    /* F                                                     */
     int64_t slot_entries;  /* sum of the slot sizes s_i                             */
     int64_t overflow_rows; /* rows with more nonzeros than their slot               */
-    int64_t overflow_nnz;  /* their nonzeros (recomputed by ssp_spgemm_copy)        */
+    int64_t overflow_nnz;  /* their nonzeros                                        */
     int64_t slot_bytes;    /* bytes of the slot area                                */
+    int64_t spill_rows;    /* overflowing rows the overflow area holds (the rest of
+                              the overflowing rows are recomputed by ssp_spgemm_copy) */
+    int64_t spill_nnz;     /* their nonzeros held in the area                       */
+    int64_t spill_bytes;   /* bytes of the overflow area and its records            */
 } ssp_spgemm_info;
 
 SSP_API ssp_status ssp_spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val,
                                       const ssp_csr* B, const double* B_val,
                                       const int64_t* row_cap, int32_t margin_pct,
-                                      int64_t* C_rpt, ssp_spgemm_info* info, void* stream);
+                                      int32_t spill_pct, int64_t* C_rpt,
+                                      ssp_spgemm_info* info, void* stream);
 SSP_API ssp_status ssp_spgemm_copy(ssp_handle h, int32_t* C_col, double* C_val,
                                    int64_t capacity, void* stream);
 

@@ -218,12 +218,14 @@ def exact_structure(A: DeviceCSR, B: DeviceCSR, *, handle=None, stream=None, out
 
 
 def spgemm(A: DeviceCSR, A_val, B: DeviceCSR, B_val, row_cap, *, margin_pct: int = 0,
-           handle=None, stream=None, capacity=None):
+           spill_pct: int = 0, handle=None, stream=None, capacity=None):
     """Numeric C = A.B sized by per-row capacities (normally the prediction).
 
     ``ssp_spgemm_compute`` then ``ssp_spgemm_copy``: returns ``(C_rpt int64[M+1],
-    C_col int32[nnz], C_val float64[nnz], info dict)``.  ``capacity`` (entries
-    of C to allocate) defaults to the exact NNZ(C) the compute call reports."""
+    C_col int32[nnz], C_val float64[nnz], info dict)``.  ``margin_pct`` enlarges
+    every row's slot, ``spill_pct`` sizes the overflow area the rows share (a
+    percentage of the slot entries).  ``capacity`` (entries of C to allocate)
+    defaults to the exact NNZ(C) the compute call reports."""
     h = handle or default_handle(A.device)
     M = A.nrows
     dev = A.device
@@ -238,7 +240,8 @@ def spgemm(A: DeviceCSR, A_val, B: DeviceCSR, B_val, row_cap, *, margin_pct: int
     status = h._lib.ssp_spgemm_compute(h.ptr, ctypes.byref(a), A_val.data_ptr() if A.nnz else 0,
                                        ctypes.byref(b), B_val.data_ptr() if B.nnz else 0,
                                        row_cap.data_ptr() if M else 0, int(margin_pct),
-                                       C_rpt.data_ptr(), ctypes.byref(info), _stream_ptr(stream))
+                                       int(spill_pct), C_rpt.data_ptr(), ctypes.byref(info),
+                                       _stream_ptr(stream))
     h.check(status, "ssp_spgemm_compute")
     nnz = int(info.nnz)
     cap = nnz if capacity is None else int(capacity)

@@ -50,7 +50,7 @@ class SspCase(ctypes.Structure):
 class SspSpgemmInfo(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in
                 ("nnz", "total_flop", "slot_entries", "overflow_rows", "overflow_nnz",
-                 "slot_bytes")]
+                 "slot_bytes", "spill_rows", "spill_nnz", "spill_bytes")]
 
     def as_dict(self) -> dict:
         return {n: int(getattr(self, n)) for n, _ in self._fields_}
@@ -182,8 +182,8 @@ def load():
                                  ctypes.POINTER(dbl), vp]
     lib.ssp_version.argtypes = []
     lib.ssp_version.restype = ctypes.c_char_p
-    lib.ssp_spgemm_compute.argtypes = [vp, csr_p, vp, csr_p, vp, vp, ctypes.c_int32, vp,
-                                       ctypes.POINTER(SspSpgemmInfo), vp]
+    lib.ssp_spgemm_compute.argtypes = [vp, csr_p, vp, csr_p, vp, vp, ctypes.c_int32, ctypes.c_int32,
+                                       vp, ctypes.POINTER(SspSpgemmInfo), vp]
     lib.ssp_spgemm_compute.restype = cint
     lib.ssp_spgemm_copy.argtypes = [vp, vp, vp, ctypes.c_int64, vp]
     lib.ssp_spgemm_copy.restype = cint

@@ -32,6 +32,24 @@ constexpr int64_t kNumScanBlock = (int64_t)kNumScanThreads * kNumScanRows;
 constexpr int32_t kNumMarginMax = 10000;  // percent
 constexpr int kNumCopyRows = 256;         // rows per workgroup of the copy pass
 
+// A run of a row's entries kept in the overflow area: `n` entries from
+// position `pos` of the row (in column order) at offset `off` of the area.
+struct SpillRec {
+    int64_t off;
+    int32_t row, pos, n, pad;
+};
+
+// Overflow area: the rows share it through one 64-bit counter (agg[6]) that
+// holds the records taken above bit kSpillShift and the area's entries taken
+// below.  A longer row takes the area in chunks of sp_chunk entries (at most
+// kSpillChunk; smaller when the area is small for the workgroups that may
+// hold a chunk each) for its workgroup, so its entries past the slot form few
+// runs.
+constexpr int kSpillShift = 40;
+constexpr int64_t kSpillChunk = 1 << 16;
+constexpr int64_t kSpillCapMax = 1LL << 38;   // area entries, at most
+constexpr int64_t kSpillRecMax = 1LL << 23;   // records, at most
+
 // Arguments of the numeric kernels (one product per call; its CSR arrays are
 // in the case table).
 struct NumArgs {
@@ -52,9 +70,84 @@ struct NumArgs {
     int64_t mask_words;
     int32_t pool_slots;
     int32_t margin;                 // percent added to each capacity
-    SSP_GLOBAL int64_t* part;       // per-block partials of the scans: 3 x blocks
-    SSP_GLOBAL uint64_t* agg;       // [0] NNZ(C) [1] overflow rows [2] their nonzeros [3] slot entries
+    SSP_GLOBAL int64_t* part;       // per-block partials of the scans: 5 x blocks
+    // [0] NNZ(C) [1] overflow rows [2] their nonzeros [3] slot entries [4] longest A row of
+    // a long row [5] B unsorted [6] overflow-area counter [8] rows the area holds [9] their
+    // entries there
+    SSP_GLOBAL uint64_t* agg;
+    SSP_GLOBAL int32_t* sp_col;     // overflow area (sp_cap entries): columns
+    SSP_GLOBAL double* sp_val;      //                                 values
+    SSP_GLOBAL SpillRec* sp_rec;    // its records (rec_cap)
+    SSP_GLOBAL uint8_t* sp_state;   // M: 0 the row is not in the area, 1 its first s_i entries
+                                    // are in its slot and the rest in records, 2 all in records
+    int64_t sp_cap, rec_cap, sp_chunk;
 };
+constexpr int kNumAgg = 16;
+
+// Takes n entries of the overflow area and, with `rec`, one record: their
+// offsets, or false when the area or the records are used up.  The counter
+// is read first, so calls after the area has run out leave it unchanged (it
+// overshoots by at most the calls in flight: no carry into the record field).
+// Every record below the final record count is written: one taken by a call
+// that then fails (the area ran out meanwhile) is written empty (row -1).
+__device__ __forceinline__ bool spill_take(const NumArgs& na, int64_t n, bool rec, int64_t* off,
+                                           int64_t* r)
+{
+    constexpr uint64_t kLow = (1ull << kSpillShift) - 1;
+    SSP_GLOBAL uint64_t* ctr = &na.agg[6];
+    const uint64_t cur = __hip_atomic_load(ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    if ((int64_t)(cur & kLow) + n > na.sp_cap || (rec && (int64_t)(cur >> kSpillShift) >= na.rec_cap))
+        return false;
+    const uint64_t add = (rec ? (1ull << kSpillShift) : 0ull) + (uint64_t)n;
+    const uint64_t old = __hip_atomic_fetch_add(ctr, add, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    *off = (int64_t)(old & kLow);
+    *r = (int64_t)(old >> kSpillShift);
+    const bool rec_ok = rec && *r < na.rec_cap;
+    if (*off + n <= na.sp_cap && (!rec || rec_ok)) return true;
+    if (rec_ok) {  // (a record below the final count: written, empty)
+        SpillRec x;
+        x.off = 0;
+        x.row = -1;
+        x.pos = 0;
+        x.n = 0;
+        x.pad = 0;
+        na.sp_rec[*r] = x;
+    }
+    return false;
+}
+
+// Records a run of a row (false when the records are used up).
+__device__ __forceinline__ bool spill_record(const NumArgs& na, int64_t row, int64_t pos,
+                                             int64_t off, int64_t n)
+{
+    int64_t o, r;
+    if (!spill_take(na, 0, true, &o, &r)) return false;
+    SpillRec x;
+    x.off = off;
+    x.row = (int32_t)row;
+    x.pos = (int32_t)pos;
+    x.n = (int32_t)n;
+    x.pad = 0;
+    na.sp_rec[r] = x;
+    return true;
+}
+
+// The area for a whole row of c entries, with its record: the offset in *off.
+__device__ __forceinline__ bool spill_take_row(const NumArgs& na, int64_t row, int64_t c,
+                                               int64_t* off)
+{
+    int64_t o, r;
+    if (!spill_take(na, c, true, &o, &r)) return false;
+    SpillRec x;
+    x.off = o;
+    x.row = (int32_t)row;
+    x.pos = 0;
+    x.n = (int32_t)c;
+    x.pad = 0;
+    na.sp_rec[r] = x;
+    *off = o;
+    return true;
+}
 
 // Slot size of a row: its capacity clamped to [0, N], plus ceil(margin %),
 // at most N (a row of C has at most N entries).
@@ -76,14 +169,18 @@ __device__ __forceinline__ bool num_fits(const NumArgs& na, int64_t i, int64_t c
 // Value of row i in scan KIND: 0 the slot size, 1 the row's nonzeros.  KIND 1
 // also counts the overflowing rows and their nonzeros.
 template <int KIND>
-__device__ __forceinline__ int64_t num_scan_value(const NumArgs& na, int64_t i, int64_t* orow,
-                                                  int64_t* onnz)
+__device__ __forceinline__ int64_t num_scan_value(const NumArgs& na, int64_t i, int64_t* o)
 {
     if (KIND == 0) return num_slot_size(na.cap[i], na.margin, na.N);
     const int64_t c = na.cnt[i];
     if (!num_fits(na, i, c)) {
-        *orow += 1;
-        *onnz += c;
+        o[0] += 1;
+        o[1] += c;
+        const int st = na.sp_state[i];
+        if (st) {
+            o[2] += 1;
+            o[3] += st == 1 ? c - (na.slot_off[i + 1] - na.slot_off[i]) : c;
+        }
     }
     return c;
 }
@@ -95,21 +192,21 @@ __global__ __launch_bounds__(kNumScanThreads) void k_num_scan_part(NumArgs na)
     __shared__ int64_t s_red[kNumScanThreads / kWave + 1];
     const int64_t nblk = (na.M + kNumScanBlock - 1) / kNumScanBlock;
     for (int64_t b = blockIdx.x; b < nblk; b += gridDim.x) {
-        int64_t sum = 0, orow = 0, onnz = 0;
+        int64_t sum = 0, o[4] = {0, 0, 0, 0};
         const int64_t r0 = b * kNumScanBlock + (int64_t)threadIdx.x * kNumScanRows;
 #pragma unroll
         for (int u = 0; u < kNumScanRows; ++u)
-            if (r0 + u < na.M) sum += num_scan_value<KIND>(na, r0 + u, &orow, &onnz);
+            if (r0 + u < na.M) sum += num_scan_value<KIND>(na, r0 + u, o);
         sum = block_sum<kNumScanThreads, int64_t>(sum, s_red);
         if (KIND == 1) {
-            orow = block_sum<kNumScanThreads, int64_t>(orow, s_red);
-            onnz = block_sum<kNumScanThreads, int64_t>(onnz, s_red);
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q] = block_sum<kNumScanThreads, int64_t>(o[q], s_red);
         }
         if (threadIdx.x == 0) {
             na.part[b] = sum;
             if (KIND == 1) {
-                na.part[nblk + b] = orow;
-                na.part[2 * nblk + b] = onnz;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) na.part[(q + 1) * nblk + b] = o[q];
             }
         }
     }
@@ -123,13 +220,13 @@ __global__ __launch_bounds__(kNumScanThreads) void k_num_scan_top(NumArgs na)
     __shared__ int64_t s_red[kNumScanThreads / kWave + 1];
     const int64_t nblk = (na.M + kNumScanBlock - 1) / kNumScanBlock;
     SSP_GLOBAL int64_t* out = KIND == 0 ? na.slot_off : na.C_rpt;
-    int64_t run = 0, orow = 0, onnz = 0;
+    int64_t run = 0, o[4] = {0, 0, 0, 0};
     for (int64_t b0 = 0; b0 < nblk; b0 += kNumScanThreads) {
         const int64_t b = b0 + threadIdx.x;
         const int64_t v = b < nblk ? na.part[b] : 0;
         if (KIND == 1 && b < nblk) {
-            orow += na.part[nblk + b];
-            onnz += na.part[2 * nblk + b];
+#pragma unroll
+            for (int q = 0; q < 4; ++q) o[q] += na.part[(q + 1) * nblk + b];
         }
         int64_t tot;
         const int64_t ex = block_excl_scan<kNumScanThreads, int64_t>(v, s_red, &tot);
@@ -137,8 +234,8 @@ __global__ __launch_bounds__(kNumScanThreads) void k_num_scan_top(NumArgs na)
         run += tot;
     }
     if (KIND == 1) {
-        orow = block_sum<kNumScanThreads, int64_t>(orow, s_red);
-        onnz = block_sum<kNumScanThreads, int64_t>(onnz, s_red);
+#pragma unroll
+        for (int q = 0; q < 4; ++q) o[q] = block_sum<kNumScanThreads, int64_t>(o[q], s_red);
     }
     if (threadIdx.x == 0) {
         out[na.M] = run;
@@ -146,8 +243,10 @@ __global__ __launch_bounds__(kNumScanThreads) void k_num_scan_top(NumArgs na)
             na.agg[3] = (uint64_t)run;
         } else {
             na.agg[0] = (uint64_t)run;
-            na.agg[1] = (uint64_t)orow;
-            na.agg[2] = (uint64_t)onnz;
+            na.agg[1] = (uint64_t)o[0];
+            na.agg[2] = (uint64_t)o[1];
+            na.agg[8] = (uint64_t)o[2];
+            na.agg[9] = (uint64_t)o[3];
         }
     }
 }
@@ -186,9 +285,15 @@ __global__ __launch_bounds__(kNumScanThreads) void k_num_scan_rows(NumArgs na)
 // distinct columns the pass must hold.  The first pass only has to keep the
 // rows that fit their slot, so b = min(products, N, slot size); a row whose
 // columns outnumber the table stops (every probe sequence ends after 2^lg
-// steps) and is counted by the symbolic kernel instead.  The fallback pass
-// knows each row's exact count and sizes b by it.
+// steps) and is counted by the symbolic kernel instead.  With an overflow
+// area, a row longer than its slot that completes with at most half its
+// table goes to the area whole, and rows of at most kNumSpillWhole products
+// get b = min(products, N), so they all complete (their tables stay within
+// one wave's; larger tables for longer rows cost more time than the rows
+// that then no longer fail: 8.9 -> 17.4 ms on the squared 128^3 stencil).
+// The fallback pass knows each row's exact count and sizes b by it.
 constexpr int kNumWaveSlots = 512;  // table of a row handled by one wave
+constexpr uint32_t kNumSpillWhole = kNumWaveSlots / 2;
 constexpr int kNumUnroll = 4;       // products per lane whose loads are in flight together
 constexpr int kNumWaveWaves = 4;    // such rows per workgroup
 
@@ -206,7 +311,7 @@ __device__ __forceinline__ uint64_t num_bound(const NumArgs& na, int64_t row, ui
     if (PASS == 2) return (uint64_t)na.cnt[row];
     const int64_t s = na.slot_off[row + 1] - na.slot_off[row];
     int64_t b = (int64_t)rf < na.N ? (int64_t)rf : na.N;
-    return (uint64_t)(b < s ? b : s);
+    return (uint64_t)(b < s || (na.sp_cap > 0 && rf <= kNumSpillWhole) ? b : s);
 }
 
 // Adds v to column c's slot (open addressing, linear probing; columns are
@@ -331,7 +436,7 @@ __global__ __launch_bounds__(kNumWaveWaves* kWave) void k_num_wave(const CaseDes
          k += gridDim.x * kNumWaveWaves) {
         const BinItem item = num_hash_item(L, cnt, k);
         const int64_t row = item.row;
-        if (PASS == 2 && num_fits(na, row, na.cnt[row])) continue;
+        if (PASS == 2 && (num_fits(na, row, na.cnt[row]) || na.sp_state[row])) continue;
         const uint32_t T = num_table_size(num_bound<PASS>(na, row, item.rf));
         if (T > (uint32_t)kNumWaveSlots) continue;  // (a workgroup kernel's row)
         const int lg = __builtin_ctz(T);
@@ -409,11 +514,18 @@ __global__ __launch_bounds__(kNumWaveWaves* kWave) void k_num_wave(const CaseDes
         uint32_t pos = inc - mine;
         wave_sync();
         int64_t dst;
-        bool write;
+        bool write, spill = false;
         if (PASS == 1) {
             if (lane == 0) na.cnt[row] = (int64_t)c;
             dst = na.slot_off[row];
             write = (int64_t)c <= na.slot_off[row + 1] - dst;
+            if (!write && na.sp_cap > 0 && 2 * c <= T) {  // the whole row to the area
+                int64_t o = -1;
+                if (lane == 0 && spill_take_row(na, row, c, &o)) na.sp_state[row] = 2;
+                o = __shfl(o, 0, kWave);
+                spill = write = o >= 0;
+                dst = o;
+            }
         } else {
             dst = na.C_rpt[row];
             write = dst + (int64_t)c <= na.capacity;
@@ -429,8 +541,9 @@ __global__ __launch_bounds__(kNumWaveWaves* kWave) void k_num_wave(const CaseDes
             const uint32_t c4 = (c + 3u) & ~3u;
             if ((uint32_t)lane < c4 - c) keys[c + lane] = kEmpty;
             wave_sync();
-            num_write_ranked<kWave, EPT>(keys, vals, c, lane, PASS == 1 ? na.slot_col : na.C_col,
-                                         PASS == 1 ? na.slot_val : na.C_val, dst);
+            num_write_ranked<kWave, EPT>(keys, vals, c, lane,
+                                         PASS == 2 ? na.C_col : spill ? na.sp_col : na.slot_col,
+                                         PASS == 2 ? na.C_val : spill ? na.sp_val : na.slot_val, dst);
         }
         wave_sync();  // the table is reset for the next row
     }
@@ -453,13 +566,15 @@ __global__ __launch_bounds__(TEAM) void k_num_hash(const CaseDesc* __restrict__ 
     __shared__ double s_a[TEAM];
     __shared__ uint32_t s_red[TEAM / kWave + 1];
     __shared__ uint32_t s_fail;
+    __shared__ int64_t s_spill;
     const uint32_t n = *count;
     const int t = threadIdx.x;
     const Csr A = cs[0].A, B = cs[0].B;
     for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
         const BinItem item = items[it];
         const int64_t row = item.row;
-        if (PASS == 2 && num_fits(na, row, na.cnt[row])) continue;  // (the same for the whole team)
+        if (PASS == 2 && (num_fits(na, row, na.cnt[row]) || na.sp_state[row]))
+            continue;  // (the same for the whole team)
         const uint32_t T = num_table_size(num_bound<PASS>(na, row, item.rf));
         if (T <= (uint32_t)kNumWaveSlots) continue;  // (a one-wave row)
         const int lg = __builtin_ctz(T);
@@ -534,11 +649,21 @@ __global__ __launch_bounds__(TEAM) void k_num_hash(const CaseDesc* __restrict__ 
         uint32_t c;
         uint32_t pos = block_excl_scan<TEAM, uint32_t>(mine, s_red, &c);
         int64_t dst;
-        bool write;
+        bool write, spill = false;
         if (PASS == 1) {
             if (t == 0) na.cnt[row] = (int64_t)c;
             dst = na.slot_off[row];
             write = (int64_t)c <= na.slot_off[row + 1] - dst;
+            if (!write && na.sp_cap > 0 && 2 * c <= T) {  // the whole row to the area
+                if (t == 0) {
+                    int64_t o = -1;
+                    if (spill_take_row(na, row, c, &o)) na.sp_state[row] = 2;
+                    s_spill = o;
+                }
+                __syncthreads();
+                spill = write = s_spill >= 0;
+                dst = s_spill;
+            }
         } else {
             dst = na.C_rpt[row];
             write = dst + (int64_t)c <= na.capacity;
@@ -554,8 +679,9 @@ __global__ __launch_bounds__(TEAM) void k_num_hash(const CaseDesc* __restrict__ 
             const uint32_t c4 = (c + 3u) & ~3u;
             if ((uint32_t)t < c4 - c) keys[c + t] = kEmpty;
             __syncthreads();
-            num_write_ranked<TEAM, SPT / 2>(keys, vals, c, t, PASS == 1 ? na.slot_col : na.C_col,
-                                            PASS == 1 ? na.slot_val : na.C_val, dst);
+            num_write_ranked<TEAM, SPT / 2>(keys, vals, c, t,
+                                            PASS == 2 ? na.C_col : spill ? na.sp_col : na.slot_col,
+                                            PASS == 2 ? na.C_val : spill ? na.sp_val : na.slot_val, dst);
         }
         __syncthreads();  // the table is reset for the next row
     }
@@ -806,12 +932,13 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense(const CaseDesc* __r
 
 // ------------------------------------------------------------- copy pass
 
-// Rows that fitted their slot are copied to C at their final offsets.  Each
-// workgroup copies a chunk of kNumCopyChunk entries of C (so a long row is
-// shared by many workgroups): it finds the rows that overlap its chunk by
-// binary search over C's row offsets and takes them kNumCopyRows at a time,
-// their entries shared out over the threads (each finds its row by binary
-// search in LDS).
+// Rows that fitted their slot are copied to C at their final offsets, and so
+// are the slot parts of longer rows whose other entries the overflow area
+// holds.  Each workgroup copies a chunk of kNumCopyChunk entries of C (so a
+// long row is shared by many workgroups): it finds the rows that overlap its
+// chunk by binary search over C's row offsets and takes them kNumCopyRows at
+// a time, their entries shared out over the threads (each finds its row by
+// binary search in LDS).
 constexpr int64_t kNumCopyChunk = 8192;
 
 __global__ __launch_bounds__(kNumCopyRows) void k_num_copy(NumArgs na)
@@ -846,9 +973,12 @@ __global__ __launch_bounds__(kNumCopyRows) void k_num_copy(NumArgs na)
             int64_t n = 0, src = 0, dst = 0;
             if (i <= r_last) {
                 const int64_t c = na.cnt[i], beg = na.C_rpt[i];
+                const int64_t s = na.slot_off[i + 1] - na.slot_off[i];
+                // entries of the row in its slot
+                const int64_t m = c <= s ? c : (na.sp_state[i] == 1 ? s : 0);
                 const int64_t lo = beg > e0 ? beg : e0;
-                const int64_t hi = (beg + c) < e1 ? (beg + c) : e1;
-                if (num_fits(na, i, c) && beg + c <= na.capacity && hi > lo) {
+                const int64_t hi = (beg + m) < e1 ? (beg + m) : e1;
+                if (beg + c <= na.capacity && hi > lo) {
                     n = hi - lo;
                     src = na.slot_off[i] + (lo - beg);
                     dst = lo;
@@ -877,6 +1007,28 @@ __global__ __launch_bounds__(kNumCopyRows) void k_num_copy(NumArgs na)
     }
 }
 
+// The runs the overflow area holds, to their place in C: one run per
+// workgroup at a time (a run has at most kSpillChunk entries, or a window's).
+// Empty records (row -1) and runs of rows that the area could not hold to the
+// end are skipped (those rows are recomputed); so is a run outside its row or
+// the area.
+__global__ __launch_bounds__(256) void k_num_spill_copy(NumArgs na, int64_t nrec)
+{
+    for (int64_t r = blockIdx.x; r < nrec; r += gridDim.x) {
+        const SpillRec x = na.sp_rec[r];
+        if (x.row < 0 || (int64_t)x.row >= na.M || x.n <= 0 || !na.sp_state[x.row]) continue;
+        const int64_t beg = na.C_rpt[x.row], c = na.cnt[x.row];
+        if (beg + c > na.capacity || x.pos < 0 || (int64_t)x.pos + x.n > c || x.off < 0 ||
+            x.off + x.n > na.sp_cap)
+            continue;
+        const int64_t d = beg + x.pos;
+        for (int32_t q = threadIdx.x; q < x.n; q += 256) {
+            na.C_col[d + q] = na.sp_col[x.off + q];
+            na.C_val[d + q] = na.sp_val[x.off + q];
+        }
+    }
+}
+
 // ------------------------------------------- dense rows by column windows
 
 // Rows of more than kNumBin3Max products when every row of B lists its
@@ -889,8 +1041,11 @@ __global__ __launch_bounds__(kNumCopyRows) void k_num_copy(NumArgs na)
 // the window is skipped, the others find their end in the window by
 // exponential search.  Window by window the set bits are ranked (popcount
 // scan) and the row's entries written in column order; the first pass writes
-// only what fits the row's slot (a row that turns out not to fit is redone by
-// the fallback pass anyway) and records the exact count.
+// what fits the row's slot to the slot and, with an overflow area, the rest
+// to the area: thread 0 keeps the workgroup's current chunk of the area and
+// the row's current run (positions and area offsets both consecutive), and
+// records a run when the chunk changes or the row ends.  A row that the area
+// cannot hold is redone by the fallback pass.  The exact count is recorded.
 constexpr int kNumWinCols = 16384;
 
 // agg[5] != 0 when some row of B has a column smaller than its predecessor.
@@ -941,12 +1096,18 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
     __shared__ double s_a[TEAM];
     __shared__ uint64_t s_red[TEAM / kWave + 1];
     __shared__ uint32_t s_k;
+    __shared__ int64_t s_spill;
     const int t = threadIdx.x;
     const uint32_t nheavy = ctl->bin_cnt[4], total = nheavy + ctl->bin_cnt[6];
     uint32_t* next = &ctl->num_next[PASS - 1];
     const Csr A = cs[0].A, B = cs[0].B;
     const int64_t N = B.ncols;
     int2* cur = cursors + (int64_t)blockIdx.x * cur_stride;  // (position, its column) per A entry
+    // (thread 0) the workgroup's chunk of the overflow area [ck, ck_end); the
+    // row's run: area offset, first position, entries; whether the area
+    // holds the row so far
+    int64_t ck = 0, ck_end = 0, run_off = 0, run_pos = 0, run_n = 0;
+    bool held = true;
     for (int i = t; i < kNumWinCols; i += TEAM) s_acc[i] = 0.0;
     for (int i = t; i < WW; i += TEAM) s_flag[i] = 0u;
     for (;;) {
@@ -956,7 +1117,7 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
         if (k >= total) break;
         const BigItem item = items[big_index(k, nheavy, cap4)];
         const int64_t row = item.row;
-        if (PASS == 2 && num_fits(na, row, na.cnt[row])) {
+        if (PASS == 2 && (num_fits(na, row, na.cnt[row]) || na.sp_state[row])) {
             __syncthreads();  // (s_k is rewritten)
             continue;
         }
@@ -1052,6 +1213,46 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
             const uint32_t bits = t < WW ? s_flag[t] : 0u;
             uint64_t wtot;
             const uint64_t ex = block_excl_scan<TEAM, uint64_t>((uint64_t)__popc(bits), s_red, &wtot);
+            // entries from position `from` on go to the overflow area at `sp`
+            // (-1: nowhere)
+            const int64_t wend = c_total + (int64_t)wtot;
+            const int64_t from = cap > c_total ? cap : c_total;
+            int64_t sp = -1;
+            if (PASS == 1 && na.sp_cap > 0 && wend > cap) {  // (uniform)
+                if (t == 0) {
+                    const int64_t n = wend - from;  // (<= kNumWinCols)
+                    if (held && ck + n > ck_end) {  // a new chunk: the run ends
+                        if (run_n > 0) held = spill_record(na, row, run_pos, run_off, run_n);
+                        run_n = 0;
+                        // a chunk, else (the area nearly used up) just this window's entries
+                        const int64_t want = n > na.sp_chunk ? n : na.sp_chunk;
+                        int64_t o, r;
+                        if (held && spill_take(na, want, false, &o, &r)) {
+                            ck = o;
+                            ck_end = o + want;
+                        } else if (held && want > n && spill_take(na, n, false, &o, &r)) {
+                            ck = o;
+                            ck_end = o + n;
+                        } else {
+                            held = false;
+                            ck = ck_end = 0;
+                        }
+                    }
+                    if (held) {
+                        if (run_n == 0) {
+                            run_off = ck;
+                            run_pos = from;
+                        }
+                        s_spill = ck;
+                        ck += n;
+                        run_n += n;
+                    } else {
+                        s_spill = -1;
+                    }
+                }
+                __syncthreads();
+                sp = s_spill;
+            }
             int64_t o = c_total + (int64_t)ex;
             uint32_t bb = bits;
             while (bb) {
@@ -1061,6 +1262,9 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
                 if (o < cap) {
                     ocol[dst + o] = (int32_t)(lo + x);
                     oval[dst + o] = s_acc[x];
+                } else if (sp >= 0) {
+                    na.sp_col[sp + (o - from)] = (int32_t)(lo + x);
+                    na.sp_val[sp + (o - from)] = s_acc[x];
                 }
                 s_acc[x] = 0.0;
                 ++o;
@@ -1069,7 +1273,15 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
             c_total += (int64_t)wtot;
             __syncthreads();
         }
-        if (PASS == 1 && t == 0) na.cnt[row] = c_total;
+        if (PASS == 1 && t == 0) {
+            na.cnt[row] = c_total;
+            if (na.sp_cap > 0 && c_total > cap) {  // the row's last run
+                if (held && run_n > 0) held = spill_record(na, row, run_pos, run_off, run_n);
+                if (held) na.sp_state[row] = 1;
+                run_n = 0;
+                held = true;
+            }
+        }
         __syncthreads();
     }
 }

@@ -18,6 +18,8 @@ struct NumState {
     bool win = false;                 // long rows by LDS column windows (B's rows sorted)
     int2* cursors = nullptr;          // their per-entry cursors (pool memory)
     int64_t cur_stride = 0;
+    int64_t nrec = 0;                 // records of the overflow area
+    int64_t recompute = 0;            // overflowing rows the area does not hold
     ssp_spgemm_info info{};
 };
 
@@ -143,7 +145,7 @@ constexpr int64_t kNumPoolBytesMax = 1LL << 31;  // dense accumulators of a call
 
 ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, const ssp_csr* B,
                           const double* B_val, const int64_t* row_cap, int32_t margin_pct,
-                          int64_t* C_rpt, ssp_spgemm_info* info, hipStream_t s)
+                          int32_t spill_pct, int64_t* C_rpt, ssp_spgemm_info* info, hipStream_t s)
 {
     // the previous call's copy pass may still read the slots and use the accumulators
     if (h->num_ev) SSP_HIP(h, hipEventSynchronize(h->num_ev));
@@ -160,9 +162,10 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     size_t o = align256(P.total);
     const size_t o_cnt = o;  o = align256(o + (size_t)std::max<int64_t>(M, 1) * sizeof(int64_t));
     const size_t o_slot = o; o = align256(o + (size_t)(M + 1) * sizeof(int64_t));
-    const size_t o_part = o; o = align256(o + (size_t)std::max<int64_t>(3 * nblk, 1) * sizeof(int64_t));
-    const size_t o_agg = o;  o = align256(o + 8 * sizeof(uint64_t));
+    const size_t o_part = o; o = align256(o + (size_t)std::max<int64_t>(5 * nblk, 1) * sizeof(int64_t));
+    const size_t o_agg = o;  o = align256(o + kNumAgg * sizeof(uint64_t));
     const size_t o_abort = o; o = align256(o + (size_t)std::max<int64_t>(M, 1) * sizeof(BinItem));
+    const size_t o_state = o; o = align256(o + (size_t)std::max<int64_t>(M, 1));
     ssp_status st = grow_buffer(h, &h->num_ws, &h->num_ws_bytes, o, true);
     if (st != SSP_OK) return st;
     char* base = static_cast<char*>(h->num_ws);
@@ -185,6 +188,7 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     na.part = (decltype(na.part))(base + o_part);
     na.agg = (decltype(na.agg))(base + o_agg);
     S->abort_list = reinterpret_cast<BinItem*>(base + o_abort);
+    na.sp_state = (decltype(na.sp_state))(base + o_state);
     na.C_rpt = (decltype(na.C_rpt))C_rpt;
     na.M = M;
     na.N = N;
@@ -193,7 +197,12 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     // 1. row FLOP and bins (Alg. 1), slot sizes and their offsets
     launch_setup(h, P, S->b, s, false, true);
     SSP_LAUNCHED(h);
-    hipLaunchKernelGGL(k_num_zero, dim3(1), dim3(64), 0, s, (uint64_t*)na.agg, (int64_t)8);
+    hipLaunchKernelGGL(k_num_zero, dim3(1), dim3(64), 0, s, (uint64_t*)na.agg, (int64_t)kNumAgg);
+    {
+        const int64_t words = (std::max<int64_t>(M, 1) + 7) / 8;
+        hipLaunchKernelGGL(k_num_zero, dim3((unsigned)std::min<int64_t>((words + 255) / 256, 4LL * cus)),
+                           dim3(256), 0, s, (uint64_t*)na.sp_state, words);
+    }
     launch_flop<FLOP_EXACT_BIN>(h, P, S->b, s, true);
     {
         PhaseTimer pt(h, PH_NUM_SCAN, s);
@@ -207,7 +216,7 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     }
     SSP_LAUNCHED(h);
     SSP_HIP(h, hipStreamSynchronize(s));
-    uint64_t agg[8];
+    uint64_t agg[kNumAgg];
     Ctl ctl;
     SSP_HIP(h, hipMemcpy(agg, na.agg, sizeof(agg), hipMemcpyDeviceToHost));
     SSP_HIP(h, hipMemcpy(&ctl, S->b.ctl, sizeof(ctl), hipMemcpyDeviceToHost));
@@ -217,11 +226,24 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     S->bins[2] = ctl.bin_cnt[3];
     S->bins[3] = ctl.bin_cnt[4] + ctl.bin_cnt[6];
 
-    // 2. the slot area and the dense accumulators
+    // 2. the slot area, the overflow area and its records, the dense accumulators
     const size_t slot_bytes = (size_t)std::max<int64_t>(slots, 1) * (sizeof(double) + sizeof(int32_t));
-    if ((st = grow_buffer(h, &h->num_slots, &h->num_slots_bytes, slot_bytes, true)) != SSP_OK) return st;
-    na.slot_val = (decltype(na.slot_val))h->num_slots;
-    na.slot_col = (decltype(na.slot_col))((char*)h->num_slots + (size_t)std::max<int64_t>(slots, 1) * sizeof(double));
+    const int64_t spc = std::min<int64_t>(kSpillCapMax, (int64_t)(((__int128)slots * spill_pct + 99) / 100));
+    const int64_t rec_cap = spc > 0 ? std::min<int64_t>(kSpillRecMax, M + spc / kSpillChunk + 4096) : 0;
+    size_t q = align256((size_t)std::max<int64_t>(slots, 1) * sizeof(double));
+    const size_t q_col = q;   q = align256(q + (size_t)std::max<int64_t>(slots, 1) * sizeof(int32_t));
+    const size_t q_spv = q;   q = align256(q + (size_t)spc * sizeof(double));
+    const size_t q_spc = q;   q = align256(q + (size_t)spc * sizeof(int32_t));
+    const size_t q_rec = q;   q = align256(q + (size_t)rec_cap * sizeof(SpillRec));
+    if ((st = grow_buffer(h, &h->num_slots, &h->num_slots_bytes, q, true)) != SSP_OK) return st;
+    char* sb = static_cast<char*>(h->num_slots);
+    na.slot_val = (decltype(na.slot_val))sb;
+    na.slot_col = (decltype(na.slot_col))(sb + q_col);
+    na.sp_val = (decltype(na.sp_val))(sb + q_spv);
+    na.sp_col = (decltype(na.sp_col))(sb + q_spc);
+    na.sp_rec = (decltype(na.sp_rec))(sb + q_rec);
+    na.sp_cap = spc;
+    na.rec_cap = rec_cap;
     S->win = S->bins[3] > 0 && agg[5] == 0;
     if (S->win) {
         // LDS windows: no accumulators in global memory, a cursor per A entry
@@ -256,6 +278,11 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
         }
     }
 
+    // chunks of the area for the long rows' workgroups: up to kSpillChunk
+    // entries, the grid's chunks together at most an eighth of the area
+    na.sp_chunk = std::max<int64_t>(1024, std::min<int64_t>(
+                                              kSpillChunk, spc / (8 * std::max<int64_t>(1, S->dense_grid))));
+
     // 3. the numeric pass into the slots, then C's row offsets (a launched
     //    pass leaves the accumulators zero; one that failed to launch may not)
     const bool was_clean = h->num_pool_clean;
@@ -279,6 +306,13 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
     inf.overflow_rows = (int64_t)agg[1];
     inf.overflow_nnz = (int64_t)agg[2];
     inf.slot_bytes = (int64_t)slot_bytes;
+    inf.spill_rows = (int64_t)agg[8];
+    inf.spill_nnz = (int64_t)agg[9];
+    inf.spill_bytes = spc > 0 ? spc * (int64_t)(sizeof(double) + sizeof(int32_t)) +
+                                    rec_cap * (int64_t)sizeof(SpillRec)
+                              : 0;
+    S->nrec = std::min<int64_t>((int64_t)(agg[6] >> kSpillShift), rec_cap);
+    S->recompute = inf.overflow_rows - inf.spill_rows;
     *info = inf;
     h->num_state = S;
     return SSP_OK;
@@ -300,14 +334,17 @@ ssp_status spgemm_copy(ssp_handle h, int32_t* C_col, double* C_val, int64_t capa
     na.C_val = (decltype(na.C_val))C_val;
     na.capacity = capacity;
     const int cus = h->num_cus;
-    if (S->info.nnz > S->info.overflow_nnz) {
+    if (S->info.nnz > S->info.overflow_nnz || S->info.spill_rows > 0) {
         PhaseTimer pt(h, PH_NUM_COPY, s);
         const int64_t blocks = (S->info.nnz + kNumCopyChunk - 1) / kNumCopyChunk;
         hipLaunchKernelGGL(k_num_copy, dim3((unsigned)std::max<int64_t>(1, std::min<int64_t>(blocks, 16LL * cus))),
                            dim3(kNumCopyRows), 0, s, na);
+        if (S->info.spill_rows > 0 && S->nrec > 0)
+            hipLaunchKernelGGL(k_num_spill_copy, dim3((unsigned)std::min<int64_t>(S->nrec, 16LL * cus)),
+                               dim3(256), 0, s, na, S->nrec);
     }
     SSP_LAUNCHED(h);
-    if (S->info.overflow_rows > 0) {
+    if (S->recompute > 0) {
         const bool was_clean = h->num_pool_clean;
         h->num_pool_clean = false;
         // (the dense fallback's work queue starts at 0 on every copy call)
@@ -328,18 +365,19 @@ extern "C" {
 
 ssp_status ssp_spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val,
                               const ssp_csr* B, const double* B_val, const int64_t* row_cap,
-                              int32_t margin_pct, int64_t* C_rpt, ssp_spgemm_info* info,
-                              void* stream)
+                              int32_t margin_pct, int32_t spill_pct, int64_t* C_rpt,
+                              ssp_spgemm_info* info, void* stream)
 {
     if (!h || !info || !C_rpt) return SSP_ERR_INVALID_ARG;
     const ssp_status s = check_pair(A, B);
     if (s != SSP_OK) return s;
     if (margin_pct < 0 || margin_pct > kNumMarginMax) return SSP_ERR_INVALID_ARG;
+    if (spill_pct < 0 || spill_pct > kNumMarginMax) return SSP_ERR_INVALID_ARG;
     if ((A->nnz > 0 && !A_val) || (B->nnz > 0 && !B_val) || (A->nrows > 0 && !row_cap))
         return SSP_ERR_INVALID_ARG;
     DeviceGuard g(h->device);
     if (!g.ok()) return SSP_ERR_NO_DEVICE;
-    return spgemm_compute(h, A, A_val, B, B_val, row_cap, margin_pct, C_rpt, info,
+    return spgemm_compute(h, A, A_val, B, B_val, row_cap, margin_pct, spill_pct, C_rpt, info,
                           static_cast<hipStream_t>(stream));
 }
 

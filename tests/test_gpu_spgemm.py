@@ -33,20 +33,25 @@ def _say(msg):
     print(msg, flush=True)
 
 
-def _run(ssp, A, B, av, bv, cap, margin, Ad=None, Bd=None, capacity=None):
+def _run(ssp, A, B, av, bv, cap, margin, Ad=None, Bd=None, capacity=None, spill=0):
     Ad = Ad if Ad is not None else ssp.DeviceCSR.from_csr(A, "cuda:0")
     Bd = Bd if Bd is not None else (Ad if B is A else ssp.DeviceCSR.from_csr(B, "cuda:0"))
     tav = torch.from_numpy(np.ascontiguousarray(av)).to("cuda:0")
     tbv = tav if bv is av else torch.from_numpy(np.ascontiguousarray(bv)).to("cuda:0")
     tcap = cap if isinstance(cap, torch.Tensor) else torch.from_numpy(
         np.ascontiguousarray(cap, dtype=np.int64)).to("cuda:0")
-    rpt, col, val, info = ssp.spgemm(Ad, tav, Bd, tbv, tcap, margin_pct=margin, capacity=capacity)
+    rpt, col, val, info = ssp.spgemm(Ad, tav, Bd, tbv, tcap, margin_pct=margin, spill_pct=spill,
+                                     capacity=capacity)
     torch.cuda.synchronize()
     return rpt.cpu().numpy(), col.cpu().numpy(), val.cpu().numpy(), info, tcap.cpu().numpy()
 
 
-def check(ssp, A, B, av, bv, cap, margin, exact_values, what, **kw):
-    _say(f"spgemm {what}: M={A.nrows} K={A.ncols} N={B.ncols} margin={margin}")
+def check(ssp, A, B, av, bv, cap, margin, exact_values, what, held=None, **kw):
+    """Runs the product and compares it with the oracle.  ``held``: every
+    overflowing row must end in the overflow area (True), none (False), or
+    either (None: an area that may run short)."""
+    _say(f"spgemm {what}: M={A.nrows} K={A.ncols} N={B.ncols} margin={margin} "
+         f"spill={kw.get('spill', 0)}")
     rpt, col, val, info, cap_np = _run(ssp, A, B, av, bv, cap, margin, **kw)
     orpt, ocol, oval, oabs, oterms = oracle.spgemm(A, av, B, bv)
     assert np.array_equal(rpt, orpt), f"{what}: C_rpt"
@@ -62,7 +67,35 @@ def check(ssp, A, B, av, bv, cap, margin, exact_values, what, **kw):
     for k, v in lay.items():
         assert info[k] == v, f"{what}: info.{k} gpu={info[k]} oracle={v}"
     assert info["total_flop"] == F, f"{what}: F"
+    assert 0 <= info["spill_rows"] <= info["overflow_rows"], what
+    assert 0 <= info["spill_nnz"] <= info["overflow_nnz"], what
+    if kw.get("spill", 0) == 0:
+        assert info["spill_rows"] == info["spill_nnz"] == info["spill_bytes"] == 0, what
+    if held is not None:
+        # an area large enough: every overflowing row of at most 256 products
+        # or (B's rows sorted) more than 2048 ends in it, a row in between may
+        # (when it completes within half its table); a row of more than 2048
+        # products keeps its first s_i entries in its slot, a shorter row none
+        cnt = np.diff(orpt)
+        rf = np.asarray(oracle.row_flop(A, B)[0])
+        slot = _slots(cap_np, margin, B.ncols)
+        over = cnt > slot
+        sure = over & ((rf <= 256) | (rf > 2048))
+        maybe = over & ~sure
+        kept = np.where(rf > 2048, cnt - slot, cnt)
+        if held:
+            assert sure.sum() <= info["spill_rows"] <= sure.sum() + maybe.sum(), what
+            assert kept[sure].sum() <= info["spill_nnz"] <= kept[sure].sum() + kept[maybe].sum(), what
+            if not maybe.any():
+                assert info["spill_rows"] == lay["overflow_rows"], what
+        else:
+            assert info["spill_rows"] == 0, what
     return info
+
+
+def _slots(cap, margin, N):
+    c = np.clip(np.asarray(cap, dtype=np.int64), 0, N)
+    return np.minimum(N, c + (c * margin + 99) // 100)
 
 
 def _values(M, seed, kind):
@@ -239,3 +272,100 @@ def test_spgemm_long_rows_unsorted_wide_b(ssp):
     counts, _ = oracle.exact(A, B)
     check(ssp, A, B, av, bv, counts, 0, True, "dense, unsorted B, N = 600000")
     check(ssp, A, B, av, bv, counts - 7, 0, True, "dense, unsorted B, N = 600000, overflow")
+
+
+# ------------------------------------------------ the overflow area
+
+
+def test_spgemm_overflow_area_holds_every_row(ssp):
+    # power-law rows in every bin, under-predicted: with a large area no row is recomputed
+    A = workloads.rmat(1 << 13, 12, 6)
+    av = _values(A, 4, "uniform")
+    Ad = ssp.DeviceCSR.from_csr(A, "cuda:0")
+    pred, _ = ssp.predict_structure(Ad, Ad, 0.01, 3)[:2]
+    info = check(ssp, A, A, av, av, pred, 0, False, "rmat13 pred, area 400%", Ad=Ad, Bd=Ad,
+                 spill=400, held=True)
+    assert info["overflow_rows"] > 0 and info["spill_bytes"] > 0
+    avi = _values(A, 4, "int")
+    check(ssp, A, A, avi, avi, pred, 10, True, "rmat13 pred +10%, area 400%", Ad=Ad, Bd=Ad,
+          spill=400, held=True)
+
+
+def test_spgemm_overflow_area_runs_short(ssp):
+    # an area too small for every overflowing row: the rest are recomputed
+    A = workloads.rmat(1 << 13, 12, 6)
+    av = _values(A, 4, "int")
+    Ad = ssp.DeviceCSR.from_csr(A, "cuda:0")
+    pred, _ = ssp.predict_structure(Ad, Ad, 0.01, 3)[:2]
+    for pct in (1, 5, 20):
+        info = check(ssp, A, A, av, av, pred, 0, True, f"rmat13 pred, area {pct}%", Ad=Ad,
+                     Bd=Ad, spill=pct)
+        if pct == 1:
+            assert info["spill_rows"] < info["overflow_rows"]
+
+
+def test_spgemm_overflow_area_long_rows_across_windows(ssp):
+    # rows of about 4096 products over 70,000 columns (five column windows):
+    # the entries past the slot span windows; sorted B with repeated columns too
+    A = workloads.uniform(1500, 2000, 64, 2)
+    B = workloads.uniform(2000, 70000, 64, 3)
+    av, bv = _values(A, 1, "int"), _values(B, 2, "int")
+    counts, _ = oracle.exact(A, B)
+    check(ssp, A, B, av, bv, counts // 3, 0, True, "dense, area 300%", spill=300, held=True)
+    check(ssp, A, B, av, bv, counts - 1, 0, True, "dense, one entry over", spill=50, held=True)
+    check(ssp, A, B, av, bv, np.zeros(A.nrows, dtype=np.int64), 0, True,
+          "dense, zero caps (no slots, so no area)", spill=300, held=False)
+    B0 = workloads.uniform(1500, 50000, 40, 8)
+    B2, bv2 = _doubled_entries(B0, _values(B0, 3, "int"))
+    A2 = workloads.uniform(500, 1500, 48, 7)
+    av2 = _values(A2, 4, "int")
+    c2, _ = oracle.exact(A2, B2)
+    check(ssp, A2, B2, av2, bv2, c2 // 2, 0, True, "dense, repeated columns, area", spill=200,
+          held=True)
+
+
+def test_spgemm_overflow_area_chunks(ssp):
+    # more entries past the slots than one chunk of the area per workgroup:
+    # a row's run breaks where its workgroup takes the next chunk
+    A = workloads.uniform(20000, 2000, 64, 21)
+    B = workloads.uniform(2000, 40000, 64, 22)
+    av, bv = _values(A, 5, "int"), _values(B, 6, "int")
+    counts, _ = oracle.exact(A, B)
+    info = check(ssp, A, B, av, bv, counts // 4, 0, True, "dense, area in many chunks",
+                 spill=400, held=True)
+    assert info["spill_nnz"] > 256 * (1 << 16)
+
+
+def test_spgemm_overflow_area_unsorted_b(ssp):
+    # unsorted B: the long rows' kernel keeps no overflow, the short rows do
+    A = workloads.uniform(600, 2000, 64, 5)
+    Bs = workloads.uniform(2000, 30000, 64, 6)
+    B, bv = _shuffled_rows(Bs, _values(Bs, 2, "int"), 3)
+    av = _values(A, 1, "int")
+    counts, _ = oracle.exact(A, B)
+    check(ssp, A, B, av, bv, counts - 5, 0, True, "dense, unsorted B, area", spill=300,
+          held=False)
+    Z = workloads.zipf(3000, 8, 9)
+    zv = _values(Z, 3, "int")
+    zc, _ = oracle.exact(Z, Z)
+    Zs, zsv = _shuffled_rows(Z, zv, 4)
+    check(ssp, Zs, Zs, zsv, zsv, zc // 2, 0, True, "zipf, unsorted, area", spill=300)
+
+
+def test_spgemm_overflow_area_repeated_calls(ssp):
+    # the area's counters and row states start afresh on every call; a
+    # smaller product after a larger one
+    A = workloads.rmat(1 << 13, 12, 6)
+    av = _values(A, 4, "int")
+    counts, _ = oracle.exact(A, A)
+    Ad = ssp.DeviceCSR.from_csr(A, "cuda:0")
+    check(ssp, A, A, av, av, counts // 2, 0, True, "rmat13 half caps, area", Ad=Ad, Bd=Ad,
+          spill=200, held=True)
+    check(ssp, A, A, av, av, counts, 0, True, "rmat13 exact caps, area", Ad=Ad, Bd=Ad,
+          spill=200, held=True)
+    S = workloads.uniform(900, 900, 10, 3)
+    sv = _values(S, 5, "int")
+    sc, _ = oracle.exact(S, S)
+    check(ssp, S, S, sv, sv, sc // 2, 0, True, "uniform900 half caps, area", spill=300,
+          held=True)
+    check(ssp, A, A, av, av, counts // 2, 0, True, "rmat13 half caps, no area", Ad=Ad, Bd=Ad)
