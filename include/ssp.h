@@ -272,7 +272,7 @@ SSP_API ssp_status ssp_batch_graph_destroy(ssp_batch_graph graph);
  *                 columns but bin 3 would hash, bin-3 rows go to the long-row
  *                 kernel; 0: never.
  *   split_target: long rows above this many products are split into parts
- *                 (2^12..2^40; default 2^18).
+ *                 (2^12..2^40; default 2^19).
  *   est_max_rf  : the prediction's per-row ceiling ceil(rf z* / f*) takes a
  *                 double-precision estimate corrected in integers for rows
  *                 of fewer than est_max_rf products, a 128-bit division for

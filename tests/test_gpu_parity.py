@@ -264,8 +264,8 @@ def test_prediction_ceiling_at_whole_quotients(ssp, kinds, num, den):
 def _long_rows(ncols, nbig, seed):
     # long rows whose entries name B rows of all three length classes the
     # long-row kernel treats differently: huge (>= 2048 entries), medium
-    # (32..2047) and short (< 32); the largest rows exceed the split
-    # threshold (2^18 products) several times over
+    # (32..2047) and short (< 32); the largest rows exceed the default split
+    # threshold (2^19 products) more than twice over
     rng = np.random.default_rng(seed)
     K = 3000
     brows = []
@@ -294,7 +294,7 @@ def _long_rows(ncols, nbig, seed):
 def test_split_long_rows(ssp):
     A, B = _long_rows(300_000, 8, 1)
     rf, _ = oracle.row_flop(A, B)
-    assert rf.max() > 4 * 2 ** 18
+    assert rf.max() > 2 * 2 ** 19
     _say(f"split long rows max rf={rf.max()}")
     check_all(ssp, A, B, 1.0, 1)
     check_all(ssp, A, B, 0.3, 2)
