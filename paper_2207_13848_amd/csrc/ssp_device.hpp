@@ -414,18 +414,16 @@ __device__ __forceinline__ uint32_t rank_in(uint64_t mask)
 }
 
 // OR `bits` into word `word` of an LDS bitmap for every lane of the wave
-// (all 64 lanes must call it; an inactive lane passes word = kNoWord).
-// First the word is read and only bits not yet set go on: repeated columns
-// (hub columns appear in most B rows) then cost a broadcast read instead of
-// an LDS atomic, and atomics on one word serialise.  Bits are only ever set,
-// so a stale read merely costs an extra atomic.  Runs of neighbouring lanes
-// that still target one word (sorted B rows put consecutive products in one
-// word) are then combined by a segmented OR over the wave, one atomic per run.
+// (all 64 lanes must call it; an inactive lane passes word = kNoWord).  Runs
+// of neighbouring lanes that target one word (sorted B rows put consecutive
+// products in one word) are combined by a segmented OR over the wave, one
+// atomic per run, since atomics on one word serialise.  The words are not
+// read first to skip bits already set: that read's latency cost more than
+// the atomics it saved (bins of R-MAT 2^16: 26.4 -> 25.4 us without it).
 constexpr uint32_t kNoWord = 0xFFFFFFFFu;
 
-// Atomic part of the above for lanes whose bits are known to be needed
-// (word = kNoWord for lanes with nothing to set).
-__device__ __forceinline__ void wave_bitmap_or_needed(uint32_t* bm, uint32_t word, uint32_t need)
+// The segmented OR (word = kNoWord for lanes with nothing to set).
+__device__ __forceinline__ void wave_bitmap_or_runs(uint32_t* bm, uint32_t word, uint32_t bits)
 {
     const int lane = lane_id();
     const uint64_t valid = __ballot(word != kNoWord);
@@ -434,10 +432,10 @@ __device__ __forceinline__ void wave_bitmap_or_needed(uint32_t* bm, uint32_t wor
     const bool head = lane == 0 || prev != word;
     const uint64_t heads = __ballot(head && word != kNoWord);
     if (heads == valid) {  // no two neighbours share a word
-        if (word != kNoWord) atomicOr(&bm[word], need);
+        if (word != kNoWord) atomicOr(&bm[word], bits);
         return;
     }
-    uint32_t acc = need;
+    uint32_t acc = bits;
 #pragma unroll
     for (int off = 1; off < kWave; off <<= 1) {
         const uint32_t ow = __shfl_down(word, off, kWave);
@@ -449,9 +447,7 @@ __device__ __forceinline__ void wave_bitmap_or_needed(uint32_t* bm, uint32_t wor
 
 __device__ __forceinline__ void wave_bitmap_or(uint32_t* bm, uint32_t word, uint32_t bits)
 {
-    uint32_t need = 0;
-    if (word != kNoWord) need = bits & ~bm[word];
-    wave_bitmap_or_needed(bm, need ? word : kNoWord, need);
+    wave_bitmap_or_runs(bm, word, word != kNoWord ? bits : 0u);
 }
 
 // Word w of a bitmap lives at w ^ ((w >> 6) & 63): its 64-word row keeps its
@@ -465,16 +461,17 @@ __device__ __forceinline__ uint32_t swz(uint32_t w) { return w ^ ((w >> 6) & 63u
 // V columns per lane (kNoWord = none), normally neighbours in one B row:
 // runs of them that fall in one bitmap word (sorted rows make such runs
 // contiguous) are first combined inside the lane; then every remaining word
-// is read and only the bits not yet set go on to an LDS atomic OR.  Bits are
-// only ever set, so a stale read costs at most an extra atomic, and columns
-// seen before (hub columns appear in most B rows) cost a read instead of an
-// atomic.  Unsorted or repeated columns stay correct, merely slower.  Columns
-// outside the window [clo, clo + wc) are skipped.  No cross-lane traffic.
+// goes to an LDS atomic OR, which returns nothing, so the wave does not wait
+// on it.  (Reading each word first and ORing only the bits not yet set saved
+// atomics on columns seen before, but put the read's latency on every insert:
+// the long-row kernel on R-MAT 2^20 took 114 us that way, 98 us without.)
+// Unsorted or repeated columns stay correct.  Columns outside the window
+// [clo, clo + wc) are skipped.  No cross-lane traffic.
 template <int V>
 __device__ __forceinline__ void lane_bitmap_insert(uint32_t* bm, const uint32_t (&col)[V],
                                                    uint32_t clo, uint32_t wc)
 {
-    uint32_t word[V], bits[V], old[V];
+    uint32_t word[V], bits[V];
 #pragma unroll
     for (int v = 0; v < V; ++v) {
         const uint32_t cw = col[v] - clo;  // columns < 2^31: wraps above wc when col < clo
@@ -489,12 +486,8 @@ __device__ __forceinline__ void lane_bitmap_insert(uint32_t* bm, const uint32_t 
         word[v - 1] = same ? kNoWord : word[v - 1];
     }
 #pragma unroll
-    for (int v = 0; v < V; ++v) old[v] = bm[word[v] != kNoWord ? swz(word[v]) : 0u];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const uint32_t need = word[v] != kNoWord ? (bits[v] & ~old[v]) : 0u;
-        if (need) atomicOr(&bm[swz(word[v])], need);
-    }
+    for (int v = 0; v < V; ++v)
+        if (word[v] != kNoWord) atomicOr(&bm[swz(word[v])], bits[v]);
 }
 
 // The same for one window holding all N columns (columns are < N, so no
@@ -510,31 +503,21 @@ __device__ __forceinline__ void lane_bitmap_insert4(uint32_t* bm, const int32_t 
     b2 |= s2 ? b1 : 0u;
     b3 |= s3 ? b2 : 0u;
     const uint32_t p0 = swz(w0), p1 = swz(w1), p2 = swz(w2), p3 = swz(w3);
-    const uint32_t o0 = bm[p0], o1 = bm[p1], o2 = bm[p2], o3 = bm[p3];
-    // a word is written at the end of its run only
-    const uint32_t n0 = s1 ? 0u : (b0 & ~o0);
-    const uint32_t n1 = s2 ? 0u : (b1 & ~o1);
-    const uint32_t n2 = s3 ? 0u : (b2 & ~o2);
-    const uint32_t n3 = b3 & ~o3;
-    if (n0) atomicOr(&bm[p0], n0);
-    if (n1) atomicOr(&bm[p1], n1);
-    if (n2) atomicOr(&bm[p2], n2);
-    if (n3) atomicOr(&bm[p3], n3);
+    // a word is ORed at the end of its run only
+    if (!s1) atomicOr(&bm[p0], b0);
+    if (!s2) atomicOr(&bm[p1], b1);
+    if (!s3) atomicOr(&bm[p2], b2);
+    atomicOr(&bm[p3], b3);
 }
 
 // V independent columns per lane (kNoWord = none), one window holding all
-// N columns: read-filtered LDS OR, no merging.
+// N columns: an LDS OR per column, no merging.
 template <int V>
 __device__ __forceinline__ void lane_bitmap_insert_all(uint32_t* bm, const uint32_t (&col)[V])
 {
-    uint32_t old[V];
 #pragma unroll
-    for (int v = 0; v < V; ++v) old[v] = bm[col[v] != kNoWord ? swz(col[v] >> 5) : 0u];
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-        const uint32_t need = col[v] != kNoWord ? ((1u << (col[v] & 31)) & ~old[v]) : 0u;
-        if (need) atomicOr(&bm[swz(col[v] >> 5)], need);
-    }
+    for (int v = 0; v < V; ++v)
+        if (col[v] != kNoWord) atomicOr(&bm[swz(col[v] >> 5)], 1u << (col[v] & 31));
 }
 
 // Global-memory pointers (device code): see ssp_internal.hpp.
