@@ -845,20 +845,18 @@ constexpr uint32_t kEmpty = 0xFFFFFFFFu;
 
 // Open addressing with linear probing on an LDS table of 2^lg words;
 // returns 1 when `c` was not yet present.  Columns are < 2^31, so the
-// all-ones word marks an empty slot.
+// all-ones word marks an empty slot.  Every probe is one compare-and-swap,
+// whose returned word tells an insert, a repeat and an occupied slot apart
+// (a plain read first, then the swap on an empty slot, took two dependent
+// LDS round trips per new column: bins of uniform 2^20 d 32 90 -> 75 us).
 __device__ __forceinline__ uint32_t hash_insert(uint32_t* tab, uint32_t c, int lg)
 {
     const uint32_t mask = (1u << lg) - 1u;
     uint32_t h = (c * 0x9E3779B1u) >> (32 - lg);
     for (;;) {
-        const uint32_t cur = __hip_atomic_load(&tab[h], __ATOMIC_RELAXED,
-                                               __HIP_MEMORY_SCOPE_WORKGROUP);
-        if (cur == c) return 0u;
-        if (cur == kEmpty) {
-            const uint32_t prev = atomicCAS(&tab[h], kEmpty, c);
-            if (prev == kEmpty) return 1u;
-            if (prev == c) return 0u;
-        }
+        const uint32_t prev = atomicCAS(&tab[h], kEmpty, c);
+        if (prev == kEmpty) return 1u;
+        if (prev == c) return 0u;
         h = (h + 1u) & mask;
     }
 }

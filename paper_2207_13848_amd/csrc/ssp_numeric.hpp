@@ -323,14 +323,10 @@ __device__ __forceinline__ bool num_hash_add(uint32_t* keys, double* vals, uint3
     const uint32_t mask = (1u << lg) - 1u;
     uint32_t h = (c * 0x9E3779B1u) >> (32 - lg);
     for (uint32_t n = 0; n <= mask; ++n) {
-        const uint32_t cur =
-            __hip_atomic_load(&keys[h], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
-        bool hit = cur == c;
-        if (!hit && cur == kEmpty) {
-            const uint32_t prev = atomicCAS(&keys[h], kEmpty, c);
-            hit = prev == kEmpty || prev == c;
-        }
-        if (hit) {
+        // (one compare-and-swap per probe: its returned word tells an
+        // insert, a repeat and an occupied slot apart)
+        const uint32_t prev = atomicCAS(&keys[h], kEmpty, c);
+        if (prev == kEmpty || prev == c) {
             __hip_atomic_fetch_add(&vals[h], v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
             return true;
         }
