@@ -413,41 +413,18 @@ __device__ __forceinline__ uint32_t rank_in(uint64_t mask)
                                      __builtin_amdgcn_mbcnt_lo((uint32_t)mask, 0u));
 }
 
-// OR `bits` into word `word` of an LDS bitmap for every lane of the wave
-// (all 64 lanes must call it; an inactive lane passes word = kNoWord).  Runs
-// of neighbouring lanes that target one word (sorted B rows put consecutive
-// products in one word) are combined by a segmented OR over the wave, one
-// atomic per run, since atomics on one word serialise.  The words are not
-// read first to skip bits already set: that read's latency cost more than
-// the atomics it saved (bins of R-MAT 2^16: 26.4 -> 25.4 us without it).
+// OR `bits` into word `word` of an LDS bitmap (kNoWord: nothing), one LDS
+// atomic per lane that returns nothing.  Neither reading the word first to
+// skip bits already set nor combining neighbouring lanes that name one word
+// by a segmented OR over the wave paid for itself: the read put an LDS round
+// trip on every insert, the combining cost a dozen cross-lane shuffles to
+// save a few atomics on one word (bins of R-MAT 2^16: 26.4 us with both, 25.4
+// without the read, 18.9 without either).
 constexpr uint32_t kNoWord = 0xFFFFFFFFu;
 
-// The segmented OR (word = kNoWord for lanes with nothing to set).
-__device__ __forceinline__ void wave_bitmap_or_runs(uint32_t* bm, uint32_t word, uint32_t bits)
+__device__ __forceinline__ void lds_bitmap_or(uint32_t* bm, uint32_t word, uint32_t bits)
 {
-    const int lane = lane_id();
-    const uint64_t valid = __ballot(word != kNoWord);
-    if (valid == 0) return;
-    const uint32_t prev = __shfl_up(word, 1, kWave);
-    const bool head = lane == 0 || prev != word;
-    const uint64_t heads = __ballot(head && word != kNoWord);
-    if (heads == valid) {  // no two neighbours share a word
-        if (word != kNoWord) atomicOr(&bm[word], bits);
-        return;
-    }
-    uint32_t acc = bits;
-#pragma unroll
-    for (int off = 1; off < kWave; off <<= 1) {
-        const uint32_t ow = __shfl_down(word, off, kWave);
-        const uint32_t ob = __shfl_down(acc, off, kWave);
-        if (lane + off < kWave && ow == word) acc |= ob;
-    }
-    if (head && word != kNoWord) atomicOr(&bm[word], acc);
-}
-
-__device__ __forceinline__ void wave_bitmap_or(uint32_t* bm, uint32_t word, uint32_t bits)
-{
-    wave_bitmap_or_runs(bm, word, word != kNoWord ? bits : 0u);
+    if (word != kNoWord) atomicOr(&bm[word], bits);
 }
 
 // Word w of a bitmap lives at w ^ ((w >> 6) & 63): its 64-word row keeps its

@@ -990,7 +990,7 @@ __device__ __forceinline__ void sym_rows(const CaseDesc* __restrict__ cs,
 #pragma unroll
                 for (int u = 0; u < U; ++u) {
                     if (bitmap)
-                        wave_bitmap_or(tab, c[u] == kNoWord ? kNoWord : (c[u] >> 5), 1u << (c[u] & 31));
+                        lds_bitmap_or(tab, c[u] == kNoWord ? kNoWord : (c[u] >> 5), 1u << (c[u] & 31));
                     else if (c[u] != kNoWord)
                         cnt += hash_insert(tab, c[u], lg);
                 }

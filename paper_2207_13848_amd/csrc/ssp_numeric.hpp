@@ -845,7 +845,7 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense(const CaseDesc* __r
                         wmax = word > wmax ? word : wmax;
                     }
                     if (LDSMASK)
-                        wave_bitmap_or(s_mask, word, bit);
+                        lds_bitmap_or(s_mask, word, bit);
                     else
                         wave_or_global(gmask, word, bit);
                 }
