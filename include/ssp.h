@@ -330,8 +330,11 @@ SSP_API ssp_status ssp_autotune(ssp_handle h, int n, const ssp_case* cases, int 
  *             Returns the matrix id in *id.
  *  submit   : C = mats[a] . mats[b]; nnz_pred (device int64[nrows of a]) and
  *             stats (device or NULL) must stay alive until the request is done.
- *             Host-checkable errors return at once; SSP_ERR_BUDGET if the
- *             request alone does not fit a slot.  Thread-safe.
+ *             The slots' streams do not wait for the caller's: work the caller
+ *             queued on the output buffers (a fill, an earlier use of the
+ *             memory) must have finished before submit.  Host-checkable errors
+ *             return at once; SSP_ERR_BUDGET if the request alone does not fit
+ *             a slot.  Thread-safe.
  *  poll     : SSP_OK when done, SSP_ERR_NOT_READY while queued or running,
  *             the failure status otherwise, SSP_ERR_INVALID_ARG for an
  *             unknown ticket.

@@ -38,9 +38,19 @@ def pool(ssp):
     return mats, [ssp.DeviceCSR.from_csr(m, "cuda:0") for m in mats]
 
 
-def _submit(srv, ids, devs, j, rate, seed):
-    out = torch.empty(devs[j].nrows, dtype=torch.int64, device="cuda:0")
-    st = torch.zeros(8, dtype=torch.int64, device="cuda:0")
+def _buffers(devs, j):
+    """Output buffers of a request on matrix j.  The server's streams do not
+    wait for torch's, so the caller synchronizes before handing them over
+    (the fill, and any earlier use of the memory, must be done)."""
+    return (torch.empty(devs[j].nrows, dtype=torch.int64, device="cuda:0"),
+            torch.zeros(8, dtype=torch.int64, device="cuda:0"))
+
+
+def _submit(srv, ids, devs, j, rate, seed, bufs=None):
+    if bufs is None:
+        bufs = _buffers(devs, j)
+        torch.cuda.synchronize()
+    out, st = bufs
     t = srv.submit(ids[j], ids[j], rate, seed, out, st)
     return t, j, rate, seed, out, st
 
@@ -66,12 +76,17 @@ def test_server_results_equal_single_calls(ssp, pool):
     rng = np.random.default_rng(7)
     reqs = []
     # a burst, then a trickle: arrivals while batches run join later batches
-    for i in range(60):
-        reqs.append(_submit(srv, ids, devs, int(rng.integers(len(devs))),
-                            float(rng.choice([0.01, 0.05, 0.3])), 100 + i))
-    for i in range(40):
+    # (every request's buffers made ready before the first submission)
+    burst = [(int(rng.integers(len(devs))), float(rng.choice([0.01, 0.05, 0.3])), 100 + i)
+             for i in range(60)]
+    trickle = [(int(rng.integers(len(devs))), 0.02, 300 + i) for i in range(40)]
+    bufs = [_buffers(devs, j) for j, _, _ in burst + trickle]
+    torch.cuda.synchronize()
+    for i, (j, rate, seed) in enumerate(burst):
+        reqs.append(_submit(srv, ids, devs, j, rate, seed, bufs[i]))
+    for i, (j, rate, seed) in enumerate(trickle):
         time.sleep(float(rng.exponential(2e-4)))
-        reqs.append(_submit(srv, ids, devs, int(rng.integers(len(devs))), 0.02, 300 + i))
+        reqs.append(_submit(srv, ids, devs, j, rate, seed, bufs[len(burst) + i]))
     for r in reqs:
         srv.wait(r[0], 120.0)
     info = srv.info()
@@ -103,9 +118,14 @@ def test_server_request_alone_equals_request_in_mix(ssp, pool):
     t, *_, out_alone, st_alone = _submit(srv, ids, devs, 1, 0.05, 42)
     srv.wait(t, 60.0)
     srv.reset_stats()
-    mix = [_submit(srv, ids, devs, k % len(devs), 0.03, 500 + k) for k in range(12)]
-    probe = _submit(srv, ids, devs, 1, 0.05, 42)
-    mix += [_submit(srv, ids, devs, (3 * k + 1) % len(devs), 0.04, 900 + k) for k in range(12)]
+    first = [(k % len(devs), 0.03, 500 + k) for k in range(12)]
+    second = [((3 * k + 1) % len(devs), 0.04, 900 + k) for k in range(12)]
+    bufs = [_buffers(devs, j) for j, _, _ in first + [(1, 0, 0)] + second]
+    torch.cuda.synchronize()
+    mix = [_submit(srv, ids, devs, j, r, sd, bufs[i]) for i, (j, r, sd) in enumerate(first)]
+    probe = _submit(srv, ids, devs, 1, 0.05, 42, bufs[len(first)])
+    mix += [_submit(srv, ids, devs, j, r, sd, bufs[len(first) + 1 + i])
+            for i, (j, r, sd) in enumerate(second)]
     for r in mix + [probe]:
         srv.wait(r[0], 120.0)
     info = srv.info()
