@@ -1536,11 +1536,11 @@ __device__ __forceinline__ void emit_row(const CaseDesc* __restrict__ cs, int c,
 // Merge-path tile b of a case covers the items [b T, (b+1) T) of the sequence
 // that interleaves A's entries with one end marker per row (Merrill &
 // Garland, SC16), so every tile has at most T = kFlopTile rows + entries
-// whatever the row lengths.  A tile's entries are loaded in runs of 64
-// consecutive entries per load instruction (fully coalesced, non-temporal so
-// the stream does not evict B's row pointers from L2) and each contributes
-// the length of the B row it names (one 8-byte gather, consecutive entries in
-// consecutive lanes).  An exclusive scan of these lengths (in 32 bits when the
+// whatever the row lengths.  A tile's entries are loaded four consecutive
+// ones per lane with 16-byte loads (fully coalesced, non-temporal so the
+// stream does not evict B's row lengths from L2), put in entry order across
+// the lanes through LDS, and each contributes the length of the B row it
+// names (one gather per entry, consecutive entries in consecutive lanes).  An exclusive scan of these lengths (in 32 bits when the
 // lengths allow) gives the running product count at every row boundary, and a
 // row's count is the difference of its two boundaries.  Rows that begin in an
 // earlier tile or end in a later one leave their partial counts in the tile's
@@ -1563,8 +1563,10 @@ struct FlopTileRegs {
     SSP_GLOBAL int64_t* out;
     int64_t M, nnzA, K;
     int64_t i0, i1, j0, j1, a0;
-    int32_t col[8];  // entry q HALF + 256 wave + 64 l + lane in col[4 q + l]
-    int32_t rp[kFlopTile / kFlopThreads + 1];
+    // entry q HALF + 256 wave + 64 l + lane in col[4 q + l] (VEC: as loaded,
+    // entry q HALF + 256 wave + 4 lane + l, until the tile is processed)
+    int32_t col[8];
+    int32_t rp[kFlopTile / kFlopThreads + 1];  // (VEC: rows 4 NT u + 4 t + k in rp[4 u + k])
 };
 
 // Issues the loads of global tile g of case c, whose rows are [i0, i1].
@@ -1603,8 +1605,15 @@ __device__ __forceinline__ void flop_issue_tile(const CaseDesc* __restrict__ cs,
         // buffer loads: the row bounds past the tile's read 0 (no clamps)
         const __amdgpu_buffer_rsrc_t rr = buffer_rsrc(R.Arpt + i0, 4 * (uint64_t)nb);
 #pragma unroll
-        for (int u = 0; u < NRP; ++u)
-            R.rp[u] = __builtin_amdgcn_raw_buffer_load_b32(rr, 4u * (uint32_t)(t + u * NT), 0, 0);
+        for (int u = 0; u < 2; ++u) {  // rows 4 NT u + 4 t .. + 3, one 16-byte load
+            typedef int32_t v4i __attribute__((ext_vector_type(4)));
+            const v4i v = __builtin_amdgcn_raw_buffer_load_b128(
+                rr, 16u * (uint32_t)t + 16u * (uint32_t)NT * u, 0, 0);
+            R.rp[4 * u + 0] = v.x;
+            R.rp[4 * u + 1] = v.y;
+            R.rp[4 * u + 2] = v.z;
+            R.rp[4 * u + 3] = v.w;
+        }
     } else {
 #pragma unroll
         for (int u = 0; u < NRP; ++u) {
@@ -1615,26 +1624,34 @@ __device__ __forceinline__ void flop_issue_tile(const CaseDesc* __restrict__ cs,
     // Loads are unconditional (masked later): a load under a lane condition
     // becomes a branch, and loads in separate branches are not kept in flight
     // together.  The fast form (VEC) reads through buffer resources, whose
-    // lanes past the end read 0, the other form from clamped addresses.  Each
-    // wave loads its 256 entries of a half as four runs of 64 consecutive
-    // entries, one per load instruction, so that the gathers see consecutive
-    // entries in consecutive lanes: in banded and stencil-like rows those name
-    // nearby B rows, whose row pointers then share few cache lines per
-    // instruction (the first-level cache looks up one line per clock).
+    // lanes past the end read 0 (per 4-byte word: a 16-byte load that
+    // straddles the end still returns the words before it), the other form
+    // from clamped addresses.  VEC: each wave loads its 256 entries of a half
+    // with one 16-byte load per lane and the tile's row bounds with two per
+    // thread, the fewest load instructions for the address units (nine 4-byte
+    // loads of row bounds and four of entries per half before: stencil 95 ->
+    // 91 us); the other form loads four runs of 64 consecutive entries.  Either
+    // way the gathers see consecutive entries in consecutive lanes: in banded
+    // and stencil-like rows those name nearby B rows, whose row pointers then
+    // share few cache lines per instruction (the first-level cache looks up
+    // one line per clock).
     const int lane = t & (kWave - 1), wv = __builtin_amdgcn_readfirstlane(t / kWave);
 #pragma unroll
     for (int q = 0; q < 2; ++q) {
         const int64_t sb = R.a0 + q * HALF + 4 * kWave * wv;  // uniform
         if (VEC) {
             // a buffer over the wave's segment: entries past the last read 0;
-            // one offset register, the runs at instruction offsets
+            // four consecutive entries per lane in one 16-byte load (put in
+            // entry order across the lanes through LDS before the gathers)
             // (non-temporal: the stream should not evict B's row pointers)
             const __amdgpu_buffer_rsrc_t rc =
                 buffer_rsrc(Acol + (sb < nnzA ? sb : 0), sb < nnzA ? 4 * (uint64_t)(nnzA - sb) : 0);
-#pragma unroll
-            for (int l = 0; l < 4; ++l)
-                R.col[4 * q + l] = __builtin_amdgcn_raw_buffer_load_b32(
-                    rc, 4u * (uint32_t)lane + 4u * kWave * l, 0, 2);
+            typedef int32_t v4i __attribute__((ext_vector_type(4)));
+            const v4i v = __builtin_amdgcn_raw_buffer_load_b128(rc, 16u * (uint32_t)lane, 0, 2);
+            R.col[4 * q + 0] = v.x;
+            R.col[4 * q + 1] = v.y;
+            R.col[4 * q + 2] = v.z;
+            R.col[4 * q + 3] = v.w;
         } else {
 #pragma unroll
             for (int l = 0; l < 4; ++l) {
@@ -1670,7 +1687,9 @@ void k_flop(const CaseDesc* __restrict__ cs,
 {
     constexpr int NT = kFlopThreads, CH = kFlopChunk, HALF = CH / 2;
     constexpr int T = (int)kFlopTile, NRP = kFlopTile / kFlopThreads + 1;
-    __shared__ int32_t s_bnd[T + 2];
+    // the tile's row bounds (T + 2 at most; VEC fills all 8 NT: two 16-byte loads per thread)
+    static_assert(T + 2 <= 8 * NT, "row bounds of a tile fit two 16-byte loads per thread");
+    __shared__ __align__(16) int32_t s_bnd[8 * NT];
     __shared__ __align__(16) uint32_t s_x[CH];
     __shared__ uint64_t s_pre0[NT], s_pre1[NT];
     __shared__ uint64_t s_w[2 * (NT / kWave)];
@@ -1722,6 +1741,23 @@ void k_flop(const CaseDesc* __restrict__ cs,
         // j0 <= j < j1; relative to a0 both bounds are small (j0 - a0 < 4,
         // j1 - a0 <= kFlopChunk).
         const int rlo = (int)(j0 - a0), rhi = (int)(j1 - a0);
+        if (VEC) {
+            // the wave's entries, loaded four consecutive per lane, into entry
+            // q HALF + 256 wave + 64 l + lane in col[4 q + l] (the wave's own
+            // segment of s_x, free until the lengths are written there)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+                *reinterpret_cast<uint4*>(&s_x[q * HALF + 4 * kWave * wid + 4 * lane]) =
+                    make_uint4((uint32_t)cur.col[4 * q], (uint32_t)cur.col[4 * q + 1],
+                               (uint32_t)cur.col[4 * q + 2], (uint32_t)cur.col[4 * q + 3]);
+            __builtin_amdgcn_wave_barrier();
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int l = 0; l < 4; ++l)
+                    cur.col[4 * q + l] = (int32_t)s_x[q * HALF + kWave * (4 * wid + l) + lane];
+            __builtin_amdgcn_wave_barrier();
+        }
         // (VEC: 0 or 1, the half of the loaded word that is the length; 2:
         // the length itself)
         uint32_t xodd[8];
@@ -1805,10 +1841,17 @@ void k_flop(const CaseDesc* __restrict__ cs,
         }
         const int64_t rlast = i1 < M ? i1 : M - 1;
         const int nb = (int)(rlast - i0 + 2);
+        if (VEC) {
 #pragma unroll
-        for (int u = 0; u < NRP; ++u) {
-            const int k = t + u * NT;
-            if (u * NT < nb && k < nb) s_bnd[k] = cur.rp[u];
+            for (int u = 0; u < 2; ++u)
+                *reinterpret_cast<int4*>(&s_bnd[4 * NT * u + 4 * t]) =
+                    make_int4(cur.rp[4 * u], cur.rp[4 * u + 1], cur.rp[4 * u + 2], cur.rp[4 * u + 3]);
+        } else {
+#pragma unroll
+            for (int u = 0; u < NRP; ++u) {
+                const int k = t + u * NT;
+                if (u * NT < nb && k < nb) s_bnd[k] = cur.rp[u];
+            }
         }
         // the lengths in entry order; each thread then takes its four
         // consecutive entries of each half (the wave's own segment of s_x:
