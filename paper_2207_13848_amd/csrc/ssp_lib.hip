@@ -449,7 +449,10 @@ Plan make_plan(ssp_handle h, const std::vector<CaseIn>& in, PlanKind kind,
         d.bin_max[2] = tu.bin_max[2];
         d.hash_mult = tu.hash_mult;
         d.long_len = tu.long_len;
-        d.split_target = tu.split_target;
+        // (a split part of a narrow window costs a smaller bitmap to clear, store
+        // and merge: the target shrinks with the window, at least 2^12 products)
+        d.split_target = std::max<uint64_t>(
+            1ull << 12, tu.split_target / (uint64_t)(kWinWords / std::max<int32_t>(d.win_words, 64)));
         d.est_max_rf = tu.est_max_rf;
         int32_t mpr = 0;  // merge items of a split row: slices of every window
         for (int32_t w = 0; w < d.nwin; ++w) {
