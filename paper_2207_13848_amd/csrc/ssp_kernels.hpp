@@ -134,8 +134,10 @@ __device__ inline void write_merge_items(MergeItem* dst, int32_t row, int32_t sl
 }
 
 // Bin-4 items of one long row (single lane; the exact path, which appends
-// with atomics).  A row above kSplitTarget products is cut into P parts when
-// enough global part windows are left; part p takes the entries e0 + p,
+// with atomics).  A row above the split target, or with more entries than one
+// chunk of the long-row kernel's workgroup, is cut into P parts (the split
+// rule of the sampled path, split_info) when enough global part windows are
+// left; part p takes the entries e0 + p,
 // e0 + p + P, e0 + p + 2P, ...  In skewed rows the heavy entries (hub
 // columns, long B rows) sit together, and a stride deals them out evenly, so
 // the parts get near-equal product counts without a scan of the row.
@@ -146,10 +148,12 @@ __device__ inline void append_big(int32_t row, uint64_t rf, int32_t e0, int32_t 
     const int64_t alen = (int64_t)e1 - e0;
     int32_t nparts = 1, slot = -1;
     const uint64_t T = cd.split_target;
-    if (rf > T && cd.nwin <= kMaxSplitWindows && alen > 1 &&
+    const uint64_t chunks = (uint64_t)((alen + kBin4Team - 1) / kBin4Team);
+    if ((rf > T || chunks > 1) && cd.nwin <= kMaxSplitWindows && alen > 1 &&
         __hip_atomic_load(&ctl->pw_ctr, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
             L.part_windows) {  // (bounds the counter: it cannot wrap)
         uint64_t want = (rf + T - 1) / T;
+        if (want < chunks) want = chunks;
         if (want > (uint64_t)kMaxParts) want = kMaxParts;
         if (want > (uint64_t)alen) want = (uint64_t)alen;
         const uint32_t need = (uint32_t)want * (uint32_t)cd.nwin;
@@ -408,9 +412,12 @@ __device__ __forceinline__ SampledRow classify_row(int64_t g, const SamplerArgs&
 }
 
 // How a bin-4 row splits at split level `lv`: eligible rows (above the
-// level's target, windows few enough, at least two entries) want one part
-// per target's worth of products, at most kMaxParts and one per entry; rows
-// above a quarter of the target are heavy (eligible rows are).
+// level's target or with more entries than one chunk of the long-row
+// kernel's workgroup, windows few enough, at least two entries) want one
+// part per target's worth of products and at least one per chunk of
+// entries (the chunks of one item run one after another), at most kMaxParts
+// and one per entry; eligible rows and rows above a quarter of the target
+// are heavy (a row's parts are written to the heavy list together).
 struct SplitInfo {
     uint32_t want;  // parts when split (1 unless eligible)
     bool elig, heavy;
@@ -423,12 +430,15 @@ __device__ __forceinline__ SplitInfo split_info(const SampledRow& r, const Sampl
     const uint64_t T = a.split_target << lv;
     si.heavy = r.rf > (T >> kHeavyShift);
     const int64_t alen = (int64_t)r.e1 - r.e0;
-    if (r.rf > T && a.nwin <= kMaxSplitWindows && alen > 1) {
+    const uint64_t chunks = (uint64_t)((alen + kBin4Team - 1) / kBin4Team);
+    if ((r.rf > T || chunks > 1) && a.nwin <= kMaxSplitWindows && alen > 1) {
         uint64_t want = (r.rf + T - 1) / T;
+        if (want < chunks) want = chunks;
         if (want > (uint64_t)kMaxParts) want = kMaxParts;
         if (want > (uint64_t)alen) want = (uint64_t)alen;
         si.want = (uint32_t)want;
         si.elig = true;
+        si.heavy = true;  // (the parts of a row go to the heavy list together)
     }
     return si;
 }
