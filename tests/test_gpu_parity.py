@@ -300,6 +300,33 @@ def test_split_long_rows(ssp):
     check_all(ssp, A, B, 0.3, 2)
 
 
+def test_rows_of_many_entries_and_few_products(ssp):
+    # long rows (bin 4) with more entries than one 1024-entry chunk but few
+    # products (short B rows): split by chunks although far below the split
+    # target; among them ordinary light long rows, so the parts and the light
+    # list meet in the bin-4 list
+    rng = np.random.default_rng(11)
+    K, N = 20000, 1 << 20
+    brows = [sorted(rng.choice(N, size=int(rng.integers(1, 6)), replace=False).tolist())
+             for _ in range(K)]
+    B = from_rows(brows, N)
+    arows = []
+    for i in range(300):
+        if i % 10 == 0:  # 1025..4000 entries: two to four chunks
+            arows.append(rng.choice(K, size=int(rng.integers(1025, 4000)), replace=False).tolist())
+        elif i % 10 == 1:  # light long rows: a few hundred entries
+            arows.append(rng.choice(K, size=int(rng.integers(400, 900)), replace=False).tolist())
+        else:
+            arows.append(rng.choice(K, size=int(rng.integers(0, 40)), replace=False).tolist())
+    A = from_rows(arows, K)
+    rf, _ = oracle.row_flop(A, B)
+    alen = np.diff(A.rpt)
+    assert (alen > 1024).sum() >= 20 and rf.max() < 2 ** 17
+    _say(f"many-entry rows: max len {alen.max()} max rf {rf.max()}")
+    check_all(ssp, A, B, 1.0, 5)
+    check_all(ssp, A, B, 0.5, 6)
+
+
 def test_long_rows_over_several_bitmap_windows(ssp):
     # N > 2^20 columns: the long-row bitmap covers the columns in windows
     A, B = _long_rows((1 << 21) + 12345, 5, 2)
