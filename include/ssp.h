@@ -267,7 +267,7 @@ SSP_API ssp_status ssp_batch_graph_destroy(ssp_batch_graph graph);
  *                 bin_max[0..2] * hash_mult <= 256, 2048, 16384.
  *   long_len    : the long-row kernel walks B rows of at least long_len
  *                 columns in 256-column units by wavefront, shorter ones
- *                 flattened over the workgroup (8..1024; default 32).
+ *                 flattened over the workgroup (8..1024; default 16).
  *   big3        : 1 (default): when one 2^20-column bitmap covers all of B's
  *                 columns but bin 3 would hash, bin-3 rows go to the long-row
  *                 kernel; 0: never.

@@ -27,7 +27,7 @@ constexpr int64_t kBin2WaveRows = 8192;
 // Bin-4 bitmap window: at most 32768 words = 2^20 columns = 128 KiB of LDS.
 constexpr int kWinWords = 32768;
 constexpr uint64_t kSplitTarget = 1ull << 19; // products per part of a split row (default)
-constexpr uint32_t kLongLenDefault = 32;      // B rows walked in units by the long-row kernel
+constexpr uint32_t kLongLenDefault = 16;      // B rows walked in units by the long-row kernel
 constexpr int kMaxParts = 64;
 // Global part bitmaps of kWinWords words: a call holds kPartWindowsBase, a
 // batch kPartWindowsBase per 32 cases up to kPartWindowsMax.

@@ -98,5 +98,5 @@ def test_product_path_does_not_touch_the_oracle():
 
 def test_default_tuning_matches_the_documented_defaults():
     import paper_2207_13848_amd as ssp
-    assert ssp.default_tuning() == {"bin_max": [128, 1024, 8192], "hash_mult": 2, "long_len": 32,
+    assert ssp.default_tuning() == {"bin_max": [128, 1024, 8192], "hash_mult": 2, "long_len": 16,
                                     "big3": 1, "split_target": 1 << 19, "est_max_rf": 1 << 48}

@@ -264,7 +264,8 @@ def test_prediction_ceiling_at_whole_quotients(ssp, kinds, num, den):
 def _long_rows(ncols, nbig, seed):
     # long rows whose entries name B rows of all three length classes the
     # long-row kernel treats differently: huge (>= 2048 entries), medium
-    # (32..2047) and short (< 32); the largest rows exceed the default split
+    # (walked in units: at least the tuning's long_len, 16 by default) and
+    # short (flattened; lengths 0..19 here); the largest rows exceed the default split
     # threshold (2^19 products) more than twice over
     rng = np.random.default_rng(seed)
     K = 3000
