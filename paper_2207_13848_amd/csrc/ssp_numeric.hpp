@@ -287,13 +287,14 @@ __global__ __launch_bounds__(kNumScanThreads) void k_num_scan_rows(NumArgs na)
 // columns outnumber the table stops (every probe sequence ends after 2^lg
 // steps) and is counted by the symbolic kernel instead.  With an overflow
 // area, a row longer than its slot that completes with at most half its
-// table goes to the area whole, and rows of at most kNumSpillWhole products
-// get b = min(products, N), so they all complete (their tables stay within
-// one wave's; larger tables for longer rows cost more time than the rows
-// that then no longer fail: 8.9 -> 17.4 ms on the squared 128^3 stencil).
-// The fallback pass knows each row's exact count and sizes b by it.
+// table goes to the area whole, and rows get b = min(products, N), so they
+// all complete, unless that would move a row whose slot's table fits one
+// wave to the workgroup kernel (a row of 125 distinct columns among 729
+// products, as in the squared 27-point stencil, stays in the one-wave
+// kernel: moving all such rows took that pass from 8.9 to 17.4 ms on the
+// 128^3 grid).  The fallback pass knows each row's exact count and sizes b by
+// it.
 constexpr int kNumWaveSlots = 512;  // table of a row handled by one wave
-constexpr uint32_t kNumSpillWhole = kNumWaveSlots / 2;
 constexpr int kNumUnroll = 4;       // products per lane whose loads are in flight together
 constexpr int kNumWaveWaves = 4;    // such rows per workgroup
 
@@ -310,8 +311,11 @@ __device__ __forceinline__ uint64_t num_bound(const NumArgs& na, int64_t row, ui
 {
     if (PASS == 2) return (uint64_t)na.cnt[row];
     const int64_t s = na.slot_off[row + 1] - na.slot_off[row];
-    int64_t b = (int64_t)rf < na.N ? (int64_t)rf : na.N;
-    return (uint64_t)(b < s || (na.sp_cap > 0 && rf <= kNumSpillWhole) ? b : s);
+    const int64_t b = (int64_t)rf < na.N ? (int64_t)rf : na.N;
+    // (2 b <= kNumWaveSlots: the table for all the products fits one wave;
+    // 2 s > kNumWaveSlots: the slot's table does not)
+    const bool all = na.sp_cap > 0 && (2 * b <= kNumWaveSlots || 2 * s > kNumWaveSlots);
+    return (uint64_t)(b <= s || all ? b : s);
 }
 
 // Adds v to column c's slot (open addressing, linear probing; columns are
@@ -428,120 +432,139 @@ __global__ __launch_bounds__(kNumWaveWaves* kWave) void k_num_wave(const CaseDes
     const uint32_t* cnt = ctl->bin_cnt;
     const uint32_t total = cnt[1] + cnt[2] + cnt[3];
     const Csr A = cs[0].A, B = cs[0].B;
-    for (uint32_t k = blockIdx.x * kNumWaveWaves + w; k < total;
-         k += gridDim.x * kNumWaveWaves) {
-        const BinItem item = num_hash_item(L, cnt, k);
-        const int64_t row = item.row;
-        if (PASS == 2 && (num_fits(na, row, na.cnt[row]) || na.sp_state[row])) continue;
-        const uint32_t T = num_table_size(num_bound<PASS>(na, row, item.rf));
-        if (T > (uint32_t)kNumWaveSlots) continue;  // (a workgroup kernel's row)
-        const int lg = __builtin_ctz(T);
-#pragma unroll
-        for (int u = 0; u < SPT; ++u) {
-            const uint32_t s = (uint32_t)lane + (uint32_t)u * kWave;
-            if (s < T) {
-                keys[s] = kEmpty;
-                vals[s] = 0.0;
+    const uint64_t stride = (uint64_t)gridDim.x * kNumWaveWaves;
+    // The wave's items are k0 + j * stride; 64 of them are looked at together,
+    // one per lane, and the wave then takes the rows it owns (a table of at
+    // most kNumWaveSlots slots, not yet done) in order, each from its lane.
+    for (uint64_t k0 = (uint64_t)blockIdx.x * kNumWaveWaves + w; k0 < total;
+         k0 += stride * kWave) {
+        const uint64_t km = k0 + (uint64_t)lane * stride;
+        uint32_t lgm = 0;
+        BinItem x{};
+        if (km < total) {
+            x = num_hash_item(L, cnt, (uint32_t)km);
+            if (!(PASS == 2 && (num_fits(na, x.row, na.cnt[x.row]) || na.sp_state[x.row]))) {
+                const uint32_t Tm = num_table_size(num_bound<PASS>(na, x.row, x.rf));
+                if (Tm <= (uint32_t)kNumWaveSlots) lgm = (uint32_t)__builtin_ctz(Tm);
             }
         }
-        wave_sync();
-        bool ok = true;
-        const int32_t a0 = A.rpt[row], a1 = A.rpt[row + 1];
-        for (int32_t a = a0; a < a1; a += kWave) {
-            const int32_t j = a + lane;
-            uint32_t len = 0;
-            int32_t b0 = 0;
-            double av = 0.0;
-            if (j < a1) {
-                const int32_t kk = A.col[j];
-                b0 = B.rpt[kk];
-                len = (uint32_t)(B.rpt[kk + 1] - b0);
-                av = na.Aval[j];
-            }
-            const uint32_t inc = wave_incl_scan(len);
-            const uint32_t tot = lane63(inc);
-            s_b0[w][lane] = b0;
-            s_off[w][lane] = inc - len;
-            s_a[w][lane] = av;
-            wave_sync();
-            const int nent = (a1 - a) < kWave ? (a1 - a) : kWave;
-            // kNumUnroll products per lane at a time: their loads in flight together
-            for (uint32_t p0 = 0; p0 < tot; p0 += kWave * kNumUnroll) {
-                uint32_t col[kNumUnroll];
-                double v[kNumUnroll];
+        uint64_t todo = __ballot(lgm != 0);
+        while (todo) {
+            const int src = __builtin_ctzll(todo);
+            todo &= todo - 1;
+            const BinItem item{__builtin_amdgcn_readlane(x.row, src),
+                               (uint32_t)__builtin_amdgcn_readlane((int)x.rf, src), 0, 0};
+            const int64_t row = item.row;
+            const int lg = __builtin_amdgcn_readlane((int)lgm, src);
+            const uint32_t T = 1u << lg;
 #pragma unroll
-                for (int u = 0; u < kNumUnroll; ++u) {
-                    const uint32_t pr = p0 + (uint32_t)(u * kWave + lane);
-                    const uint32_t p = pr < tot ? pr : tot - 1;  // (clamped: loads unconditional)
-                    int lo = 0, hi = nent;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_off[w][mid] <= p) lo = mid;
-                        else hi = mid;
+            for (int u = 0; u < SPT; ++u) {
+                const uint32_t s = (uint32_t)lane + (uint32_t)u * kWave;
+                if (s < T) {
+                    keys[s] = kEmpty;
+                    vals[s] = 0.0;
+                }
+            }
+            wave_sync();
+            bool ok = true;
+            const int32_t a0 = A.rpt[row], a1 = A.rpt[row + 1];
+            for (int32_t a = a0; a < a1; a += kWave) {
+                const int32_t j = a + lane;
+                uint32_t len = 0;
+                int32_t b0 = 0;
+                double av = 0.0;
+                if (j < a1) {
+                    const int32_t kk = A.col[j];
+                    b0 = B.rpt[kk];
+                    len = (uint32_t)(B.rpt[kk + 1] - b0);
+                    av = na.Aval[j];
+                }
+                const uint32_t inc = wave_incl_scan(len);
+                const uint32_t tot = lane63(inc);
+                s_b0[w][lane] = b0;
+                s_off[w][lane] = inc - len;
+                s_a[w][lane] = av;
+                wave_sync();
+                const int nent = (a1 - a) < kWave ? (a1 - a) : kWave;
+                // kNumUnroll products per lane at a time: their loads in flight together
+                for (uint32_t p0 = 0; p0 < tot; p0 += kWave * kNumUnroll) {
+                    uint32_t col[kNumUnroll];
+                    double v[kNumUnroll];
+#pragma unroll
+                    for (int u = 0; u < kNumUnroll; ++u) {
+                        const uint32_t pr = p0 + (uint32_t)(u * kWave + lane);
+                        // (clamped: the loads are unconditional)
+                        const uint32_t p = pr < tot ? pr : tot - 1;
+                        int lo = 0, hi = nent;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_off[w][mid] <= p) lo = mid;
+                            else hi = mid;
+                        }
+                        const int32_t q = s_b0[w][lo] + (int32_t)(p - s_off[w][lo]);
+                        col[u] = (uint32_t)B.col[q];
+                        v[u] = s_a[w][lo] * na.Bval[q];
                     }
-                    const int32_t q = s_b0[w][lo] + (int32_t)(p - s_off[w][lo]);
-                    col[u] = (uint32_t)B.col[q];
-                    v[u] = s_a[w][lo] * na.Bval[q];
+#pragma unroll
+                    for (int u = 0; u < kNumUnroll; ++u)
+                        if (p0 + (uint32_t)(u * kWave + lane) < tot)
+                            ok = num_hash_add(keys, vals, col[u], v[u], lg) && ok;
                 }
-#pragma unroll
-                for (int u = 0; u < kNumUnroll; ++u)
-                    if (p0 + (uint32_t)(u * kWave + lane) < tot)
-                        ok = num_hash_add(keys, vals, col[u], v[u], lg) && ok;
+                wave_sync();
             }
+            if (__ballot(!ok)) {  // (the first pass only: the fallback's tables hold every row)
+                if (lane == 0) num_abort_row(row, item.rf, ctl, abort_list);
+                continue;
+            }
+            // compaction of the occupied slots
+            uint32_t kk[SPT];
+            double vv[SPT];
+            uint32_t mine = 0;
+#pragma unroll
+            for (int u = 0; u < SPT; ++u) {
+                const uint32_t s = (uint32_t)lane * SPT + u;
+                kk[u] = s < T ? keys[s] : kEmpty;
+                vv[u] = s < T ? vals[s] : 0.0;
+                mine += kk[u] != kEmpty ? 1u : 0u;
+            }
+            const uint32_t inc = wave_incl_scan(mine);
+            const uint32_t c = lane63(inc);
+            uint32_t pos = inc - mine;
             wave_sync();
-        }
-        if (__ballot(!ok)) {  // (the first pass only: the fallback's tables hold every row)
-            if (lane == 0) num_abort_row(row, item.rf, ctl, abort_list);
-            continue;
-        }
-        // compaction of the occupied slots
-        uint32_t kk[SPT];
-        double vv[SPT];
-        uint32_t mine = 0;
-#pragma unroll
-        for (int u = 0; u < SPT; ++u) {
-            const uint32_t s = (uint32_t)lane * SPT + u;
-            kk[u] = s < T ? keys[s] : kEmpty;
-            vv[u] = s < T ? vals[s] : 0.0;
-            mine += kk[u] != kEmpty ? 1u : 0u;
-        }
-        const uint32_t inc = wave_incl_scan(mine);
-        const uint32_t c = lane63(inc);
-        uint32_t pos = inc - mine;
-        wave_sync();
-        int64_t dst;
-        bool write, spill = false;
-        if (PASS == 1) {
-            if (lane == 0) na.cnt[row] = (int64_t)c;
-            dst = na.slot_off[row];
-            write = (int64_t)c <= na.slot_off[row + 1] - dst;
-            if (!write && na.sp_cap > 0 && 2 * c <= T) {  // the whole row to the area
-                int64_t o = -1;
-                if (lane == 0 && spill_take_row(na, row, c, &o)) na.sp_state[row] = 2;
-                o = __shfl(o, 0, kWave);
-                spill = write = o >= 0;
-                dst = o;
-            }
-        } else {
-            dst = na.C_rpt[row];
-            write = dst + (int64_t)c <= na.capacity;
-        }
-        if (write) {  // (then c <= T / 2)
-#pragma unroll
-            for (int u = 0; u < SPT; ++u)
-                if (kk[u] != kEmpty) {
-                    keys[pos] = kk[u];
-                    vals[pos] = vv[u];
-                    ++pos;
+            int64_t dst;
+            bool write, spill = false;
+            if (PASS == 1) {
+                if (lane == 0) na.cnt[row] = (int64_t)c;
+                dst = na.slot_off[row];
+                write = (int64_t)c <= na.slot_off[row + 1] - dst;
+                if (!write && na.sp_cap > 0 && 2 * c <= T) {  // the whole row to the area
+                    int64_t o = -1;
+                    if (lane == 0 && spill_take_row(na, row, c, &o)) na.sp_state[row] = 2;
+                    o = __shfl(o, 0, kWave);
+                    spill = write = o >= 0;
+                    dst = o;
                 }
-            const uint32_t c4 = (c + 3u) & ~3u;
-            if ((uint32_t)lane < c4 - c) keys[c + lane] = kEmpty;
-            wave_sync();
-            num_write_ranked<kWave, EPT>(keys, vals, c, lane,
-                                         PASS == 2 ? na.C_col : spill ? na.sp_col : na.slot_col,
-                                         PASS == 2 ? na.C_val : spill ? na.sp_val : na.slot_val, dst);
+            } else {
+                dst = na.C_rpt[row];
+                write = dst + (int64_t)c <= na.capacity;
+            }
+            if (write) {  // (then c <= T / 2)
+#pragma unroll
+                for (int u = 0; u < SPT; ++u)
+                    if (kk[u] != kEmpty) {
+                        keys[pos] = kk[u];
+                        vals[pos] = vv[u];
+                        ++pos;
+                    }
+                const uint32_t c4 = (c + 3u) & ~3u;
+                if ((uint32_t)lane < c4 - c) keys[c + lane] = kEmpty;
+                wave_sync();
+                num_write_ranked<kWave, EPT>(
+                    keys, vals, c, lane, PASS == 2 ? na.C_col : spill ? na.sp_col : na.slot_col,
+                    PASS == 2 ? na.C_val : spill ? na.sp_val : na.slot_val, dst);
+            }
+            wave_sync();  // the table is reset for the next row
         }
-        wave_sync();  // the table is reset for the next row
     }
 }
 
@@ -563,123 +586,150 @@ __global__ __launch_bounds__(TEAM) void k_num_hash(const CaseDesc* __restrict__ 
     __shared__ uint32_t s_red[TEAM / kWave + 1];
     __shared__ uint32_t s_fail;
     __shared__ int64_t s_spill;
+    __shared__ int32_t s_row[TEAM];
+    __shared__ uint32_t s_rf[TEAM];
+    __shared__ uint8_t s_lg[TEAM];
     const uint32_t n = *count;
     const int t = threadIdx.x;
     const Csr A = cs[0].A, B = cs[0].B;
-    for (uint32_t it = blockIdx.x; it < n; it += gridDim.x) {
-        const BinItem item = items[it];
-        const int64_t row = item.row;
-        if (PASS == 2 && (num_fits(na, row, na.cnt[row]) || na.sp_state[row]))
-            continue;  // (the same for the whole team)
-        const uint32_t T = num_table_size(num_bound<PASS>(na, row, item.rf));
-        if (T <= (uint32_t)kNumWaveSlots) continue;  // (a one-wave row)
-        const int lg = __builtin_ctz(T);
-        for (uint32_t s = t; s < T; s += TEAM) {
-            keys[s] = kEmpty;
-            vals[s] = 0.0;
-        }
-        if (t == 0) s_fail = 0;
-        __syncthreads();
-        bool ok = true;
-        const int32_t a0 = A.rpt[row], a1 = A.rpt[row + 1];
-        for (int32_t a = a0; a < a1; a += TEAM) {
-            const int32_t j = a + t;
-            uint32_t len = 0;
-            int32_t b0 = 0;
-            double av = 0.0;
-            if (j < a1) {
-                const int32_t k = A.col[j];
-                b0 = B.rpt[k];
-                len = (uint32_t)(B.rpt[k + 1] - b0);
-                av = na.Aval[j];
+    const uint64_t G = gridDim.x;
+    // The workgroup's items are blockIdx.x + k * gridDim.x.  TEAM of them are
+    // looked at together, one per thread, and the rows this kernel owns (a
+    // table of more than kNumWaveSlots slots, not yet done) are listed in LDS
+    // in the same order: most items of a bin can belong to the one-wave kernel
+    // (or, in the second pass, need nothing), and skipping them one at a time
+    // costs a chain of dependent loads each.
+    for (uint64_t r0 = blockIdx.x; r0 < n; r0 += G * TEAM) {
+        const uint64_t mine_it = r0 + (uint64_t)t * G;
+        uint32_t lgm = 0;
+        BinItem x{};
+        if (mine_it < n) {
+            x = items[mine_it];
+            if (!(PASS == 2 && (num_fits(na, x.row, na.cnt[x.row]) || na.sp_state[x.row]))) {
+                const uint32_t Tm = num_table_size(num_bound<PASS>(na, x.row, x.rf));
+                if (Tm > (uint32_t)kNumWaveSlots) lgm = (uint32_t)__builtin_ctz(Tm);
             }
-            uint32_t tot;
-            const uint32_t off = block_excl_scan<TEAM, uint32_t>(len, s_red, &tot);
-            s_b0[t] = b0;
-            s_off[t] = off;
-            s_a[t] = av;
+        }
+        uint32_t nsel;
+        const uint32_t at = block_excl_scan<TEAM, uint32_t>(lgm ? 1u : 0u, s_red, &nsel);
+        if (lgm) {
+            s_row[at] = x.row;
+            s_rf[at] = x.rf;
+            s_lg[at] = (uint8_t)lgm;
+        }
+        __syncthreads();
+        for (uint32_t q = 0; q < nsel; ++q) {
+            const BinItem item{s_row[q], s_rf[q], 0, 0};
+            const int64_t row = item.row;
+            const int lg = s_lg[q];
+            const uint32_t T = 1u << lg;
+            for (uint32_t s = t; s < T; s += TEAM) {
+                keys[s] = kEmpty;
+                vals[s] = 0.0;
+            }
+            if (t == 0) s_fail = 0;
             __syncthreads();
-            const int nent = (a1 - a) < TEAM ? (a1 - a) : TEAM;
-            for (uint32_t p0 = 0; p0 < tot; p0 += TEAM * kNumUnroll) {
-                uint32_t col[kNumUnroll];
-                double v[kNumUnroll];
-#pragma unroll
-                for (int u = 0; u < kNumUnroll; ++u) {
-                    const uint32_t pr = p0 + (uint32_t)(u * TEAM + t);
-                    const uint32_t p = pr < tot ? pr : tot - 1;
-                    int lo = 0, hi = nent;
-                    while (hi - lo > 1) {
-                        const int mid = (lo + hi) >> 1;
-                        if (s_off[mid] <= p) lo = mid;
-                        else hi = mid;
-                    }
-                    const int32_t q = s_b0[lo] + (int32_t)(p - s_off[lo]);
-                    col[u] = (uint32_t)B.col[q];
-                    v[u] = s_a[lo] * na.Bval[q];
+            bool ok = true;
+            const int32_t a0 = A.rpt[row], a1 = A.rpt[row + 1];
+            for (int32_t a = a0; a < a1; a += TEAM) {
+                const int32_t j = a + t;
+                uint32_t len = 0;
+                int32_t b0 = 0;
+                double av = 0.0;
+                if (j < a1) {
+                    const int32_t k = A.col[j];
+                    b0 = B.rpt[k];
+                    len = (uint32_t)(B.rpt[k + 1] - b0);
+                    av = na.Aval[j];
                 }
+                uint32_t tot;
+                const uint32_t off = block_excl_scan<TEAM, uint32_t>(len, s_red, &tot);
+                s_b0[t] = b0;
+                s_off[t] = off;
+                s_a[t] = av;
+                __syncthreads();
+                const int nent = (a1 - a) < TEAM ? (a1 - a) : TEAM;
+                for (uint32_t p0 = 0; p0 < tot; p0 += TEAM * kNumUnroll) {
+                    uint32_t col[kNumUnroll];
+                    double v[kNumUnroll];
 #pragma unroll
-                for (int u = 0; u < kNumUnroll; ++u)
-                    if (p0 + (uint32_t)(u * TEAM + t) < tot)
-                        ok = num_hash_add(keys, vals, col[u], v[u], lg) && ok;
-            }
-            __syncthreads();
-        }
-        if (!ok) s_fail = 1;
-        __syncthreads();
-        if (s_fail) {
-            if (t == 0) num_abort_row(row, item.rf, ctl, abort_list);
-            __syncthreads();
-            continue;
-        }
-        // compaction of the occupied slots
-        uint32_t kk[SPT];
-        double vv[SPT];
-        uint32_t mine = 0;
+                    for (int u = 0; u < kNumUnroll; ++u) {
+                        const uint32_t pr = p0 + (uint32_t)(u * TEAM + t);
+                        const uint32_t p = pr < tot ? pr : tot - 1;
+                        int lo = 0, hi = nent;
+                        while (hi - lo > 1) {
+                            const int mid = (lo + hi) >> 1;
+                            if (s_off[mid] <= p) lo = mid;
+                            else hi = mid;
+                        }
+                        const int32_t q = s_b0[lo] + (int32_t)(p - s_off[lo]);
+                        col[u] = (uint32_t)B.col[q];
+                        v[u] = s_a[lo] * na.Bval[q];
+                    }
 #pragma unroll
-        for (int u = 0; u < SPT; ++u) {
-            const uint32_t s = (uint32_t)t * SPT + u;
-            kk[u] = s < T ? keys[s] : kEmpty;
-            vv[u] = s < T ? vals[s] : 0.0;
-            mine += kk[u] != kEmpty ? 1u : 0u;
-        }
-        uint32_t c;
-        uint32_t pos = block_excl_scan<TEAM, uint32_t>(mine, s_red, &c);
-        int64_t dst;
-        bool write, spill = false;
-        if (PASS == 1) {
-            if (t == 0) na.cnt[row] = (int64_t)c;
-            dst = na.slot_off[row];
-            write = (int64_t)c <= na.slot_off[row + 1] - dst;
-            if (!write && na.sp_cap > 0 && 2 * c <= T) {  // the whole row to the area
-                if (t == 0) {
-                    int64_t o = -1;
-                    if (spill_take_row(na, row, c, &o)) na.sp_state[row] = 2;
-                    s_spill = o;
+                    for (int u = 0; u < kNumUnroll; ++u)
+                        if (p0 + (uint32_t)(u * TEAM + t) < tot)
+                            ok = num_hash_add(keys, vals, col[u], v[u], lg) && ok;
                 }
                 __syncthreads();
-                spill = write = s_spill >= 0;
-                dst = s_spill;
             }
-        } else {
-            dst = na.C_rpt[row];
-            write = dst + (int64_t)c <= na.capacity;
-        }
-        if (write) {  // (then c <= T / 2)
-#pragma unroll
-            for (int u = 0; u < SPT; ++u)
-                if (kk[u] != kEmpty) {
-                    keys[pos] = kk[u];
-                    vals[pos] = vv[u];
-                    ++pos;
-                }
-            const uint32_t c4 = (c + 3u) & ~3u;
-            if ((uint32_t)t < c4 - c) keys[c + t] = kEmpty;
+            if (!ok) s_fail = 1;
             __syncthreads();
-            num_write_ranked<TEAM, SPT / 2>(keys, vals, c, t,
-                                            PASS == 2 ? na.C_col : spill ? na.sp_col : na.slot_col,
-                                            PASS == 2 ? na.C_val : spill ? na.sp_val : na.slot_val, dst);
+            if (s_fail) {
+                if (t == 0) num_abort_row(row, item.rf, ctl, abort_list);
+                __syncthreads();
+                continue;
+            }
+            // compaction of the occupied slots
+            uint32_t kk[SPT];
+            double vv[SPT];
+            uint32_t mine = 0;
+#pragma unroll
+            for (int u = 0; u < SPT; ++u) {
+                const uint32_t s = (uint32_t)t * SPT + u;
+                kk[u] = s < T ? keys[s] : kEmpty;
+                vv[u] = s < T ? vals[s] : 0.0;
+                mine += kk[u] != kEmpty ? 1u : 0u;
+            }
+            uint32_t c;
+            uint32_t pos = block_excl_scan<TEAM, uint32_t>(mine, s_red, &c);
+            int64_t dst;
+            bool write, spill = false;
+            if (PASS == 1) {
+                if (t == 0) na.cnt[row] = (int64_t)c;
+                dst = na.slot_off[row];
+                write = (int64_t)c <= na.slot_off[row + 1] - dst;
+                if (!write && na.sp_cap > 0 && 2 * c <= T) {  // the whole row to the area
+                    if (t == 0) {
+                        int64_t o = -1;
+                        if (spill_take_row(na, row, c, &o)) na.sp_state[row] = 2;
+                        s_spill = o;
+                    }
+                    __syncthreads();
+                    spill = write = s_spill >= 0;
+                    dst = s_spill;
+                }
+            } else {
+                dst = na.C_rpt[row];
+                write = dst + (int64_t)c <= na.capacity;
+            }
+            if (write) {  // (then c <= T / 2)
+#pragma unroll
+                for (int u = 0; u < SPT; ++u)
+                    if (kk[u] != kEmpty) {
+                        keys[pos] = kk[u];
+                        vals[pos] = vv[u];
+                        ++pos;
+                    }
+                const uint32_t c4 = (c + 3u) & ~3u;
+                if ((uint32_t)t < c4 - c) keys[c + t] = kEmpty;
+                __syncthreads();
+                num_write_ranked<TEAM, SPT / 2>(
+                    keys, vals, c, t, PASS == 2 ? na.C_col : spill ? na.sp_col : na.slot_col,
+                    PASS == 2 ? na.C_val : spill ? na.sp_val : na.slot_val, dst);
+            }
+            __syncthreads();  // the table is reset for the next row
         }
-        __syncthreads();  // the table is reset for the next row
     }
 }
 
@@ -1045,8 +1095,11 @@ __global__ __launch_bounds__(256) void k_num_spill_copy(NumArgs na, int64_t nrec
 constexpr int kNumWinCols = 16384;
 
 // agg[5] != 0 when some row of B has a column smaller than its predecessor.
-__global__ __launch_bounds__(256) void k_num_check_sorted(Csr B, NumArgs na)
+// Only the long rows' kernels depend on it: with no such row (bins 4 and 6
+// empty, counted by the row-FLOP pass before this launch) nothing is read.
+__global__ __launch_bounds__(256) void k_num_check_sorted(Csr B, const Ctl* ctl, NumArgs na)
 {
+    if (ctl->bin_cnt[4] + ctl->bin_cnt[6] == 0) return;
     const int lane = lane_id();
     const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kWave;
     const int64_t nwaves = (int64_t)gridDim.x * 256 / kWave;
@@ -1090,6 +1143,9 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
     __shared__ int32_t s_b0[TEAM];
     __shared__ uint32_t s_off[TEAM];
     __shared__ double s_a[TEAM];
+    __shared__ int32_t s_cur[TEAM];   // per A entry: the cursor in its B row,
+    __shared__ int32_t s_ccol[TEAM];  // the column there (INT32_MAX past the end),
+    __shared__ int32_t s_pe[TEAM];    // the B row's end
     __shared__ uint64_t s_red[TEAM / kWave + 1];
     __shared__ uint32_t s_k;
     __shared__ int64_t s_spill;
@@ -1118,13 +1174,30 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
             continue;
         }
         const int32_t a0 = item.e_lo, a1 = item.e_hi;
-        // cursors at the start of every named B row
-        for (int32_t e = a0 + t; e < a1; e += TEAM) {
-            const int32_t kk = A.col[e];
-            const int32_t p = B.rpt[kk], pe = B.rpt[kk + 1];
-            cur[e - a0] = make_int2(p, p < pe ? B.col[p] : INT32_MAX);
+        // Each A entry's state: its B row's cursor (the next position, and
+        // that position's column) and end, and its A value.  A row of at most
+        // TEAM entries keeps it in LDS for all the windows; a longer row keeps
+        // the cursors in global scratch and loads TEAM entries' state per
+        // window.
+        const bool in_lds = a1 - a0 <= TEAM;  // (uniform)
+        if (in_lds) {
+            const int32_t e = a0 + t;
+            if (e < a1) {
+                const int32_t kk = A.col[e];
+                const int32_t p = B.rpt[kk], pe = B.rpt[kk + 1];
+                s_cur[t] = p;
+                s_pe[t] = pe;
+                s_ccol[t] = p < pe ? B.col[p] : INT32_MAX;
+                s_a[t] = na.Aval[e];
+            }
+        } else {
+            for (int32_t e = a0 + t; e < a1; e += TEAM) {
+                const int32_t kk = A.col[e];
+                const int32_t p = B.rpt[kk], pe = B.rpt[kk + 1];
+                cur[e - a0] = make_int2(p, p < pe ? B.col[p] : INT32_MAX);
+            }
+            __threadfence_block();
         }
-        __threadfence_block();
         __syncthreads();
         int64_t dst, cap;
         if (PASS == 1) {
@@ -1141,17 +1214,79 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
             const int64_t hi = (lo + kNumWinCols) < N ? (lo + kNumWinCols) : N;
             uint32_t any = 0;
             for (int32_t a = a0; a < a1; a += TEAM) {
-                const int32_t e = a + t;
-                uint32_t len = 0;
-                int32_t p = 0;
-                double av = 0.0;
-                if (e < a1) {
-                    const int2 c = cur[e - a0];
-                    p = c.x;
-                    if ((int64_t)c.y < hi) {  // (INT32_MAX: the B row is used up)
-                        const int32_t pe = B.rpt[A.col[e] + 1];
-                        // first position in (p, pe) whose column is >= hi, by
-                        // exponential then binary search (columns non-decreasing)
+                const int nent = (a1 - a) < TEAM ? (a1 - a) : TEAM;
+                if (!in_lds) {
+                    if (t < nent) {
+                        const int32_t e = a + t;
+                        const int2 c = cur[e - a0];
+                        s_cur[t] = c.x;
+                        s_ccol[t] = c.y;
+                        if ((int64_t)c.y < hi) {  // (INT32_MAX: the B row is used up)
+                            s_pe[t] = B.rpt[A.col[e] + 1];
+                            s_a[t] = na.Aval[e];
+                        }
+                    }
+                    __syncthreads();
+                }
+                // Each entry's products in the window are the positions from
+                // its cursor to the first one whose column is >= hi (columns
+                // non-decreasing).  G lanes search for that position together,
+                // the most that still give every entry of the chunk a group:
+                // each round probes G evenly spaced positions of the open
+                // interval and keeps the gap where the columns cross hi, so a
+                // span of m positions takes log_G(m) rounds of one load each.
+                int G = kWave;
+                while (G > 1 && TEAM / G < nent) G >>= 1;
+                if (G > 1) {
+                    const int lane = t & (kWave - 1);
+                    const int gbase = lane & ~(G - 1);
+                    const int j = lane - gbase;
+                    const int ei = t / G;
+                    const uint64_t gmask = G == kWave ? ~0ull : (((1ull << G) - 1ull) << gbase);
+                    bool act = false;
+                    int32_t L = 0, R = 0, Rc = INT32_MAX;
+                    if (ei < nent) {
+                        L = s_cur[ei];
+                        act = (int64_t)s_ccol[ei] < hi;
+                        R = act ? s_pe[ei] : L;
+                    }
+                    const int32_t p = L;
+                    // (L: a position whose column is < hi; R: the end of the B
+                    // row or a position whose column, Rc, is >= hi)
+                    for (;;) {
+                        const bool go = act && R - L > 1;
+                        if (!__ballot(go)) break;  // (uniform over the wave)
+                        const int32_t step = go ? (R - L - 1 + G - 1) / G : 1;
+                        const int32_t pos = L + 1 + j * step;
+                        const bool probe = go && pos < R;
+                        int32_t cv = INT32_MAX;
+                        if (probe) cv = B.col[pos];
+                        const uint64_t okm = __ballot(probe && (int64_t)cv < hi) & gmask;
+                        const int n = __popcll(okm);  // (the probes below hi: a prefix)
+                        const int32_t fc = __shfl(cv, gbase + (n < G ? n : G - 1), kWave);
+                        if (go) {
+                            const int32_t fp = L + 1 + n * step;  // the first probe >= hi
+                            if (n > 0) L += 1 + (n - 1) * step;
+                            if (fp < R) {
+                                R = fp;
+                                Rc = fc;
+                            }
+                        }
+                    }
+                    if (ei < nent && j == 0) {
+                        s_b0[ei] = p;
+                        s_off[ei] = act ? (uint32_t)(R - p) : 0u;
+                        if (act) {
+                            s_cur[ei] = R;
+                            s_ccol[ei] = Rc;
+                        }
+                    }
+                } else if (t < nent) {
+                    // one entry per thread: exponential then binary search
+                    const int32_t p = s_cur[t];
+                    uint32_t len = 0;
+                    if ((int64_t)s_ccol[t] < hi) {
+                        const int32_t pe = s_pe[t];
                         int32_t good = p, step = 1;
                         while (good + step < pe && (int64_t)B.col[good + step] < hi) {
                             good += step;
@@ -1164,18 +1299,22 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
                             else bad = mid;
                         }
                         len = (uint32_t)(bad - p);
-                        cur[e - a0] = make_int2(bad, bad < pe ? B.col[bad] : INT32_MAX);
-                        av = na.Aval[e];
+                        s_cur[t] = bad;
+                        s_ccol[t] = bad < pe ? B.col[bad] : INT32_MAX;
                     }
+                    s_b0[t] = p;
+                    s_off[t] = len;
                 }
+                __syncthreads();
                 uint32_t tot;
+                const uint32_t len = t < nent ? s_off[t] : 0u;
                 const uint32_t off = block_excl_scan<TEAM, uint32_t>(len, (uint32_t*)s_red, &tot);
-                s_b0[t] = p;
-                s_off[t] = off;
-                s_a[t] = av;
+                if (t < nent) {
+                    s_off[t] = off;
+                    if (!in_lds) cur[a + t - a0] = make_int2(s_cur[t], s_ccol[t]);
+                }
                 __syncthreads();
                 any |= tot;
-                const int nent = (a1 - a) < TEAM ? (a1 - a) : TEAM;
                 for (uint32_t p0 = 0; p0 < tot; p0 += TEAM * kNumUnroll) {
                     uint32_t colv[kNumUnroll];
                     double vv[kNumUnroll];

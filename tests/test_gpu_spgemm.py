@@ -274,6 +274,43 @@ def test_spgemm_long_rows_unsorted_wide_b(ssp):
     check(ssp, A, B, av, bv, counts - 7, 0, True, "dense, unsorted B, N = 600000, overflow")
 
 
+def test_spgemm_window_search_entry_counts(ssp):
+    # long rows of 1 to 2100 A entries over sorted B rows of up to 12,000
+    # entries spanning seven column windows: every group size of the window
+    # search (64 lanes per A entry down to one thread per entry), rows whose
+    # entries fill several chunks of the workgroup (their cursors in global
+    # scratch), B rows with every column twice, and short rows beside them
+    rng = np.random.default_rng(31)
+    K, N = 4000, 110000
+    longb = rng.random(K) < 0.1
+    blen = np.where(longb, rng.integers(3000, 6000, K), rng.integers(0, 60, K))
+    brows = []
+    for k in range(K):
+        r = np.sort(rng.choice(N, size=int(blen[k]), replace=False))
+        if longb[k] and k % 4 == 0:
+            r = np.repeat(r, 2)
+        brows.append(r)
+    B = from_rows(brows, N)
+    long_ids, short_ids = np.nonzero(longb)[0], np.nonzero(~longb)[0]
+    arows = []
+    for n in (1, 2, 3, 16, 17, 33, 64, 100, 257, 300, 513, 600, 1024, 1025, 1100, 2049, 2100):
+        first = rng.choice(long_ids, size=min(n, 3), replace=False)
+        rest = rng.choice(K, size=n - len(first), replace=False) if n > 3 else []
+        arows.append(np.concatenate([first, np.asarray(rest, dtype=np.int64)]))
+    for _ in range(40):  # short rows (the hash bins)
+        arows.append(rng.choice(short_ids, size=int(rng.integers(0, 8)), replace=False))
+    rng.shuffle(arows)
+    A = from_rows([np.sort(r) for r in arows], K)
+    av, bv = _values(A, 12, "int"), _values(B, 13, "int")
+    counts, _ = oracle.exact(A, B)
+    rf = np.asarray(oracle.row_flop(A, B)[0])
+    assert (rf > 2048).sum() >= 17
+    check(ssp, A, B, av, bv, counts, 0, True, "window search, exact caps")
+    check(ssp, A, B, av, bv, counts - 1, 0, True, "window search, fallback pass")
+    check(ssp, A, B, av, bv, counts // 3, 0, True, "window search, area 300%", spill=300,
+          held=True)
+
+
 # ------------------------------------------------ the overflow area
 
 
