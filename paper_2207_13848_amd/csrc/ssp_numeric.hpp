@@ -1344,8 +1344,14 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
                 __syncthreads();
             }
             if (!any) continue;  // (uniform: no product of the row in this window)
-            // the window's entries in column order, then cleared
-            const uint32_t bits = t < WW ? s_flag[t] : 0u;
+            // The window's entries in column order, then cleared.  Wave v
+            // takes the bitmap words [32 v, 32 v + 32) and its lanes write
+            // consecutive entries, so each store of a wave is coalesced (a
+            // lane per word would scatter them 32 entries apart).
+            static_assert(TEAM / kWave * 32 == WW, "32 bitmap words per wave");
+            const int wv = t / kWave, ln = t % kWave;
+            const int widx = wv * 32 + ln;
+            const uint32_t bits = ln < 32 ? s_flag[widx] : 0u;
             uint64_t wtot;
             const uint64_t ex = block_excl_scan<TEAM, uint64_t>((uint64_t)__popc(bits), s_red, &wtot);
             // entries from position `from` on go to the overflow area at `sp`
@@ -1388,23 +1394,47 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
                 __syncthreads();
                 sp = s_spill;
             }
-            int64_t o = c_total + (int64_t)ex;
-            uint32_t bb = bits;
-            while (bb) {
-                const uint32_t b = (uint32_t)__builtin_ctz(bb);
-                bb &= bb - 1u;
-                const uint32_t x = (uint32_t)t * 32u + b;
+            // (the wave's first entry, its count, and each word's first entry
+            // within the wave, in s_off: free until the next window)
+            const uint64_t ex0 = __shfl(ex, 0, kWave);
+            const uint32_t wn = (uint32_t)(__shfl(ex, 32, kWave) - ex0);
+            if (ln < 32) s_off[widx] = (uint32_t)(ex - ex0);
+            wave_sync();
+            const uint32_t* wpre = &s_off[wv * 32];
+            for (uint32_t k = (uint32_t)ln; k < wn; k += kWave) {
+                // the word holding the wave's k-th entry (the last word whose
+                // first entry is <= k: words without entries share the next
+                // one's), then the rank of the entry's bit within it
+                int w0 = 0, w1 = 32;
+                while (w1 - w0 > 1) {
+                    const int mid = (w0 + w1) >> 1;
+                    if (wpre[mid] <= k) w0 = mid;
+                    else w1 = mid;
+                }
+                uint32_t b = s_flag[wv * 32 + w0], r = k - wpre[w0], pos = 0, c;
+                c = (uint32_t)__popc(b & 0xFFFFu);
+                if (r >= c) { r -= c; b >>= 16; pos += 16; }
+                c = (uint32_t)__popc(b & 0xFFu);
+                if (r >= c) { r -= c; b >>= 8; pos += 8; }
+                c = (uint32_t)__popc(b & 0xFu);
+                if (r >= c) { r -= c; b >>= 4; pos += 4; }
+                c = (uint32_t)__popc(b & 0x3u);
+                if (r >= c) { r -= c; b >>= 2; pos += 2; }
+                if (r >= (b & 1u)) pos += 1;
+                const uint32_t x = (uint32_t)(wv * 32 + w0) * 32u + pos;
+                const int64_t o = c_total + (int64_t)ex0 + (int64_t)k;
+                const double v = s_acc[x];
                 if (o < cap) {
                     ocol[dst + o] = (int32_t)(lo + x);
-                    oval[dst + o] = s_acc[x];
+                    oval[dst + o] = v;
                 } else if (sp >= 0) {
                     na.sp_col[sp + (o - from)] = (int32_t)(lo + x);
-                    na.sp_val[sp + (o - from)] = s_acc[x];
+                    na.sp_val[sp + (o - from)] = v;
                 }
                 s_acc[x] = 0.0;
-                ++o;
             }
-            if (t < WW) s_flag[t] = 0u;
+            wave_sync();
+            if (ln < 32) s_flag[widx] = 0u;
             c_total += (int64_t)wtot;
             __syncthreads();
         }

@@ -279,7 +279,8 @@ def test_spgemm_window_search_entry_counts(ssp):
     # entries spanning seven column windows: every group size of the window
     # search (64 lanes per A entry down to one thread per entry), rows whose
     # entries fill several chunks of the workgroup (their cursors in global
-    # scratch), B rows with every column twice, and short rows beside them
+    # scratch), rows of few products per window, B rows with every column
+    # twice, and short rows beside them
     rng = np.random.default_rng(31)
     K, N = 4000, 110000
     longb = rng.random(K) < 0.1
@@ -297,6 +298,10 @@ def test_spgemm_window_search_entry_counts(ssp):
         first = rng.choice(long_ids, size=min(n, 3), replace=False)
         rest = rng.choice(K, size=n - len(first), replace=False) if n > 3 else []
         arows.append(np.concatenate([first, np.asarray(rest, dtype=np.int64)]))
+    for nl, ns in ((1, 7), (2, 14), (1, 30), (1, 63), (3, 61)):
+        # long rows with few products per window
+        arows.append(np.concatenate([rng.choice(long_ids, size=nl, replace=False),
+                                     rng.choice(short_ids, size=ns, replace=False)]))
     for _ in range(40):  # short rows (the hash bins)
         arows.append(rng.choice(short_ids, size=int(rng.integers(0, 8)), replace=False))
     rng.shuffle(arows)
@@ -304,7 +309,7 @@ def test_spgemm_window_search_entry_counts(ssp):
     av, bv = _values(A, 12, "int"), _values(B, 13, "int")
     counts, _ = oracle.exact(A, B)
     rf = np.asarray(oracle.row_flop(A, B)[0])
-    assert (rf > 2048).sum() >= 17
+    assert (rf > 2048).sum() >= 22
     check(ssp, A, B, av, bv, counts, 0, True, "window search, exact caps")
     check(ssp, A, B, av, bv, counts - 1, 0, True, "window search, fallback pass")
     check(ssp, A, B, av, bv, counts // 3, 0, True, "window search, area 300%", spill=300,
