@@ -1083,11 +1083,13 @@ __global__ __launch_bounds__(256) void k_num_spill_copy(NumArgs na, int64_t nrec
 // is accumulated one window of kNumWinCols columns at a time, entirely in LDS
 // (a dense float64 window and its bitmap), with no global atomics.  A cursor
 // per A entry of the row (its next position in the named B row, and that
-// position's column) lives in global scratch between windows, so every
-// product is read once: in a window an entry whose cursor column lies beyond
-// the window is skipped, the others find their end in the window by
-// exponential search.  Window by window the set bits are ranked (popcount
-// scan) and the row's entries written in column order; the first pass writes
+// position's column) lives in LDS between windows, or in global scratch for
+// rows of more entries than the workgroup has threads, so every product is
+// read once: in a window an entry whose cursor column lies beyond the window
+// is skipped, the others find their end in the window (a search by up to 64
+// lanes per entry).  Window by window the set bits are ranked (popcount scan)
+// and the row's entries written in column order, each wave's stores
+// coalesced; the first pass writes
 // what fits the row's slot to the slot and, with an overflow area, the rest
 // to the area: thread 0 keeps the workgroup's current chunk of the area and
 // the row's current run (positions and area offsets both consecutive), and
