@@ -1103,15 +1103,23 @@ constexpr int kNumWinCols = 16384;
 __global__ __launch_bounds__(256) void k_num_check_sorted(Csr B, const Ctl* ctl, NumArgs na)
 {
     if (ctl->bin_cnt[4] + ctl->bin_cnt[6] == 0) return;
-    const int lane = lane_id();
-    const int64_t wave = ((int64_t)blockIdx.x * 256 + threadIdx.x) / kWave;
-    const int64_t nwaves = (int64_t)gridDim.x * 256 / kWave;
+    // Flat over the entries (a thread per pair of neighbours, so a row of any
+    // length is shared out): a descent is an error unless the second entry
+    // starts a row, which a binary search over the row pointers tells (the
+    // last row starting at or before the first entry ends right after it).
     bool bad = false;
-    for (int64_t r = wave; r < B.nrows; r += nwaves) {
-        const int32_t b0 = B.rpt[r], b1 = B.rpt[r + 1];
-        for (int32_t q = b0 + lane; q + 1 < b1; q += kWave) bad = bad || (B.col[q] > B.col[q + 1]);
+    const int64_t stride = (int64_t)gridDim.x * 256;
+    for (int64_t q = (int64_t)blockIdx.x * 256 + threadIdx.x; q + 1 < B.nnz; q += stride) {
+        if (B.col[q] <= B.col[q + 1]) continue;
+        int64_t lo = 0, hi = B.nrows;  // (B.rpt[0] = 0 <= q < B.rpt[B.nrows] = B.nnz)
+        while (hi - lo > 1) {
+            const int64_t mid = (lo + hi) >> 1;
+            if ((int64_t)B.rpt[mid] <= q) lo = mid;
+            else hi = mid;
+        }
+        bad = bad || (int64_t)B.rpt[lo + 1] != q + 1;
     }
-    if (__ballot(bad) && lane == 0) atomicOr((unsigned long long*)&na.agg[5], 1ull);
+    if (__ballot(bad) && lane_id() == 0) atomicOr((unsigned long long*)&na.agg[5], 1ull);
 }
 
 // agg[4] = the largest number of A entries of a bin-4 row.

@@ -209,7 +209,7 @@ ssp_status spgemm_compute(ssp_handle h, const ssp_csr* A, const double* A_val, c
         launch_num_scan(na, 0, cus, s);
         // (for the long rows: whether B's rows are sorted, their longest A row)
         if (B->nrows > 0 && B->nnz > 0)
-            hipLaunchKernelGGL(k_num_check_sorted, dim3((unsigned)std::min<int64_t>((B->nrows + 3) / 4, 8LL * cus)),
+            hipLaunchKernelGGL(k_num_check_sorted, dim3((unsigned)std::min<int64_t>((B->nnz + 255) / 256, 8LL * cus)),
                                dim3(256), 0, s, P.cs[0].B, (const Ctl*)S->b.ctl, na);
         hipLaunchKernelGGL(k_num_maxlen, dim3((unsigned)(2 * cus)), dim3(256), 0, s,
                            (const BigItem*)S->b.L.b4, S->b.ctl, S->b.L.cap4, na);
