@@ -397,9 +397,10 @@ SSP_API ssp_status ssp_validate_csr(ssp_handle h, const ssp_csr* M, int64_t* n_b
  * fits.  A row with more nonzeros than its slot keeps them in the overflow
  * area while the area lasts: a row of more than 2048 products the entries
  * past its first s_i (B's rows sorted), a shorter row all of them when it
- * completes within half its hash table (rows of at most 256 products always
- * do: with spill_pct > 0 their tables are sized for all their products).
- * The other overflowing rows are recomputed.  C_rpt then receives
+ * completes within half its hash table (with spill_pct > 0 a row's table is
+ * sized for all its products, so the row does, unless the table sized by
+ * its slot fits the one-wave kernel's 512 slots and a table for all its
+ * products would not).  The other overflowing rows are recomputed.  C_rpt then receives
  * C's row offsets from the exact counts.  Waits for `stream` twice (the slot
  * area's size and the results are read on the host) and fills *info.
  *   A_val, B_val : device double[A.nnz], double[B.nnz]; duplicate entries add.
