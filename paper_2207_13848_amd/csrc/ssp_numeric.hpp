@@ -1096,6 +1096,11 @@ __global__ __launch_bounds__(256) void k_num_spill_copy(NumArgs na, int64_t nrec
 // records a run when the chunk changes or the row ends.  A row that the area
 // cannot hold is redone by the fallback pass.  The exact count is recorded.
 constexpr int kNumWinCols = 16384;
+// Products per thread whose loads are in flight together in a window: two
+// (and slots past the window's products skipped), since most windows hold
+// far fewer products than the workgroup has threads (R-MAT 2^18: 46.5 ms
+// with four, 44.1 with one, 42.9 with two; eight and sixteen were slower).
+constexpr int kNumWinUnroll = 2;
 
 // agg[5] != 0 when some row of B has a column smaller than its predecessor.
 // Only the long rows' kernels depend on it: with no such row (bins 4 and 6
@@ -1326,11 +1331,14 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
                 }
                 __syncthreads();
                 any |= tot;
-                for (uint32_t p0 = 0; p0 < tot; p0 += TEAM * kNumUnroll) {
-                    uint32_t colv[kNumUnroll];
-                    double vv[kNumUnroll];
+                for (uint32_t p0 = 0; p0 < tot; p0 += TEAM * kNumWinUnroll) {
+                    uint32_t colv[kNumWinUnroll];
+                    double vv[kNumWinUnroll];
 #pragma unroll
-                    for (int u = 0; u < kNumUnroll; ++u) {
+                    for (int u = 0; u < kNumWinUnroll; ++u) {
+                        colv[u] = 0;
+                        vv[u] = 0.0;
+                        if (p0 + (uint32_t)(u * TEAM) >= tot) continue;  // (uniform: no product)
                         const uint32_t pr = p0 + (uint32_t)(u * TEAM + t);
                         const uint32_t pp = pr < tot ? pr : tot - 1;
                         int lo2 = 0, hi2 = nent;
@@ -1344,7 +1352,7 @@ __global__ __launch_bounds__(kNumDenseTeam) void k_num_dense_win(const CaseDesc*
                         vv[u] = s_a[lo2] * na.Bval[q];
                     }
 #pragma unroll
-                    for (int u = 0; u < kNumUnroll; ++u) {
+                    for (int u = 0; u < kNumWinUnroll; ++u) {
                         if (p0 + (uint32_t)(u * TEAM + t) >= tot) continue;
                         const uint32_t x = colv[u] - (uint32_t)lo;  // (in [0, kNumWinCols))
                         __hip_atomic_fetch_add(&s_acc[x], vv[u], __ATOMIC_RELAXED,
